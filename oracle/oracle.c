@@ -1,0 +1,611 @@
+/*
+ * Reference oracle for the Monte Carlo estimator of exp(tA) v
+ * (Acebron, "A Monte Carlo method for computing the action of a matrix
+ * exponential on a vector", arXiv:1904.12759).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is plain, slow, sequential FP64 C that
+ * follows the method step by step.  It shares no code with the HIP library and
+ * is used only by the tests, by the smoke check and by the CPU-baseline leg of
+ * the benchmark.  Nothing in the product path may call it.
+ *
+ * What it computes (paper Sec. 2, Lemma 1 / Theorem 1, and Sec. 3, Eq. (paths),
+ * Algorithm 1):
+ *   A = D - L with L a Laplacian-like matrix: off-diagonal entries of A are the
+ *   jump rates of a continuous-time Markov chain with generator Q = -L.  With
+ *   our general reading, for row i
+ *       r_i   = sum_{j != i} a_ij        (total jump rate, L_ii)
+ *       d_i   = a_ii + r_i               (diagonal of D)
+ *       k_ij  = a_ij / r_i               (jump law of Eq. (paths))
+ *   A walker started at i spends Exp(r_x) holding times in each visited state
+ *   x, jumps with law k_x., and stops at the horizon t.  The weight is
+ *   exp(integral of d(X_s) ds) evaluated exactly (EXACT, the N -> infinity
+ *   limit of the splittings), with the trapezoid rule on the grid k*dt
+ *   (STRANG, Eq. (eq_general1) and Theorem 1) or with the right Riemann sum on
+ *   the grid (LIE, Eq. (deff)).  The single-entry estimate is the mean over
+ *   walkers of weight * v[X_t] (Algorithm 1 with the sample mean taken over the
+ *   M walkers, Sec. 5).
+ *
+ * Conventions fixed where the paper leaves a choice (each is a reading of the
+ * paper, the same one the library follows):
+ *   - random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed
+ *     (low word first), counter = (event index, walker ordinal, start node,
+ *     instance id).  One counter value per holding interval.
+ *   - U = (m + 1) * 2^-53 with m = (o0 << 21) | (o1 >> 11), so U in (0, 1];
+ *     holding time S = -log(U) / r_x computed as -log(U) * (1/r_x).
+ *   - the holding time is drawn in the state it is spent in; a jump happens iff
+ *     s + S < t (strict), i.e. the residual holding time at a grid point is
+ *     carried over (memorylessness) instead of being redrawn as in the printed
+ *     Algorithm 1; the two are equal in law.
+ *   - jump target: Vose alias table over the positive off-diagonal entries of
+ *     the row (CSR order), slot = floor(o2 * deg / 2^32), "keep the slot's own
+ *     column" iff o3 < floor(q * 2^32).  This replaces the row scan of Sec. 4
+ *     with an O(1) draw of the same law (up to 2^-32 quantisation).
+ *   - grid membership: grid point k belongs to state X(k dt) where the state
+ *     entered at time s owns the grid points K(s) <= k < K(next jump), with
+ *     K(s) = min(N, ceil(s * (N / t))) evaluated in IEEE FP64.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+/* ------------------------------------------------------------------ status */
+enum {
+    OR_OK = 0,
+    OR_ERR_INVALID_ARG = 1,
+    OR_ERR_NOT_METZLER = 2,
+    OR_ERR_NONFINITE = 3,
+    OR_ERR_OUT_OF_RANGE = 4,
+    OR_ERR_NO_MEMORY = 6,
+    OR_ERR_WALK_LIMIT = 8,
+    OR_ERR_OVERFLOW = 9,
+};
+
+enum { OR_EXACT = 0, OR_STRANG = 1, OR_LIE = 2 };
+
+/* ---------------------------------------------------------- Philox4x32-10 */
+/* Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+ * SC'11: ten rounds of the Philox S-P network with multipliers
+ * 0xD2511F53, 0xCD9E8D57 and Weyl key increments 0x9E3779B9, 0xBB67AE85. */
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* U in (0,1] from the first two output words. */
+static double uniform_open0(uint32_t o0, uint32_t o1)
+{
+    uint64_t m = ((uint64_t)o0 << 21) | ((uint64_t)o1 >> 11);
+    return (double)(m + 1u) * 0x1p-53;
+}
+
+/* ------------------------------------------------------------------ model */
+typedef struct {
+    /* per row */
+    double *a_diag, *r, *d, *inv_r;
+    int64_t *deg, *begin;         /* slots of row i: begin[i] .. begin[i]+deg[i]-1 */
+    int32_t *uniform;
+    /* per slot, in CSR order of the positive off-diagonal entries */
+    int32_t *col;
+    double *val;
+    uint32_t *thr;
+    int32_t *alias;
+    int32_t *alias_slot;          /* slot (within the row) the alias column comes from */
+    double *logcorr;              /* proposal only: -b of the slot's own edge */
+} table_set;
+
+typedef struct {
+    int64_t n, nnz, nslots;
+    double t;
+    uint64_t seed;
+    int mode;
+    int64_t ngrid;                /* N, number of splitting steps */
+    double dt;                    /* t / N */
+    double inv_dt;                /* N / t */
+    uint32_t instance;
+    uint32_t max_events;
+    table_set plain;
+    int has_proposal;
+    table_set prop;
+    int64_t *slot_of_csr;         /* CSR position -> slot index, -1 if none */
+} oracle_t;
+
+static void free_tables(table_set *ts)
+{
+    free(ts->a_diag); free(ts->r); free(ts->d); free(ts->inv_r);
+    free(ts->deg); free(ts->begin); free(ts->uniform);
+    free(ts->col); free(ts->val); free(ts->thr); free(ts->alias); free(ts->alias_slot);
+    free(ts->logcorr);
+    memset(ts, 0, sizeof(*ts));
+}
+
+void oracle_destroy(oracle_t *o)
+{
+    if (!o) return;
+    free_tables(&o->plain);
+    free_tables(&o->prop);
+    free(o->slot_of_csr);
+    free(o);
+}
+
+/* Vose's alias method (M. D. Vose, IEEE TSE 17(9), 1991) for one row.
+ * q[s] = p_s * deg are the scaled probabilities; the two work lists are
+ * LIFO stacks filled by scanning s = 0 .. deg-1.  Output: per slot the
+ * integer threshold floor(q * 2^32) of keeping the slot's own column and the
+ * alias column; slots whose final q is >= 1 alias to themselves. */
+static int vose_row(int64_t deg, double *q, const int32_t *col, uint32_t *thr, int32_t *alias,
+                    int32_t *alias_slot_out)
+{
+    int64_t *small = (int64_t *)malloc(sizeof(int64_t) * (size_t)deg);
+    int64_t *large = (int64_t *)malloc(sizeof(int64_t) * (size_t)deg);
+    if (!small || !large) { free(small); free(large); return OR_ERR_NO_MEMORY; }
+    int64_t ns = 0, nl = 0;
+    int32_t *alias_slot = (int32_t *)malloc(sizeof(int32_t) * (size_t)deg);
+    if (!alias_slot) { free(small); free(large); return OR_ERR_NO_MEMORY; }
+    for (int64_t s = 0; s < deg; ++s) {
+        alias_slot[s] = (int32_t)s;
+        if (q[s] < 1.0) small[ns++] = s; else large[nl++] = s;
+    }
+    double *prob = (double *)malloc(sizeof(double) * (size_t)deg);
+    if (!prob) { free(small); free(large); free(alias_slot); return OR_ERR_NO_MEMORY; }
+    for (int64_t s = 0; s < deg; ++s) prob[s] = 1.0;
+    while (ns > 0 && nl > 0) {
+        int64_t l = small[--ns];
+        int64_t g = large[--nl];
+        prob[l] = q[l];
+        alias_slot[l] = (int32_t)g;
+        q[g] = (q[g] + q[l]) - 1.0;
+        if (q[g] < 1.0) small[ns++] = g; else large[nl++] = g;
+    }
+    /* whatever is left (large, or small through rounding) keeps itself */
+    for (int64_t s = 0; s < deg; ++s) {
+        if (prob[s] >= 1.0 || alias_slot[s] == (int32_t)s) {
+            thr[s] = 0xFFFFFFFFu;
+            alias[s] = col[s];
+            alias_slot_out[s] = (int32_t)s;
+        } else {
+            thr[s] = (uint32_t)(prob[s] * 4294967296.0);   /* floor, prob in [0,1) */
+            alias[s] = col[alias_slot[s]];
+            alias_slot_out[s] = alias_slot[s];
+        }
+    }
+    free(small); free(large); free(alias_slot); free(prob);
+    return OR_OK;
+}
+
+/* Split every row into diagonal, jump rate and jump law (paper Sec. 2 and
+ * Eq. (paths)); build the alias tables.  If bias is non-NULL the jump rates
+ * are tilted: a~_ij = a_ij * exp(b_ij), r~_i = sum a~_ij, d~_i = d_i + (r~_i - r_i)
+ * and every jump over edge ij carries the log-weight correction -b_ij. */
+static int build_tables(const oracle_t *o, const int64_t *rowptr, const int32_t *colv,
+                        const double *valv, const float *bias, const table_set *base,
+                        table_set *ts)
+{
+    int64_t n = o->n, ns = o->nslots;
+    ts->a_diag = (double *)calloc((size_t)n, sizeof(double));
+    ts->r = (double *)calloc((size_t)n, sizeof(double));
+    ts->d = (double *)calloc((size_t)n, sizeof(double));
+    ts->inv_r = (double *)calloc((size_t)n, sizeof(double));
+    ts->deg = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    ts->begin = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    ts->uniform = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+    ts->col = (int32_t *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(int32_t));
+    ts->val = (double *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(double));
+    ts->thr = (uint32_t *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(uint32_t));
+    ts->alias = (int32_t *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(int32_t));
+    ts->alias_slot = (int32_t *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(int32_t));
+    ts->logcorr = (double *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(double));
+    if (!ts->a_diag || !ts->r || !ts->d || !ts->inv_r || !ts->deg || !ts->begin ||
+        !ts->uniform || !ts->col || !ts->val || !ts->thr || !ts->alias || !ts->alias_slot ||
+        !ts->logcorr)
+        return OR_ERR_NO_MEMORY;
+
+    int64_t slot = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double diag = 0.0, rate = 0.0;
+        int64_t deg = 0;
+        ts->begin[i] = slot;
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int32_t j = colv[p];
+            double a = valv[p];
+            if (j == i) {
+                diag = diag + a;
+            } else if (a > 0.0) {
+                double at = a;
+                if (bias) {
+                    at = a * exp((double)bias[p]);
+                    if (!isfinite(at) || !(at > 0.0)) return OR_ERR_NONFINITE;
+                    ts->logcorr[slot] = -(double)bias[p];
+                }
+                ts->col[slot] = j;
+                ts->val[slot] = at;
+                rate = rate + at;
+                ++slot; ++deg;
+            }
+        }
+        ts->a_diag[i] = diag;
+        ts->r[i] = rate;
+        ts->deg[i] = deg;
+        if (base) {
+            /* tilted weight exponent d~ = d + (r~ - r); exactly d when r~ == r */
+            ts->d[i] = base->d[i] + (rate - base->r[i]);
+        } else {
+            ts->d[i] = diag + rate;
+        }
+        if (deg > 0) {
+            ts->inv_r[i] = 1.0 / rate;
+            if (!isfinite(ts->inv_r[i])) return OR_ERR_INVALID_ARG;
+        } else {
+            ts->inv_r[i] = 0.0;
+        }
+        if (!isfinite(ts->d[i])) return OR_ERR_NONFINITE;
+        /* alias table */
+        if (deg > 0) {
+            int64_t b = ts->begin[i];
+            int uni = 1;
+            for (int64_t s = 1; s < deg; ++s)
+                if (ts->val[b + s] != ts->val[b]) { uni = 0; break; }
+            ts->uniform[i] = uni;
+            if (uni) {
+                for (int64_t s = 0; s < deg; ++s) {
+                    ts->thr[b + s] = 0xFFFFFFFFu;
+                    ts->alias[b + s] = ts->col[b + s];
+                    ts->alias_slot[b + s] = (int32_t)s;
+                }
+            } else {
+                double *q = (double *)malloc(sizeof(double) * (size_t)deg);
+                if (!q) return OR_ERR_NO_MEMORY;
+                for (int64_t s = 0; s < deg; ++s)
+                    q[s] = (ts->val[b + s] * (double)deg) / rate;
+                int st = vose_row(deg, q, ts->col + b, ts->thr + b, ts->alias + b,
+                                  ts->alias_slot + b);
+                free(q);
+                if (st != OR_OK) return st;
+            }
+        }
+    }
+    return OR_OK;
+}
+
+/* Validate the CSR matrix: shape, column range, finiteness and the sign of the
+ * off-diagonal entries (they are jump rates, so they must be >= 0). */
+static int validate(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+                    const double *val, double t)
+{
+    if (n < 0 || nnz < 0) return OR_ERR_INVALID_ARG;
+    if (!(t >= 0.0) || !isfinite(t)) return OR_ERR_INVALID_ARG;
+    if (n == 0) return OR_OK;
+    if (!rowptr || rowptr[0] != 0 || rowptr[n] != nnz) return OR_ERR_INVALID_ARG;
+    if (nnz > 0 && (!col || !val)) return OR_ERR_INVALID_ARG;
+    if (nnz >= ((int64_t)1 << 32)) return OR_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < n; ++i)
+        if (rowptr[i + 1] < rowptr[i]) return OR_ERR_INVALID_ARG;
+    int err = OR_OK;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            if (col[p] < 0 || col[p] >= n) return OR_ERR_INVALID_ARG;
+            if (!isfinite(val[p])) { if (err == OR_OK) err = OR_ERR_NONFINITE; continue; }
+            if (col[p] != i && val[p] < 0.0) { if (err == OR_OK) err = OR_ERR_NOT_METZLER; }
+        }
+    }
+    return err;
+}
+
+/* Create the oracle for matrix A (CSR, host arrays), horizon t and seed. */
+int oracle_create(oracle_t **out, int64_t n, int64_t nnz, const int64_t *rowptr,
+                  const int32_t *col, const double *val, double t, uint64_t seed, int mode,
+                  double dt_req, uint32_t instance, uint32_t max_events)
+{
+    *out = NULL;
+    int st = validate(n, nnz, rowptr, col, val, t);
+    if (st != OR_OK) return st;
+    if (mode != OR_EXACT && mode != OR_STRANG && mode != OR_LIE) return OR_ERR_INVALID_ARG;
+    oracle_t *o = (oracle_t *)calloc(1, sizeof(oracle_t));
+    if (!o) return OR_ERR_NO_MEMORY;
+    o->n = n; o->nnz = nnz; o->t = t; o->seed = seed; o->mode = mode;
+    o->instance = instance;
+    o->max_events = max_events ? max_events : (1u << 24);
+    o->ngrid = 1;
+    if (mode != OR_EXACT) {
+        if (!(dt_req > 0.0) || !isfinite(dt_req)) { free(o); return OR_ERR_INVALID_ARG; }
+        double steps = ceil(t / dt_req);
+        if (steps > 2147483647.0) { free(o); return OR_ERR_INVALID_ARG; }
+        o->ngrid = steps < 1.0 ? 1 : (int64_t)steps;
+    }
+    o->dt = t / (double)o->ngrid;
+    o->inv_dt = (double)o->ngrid / t;
+    int64_t ns = 0;
+    o->slot_of_csr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!o->slot_of_csr) { free(o); return OR_ERR_NO_MEMORY; }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            if (col[p] != i && val[p] > 0.0) o->slot_of_csr[p] = ns++;
+            else o->slot_of_csr[p] = -1;
+        }
+    o->nslots = ns;
+    st = build_tables(o, rowptr, col, val, NULL, NULL, &o->plain);
+    if (st != OR_OK) { oracle_destroy(o); return st; }
+    *out = o;
+    return OR_OK;
+}
+
+/* Install (bias != NULL) or remove (bias == NULL) the tilted proposal.  The
+ * bias array has one entry per CSR position; only positive off-diagonal
+ * positions are read. */
+int oracle_set_proposal(oracle_t *o, const int64_t *rowptr, const int32_t *col,
+                        const double *val, const float *bias)
+{
+    free_tables(&o->prop);
+    o->has_proposal = 0;
+    if (!bias) return OR_OK;
+    for (int64_t p = 0; p < o->nnz; ++p)
+        if (o->slot_of_csr[p] >= 0 && !isfinite(bias[p])) return OR_ERR_NONFINITE;
+    int st = build_tables(o, rowptr, col, val, bias, &o->plain, &o->prop);
+    if (st != OR_OK) { free_tables(&o->prop); return st; }
+    o->has_proposal = 1;
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------- walk */
+typedef struct {
+    double f;          /* weight * v[X_t] */
+    double logw;       /* log of the weight */
+    int32_t x_end;     /* X_t */
+    uint32_t events;   /* holding intervals = jumps + 1 */
+    uint32_t jumps;
+    int status;
+} walk_out;
+
+/* Grid index of time s: K(s) = min(N, ceil(s * N / t)). */
+static int64_t grid_index(const oracle_t *o, double s)
+{
+    double g = ceil(s * o->inv_dt);
+    if (g >= (double)o->ngrid) return o->ngrid;
+    return (int64_t)g;
+}
+
+/* Trapezoid (STRANG) or right-Riemann (LIE) coefficient of grid point k. */
+static double grid_coef(const oracle_t *o, int64_t k)
+{
+    if (o->mode == OR_STRANG) return (k == 0 || k == o->ngrid) ? 0.5 : 1.0;
+    return k == 0 ? 0.0 : 1.0;
+}
+
+/* One walker started at node `start`, ordinal w.  The path is recorded as
+ * the sequence of visited states and entry times, then the weight is formed
+ * from the recorded path. */
+static void walk_one(const oracle_t *o, int64_t start, uint32_t w, const double *v,
+                     int use_prop, int64_t *path_x, double *path_s, double *path_c,
+                     walk_out *res)
+{
+    const table_set *ts = use_prop ? &o->prop : &o->plain;
+    uint32_t key[2] = { (uint32_t)o->seed, (uint32_t)(o->seed >> 32) };
+    int64_t x = start;
+    double s = 0.0;
+    uint32_t events = 0, jumps = 0;
+    int64_t len = 0;
+    path_x[0] = x; path_s[0] = 0.0; path_c[0] = 0.0;
+    res->status = OR_OK;
+    for (;;) {
+        if (ts->deg[x] == 0) { ++events; break; }         /* rate 0: stays until t */
+        if (events >= o->max_events) { res->status = OR_ERR_WALK_LIMIT; break; }
+        uint32_t ctr[4] = { events, w, (uint32_t)start, o->instance };
+        uint32_t rnd[4];
+        oracle_philox4x32_10(ctr, key, rnd);
+        ++events;
+        double U = uniform_open0(rnd[0], rnd[1]);
+        double S = -log(U) * ts->inv_r[x];
+        if (s + S < o->t) {
+            s = s + S;
+            int64_t slot = (int64_t)(((uint64_t)rnd[2] * (uint64_t)ts->deg[x]) >> 32);
+            int64_t q = ts->begin[x] + slot;
+            int64_t y;
+            double corr;
+            if (rnd[3] < ts->thr[q]) {
+                y = ts->col[q];
+                corr = ts->logcorr[q];
+            } else {
+                y = ts->alias[q];
+                corr = ts->logcorr[ts->begin[x] + ts->alias_slot[q]];
+            }
+            x = y;
+            ++jumps;
+            ++len;
+            path_x[len] = x; path_s[len] = s; path_c[len] = use_prop ? corr : 0.0;
+        } else {
+            break;
+        }
+    }
+    /* weight from the recorded path */
+    double logw = 0.0;
+    if (o->mode == OR_EXACT) {
+        for (int64_t m = 0; m <= len; ++m) {
+            double sb = (m < len) ? path_s[m + 1] : o->t;
+            double held = (m < len) ? (sb - path_s[m]) : (o->t - path_s[m]);
+            logw += ts->d[path_x[m]] * held;
+            logw += path_c[m];
+        }
+    } else if (o->t > 0.0) {
+        /* state at grid point k: the last recorded state entered with K(s) <= k */
+        double acc = 0.0;
+        int64_t m = 0;
+        for (int64_t k = 0; k <= o->ngrid; ++k) {
+            while (m < len && grid_index(o, path_s[m + 1]) <= k) ++m;
+            acc += grid_coef(o, k) * ts->d[path_x[m]];
+        }
+        logw = acc * o->dt;
+    }
+    res->logw = logw;
+    res->f = exp(logw) * v[x];
+    if (!isfinite(res->f) && res->status == OR_OK) res->status = OR_ERR_OVERFLOW;
+    res->x_end = (int32_t)x;
+    res->events = events;
+    res->jumps = jumps;
+}
+
+/* Per-walker trace for parity checks: walkers w0 .. w0+count-1 from `start`. */
+int oracle_trace(const oracle_t *o, const double *v, int64_t start, uint32_t w0, int64_t count,
+                 int use_prop, int32_t *x_end, uint32_t *events, uint32_t *jumps, double *f,
+                 double *logw)
+{
+    if (start < 0 || start >= o->n) return OR_ERR_OUT_OF_RANGE;
+    if (use_prop && !o->has_proposal) return OR_ERR_INVALID_ARG;
+    size_t cap = (size_t)o->max_events + 2;
+    int64_t *px = (int64_t *)malloc(sizeof(int64_t) * cap);
+    double *ps = (double *)malloc(sizeof(double) * cap);
+    double *pc = (double *)malloc(sizeof(double) * cap);
+    if (!px || !ps || !pc) { free(px); free(ps); free(pc); return OR_ERR_NO_MEMORY; }
+    int st = OR_OK;
+    for (int64_t c = 0; c < count; ++c) {
+        walk_out r;
+        walk_one(o, start, w0 + (uint32_t)c, v, use_prop, px, ps, pc, &r);
+        x_end[c] = r.x_end; events[c] = r.events; jumps[c] = r.jumps; f[c] = r.f; logw[c] = r.logw;
+        if (r.status != OR_OK && st == OR_OK) st = r.status;
+    }
+    free(px); free(ps); free(pc);
+    return st;
+}
+
+/* ------------------------------------------------------------- estimator */
+/* Neumaier's compensated sum. */
+static double neumaier_sum(const double *x, int64_t m)
+{
+    double s = 0.0, c = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double t = s + x[i];
+        if (fabs(s) >= fabs(x[i])) c += (s - t) + x[i];
+        else c += (x[i] - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+typedef struct {
+    const oracle_t *o;
+    const double *v;
+    const int64_t *idx;       /* NULL: entry e is node e */
+    int64_t k, nwalk;
+    int use_prop;
+    double *est, *se;
+    uint64_t *events, *jumps; /* per entry */
+    int nthreads, tid;
+    int status;
+} job_t;
+
+static void *run_job(void *arg)
+{
+    job_t *jb = (job_t *)arg;
+    const oracle_t *o = jb->o;
+    size_t cap = (size_t)o->max_events + 2;
+    int64_t *px = (int64_t *)malloc(sizeof(int64_t) * cap);
+    double *ps = (double *)malloc(sizeof(double) * cap);
+    double *pc = (double *)malloc(sizeof(double) * cap);
+    double *fs = (double *)malloc(sizeof(double) * (size_t)jb->nwalk);
+    double *dev = (double *)malloc(sizeof(double) * (size_t)jb->nwalk);
+    if (!px || !ps || !pc || !fs || !dev) { jb->status = OR_ERR_NO_MEMORY; goto done; }
+    for (int64_t e = jb->tid; e < jb->k; e += jb->nthreads) {
+        int64_t i = jb->idx ? jb->idx[e] : e;
+        if (i < 0 || i >= o->n) {
+            jb->est[e] = NAN; if (jb->se) jb->se[e] = NAN;
+            if (jb->status == OR_OK) jb->status = OR_ERR_OUT_OF_RANGE;
+            continue;
+        }
+        uint64_t ev = 0, ju = 0;
+        for (int64_t w = 0; w < jb->nwalk; ++w) {
+            walk_out r;
+            walk_one(o, i, (uint32_t)w, jb->v, jb->use_prop, px, ps, pc, &r);
+            if (r.status != OR_OK && jb->status == OR_OK) jb->status = r.status;
+            fs[w] = r.f;
+            ev += r.events; ju += r.jumps;
+        }
+        double mean = neumaier_sum(fs, jb->nwalk) / (double)jb->nwalk;
+        jb->est[e] = mean;
+        if (jb->se) {
+            if (jb->nwalk > 1) {
+                for (int64_t w = 0; w < jb->nwalk; ++w) dev[w] = (fs[w] - mean) * (fs[w] - mean);
+                double var = neumaier_sum(dev, jb->nwalk) / (double)(jb->nwalk - 1);
+                jb->se[e] = sqrt(var / (double)jb->nwalk);
+            } else {
+                jb->se[e] = 0.0;
+            }
+        }
+        if (jb->events) jb->events[e] = ev;
+        if (jb->jumps) jb->jumps[e] = ju;
+    }
+done:
+    free(px); free(ps); free(pc); free(fs); free(dev);
+    return NULL;
+}
+
+/* Estimate entries idx[0..k-1] (or every node when idx == NULL) of exp(tA)v
+ * with nwalk walkers each.  The result does not depend on nthreads: every
+ * entry is summed by one thread in walker-ordinal order. */
+int oracle_estimate(const oracle_t *o, const double *v, const int64_t *idx, int64_t k,
+                    int64_t nwalk, int use_prop, int nthreads, double *est, double *se,
+                    uint64_t *events, uint64_t *jumps)
+{
+    if (nwalk <= 0 || nwalk > 0xFFFFFFFFll) return OR_ERR_INVALID_ARG;
+    if (use_prop && !o->has_proposal) return OR_ERR_INVALID_ARG;
+    if (nthreads < 1) nthreads = 1;
+    job_t *jobs = (job_t *)calloc((size_t)nthreads, sizeof(job_t));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !th) { free(jobs); free(th); return OR_ERR_NO_MEMORY; }
+    for (int tI = 0; tI < nthreads; ++tI) {
+        jobs[tI] = (job_t){ o, v, idx, k, nwalk, use_prop, est, se, events, jumps,
+                            nthreads, tI, OR_OK };
+    }
+    if (nthreads == 1) {
+        run_job(&jobs[0]);
+    } else {
+        for (int tI = 0; tI < nthreads; ++tI) pthread_create(&th[tI], NULL, run_job, &jobs[tI]);
+        for (int tI = 0; tI < nthreads; ++tI) pthread_join(th[tI], NULL);
+    }
+    int st = OR_OK;
+    for (int tI = 0; tI < nthreads; ++tI)
+        if (jobs[tI].status != OR_OK && st == OR_OK) st = jobs[tI].status;
+    free(jobs); free(th);
+    return st;
+}
+
+/* ------------------------------------------------------------- accessors */
+int64_t oracle_nslots(const oracle_t *o) { return o->nslots; }
+int64_t oracle_ngrid(const oracle_t *o) { return o->ngrid; }
+double oracle_dt(const oracle_t *o) { return o->dt; }
+
+/* Copy the per-row and per-slot tables (plain, or proposal when use_prop). */
+int oracle_get_tables(const oracle_t *o, int use_prop, double *r, double *d, double *inv_r,
+                      int64_t *deg, int64_t *begin, int32_t *col, uint32_t *thr,
+                      int32_t *alias, double *logcorr)
+{
+    const table_set *ts = use_prop ? &o->prop : &o->plain;
+    if (use_prop && !o->has_proposal) return OR_ERR_INVALID_ARG;
+    int64_t n = o->n, ns = o->nslots;
+    if (r) memcpy(r, ts->r, sizeof(double) * (size_t)n);
+    if (d) memcpy(d, ts->d, sizeof(double) * (size_t)n);
+    if (inv_r) memcpy(inv_r, ts->inv_r, sizeof(double) * (size_t)n);
+    if (deg) memcpy(deg, ts->deg, sizeof(int64_t) * (size_t)n);
+    if (begin) memcpy(begin, ts->begin, sizeof(int64_t) * (size_t)n);
+    if (col) memcpy(col, ts->col, sizeof(int32_t) * (size_t)ns);
+    if (thr) memcpy(thr, ts->thr, sizeof(uint32_t) * (size_t)ns);
+    if (alias) memcpy(alias, ts->alias, sizeof(int32_t) * (size_t)ns);
+    if (logcorr) memcpy(logcorr, ts->logcorr, sizeof(double) * (size_t)ns);
+    return OR_OK;
+}
