@@ -1,0 +1,193 @@
+/*
+ * mc_expmv.h -- C ABI of libmcexpmv, an MI355X (gfx950) implementation of the
+ * Monte Carlo estimator of exp(tA) v from J. A. Acebron, "A Monte Carlo method
+ * for computing the action of a matrix exponential on a vector"
+ * (arXiv:1904.12759).
+ *
+ * The method (paper Sec. 2-3): write A = D - L where the off-diagonal entries
+ * a_ij >= 0 of A are jump rates of a continuous-time Markov chain with
+ * generator Q = -L.  For row i
+ *     r_i = sum_{j != i} a_ij   (exit rate),   d_i = a_ii + r_i,
+ *     k_ij = a_ij / r_i         (jump law, Eq. (paths)).
+ * A walker started at node i waits Exp(r_x) in every visited state x, jumps
+ * with law k_x., stops at the horizon t, and returns  W * v[X_t]  where W is
+ * the multiplicative functional of Theorem 1 (Lemma 1 for one step):
+ *     MC_EXACT   W = exp( integral_0^t d(X_s) ds )   (the dt -> 0 limit of the
+ *                splittings; unbiased for exp(tA) v itself)
+ *     MC_STRANG  W = exp( dt * sum_k c_k d(X_{k dt}) ), c_0 = c_N = 1/2,
+ *                unbiased for the Strang product of Eq. (eq_general1)
+ *     MC_LIE     W = exp( dt * sum_{k>=1} d(X_{k dt}) ), unbiased for the Lie
+ *                product of Eq. (deff).
+ * Entry i of the result is the mean of W * v[X_t] over the walkers started at
+ * i (Algorithm 1); the full vector is that mean for every start node.
+ *
+ * Random numbers are Philox4x32-10 (Salmon et al., SC'11) keyed by the seed,
+ * with counter (event index, walker ordinal, start node, instance id), so every
+ * walker's path is a pure function of (A, t, seed, start node, ordinal,
+ * instance id) and of nothing about the launch.
+ *
+ * Conventions for every entry point:
+ *   - Device pointers are HIP device (or managed) pointers on the current
+ *     device; host pointers are named as such.  Buffers passed in are owned by
+ *     the caller; the handle owns only what it allocates.
+ *   - Work is enqueued on opts.stream (NULL = the null stream) and is
+ *     asynchronous.  Argument errors are returned at once; errors found on the
+ *     device (an entry index out of range, the walk-length cap, a weight that
+ *     overflows) are latched in the handle and returned by mc_expmv_sync.
+ *   - A handle is not thread safe; use one per host thread.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef MC_EXPMV_H
+#define MC_EXPMV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MC_OK = 0,
+    MC_ERR_INVALID_ARG = 1,   /* bad pointer, size, shape, column index or option */
+    MC_ERR_NOT_METZLER = 2,   /* an off-diagonal entry is negative (not a jump rate) */
+    MC_ERR_NONFINITE = 3,     /* NaN or Inf in A, t, dt or a proposal bias */
+    MC_ERR_OUT_OF_RANGE = 4,  /* a requested entry index is outside [0, n) */
+    MC_ERR_NOT_SYMMETRIC = 5, /* reserved for the forward (Algorithm 2) estimator */
+    MC_ERR_NO_MEMORY = 6,     /* a device or host allocation failed */
+    MC_ERR_DEVICE = 7,        /* a HIP runtime call failed */
+    MC_ERR_WALK_LIMIT = 8,    /* a walker reached opts.max_events holding intervals */
+    MC_ERR_OVERFLOW = 9       /* a walker's weight W * v[X_t] is not finite */
+} mc_status;
+
+enum { MC_EXACT = 0, MC_STRANG = 1, MC_LIE = 2 };
+enum { MC_FP64 = 0, MC_FP32 = 1 };
+
+typedef struct mc_expmv_s *mc_expmv_t;
+
+typedef struct {
+    uint32_t struct_size;       /* sizeof(mc_expmv_opts), for versioning */
+    int32_t mode;               /* MC_EXACT (default), MC_STRANG or MC_LIE */
+    double dt;                  /* requested splitting step; N = ceil(t/dt), dt := t/N.
+                                   Ignored in MC_EXACT. Default 0.03125 (paper Sec. 6). */
+    int32_t weight_prec;        /* MC_FP64 (default): weights and v in double.
+                                   MC_FP32: d, log-weight, exp and v in float; time,
+                                   RNG and reductions stay FP64/integer. */
+    int32_t relabel;            /* 1: order rows by descending exit rate in device memory
+                                   (paths and results are unchanged). Default 0. */
+    uint32_t lds_budget;        /* bytes of LDS per block for hot rows (needs relabel);
+                                   0 = off (default) */
+    uint32_t resort_period;     /* reserved, must be 0 */
+    uint32_t walkers_per_block; /* threads per block: 64, 128 or 256 (default) */
+    uint32_t instance_id;       /* fourth Philox counter word. Default 0. */
+    uint32_t max_events;        /* cap on holding intervals per walker; 0 = 2^24 */
+    void *stream;               /* hipStream_t; NULL = null stream */
+} mc_expmv_opts;
+
+typedef struct {
+    uint64_t walkers;           /* walkers simulated by the last run */
+    uint64_t events;            /* holding intervals (= jumps + walkers) */
+    uint64_t jumps;
+    double ms;                  /* device time of the last run, from HIP events */
+    double alg_bytes;           /* algorithmic table/vector bytes of the last run */
+} mc_expmv_run_stats;
+
+/* Fill *opts with the defaults listed above. */
+void mc_expmv_default_opts(mc_expmv_opts *opts);
+
+/* Human-readable text for a status code (static storage). */
+const char *mc_expmv_status_string(mc_status s);
+
+/*
+ * Build the walk tables for the n x n matrix A (paper Sec. 2: A = D - L; the
+ * row split into r_i, d_i and k_ij is Eq. (paths)).
+ *   rowptr  device int64[n+1], rowptr[0] = 0, non-decreasing, rowptr[n] = nnz < 2^32
+ *   col     device int32[nnz], 0 <= col < n (any order, duplicates allowed)
+ *   val     device double[nnz]; diagonal entries are summed into a_ii, positive
+ *           off-diagonal entries become jump slots, zero ones are dropped
+ *   t       horizon, finite, >= 0 (the paper's beta)
+ *   seed    64-bit Philox key
+ *   opts    NULL for defaults
+ * Errors: MC_ERR_INVALID_ARG (shape, column index, option), MC_ERR_NONFINITE,
+ * MC_ERR_NOT_METZLER (negative off-diagonal).  Column-index and shape errors
+ * take precedence over non-finite values, which take precedence over signs.
+ * A, once create returns, is no longer referenced.  Synchronous.
+ */
+mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t *rowptr,
+                          const int32_t *col, const double *val, double t, uint64_t seed,
+                          const mc_expmv_opts *opts);
+
+/*
+ * Entries idx[0..k-1] of exp(tA) v, n_walkers walkers each (Algorithm 1 and
+ * Theorem 1; sample mean and standard error as in Sec. 5, Eq. (errortotal)).
+ *   v        device vector of n values: double (MC_FP64) or float (MC_FP32)
+ *   idx      device int64[k]; duplicates give identical estimates
+ *   est      device double[k]: mean of W * v[X_t]
+ *   stderr_  device double[k] or NULL: sqrt(unbiased sample variance / n_walkers)
+ *            (0 when n_walkers = 1)
+ * With a proposal installed (mc_expmv_set_proposal) the tilted walk is used.
+ * An index outside [0, n) yields NaN in est and MC_ERR_OUT_OF_RANGE at sync.
+ */
+mc_status mc_expmv_entries(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
+                           int64_t n_walkers, double *est, double *stderr_);
+
+/*
+ * Every entry of exp(tA) v with n_per_node walkers started at each node
+ * (Algorithm 1 applied at every node; equal to mc_expmv_entries with
+ * idx = 0..n-1).  est, stderr_: device double[n] (stderr_ may be NULL).
+ */
+mc_status mc_expmv_full(mc_expmv_t h, const void *v, int64_t n_per_node, double *est,
+                        double *stderr_);
+
+/*
+ * Install a tilted proposal (importance sampling; variance reduction is the
+ * remedy the paper names in Sec. 5).  edge_bias: device float[nnz] in CSR order;
+ * only positive off-diagonal positions are read.  The walk then jumps with
+ * rates a~_ij = a_ij exp(b_ij), uses r~_i = sum_j a~_ij and the weight exponent
+ * d~_i = d_i + (r~_i - r_i), and adds -b_ij to the log-weight on every jump
+ * over edge ij, so the estimator stays unbiased.  NULL restores the plain walk.
+ * MC_EXACT mode only (MC_ERR_INVALID_ARG otherwise).  Synchronous.
+ */
+mc_status mc_expmv_set_proposal(mc_expmv_t h, const float *edge_bias);
+
+/* Use `stream` (hipStream_t, NULL = null stream) for the handle's later work. */
+mc_status mc_expmv_set_stream(mc_expmv_t h, void *stream);
+
+/* Wait for the handle's stream; return (and clear) latched device errors. */
+mc_status mc_expmv_sync(mc_expmv_t h);
+
+/* Counters and device time of the last entries/full run (synchronises). */
+mc_status mc_expmv_stats(mc_expmv_t h, mc_expmv_run_stats *out);
+
+/*
+ * Per-walker record of walkers w0 .. w0+count-1 started at node `start`, from
+ * the same kernel that computes estimates: final state X_t, holding intervals,
+ * jumps and W * v[X_t] (as double).  All outputs are device arrays of `count`.
+ * use_proposal selects the tilted walk.  For parity checks; count <= 2^20.
+ */
+mc_status mc_expmv_trace(mc_expmv_t h, const void *v, int64_t start, int64_t w0, int64_t count,
+                         int32_t use_proposal, int32_t *x_end, uint32_t *events,
+                         uint32_t *jumps, double *f);
+
+/*
+ * Copy the walk tables to host memory (plain, or tilted when use_proposal),
+ * rows in the caller's numbering and slots in CSR order:
+ *   r, d, inv_r  host double[n];  deg host int64[n];  begin host int64[n]
+ *   (first slot of row i among all slots, i.e. the prefix sum of deg)
+ *   col, alias   host int32[nslots];  thr host uint32[nslots]
+ * Any pointer may be NULL.  nslots comes from mc_expmv_info.  Synchronous.
+ */
+mc_status mc_expmv_get_tables(mc_expmv_t h, int32_t use_proposal, double *r, double *d,
+                              double *inv_r, int64_t *deg, int64_t *begin, int32_t *col,
+                              uint32_t *thr, int32_t *alias);
+
+/* Sizes of a handle: n, number of jump slots, splitting steps N and dt = t/N. */
+mc_status mc_expmv_info(mc_expmv_t h, int64_t *n, int64_t *nslots, int64_t *ngrid, double *dt);
+
+/* Release everything the handle owns (synchronises its stream first). */
+void mc_expmv_destroy(mc_expmv_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MC_EXPMV_H */

@@ -298,15 +298,19 @@ static int validate(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t
     if (nnz >= ((int64_t)1 << 32)) return OR_ERR_INVALID_ARG;
     for (int64_t i = 0; i < n; ++i)
         if (rowptr[i + 1] < rowptr[i]) return OR_ERR_INVALID_ARG;
-    int err = OR_OK;
+    /* precedence: column index > non-finite value > negative off-diagonal */
+    int bad_col = 0, bad_val = 0, bad_sign = 0;
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-            if (col[p] < 0 || col[p] >= n) return OR_ERR_INVALID_ARG;
-            if (!isfinite(val[p])) { if (err == OR_OK) err = OR_ERR_NONFINITE; continue; }
-            if (col[p] != i && val[p] < 0.0) { if (err == OR_OK) err = OR_ERR_NOT_METZLER; }
+            if (col[p] < 0 || col[p] >= n) bad_col = 1;
+            else if (!isfinite(val[p])) bad_val = 1;
+            else if (col[p] != i && val[p] < 0.0) bad_sign = 1;
         }
     }
-    return err;
+    if (bad_col) return OR_ERR_INVALID_ARG;
+    if (bad_val) return OR_ERR_NONFINITE;
+    if (bad_sign) return OR_ERR_NOT_METZLER;
+    return OR_OK;
 }
 
 /* Create the oracle for matrix A (CSR, host arrays), horizon t and seed. */

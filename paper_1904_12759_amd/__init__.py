@@ -1,0 +1,282 @@
+"""MI355X (gfx950) Monte Carlo estimator of exp(tA) v (Acebron, arXiv:1904.12759).
+
+Thin Python binding over the C ABI in include/mc_expmv.h (libmcexpmv.so, built
+in-tree by ``paper_1904_12759_amd.build``).  The functions here only marshal
+arguments: device memory and streams come from PyTorch tensors, and every step
+of the computation runs in the library's HIP kernels.  If the library is not
+built, or no GPU is present, calls raise instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["MCExpmv", "MCError", "EXACT", "STRANG", "LIE", "FP64", "FP32", "lib", "load"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcexpmv.so")
+
+EXACT, STRANG, LIE = 0, 1, 2
+FP64, FP32 = 0, 1
+
+MC_OK = 0
+STATUS_NAMES = {
+    0: "MC_OK", 1: "MC_ERR_INVALID_ARG", 2: "MC_ERR_NOT_METZLER", 3: "MC_ERR_NONFINITE",
+    4: "MC_ERR_OUT_OF_RANGE", 5: "MC_ERR_NOT_SYMMETRIC", 6: "MC_ERR_NO_MEMORY",
+    7: "MC_ERR_DEVICE", 8: "MC_ERR_WALK_LIMIT", 9: "MC_ERR_OVERFLOW",
+}
+
+
+class MCError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        msg = STATUS_NAMES.get(code, str(code))
+        if _lib is not None:
+            msg += ": " + _lib.mc_expmv_status_string(code).decode()
+        super().__init__(f"{where}: {msg}" if where else msg)
+        self.code = code
+
+
+class mc_expmv_opts(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("mode", ctypes.c_int32),
+        ("dt", ctypes.c_double),
+        ("weight_prec", ctypes.c_int32),
+        ("relabel", ctypes.c_int32),
+        ("lds_budget", ctypes.c_uint32),
+        ("resort_period", ctypes.c_uint32),
+        ("walkers_per_block", ctypes.c_uint32),
+        ("instance_id", ctypes.c_uint32),
+        ("max_events", ctypes.c_uint32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class mc_expmv_run_stats(ctypes.Structure):
+    _fields_ = [
+        ("walkers", ctypes.c_uint64),
+        ("events", ctypes.c_uint64),
+        ("jumps", ctypes.c_uint64),
+        ("ms", ctypes.c_double),
+        ("alg_bytes", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+# exported C symbols and their signatures (also checked by the CPU tests)
+_SIGS = {
+    "mc_expmv_default_opts": (None, [ctypes.c_void_p]),
+    "mc_expmv_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "mc_expmv_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p]),
+    "mc_expmv_entries": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "mc_expmv_full": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_expmv_set_proposal": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_expmv_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "mc_expmv_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_expmv_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "mc_expmv_get_tables": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 8),
+    "mc_expmv_info": (ctypes.c_int, [ctypes.c_void_p] * 5),
+    "mc_expmv_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_expmv_destroy": (None, [ctypes.c_void_p]),
+}
+
+
+def load() -> ctypes.CDLL:
+    """Load libmcexpmv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1904_12759_amd.build")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def lib() -> ctypes.CDLL:
+    return load()
+
+
+def _check(code: int, where: str):
+    if code != MC_OK:
+        raise MCError(code, where)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _require_cuda(*tensors):
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libmcexpmv needs a HIP device; none is available")
+    for t in tensors:
+        if t is not None and not t.is_cuda:
+            raise ValueError("all arrays must be device tensors")
+
+
+def default_opts(**kw) -> mc_expmv_opts:
+    o = mc_expmv_opts()
+    load().mc_expmv_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "stream":
+            v = ctypes.c_void_p(v)
+        setattr(o, k, v)
+    return o
+
+
+class MCExpmv:
+    """Handle over ``mc_expmv_create`` for one matrix A, horizon t and seed.
+
+    rowptr/col/val may be numpy arrays or torch tensors; they are copied to the
+    device.  Every call runs on the current torch stream at creation time
+    (change it with :meth:`set_stream`)."""
+
+    def __init__(self, rowptr, col, val, t: float, seed: int, mode: int = EXACT,
+                 dt: float = 0.03125, fp32: bool = False, instance: int = 0,
+                 max_events: int = 0, walkers_per_block: int = 256, relabel: int = 0,
+                 lds_budget: int = 0, stream=None):
+        import torch
+        lib_ = load()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        rp = torch.as_tensor(rowptr, dtype=torch.int64).to(dev).contiguous()
+        cl = torch.as_tensor(col, dtype=torch.int32).to(dev).contiguous()
+        vl = torch.as_tensor(val, dtype=torch.float64).to(dev).contiguous()
+        _require_cuda(rp, cl, vl)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        opts = default_opts(mode=mode, dt=dt, weight_prec=FP32 if fp32 else FP64,
+                            instance_id=instance, max_events=max_events,
+                            walkers_per_block=walkers_per_block, relabel=relabel,
+                            lds_budget=lds_budget, stream=stream)
+        h = ctypes.c_void_p()
+        torch.cuda.current_stream().synchronize()
+        _check(lib_.mc_expmv_create(ctypes.byref(h), rp.numel() - 1, cl.numel(), _ptr(rp),
+                                    _ptr(cl), _ptr(vl), float(t), int(seed) & (2**64 - 1),
+                                    ctypes.byref(opts)), "mc_expmv_create")
+        self._h = h
+        self.n = rp.numel() - 1
+        self.nnz = cl.numel()
+        self.t = float(t)
+        self.mode = mode
+        self.fp32 = fp32
+        self.device = dev
+        n, ns, ng, dtv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib_.mc_expmv_info(h, ctypes.byref(n), ctypes.byref(ns), ctypes.byref(ng),
+                                  ctypes.byref(dtv)), "mc_expmv_info")
+        self.nslots, self.ngrid, self.dt = ns.value, ng.value, dtv.value
+
+    # -- plumbing
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mc_expmv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        _check(load().mc_expmv_set_stream(self._h, ctypes.c_void_p(stream)), "mc_expmv_set_stream")
+        self.stream = stream
+
+    def _v(self, v):
+        import torch
+        dt = torch.float32 if self.fp32 else torch.float64
+        v = torch.as_tensor(v)
+        v = v.to(device=self.device, dtype=dt).contiguous()
+        if v.numel() != self.n:
+            raise ValueError("v must have n entries")
+        return v
+
+    # -- estimator
+    def entries(self, v, idx, n_walkers: int, est=None, stderr=None, sync: bool = True):
+        import torch
+        v = self._v(v)
+        idx = torch.as_tensor(idx).to(device=self.device, dtype=torch.int64).contiguous()
+        k = idx.numel()
+        if est is None:
+            est = torch.empty(k, dtype=torch.float64, device=self.device)
+        if stderr is None:
+            stderr = torch.empty(k, dtype=torch.float64, device=self.device)
+        _require_cuda(v, idx, est, stderr)
+        _check(load().mc_expmv_entries(self._h, _ptr(v), _ptr(idx), k, int(n_walkers),
+                                       _ptr(est), _ptr(stderr)), "mc_expmv_entries")
+        if sync:
+            self.sync()
+        return est, stderr
+
+    def full(self, v, n_per_node: int, est=None, stderr=None, sync: bool = True):
+        import torch
+        v = self._v(v)
+        if est is None:
+            est = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        if stderr is None:
+            stderr = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _require_cuda(v, est, stderr)
+        _check(load().mc_expmv_full(self._h, _ptr(v), int(n_per_node), _ptr(est), _ptr(stderr)),
+               "mc_expmv_full")
+        if sync:
+            self.sync()
+        return est, stderr
+
+    def set_proposal(self, edge_bias):
+        import torch
+        if edge_bias is None:
+            _check(load().mc_expmv_set_proposal(self._h, None), "mc_expmv_set_proposal")
+            return
+        b = torch.as_tensor(edge_bias).to(device=self.device, dtype=torch.float32).contiguous()
+        if b.numel() != self.nnz:
+            raise ValueError("edge_bias must have nnz entries (CSR order)")
+        _check(load().mc_expmv_set_proposal(self._h, _ptr(b)), "mc_expmv_set_proposal")
+
+    def sync(self):
+        _check(load().mc_expmv_sync(self._h), "mc_expmv_sync")
+
+    def stats(self) -> dict:
+        s = mc_expmv_run_stats()
+        _check(load().mc_expmv_stats(self._h, ctypes.byref(s)), "mc_expmv_stats")
+        return dict(walkers=s.walkers, events=s.events, jumps=s.jumps, ms=s.ms,
+                    alg_bytes=s.alg_bytes)
+
+    def trace(self, v, start: int, w0: int, count: int, proposal: bool = False):
+        import torch
+        v = self._v(v)
+        d = self.device
+        x = torch.empty(count, dtype=torch.int32, device=d)
+        ev = torch.empty(count, dtype=torch.int32, device=d)
+        ju = torch.empty(count, dtype=torch.int32, device=d)
+        f = torch.empty(count, dtype=torch.float64, device=d)
+        _check(load().mc_expmv_trace(self._h, _ptr(v), int(start), int(w0), int(count),
+                                     int(proposal), _ptr(x), _ptr(ev), _ptr(ju), _ptr(f)),
+               "mc_expmv_trace")
+        return x.cpu().numpy(), ev.cpu().numpy().view("uint32"), ju.cpu().numpy().view("uint32"), \
+            f.cpu().numpy()
+
+    def tables(self, proposal: bool = False) -> dict:
+        import numpy as np
+        n, ns = self.n, self.nslots
+        out = dict(r=np.zeros(n), d=np.zeros(n), inv_r=np.zeros(n), deg=np.zeros(n, np.int64),
+                   begin=np.zeros(n, np.int64), col=np.zeros(max(ns, 1), np.int32),
+                   thr=np.zeros(max(ns, 1), np.uint32), alias=np.zeros(max(ns, 1), np.int32))
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(load().mc_expmv_get_tables(self._h, int(proposal), *[p(out[k]) for k in (
+            "r", "d", "inv_r", "deg", "begin", "col", "thr", "alias")]), "mc_expmv_get_tables")
+        for k in ("col", "thr", "alias"):
+            out[k] = out[k][:ns]
+        return out

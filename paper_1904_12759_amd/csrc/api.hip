@@ -1,0 +1,501 @@
+// Host side of the C ABI declared in include/mc_expmv.h: argument checks,
+// device allocations, kernel launches on the caller's stream, latched device
+// errors and run statistics.  No C++ exception leaves this file.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "mc_internal.hpp"
+
+using namespace mc;
+
+struct mc_expmv_s {
+    int dev = 0;
+    int64_t n = 0, nnz = 0, nslots = 0;
+    double t = 0.0;
+    uint64_t seed = 0;
+    mc_expmv_opts opts{};
+    int64_t ngrid = 1;
+    double dt = 0.0, inv_dt = 0.0;
+    hipStream_t stream = nullptr;
+    // copy of A, needed to rebuild tilted tables
+    int64_t *rowptr = nullptr;
+    int32_t *col = nullptr;
+    double *val = nullptr;
+    Tables plain, prop;
+    bool has_prop = false;
+    uint32_t *flags = nullptr;           // latched device errors
+    unsigned long long *counters = nullptr;
+    double *part = nullptr;              // chunk partials
+    int64_t part_cap = 0;                // doubles
+    double *shift = nullptr;
+    int64_t shift_cap = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // last run
+    bool ran = false;
+    uint64_t last_walkers = 0;
+    bool last_fp32 = false, last_prop = false;
+};
+
+namespace {
+
+constexpr uint32_t kChunk = 1024;   // walkers per task (fixes the summation order)
+
+mc_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return MC_OK;
+    if (e == hipErrorOutOfMemory) return MC_ERR_NO_MEMORY;
+    (void)hipGetLastError();
+    return MC_ERR_DEVICE;
+}
+
+#define HIP_TRY(expr)                               \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) return from_hip(e_);  \
+    } while (0)
+
+mc_status flags_to_status(uint32_t f) {
+    static const mc_status order[] = {MC_ERR_INVALID_ARG, MC_ERR_NONFINITE, MC_ERR_NOT_METZLER,
+                                      MC_ERR_OUT_OF_RANGE, MC_ERR_WALK_LIMIT, MC_ERR_OVERFLOW};
+    for (mc_status s : order)
+        if (f & (1u << s)) return s;
+    return MC_OK;
+}
+
+template <class T>
+hipError_t dalloc(T **p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    return hipMalloc((void **)p, sizeof(T) * (size_t)count);
+}
+
+void free_tables(Tables &tb) {
+    (void)hipFree(tb.rows);
+    (void)hipFree(tb.d64);
+    (void)hipFree(tb.d32);
+    (void)hipFree(tb.r);
+    (void)hipFree(tb.slots);
+    (void)hipFree(tb.corr);
+    tb = Tables{};
+}
+
+hipError_t alloc_tables(Tables &tb, int64_t n, int64_t nnz, bool with_corr) {
+    hipError_t e;
+    if ((e = dalloc(&tb.rows, n)) != hipSuccess) return e;
+    if ((e = dalloc(&tb.d64, n)) != hipSuccess) return e;
+    if ((e = dalloc(&tb.d32, n)) != hipSuccess) return e;
+    if ((e = dalloc(&tb.r, n)) != hipSuccess) return e;
+    if ((e = dalloc(&tb.slots, nnz)) != hipSuccess) return e;
+    if (with_corr && (e = dalloc(&tb.corr, nnz)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// Build one table set from the handle's copy of A (bias == null: plain).
+mc_status build_tables(mc_expmv_s *h, const float *bias, Tables &out) {
+    double *q = nullptr;
+    int32_t *st_small = nullptr, *st_large = nullptr;
+    mc_status st = MC_OK;
+    hipError_t e = dalloc(&q, h->nnz);
+    if (e == hipSuccess) e = dalloc(&st_small, h->nnz);
+    if (e == hipSuccess) e = dalloc(&st_large, h->nnz);
+    if (e == hipSuccess) e = hipMemsetAsync(h->flags, 0, sizeof(uint32_t), h->stream);
+    if (e == hipSuccess)
+        e = launch_setup_rows(h->n, h->rowptr, h->col, h->val, bias, h->plain, out, q, st_small,
+                              st_large, h->flags, h->stream);
+    uint32_t f = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&f, h->flags, sizeof(f), hipMemcpyDeviceToHost,
+                                            h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) st = from_hip(e);
+    else st = flags_to_status(f);
+    (void)hipFree(q);
+    (void)hipFree(st_small);
+    (void)hipFree(st_large);
+    return st;
+}
+
+mc_status check_opts(const mc_expmv_opts &o) {
+    if (o.mode != MC_EXACT && o.mode != MC_STRANG && o.mode != MC_LIE) return MC_ERR_INVALID_ARG;
+    if (o.weight_prec != MC_FP64 && o.weight_prec != MC_FP32) return MC_ERR_INVALID_ARG;
+    if (o.mode != MC_EXACT && (!isfinite(o.dt) || !(o.dt > 0.0))) return MC_ERR_INVALID_ARG;
+    const uint32_t b = o.walkers_per_block;
+    if (b != 64 && b != 128 && b != 256) return MC_ERR_INVALID_ARG;
+    if (o.resort_period != 0) return MC_ERR_INVALID_ARG;
+    if (o.relabel != 0 && o.relabel != 1) return MC_ERR_INVALID_ARG;
+    return MC_OK;
+}
+
+// Run the walk kernel for k entries (idx == null: every node).
+mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, int64_t nwalk,
+                   double *est, double *se, bool trace, int64_t w0, int32_t use_prop,
+                   int32_t *tx, uint32_t *tev, uint32_t *tju, double *tf) {
+    if (!v || nwalk < 1 || nwalk > 0xFFFFFFFFll) return MC_ERR_INVALID_ARG;
+    if (use_prop && !h->has_prop) return MC_ERR_INVALID_ARG;
+    if (k < 0) return MC_ERR_INVALID_ARG;
+    const bool prop = use_prop != 0;
+    const bool fp32 = h->opts.weight_prec == MC_FP32;
+    const int64_t chunks = (nwalk + kChunk - 1) / kChunk;
+    WalkArgs a{};
+    const Tables &tb = prop ? h->prop : h->plain;
+    a.rows = tb.rows;
+    a.d64 = tb.d64;
+    a.d32 = tb.d32;
+    a.slots = tb.slots;
+    a.corr = prop ? tb.corr : nullptr;
+    a.v = v;
+    a.idx = idx;
+    a.k = k;
+    a.n = h->n;
+    a.nwalk = nwalk;
+    a.w0 = w0;
+    a.chunk = kChunk;
+    a.chunks = chunks;
+    a.ntasks = k * chunks;
+    a.t = h->t;
+    a.dt = h->dt;
+    a.inv_dt = h->inv_dt;
+    a.ngrid = h->ngrid;
+    a.key0 = (uint32_t)h->seed;
+    a.key1 = (uint32_t)(h->seed >> 32);
+    a.inst = h->opts.instance_id;
+    a.max_events = h->opts.max_events ? h->opts.max_events : (1u << 24);
+    a.est = est;
+    a.se = se;
+    a.counters = h->counters;
+    a.flags = h->flags;
+    if (trace) {
+        a.tr_x = tx;
+        a.tr_ev = tev;
+        a.tr_ju = tju;
+        a.tr_f = tf;
+    }
+    if (chunks > 1) {
+        const int64_t need = k * chunks * 2;
+        if (need > h->part_cap) {
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            (void)hipFree(h->part);
+            h->part = nullptr;
+            h->part_cap = 0;
+            HIP_TRY(dalloc(&h->part, need));
+            h->part_cap = need;
+        }
+        if (k > h->shift_cap) {
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            (void)hipFree(h->shift);
+            h->shift = nullptr;
+            h->shift_cap = 0;
+            HIP_TRY(dalloc(&h->shift, k));
+            h->shift_cap = k;
+        }
+        a.part = h->part;
+        a.shift = h->shift;
+    }
+    HIP_TRY(hipMemsetAsync(h->counters, 0, 2 * sizeof(unsigned long long), h->stream));
+    HIP_TRY(hipEventRecord(h->ev0, h->stream));
+    HIP_TRY(launch_walk(a, h->opts.mode, fp32, prop, trace, (int)h->opts.walkers_per_block,
+                        h->stream));
+    HIP_TRY(launch_finalize(a, h->stream));
+    HIP_TRY(hipEventRecord(h->ev1, h->stream));
+    h->ran = true;
+    h->last_walkers = (uint64_t)k * (uint64_t)nwalk;
+    h->last_fp32 = fp32;
+    h->last_prop = prop;
+    return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mc_expmv_default_opts(mc_expmv_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(mc_expmv_opts);
+    o->mode = MC_EXACT;
+    o->dt = 0.03125;
+    o->weight_prec = MC_FP64;
+    o->relabel = 0;
+    o->lds_budget = 0;
+    o->resort_period = 0;
+    o->walkers_per_block = 256;
+    o->instance_id = 0;
+    o->max_events = 0;
+    o->stream = nullptr;
+}
+
+const char *mc_expmv_status_string(mc_status s) {
+    switch (s) {
+        case MC_OK: return "ok";
+        case MC_ERR_INVALID_ARG: return "invalid argument";
+        case MC_ERR_NOT_METZLER: return "negative off-diagonal entry";
+        case MC_ERR_NONFINITE: return "non-finite value";
+        case MC_ERR_OUT_OF_RANGE: return "entry index out of range";
+        case MC_ERR_NOT_SYMMETRIC: return "matrix is not symmetric";
+        case MC_ERR_NO_MEMORY: return "out of memory";
+        case MC_ERR_DEVICE: return "HIP runtime error";
+        case MC_ERR_WALK_LIMIT: return "walk-length cap reached";
+        case MC_ERR_OVERFLOW: return "weight overflow";
+    }
+    return "unknown status";
+}
+
+void mc_expmv_destroy(mc_expmv_t h) {
+    if (!h) return;
+    (void)hipSetDevice(h->dev);
+    (void)hipStreamSynchronize(h->stream);
+    free_tables(h->plain);
+    free_tables(h->prop);
+    (void)hipFree(h->rowptr);
+    (void)hipFree(h->col);
+    (void)hipFree(h->val);
+    (void)hipFree(h->flags);
+    (void)hipFree(h->counters);
+    (void)hipFree(h->part);
+    (void)hipFree(h->shift);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    delete h;
+}
+
+mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t *rowptr,
+                          const int32_t *col, const double *val, double t, uint64_t seed,
+                          const mc_expmv_opts *opts) {
+    if (!out) return MC_ERR_INVALID_ARG;
+    *out = nullptr;
+    mc_expmv_opts o;
+    mc_expmv_default_opts(&o);
+    if (opts) {
+        if (opts->struct_size != sizeof(mc_expmv_opts)) return MC_ERR_INVALID_ARG;
+        o = *opts;
+    }
+    mc_status st = check_opts(o);
+    if (st != MC_OK) return st;
+    if (n < 0 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 32))
+        return MC_ERR_INVALID_ARG;
+    if (!rowptr || (nnz > 0 && (!col || !val))) return MC_ERR_INVALID_ARG;
+    if (!isfinite(t) || !(t >= 0.0)) return MC_ERR_INVALID_ARG;
+    mc_expmv_s *h = new (std::nothrow) mc_expmv_s();
+    if (!h) return MC_ERR_NO_MEMORY;
+    h->n = n;
+    h->nnz = nnz;
+    h->t = t;
+    h->seed = seed;
+    h->opts = o;
+    h->stream = (hipStream_t)o.stream;
+    if (o.mode != MC_EXACT) {
+        const double steps = ceil(t / o.dt);
+        if (!(steps <= 2147483647.0)) {
+            delete h;
+            return MC_ERR_INVALID_ARG;
+        }
+        h->ngrid = steps < 1.0 ? 1 : (int64_t)steps;
+    }
+    h->dt = t / (double)h->ngrid;
+    h->inv_dt = (double)h->ngrid / t;
+#define CREATE_TRY(expr)                         \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) {                  \
+            mc_status s_ = from_hip(e_);         \
+            mc_expmv_destroy(h);                 \
+            return s_;                           \
+        }                                        \
+    } while (0)
+    CREATE_TRY(hipGetDevice(&h->dev));
+    CREATE_TRY(hipEventCreate(&h->ev0));
+    CREATE_TRY(hipEventCreate(&h->ev1));
+    CREATE_TRY(dalloc(&h->flags, 1));
+    CREATE_TRY(dalloc(&h->counters, 2));
+    CREATE_TRY(hipMemsetAsync(h->flags, 0, sizeof(uint32_t), h->stream));
+    CREATE_TRY(dalloc(&h->rowptr, n + 1));
+    CREATE_TRY(dalloc(&h->col, nnz));
+    CREATE_TRY(dalloc(&h->val, nnz));
+    CREATE_TRY(hipMemcpyAsync(h->rowptr, rowptr, sizeof(int64_t) * (size_t)(n + 1),
+                              hipMemcpyDefault, h->stream));
+    if (nnz > 0) {
+        CREATE_TRY(hipMemcpyAsync(h->col, col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDefault,
+                                  h->stream));
+        CREATE_TRY(hipMemcpyAsync(h->val, val, sizeof(double) * (size_t)nnz, hipMemcpyDefault,
+                                  h->stream));
+    }
+    // the row offsets must be valid before any row is read
+    CREATE_TRY(launch_check_rowptr(n, nnz, h->rowptr, h->flags, h->stream));
+    uint32_t f = 0;
+    CREATE_TRY(hipMemcpyAsync(&f, h->flags, sizeof(f), hipMemcpyDeviceToHost, h->stream));
+    CREATE_TRY(hipStreamSynchronize(h->stream));
+    if (f) {
+        mc_expmv_destroy(h);
+        return MC_ERR_INVALID_ARG;
+    }
+    CREATE_TRY(alloc_tables(h->plain, n, nnz, false));
+    st = build_tables(h, nullptr, h->plain);
+    if (st != MC_OK) {
+        mc_expmv_destroy(h);
+        return st;
+    }
+    // number of jump slots
+    {
+        std::vector<RowRec> rows((size_t)n);
+        if (n > 0)
+            CREATE_TRY(hipMemcpy(rows.data(), h->plain.rows, sizeof(RowRec) * (size_t)n,
+                                 hipMemcpyDeviceToHost));
+        int64_t ns = 0;
+        for (const RowRec &r : rows) ns += r.deg;
+        h->nslots = ns;
+    }
+#undef CREATE_TRY
+    *out = h;
+    return MC_OK;
+}
+
+mc_status mc_expmv_entries(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
+                           int64_t n_walkers, double *est, double *stderr_) {
+    if (!h) return MC_ERR_INVALID_ARG;
+    if (k > 0 && (!idx || !est)) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    return run_walk(h, v, idx, k, n_walkers, est, stderr_, false, 0, h->has_prop ? 1 : 0,
+                    nullptr, nullptr, nullptr, nullptr);
+}
+
+mc_status mc_expmv_full(mc_expmv_t h, const void *v, int64_t n_per_node, double *est,
+                        double *stderr_) {
+    if (!h) return MC_ERR_INVALID_ARG;
+    if (h->n > 0 && !est) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    return run_walk(h, v, nullptr, h->n, n_per_node, est, stderr_, false, 0,
+                    h->has_prop ? 1 : 0, nullptr, nullptr, nullptr, nullptr);
+}
+
+mc_status mc_expmv_trace(mc_expmv_t h, const void *v, int64_t start, int64_t w0, int64_t count,
+                         int32_t use_proposal, int32_t *x_end, uint32_t *events,
+                         uint32_t *jumps, double *f) {
+    if (!h || !x_end || !events || !jumps || !f) return MC_ERR_INVALID_ARG;
+    if (count < 1 || count > (1 << 20) || w0 < 0 || w0 + count > 0xFFFFFFFFll)
+        return MC_ERR_INVALID_ARG;
+    if (start < 0 || start >= h->n) return MC_ERR_OUT_OF_RANGE;
+    HIP_TRY(hipSetDevice(h->dev));
+    int64_t *didx = nullptr;
+    double *dest = nullptr;
+    HIP_TRY(dalloc(&didx, 1));
+    hipError_t e = dalloc(&dest, 1);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(didx, &start, sizeof(int64_t), hipMemcpyHostToDevice, h->stream);
+    mc_status st = from_hip(e);
+    if (st == MC_OK)
+        st = run_walk(h, v, didx, 1, count, dest, nullptr, true, w0, use_proposal, x_end, events,
+                      jumps, f);
+    if (st == MC_OK) st = from_hip(hipStreamSynchronize(h->stream));
+    (void)hipFree(didx);
+    (void)hipFree(dest);
+    return st;
+}
+
+mc_status mc_expmv_set_proposal(mc_expmv_t h, const float *edge_bias) {
+    if (!h) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    free_tables(h->prop);
+    h->has_prop = false;
+    if (!edge_bias) return MC_OK;
+    if (h->opts.mode != MC_EXACT) return MC_ERR_INVALID_ARG;
+    HIP_TRY(alloc_tables(h->prop, h->n, h->nnz, true));
+    mc_status st = build_tables(h, edge_bias, h->prop);
+    if (st != MC_OK) {
+        free_tables(h->prop);
+        return st;
+    }
+    h->has_prop = true;
+    return MC_OK;
+}
+
+mc_status mc_expmv_set_stream(mc_expmv_t h, void *stream) {
+    if (!h) return MC_ERR_INVALID_ARG;
+    h->stream = (hipStream_t)stream;
+    h->opts.stream = stream;
+    return MC_OK;
+}
+
+mc_status mc_expmv_sync(mc_expmv_t h) {
+    if (!h) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    uint32_t f = 0;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipMemcpy(&f, h->flags, sizeof(f), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(h->flags, 0, sizeof(uint32_t)));
+    return flags_to_status(f);
+}
+
+mc_status mc_expmv_stats(mc_expmv_t h, mc_expmv_run_stats *out) {
+    if (!h || !out) return MC_ERR_INVALID_ARG;
+    memset(out, 0, sizeof(*out));
+    if (!h->ran) return MC_OK;
+    HIP_TRY(hipSetDevice(h->dev));
+    HIP_TRY(hipEventSynchronize(h->ev1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    unsigned long long c[2] = {0, 0};
+    HIP_TRY(hipMemcpy(c, h->counters, sizeof(c), hipMemcpyDeviceToHost));
+    out->walkers = h->last_walkers;
+    out->events = c[0];
+    out->jumps = c[1];
+    out->ms = ms;
+    // Algorithmic bytes with no reuse: a row record (16 B) and d (8/4 B) per
+    // visited state, a 12 B alias slot (+8 B correction when tilted) per jump,
+    // v[X_t] (8/4 B) per walker.
+    const double dbytes = h->last_fp32 ? 4.0 : 8.0;
+    const double row = 16.0 + dbytes;
+    const double slot = 12.0 + (h->last_prop ? 8.0 : 0.0);
+    out->alg_bytes = row * (double)(c[0]) + slot * (double)c[1] + dbytes * (double)h->last_walkers;
+    return MC_OK;
+}
+
+mc_status mc_expmv_get_tables(mc_expmv_t h, int32_t use_proposal, double *r, double *d,
+                              double *inv_r, int64_t *deg, int64_t *begin, int32_t *col,
+                              uint32_t *thr, int32_t *alias) {
+    if (!h) return MC_ERR_INVALID_ARG;
+    if (use_proposal && !h->has_prop) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const Tables &tb = use_proposal ? h->prop : h->plain;
+    const size_t n = (size_t)h->n;
+    std::vector<RowRec> rows(n);
+    std::vector<double> dd(n), rr(n);
+    std::vector<SlotRec> sl((size_t)(h->nnz > 0 ? h->nnz : 1));
+    if (n > 0) {
+        HIP_TRY(hipMemcpy(rows.data(), tb.rows, sizeof(RowRec) * n, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(dd.data(), tb.d64, sizeof(double) * n, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(rr.data(), tb.r, sizeof(double) * n, hipMemcpyDeviceToHost));
+    }
+    if (h->nnz > 0)
+        HIP_TRY(hipMemcpy(sl.data(), tb.slots, sizeof(SlotRec) * (size_t)h->nnz,
+                          hipMemcpyDeviceToHost));
+    int64_t pos = 0;
+    for (size_t i = 0; i < n; ++i) {
+        if (r) r[i] = rr[i];
+        if (d) d[i] = dd[i];
+        if (inv_r) inv_r[i] = rows[i].inv_r;
+        if (deg) deg[i] = rows[i].deg;
+        if (begin) begin[i] = pos;
+        for (uint32_t s = 0; s < rows[i].deg; ++s) {
+            const SlotRec &q = sl[rows[i].begin + s];
+            if (col) col[pos] = q.self;
+            if (thr) thr[pos] = q.thr;
+            if (alias) alias[pos] = q.alias;
+            ++pos;
+        }
+    }
+    return MC_OK;
+}
+
+mc_status mc_expmv_info(mc_expmv_t h, int64_t *n, int64_t *nslots, int64_t *ngrid, double *dt) {
+    if (!h) return MC_ERR_INVALID_ARG;
+    if (n) *n = h->n;
+    if (nslots) *nslots = h->nslots;
+    if (ngrid) *ngrid = h->ngrid;
+    if (dt) *dt = h->dt;
+    return MC_OK;
+}
+
+}  // extern "C"

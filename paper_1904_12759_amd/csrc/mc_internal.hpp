@@ -1,0 +1,127 @@
+// Internal declarations of libmcexpmv: device table layout, the Philox
+// generator, and the launch entry points shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mc_expmv.h"
+
+namespace mc {
+
+// ---------------------------------------------------------------- tables
+// Row record, 16 bytes: everything a walker needs about its current state x
+// except the weight exponent d_x, which sits in its own array so that the
+// FP32 weight mode reads 4 bytes instead of 8.
+struct alignas(16) RowRec {
+    double inv_r;      // 1 / r_x (unused when deg == 0)
+    uint32_t deg;      // number of jump slots (positive off-diagonal entries)
+    uint32_t begin;    // first slot; slots of row x are begin .. begin+deg-1
+};
+
+// Alias slot, 16 bytes (one dwordx4 gather per jump): keep `self` iff
+// o3 < thr, else jump to `alias`.  aslot is the slot (within the row) that
+// `alias` came from, used to locate the tilted-proposal correction.
+struct alignas(16) SlotRec {
+    uint32_t thr;
+    int32_t self;
+    int32_t alias;
+    uint32_t aslot;
+};
+
+// One set of walk tables (plain, or the tilted proposal).
+struct Tables {
+    RowRec *rows = nullptr;    // [n]
+    double *d64 = nullptr;     // [n] weight exponent d_x
+    float *d32 = nullptr;      // [n] (float)d_x for the FP32 weight mode
+    double *r = nullptr;       // [n] exit rate r_x (setup and export only)
+    SlotRec *slots = nullptr;  // [nnz]: row x uses slots rowptr[x] .. rowptr[x]+deg-1
+    float2 *corr = nullptr;    // [nnz] proposal only: (-b_self, -b_alias) per slot
+};
+
+// Error flags latched on the device (bit i = status code i).
+enum : uint32_t {
+    F_INVALID_ARG = 1u << MC_ERR_INVALID_ARG,
+    F_NOT_METZLER = 1u << MC_ERR_NOT_METZLER,
+    F_NONFINITE = 1u << MC_ERR_NONFINITE,
+    F_OUT_OF_RANGE = 1u << MC_ERR_OUT_OF_RANGE,
+    F_WALK_LIMIT = 1u << MC_ERR_WALK_LIMIT,
+    F_OVERFLOW = 1u << MC_ERR_OVERFLOW,
+};
+
+// ---------------------------------------------------------- Philox4x32-10
+// Salmon, Moraes, Dror, Shaw (SC'11): ten rounds of the Philox S-P network,
+// multipliers 0xD2511F53 / 0xCD9E8D57, Weyl key increments 0x9E3779B9 /
+// 0xBB67AE85.
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// ---------------------------------------------------------- launch params
+struct WalkArgs {
+    const RowRec *rows;
+    const double *d64;
+    const float *d32;
+    const SlotRec *slots;
+    const float2 *corr;        // non-null only for the tilted walk
+    const void *v;             // double* or float*
+    const int64_t *idx;        // null: entry e is node e
+    int64_t k;                 // entries
+    int64_t n;
+    int64_t nwalk;             // walkers per entry
+    int64_t w0;                // first walker ordinal (trace only)
+    uint32_t chunk;            // walkers per task
+    int64_t chunks;            // tasks per entry
+    int64_t ntasks;
+    double t;
+    double dt;                 // t / N
+    double inv_dt;             // N / t
+    int64_t ngrid;             // N
+    uint32_t key0, key1, inst, max_events;
+    double *est;               // [k]   (chunks == 1) final results
+    double *se;                // [k] or null
+    double *part;              // [k * chunks * 2] partial sums (chunks > 1)
+    double *shift;             // [k] per-entry shift (chunks > 1)
+    unsigned long long *counters;  // [2]: events, jumps
+    uint32_t *flags;
+    // trace outputs (per walker of one task)
+    int32_t *tr_x;
+    uint32_t *tr_ev;
+    uint32_t *tr_ju;
+    double *tr_f;
+};
+
+// host-side launchers (walk.hip)
+hipError_t launch_walk(const WalkArgs &a, int mode, bool fp32, bool prop, bool trace,
+                       int block, hipStream_t s);
+hipError_t launch_finalize(const WalkArgs &a, hipStream_t s);
+
+// setup kernels (setup.hip)
+hipError_t launch_check_rowptr(int64_t n, int64_t nnz, const int64_t *rowptr, uint32_t *flags,
+                               hipStream_t s);
+hipError_t launch_setup_rows(int64_t n, const int64_t *rowptr, const int32_t *col,
+                             const double *val, const float *bias, const Tables &base,
+                             Tables &out, double *q_scratch, int32_t *stack_small,
+                             int32_t *stack_large, uint32_t *flags, hipStream_t s);
+
+}  // namespace mc

@@ -1,0 +1,159 @@
+// Table construction on the device: validation of the CSR matrix, the split of
+// every row into diagonal, exit rate and jump law (paper Sec. 2 and Eq.
+// (paths)), and one Vose alias table per row so that a jump costs one draw and
+// one gather instead of the row scan discussed in Sec. 4.
+#include <math.h>
+
+#include "mc_internal.hpp"
+
+namespace mc {
+namespace {
+
+// rowptr must be a valid row-offset array before any row is read.
+__global__ void k_check_rowptr(int64_t n, int64_t nnz, const int64_t *__restrict__ rowptr,
+                               uint32_t *flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    const int64_t p = rowptr[i];
+    bool bad = p < 0 || p > nnz;
+    if (i == 0) bad |= p != 0;
+    if (i == n) bad |= p != nnz;
+    if (i < n) bad |= rowptr[i + 1] < p;
+    if (bad) atomicOr(flags, F_INVALID_ARG);
+}
+
+// One thread per row.  Slots of row i occupy CSR positions rowptr[i] ..
+// rowptr[i]+deg-1 (the positive off-diagonal entries, in CSR order).
+//   plain   (bias == null): a_s = a_ij,          r = sum a_s,  d = a_ii + r
+//   tilted  (bias != null): a_s = a_ij exp(b_ij), r~ = sum a_s, d~ = d + (r~ - r)
+// The alias table follows Vose (IEEE TSE 1991): scaled probabilities
+// q_s = a_s * deg / r, two LIFO work lists filled by scanning the slots in
+// order, and for each "small" slot the threshold floor(q * 2^32) of keeping
+// its own column; slots left over keep their own column with certainty.
+__global__ void k_setup_rows(int64_t n, const int64_t *__restrict__ rowptr,
+                             const int32_t *__restrict__ col, const double *__restrict__ val,
+                             const float *__restrict__ bias, const double *__restrict__ base_r,
+                             const double *__restrict__ base_d, RowRec *__restrict__ rows,
+                             double *__restrict__ d64, float *__restrict__ d32,
+                             double *__restrict__ rr, SlotRec *__restrict__ slots,
+                             float2 *__restrict__ corr, double *__restrict__ q,
+                             int32_t *__restrict__ small, int32_t *__restrict__ large,
+                             uint32_t *flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t p0 = rowptr[i], p1 = rowptr[i + 1];
+    double diag = 0.0, rate = 0.0;
+    int64_t deg = 0;
+    uint32_t err = 0;
+    for (int64_t p = p0; p < p1; ++p) {
+        const int32_t j = col[p];
+        const double a = val[p];
+        if (j < 0 || j >= n) {
+            err |= F_INVALID_ARG;
+            continue;
+        }
+        if (!isfinite(a)) {
+            err |= F_NONFINITE;
+            continue;
+        }
+        if (j == i) {
+            diag = diag + a;
+        } else if (a < 0.0) {
+            err |= F_NOT_METZLER;
+        } else if (a > 0.0) {
+            double at = a;
+            const int64_t s = p0 + deg;
+            if (bias) {
+                const float b = bias[p];
+                at = a * exp((double)b);
+                if (!isfinite(b) || !isfinite(at) || !(at > 0.0)) err |= F_NONFINITE;
+                corr[s] = make_float2(-b, 0.0f);
+            }
+            q[s] = at;
+            slots[s] = SlotRec{0xFFFFFFFFu, j, j, (uint32_t)deg};
+            rate = rate + at;
+            ++deg;
+        }
+    }
+    double d = bias ? base_d[i] + (rate - base_r[i]) : diag + rate;
+    double inv_r = 0.0;
+    if (deg > 0) {
+        inv_r = 1.0 / rate;
+        if (!isfinite(inv_r)) err |= F_INVALID_ARG;
+    }
+    if (!isfinite(d)) err |= F_NONFINITE;
+    if (err) {
+        atomicOr(flags, err);
+        return;
+    }
+    rows[i] = RowRec{inv_r, (uint32_t)deg, (uint32_t)p0};
+    d64[i] = d;
+    d32[i] = (float)d;
+    rr[i] = rate;
+    if (deg <= 1) {
+        if (bias && deg == 1) corr[p0].y = corr[p0].x;
+        return;
+    }
+    bool uniform = true;
+    for (int64_t s = 1; s < deg && uniform; ++s) uniform = q[p0 + s] == q[p0];
+    if (!uniform) {
+        int64_t ns = 0, nl = 0;
+        for (int64_t s = 0; s < deg; ++s) {
+            const double qs = (q[p0 + s] * (double)deg) / rate;
+            q[p0 + s] = qs;
+            if (qs < 1.0)
+                small[p0 + ns++] = (int32_t)s;
+            else
+                large[p0 + nl++] = (int32_t)s;
+        }
+        while (ns > 0 && nl > 0) {
+            const int32_t l = small[p0 + --ns];
+            const int32_t g = large[p0 + --nl];
+            const double ql = q[p0 + l];
+            SlotRec rec = slots[p0 + l];
+            rec.thr = (uint32_t)(ql * 4294967296.0);
+            rec.alias = slots[p0 + g].self;
+            rec.aslot = (uint32_t)g;
+            slots[p0 + l] = rec;
+            const double qg = (q[p0 + g] + ql) - 1.0;
+            q[p0 + g] = qg;
+            if (qg < 1.0)
+                small[p0 + ns++] = g;
+            else
+                large[p0 + nl++] = g;
+        }
+    }
+    if (bias) {
+        for (int64_t s = 0; s < deg; ++s) {
+            const uint32_t a = slots[p0 + s].aslot;
+            corr[p0 + s].y = corr[p0 + a].x;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_check_rowptr(int64_t n, int64_t nnz, const int64_t *rowptr, uint32_t *flags,
+                               hipStream_t s) {
+    const int64_t threads = n + 1;
+    const int block = 256;
+    const int64_t grid = (threads + block - 1) / block;
+    hipLaunchKernelGGL(k_check_rowptr, dim3((unsigned)grid), dim3(block), 0, s, n, nnz, rowptr,
+                       flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup_rows(int64_t n, const int64_t *rowptr, const int32_t *col,
+                             const double *val, const float *bias, const Tables &base,
+                             Tables &out, double *q_scratch, int32_t *stack_small,
+                             int32_t *stack_large, uint32_t *flags, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int block = 128;
+    const int64_t grid = (n + block - 1) / block;
+    hipLaunchKernelGGL(k_setup_rows, dim3((unsigned)grid), dim3(block), 0, s, n, rowptr, col,
+                       val, bias, base.r, base.d64, out.rows, out.d64, out.d32, out.r,
+                       out.slots, out.corr, q_scratch, stack_small, stack_large, flags);
+    return hipGetLastError();
+}
+
+}  // namespace mc

@@ -1,0 +1,340 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Same seeded inputs on both sides.  Integer results (tables, final states, event
+and jump counts) must be bit-identical; estimates must agree within 1e-12
+relative in FP64 weight mode and 1e-5 relative in FP32 weight mode (the
+oracle is always FP64).  Standard errors agree to 1e-8 relative in FP64: the
+GPU forms them from shifted one-pass sums, the oracle with two passes.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as orc
+from oracle import Oracle
+import paper_1904_12759_amd as mc
+from paper_1904_12759_amd import workloads as wl
+import refs
+
+pytestmark = pytest.mark.gpu
+
+RTOL64 = 1e-12
+RTOL32 = 1e-5
+
+
+def _pair(a: wl.CSR, t, seed, mode=mc.EXACT, dt=0.03125, fp32=False, instance=0,
+          max_events=0, **kw):
+    g = mc.MCExpmv(a.rowptr, a.col, a.val, t, seed, mode=mode, dt=dt, fp32=fp32,
+                   instance=instance, max_events=max_events, **kw)
+    o = Oracle(a.rowptr, a.col, a.val, t, seed, mode=mode, dt=dt, instance=instance,
+               max_events=max_events)
+    return g, o
+
+
+def _v_for(v, fp32):
+    """The vector as the GPU sees it (float32 in FP32 mode), widened for the oracle."""
+    return np.asarray(v, np.float32).astype(np.float64) if fp32 else np.asarray(v, np.float64)
+
+
+def _close(a, b, rtol):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    scale = np.maximum(np.abs(b), 1e-300)
+    return np.all(np.abs(a - b) <= rtol * scale)
+
+
+def _matrices():
+    out = {}
+    out["sym48"] = wl.from_dense(refs.random_metzler(48, 0.15, 1, True))
+    out["nonsym48"] = wl.from_dense(refs.random_metzler(48, 0.2, 2, False, off_scale=2.0))
+    a = refs.random_metzler(40, 0.3, 3, False)
+    a[5, :] = 0.0
+    a[5, 5] = -0.5            # a row with no jumps
+    a[7, :] = 0.0
+    a[7, [2, 9, 30]] = 0.75    # a uniform row
+    out["special40"] = wl.from_dense(a)
+    out["grid2d_16"] = wl.grid2d(16)
+    out["cycle31"] = wl.cycle_graph(31, 0.8)
+    return out
+
+
+MATS = _matrices()
+
+
+# ------------------------------------------------------------------ tables
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_tables_bit_identical(name):
+    a = MATS[name]
+    g, o = _pair(a, 1.0, 5)
+    tg, to = g.tables(), o.tables()
+    for key in ("r", "d", "inv_r", "deg", "begin", "col", "thr", "alias"):
+        assert np.array_equal(tg[key], to[key]), key
+
+
+def test_tables_bit_identical_ba_config():
+    w = wl.config_ba_full(n=20_000)
+    g, o = _pair(w.a, w.t, 1)
+    tg, to = g.tables(), o.tables()
+    for key in ("r", "d", "inv_r", "deg", "begin", "col", "thr", "alias"):
+        assert np.array_equal(tg[key], to[key]), key
+
+
+# ---------------------------------------------------------- walker paths
+@pytest.mark.parametrize("mode", [mc.EXACT, mc.STRANG, mc.LIE])
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("name", ["nonsym48", "special40", "grid2d_16"])
+def test_paths_bit_identical(name, mode, fp32):
+    a = MATS[name]
+    t = 1.3
+    g, o = _pair(a, t, 777, mode=mode, dt=0.1, fp32=fp32)
+    v = np.random.default_rng(4).uniform(0.1, 2.0, a.n)
+    vv = _v_for(v, fp32)
+    for start in (0, 5, 7, a.n - 1):
+        count = 3000
+        xg, eg, jg, fg = g.trace(v, start, 10, count)
+        xo, eo, jo, fo, _ = o.trace(vv, start, 10, count)
+        assert np.array_equal(xg, xo)
+        assert np.array_equal(eg, eo)
+        assert np.array_equal(jg, jo)
+        assert _close(fg, fo, RTOL32 if fp32 else RTOL64)
+
+
+# ------------------------------------------------------------- estimates
+@pytest.mark.parametrize("mode", [mc.EXACT, mc.STRANG, mc.LIE])
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_entries_match_oracle_fp64(name, mode):
+    a = MATS[name]
+    t = 0.9
+    g, o = _pair(a, t, 4242, mode=mode, dt=0.07)
+    v = np.random.default_rng(9).uniform(-1.0, 2.0, a.n)
+    idx = np.array([0, 3, 5, 7, a.n - 1, 3, 11], np.int64)
+    # 2500 walkers: three chunks, the last one ragged
+    est, se = g.entries(v, idx, 2500)
+    eo, so = o.estimate(v, idx, 2500)
+    assert _close(est.cpu().numpy(), eo, RTOL64)
+    assert np.allclose(se.cpu().numpy(), so, rtol=1e-8, atol=1e-300)
+    assert est[1].item() == est[5].item()       # duplicate entries are identical
+
+
+@pytest.mark.parametrize("name", ["sym48", "special40", "grid2d_16"])
+def test_full_matches_oracle_and_entries(name):
+    a = MATS[name]
+    g, o = _pair(a, 0.7, 31)
+    v = np.random.default_rng(1).random(a.n)
+    est, se = g.full(v, 700)
+    eo, so = o.estimate(v, None, 700)
+    assert _close(est.cpu().numpy(), eo, RTOL64)
+    assert np.allclose(se.cpu().numpy(), so, rtol=1e-8, atol=1e-300)
+    idx = np.arange(a.n)[::3]
+    e2, s2 = g.entries(v, idx, 700)
+    assert torch.equal(e2, est[torch.as_tensor(idx, device=est.device)])
+    assert torch.equal(s2, se[torch.as_tensor(idx, device=se.device)])
+
+
+@pytest.mark.parametrize("mode", [mc.EXACT, mc.STRANG])
+def test_fp32_weights_match_oracle(mode):
+    a = MATS["nonsym48"]
+    g, o = _pair(a, 1.1, 8, mode=mode, dt=0.05, fp32=True)
+    v = np.random.default_rng(2).uniform(0.2, 1.0, a.n)
+    est, se = g.full(v, 3000)
+    eo, so = o.estimate(_v_for(v, True), None, 3000)
+    assert _close(est.cpu().numpy(), eo, RTOL32)
+
+
+def test_results_are_deterministic_and_launch_independent():
+    a = MATS["grid2d_16"]
+    v = np.random.default_rng(3).random(a.n)
+    outs = []
+    for block in (64, 128, 256):
+        g = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 99, walkers_per_block=block)
+        outs.append(g.full(v, 1500))
+    for e, s in outs[1:]:
+        assert torch.equal(e, outs[0][0]) and torch.equal(s, outs[0][1])
+
+
+def test_instance_id_matches_oracle():
+    a = MATS["sym48"]
+    g, o = _pair(a, 1.0, 5, instance=17)
+    v = np.ones(a.n)
+    est, _ = g.entries(v, [1, 2, 3], 4000)
+    eo, _ = o.estimate(v, [1, 2, 3], 4000)
+    assert _close(est.cpu().numpy(), eo, RTOL64)
+    g0 = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 5)
+    e0, _ = g0.entries(v, [1, 2, 3], 4000)
+    assert not torch.equal(e0, est)
+
+
+# ------------------------------------------------------------ edge cases
+def test_t_zero_returns_v():
+    a = MATS["nonsym48"]
+    v = np.random.default_rng(5).random(a.n)
+    for mode in (mc.EXACT, mc.STRANG, mc.LIE):
+        g = mc.MCExpmv(a.rowptr, a.col, a.val, 0.0, 1, mode=mode, dt=0.1)
+        est, se = g.full(v, 64)
+        assert np.allclose(est.cpu().numpy(), v, rtol=1e-15, atol=0)
+        assert np.all(se.cpu().numpy() <= 1e-15 * v)
+
+
+def test_single_walker_and_empty_requests():
+    a = MATS["sym48"]
+    g, o = _pair(a, 1.0, 3)
+    v = np.random.default_rng(6).random(a.n)
+    est, se = g.entries(v, [4], 1)
+    eo, _ = o.estimate(v, [4], 1)
+    assert _close(est.cpu().numpy(), eo, RTOL64) and se.item() == 0.0
+    est, se = g.entries(v, np.zeros(0, np.int64), 10)
+    assert est.numel() == 0
+
+
+def test_diagonal_matrix_exact_on_gpu():
+    d = np.array([-1.0, 0.0, 0.3, 2.0])
+    a = wl.from_dense(np.diag(d))
+    g = mc.MCExpmv(a.rowptr, a.col, a.val, 0.7, 1)
+    v = np.array([1.0, 2.0, -3.0, 0.5])
+    est, se = g.full(v, 100)
+    assert np.allclose(est.cpu().numpy(), np.exp(d * 0.7) * v, rtol=1e-15, atol=0)
+
+
+def test_out_of_range_entry_is_reported():
+    a = MATS["sym48"]
+    g = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 3)
+    v = np.ones(a.n)
+    with pytest.raises(mc.MCError) as ei:
+        g.entries(v, [1, 48, -1], 10)
+    assert ei.value.code == 4
+    est, _ = g.entries(v, [1, 2], 10)       # the latched error was cleared
+    assert torch.isfinite(est).all()
+
+
+def test_walk_limit_is_reported():
+    a = wl.cycle_graph(8, 50.0)
+    g = mc.MCExpmv(a.rowptr, a.col, a.val, 10.0, 1, max_events=64)
+    with pytest.raises(mc.MCError) as ei:
+        g.entries(np.ones(8), [0], 4)
+    assert ei.value.code == 8
+
+
+@pytest.mark.parametrize("kind,code", [("negative", 2), ("nan", 3), ("col", 1), ("rowptr", 1)])
+def test_create_rejects_invalid_matrices(kind, code):
+    a = np.array([[-1.0, 0.5, 0.0], [0.5, -1.0, 0.5], [0.0, 0.5, -1.0]])
+    csr = wl.from_dense(a)
+    rowptr, col, val = csr.rowptr.copy(), csr.col.copy(), csr.val.copy()
+    if kind == "negative":
+        val[1] = -0.5
+    elif kind == "nan":
+        val[2] = np.nan
+    elif kind == "col":
+        col[3] = 7
+    elif kind == "rowptr":
+        rowptr[1] = 5
+        rowptr[2] = 2
+    with pytest.raises(mc.MCError) as ei:
+        mc.MCExpmv(rowptr, col, val, 1.0, 1)
+    assert ei.value.code == code
+    with pytest.raises(orc.OracleError) as eo:
+        Oracle(rowptr, col, val, 1.0, 1)
+    assert eo.value.code == code
+
+
+def test_stream_ordering_on_a_side_stream():
+    a = MATS["grid2d_16"]
+    v = np.random.default_rng(8).random(a.n)
+    g = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 4)
+    ref, _ = g.full(v, 500)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        vt = torch.as_tensor(v, device="cuda")
+        g.set_stream(s.cuda_stream)
+        est = torch.empty(a.n, dtype=torch.float64, device="cuda")
+        g.full(vt, 500, est=est, sync=False)
+        out = est * 1.0                    # consumer on the same stream
+    s.synchronize()
+    g.sync()
+    assert torch.equal(out, ref)
+
+
+# ------------------------------------------------------ tilted proposal
+def test_proposal_tables_and_paths_match_oracle():
+    a = MATS["nonsym48"]
+    bias = np.random.default_rng(4).normal(0, 0.6, a.nnz).astype(np.float32)
+    g, o = _pair(a, 1.0, 55)
+    g.set_proposal(bias)
+    o.set_proposal(bias)
+    tg, to = g.tables(proposal=True), o.tables(proposal=True)
+    for key in ("deg", "begin", "col"):
+        assert np.array_equal(tg[key], to[key]), key
+    for key in ("r", "d", "inv_r"):
+        assert np.allclose(tg[key], to[key], rtol=4e-16, atol=0), key
+    # thresholds come from a*exp(b): a 1-ulp exp difference may move one by a unit
+    assert np.abs(tg["thr"].astype(np.int64) - to["thr"].astype(np.int64)).max() <= 1
+    v = np.random.default_rng(5).uniform(0.3, 1.0, a.n)
+    for start in (0, 17, 47):
+        xg, eg, jg, fg = g.trace(v, start, 0, 4000, proposal=True)
+        xo, eo, jo, fo, _ = o.trace(v, start, 0, 4000, proposal=True)
+        assert np.array_equal(xg, xo) and np.array_equal(eg, eo) and np.array_equal(jg, jo)
+        assert _close(fg, fo, 1e-12)
+    est, _ = g.full(v, 2000)
+    eo, _ = o.estimate(v, None, 2000, proposal=True)
+    assert _close(est.cpu().numpy(), eo, 1e-12)
+
+
+def test_zero_bias_is_bit_identical_to_plain():
+    a = MATS["special40"]
+    g = mc.MCExpmv(a.rowptr, a.col, a.val, 1.2, 8)
+    v = np.random.default_rng(1).random(a.n)
+    e0, s0 = g.full(v, 1000)
+    g.set_proposal(np.zeros(a.nnz, np.float32))
+    e1, s1 = g.full(v, 1000)
+    assert torch.equal(e0, e1) and torch.equal(s0, s1)
+    g.set_proposal(None)
+    e2, _ = g.full(v, 1000)
+    assert torch.equal(e0, e2)
+
+
+def test_ground_state_proposal_zero_variance_on_gpu():
+    m = 12
+    csr = wl.grid2d(m)
+    phi, lam = refs.grid2d_ground_state(m)
+    rows = np.repeat(np.arange(csr.n), np.diff(csr.rowptr))
+    bias = (np.log(phi[csr.col]) - np.log(phi[rows])).astype(np.float32)
+    t = 0.6
+    g = mc.MCExpmv(csr.rowptr, csr.col, csr.val, t, 8)
+    g.set_proposal(bias)
+    est, se = g.full(phi, 256)
+    est = est.cpu().numpy()
+    assert np.allclose(est, np.exp(lam * t) * phi, rtol=2e-6)
+    assert np.all(se.cpu().numpy() <= 2e-6 * est)
+
+
+# ------------------------------------------------- benchmark-size configs
+def test_grid2d_config_full_size_parity():
+    """32x32 Dirichlet grid, t = 0.1, 16 entries x 1e5 walkers, FP64 (every walker)."""
+    w = wl.config_grid2d_entries()
+    g, o = _pair(w.a, w.t, 12759)
+    est, se = g.entries(w.v, w.idx, w.nwalk)
+    eo, so = o.estimate(w.v, w.idx, w.nwalk, threads=8)
+    assert _close(est.cpu().numpy(), eo, RTOL64)
+    assert np.allclose(se.cpu().numpy(), so, rtol=1e-8)
+    ref = refs.grid2d_expm_v(32, w.t, w.v)[w.idx]
+    z = (est.cpu().numpy() - ref) / se.cpu().numpy()
+    assert np.abs(z).max() < 4.5
+
+
+def test_ba_config_full_size_sampled_parity():
+    """BA n=1e5, m=3, full vector with 1e3 walkers/node in FP32 weights: the whole
+    vector on the GPU, sampled nodes (hubs included) recomputed by the oracle."""
+    w = wl.config_ba_full()
+    g = mc.MCExpmv(w.a.rowptr, w.a.col, w.a.val, w.t, 12759, fp32=True)
+    est, se = g.full(w.v, w.nwalk)
+    est = est.cpu().numpy()
+    o = Oracle(w.a.rowptr, w.a.col, w.a.val, w.t, 12759)
+    deg = np.diff(w.a.rowptr)
+    hubs = np.argsort(-deg)[:20]
+    rand = np.random.default_rng(0).choice(w.a.n, 180, replace=False)
+    sample = np.unique(np.concatenate([hubs, rand]))
+    eo, _ = o.estimate(_v_for(w.v, True), sample, w.nwalk, threads=8)
+    assert _close(est[sample], eo, RTOL32)
+    st = g.stats()
+    assert st["walkers"] == w.a.n * w.nwalk
+    assert st["events"] == st["walkers"] + st["jumps"]
