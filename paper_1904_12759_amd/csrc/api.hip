@@ -30,8 +30,6 @@ struct mc_expmv_s {
     unsigned long long *counters = nullptr;
     double *part = nullptr;              // chunk partials
     int64_t part_cap = 0;                // doubles
-    double *shift = nullptr;
-    int64_t shift_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // last run
     bool ran = false;
@@ -139,12 +137,20 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
     const int64_t chunks = (nwalk + kChunk - 1) / kChunk;
     WalkArgs a{};
     const Tables &tb = prop ? h->prop : h->plain;
-    a.rows = tb.rows;
-    a.d64 = tb.d64;
-    a.d32 = tb.d32;
-    a.slots = tb.slots;
-    a.corr = prop ? tb.corr : nullptr;
-    a.v = v;
+    a.P.rows = tb.rows;
+    a.P.d64 = tb.d64;
+    a.P.d32 = tb.d32;
+    a.P.slots = tb.slots;
+    a.P.corr = prop ? tb.corr : nullptr;
+    a.P.v = v;
+    a.P.t = h->t;
+    a.P.dt = h->dt;
+    a.P.inv_dt = h->inv_dt;
+    a.P.ngrid = (int32_t)h->ngrid;
+    a.P.key0 = (uint32_t)h->seed;
+    a.P.key1 = (uint32_t)(h->seed >> 32);
+    a.P.inst = h->opts.instance_id;
+    a.P.max_events = h->opts.max_events ? h->opts.max_events : (1u << 24);
     a.idx = idx;
     a.k = k;
     a.n = h->n;
@@ -153,26 +159,18 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
     a.chunk = kChunk;
     a.chunks = chunks;
     a.ntasks = k * chunks;
-    a.t = h->t;
-    a.dt = h->dt;
-    a.inv_dt = h->inv_dt;
-    a.ngrid = h->ngrid;
-    a.key0 = (uint32_t)h->seed;
-    a.key1 = (uint32_t)(h->seed >> 32);
-    a.inst = h->opts.instance_id;
-    a.max_events = h->opts.max_events ? h->opts.max_events : (1u << 24);
     a.est = est;
     a.se = se;
     a.counters = h->counters;
     a.flags = h->flags;
     if (trace) {
-        a.tr_x = tx;
-        a.tr_ev = tev;
-        a.tr_ju = tju;
-        a.tr_f = tf;
+        a.trace.x = tx;
+        a.trace.ev = tev;
+        a.trace.ju = tju;
+        a.trace.f = tf;
     }
     if (chunks > 1) {
-        const int64_t need = k * chunks * 2;
+        const int64_t need = k * chunks * 3;
         if (need > h->part_cap) {
             HIP_TRY(hipStreamSynchronize(h->stream));
             (void)hipFree(h->part);
@@ -181,16 +179,7 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
             HIP_TRY(dalloc(&h->part, need));
             h->part_cap = need;
         }
-        if (k > h->shift_cap) {
-            HIP_TRY(hipStreamSynchronize(h->stream));
-            (void)hipFree(h->shift);
-            h->shift = nullptr;
-            h->shift_cap = 0;
-            HIP_TRY(dalloc(&h->shift, k));
-            h->shift_cap = k;
-        }
         a.part = h->part;
-        a.shift = h->shift;
     }
     HIP_TRY(hipMemsetAsync(h->counters, 0, 2 * sizeof(unsigned long long), h->stream));
     HIP_TRY(hipEventRecord(h->ev0, h->stream));
@@ -253,7 +242,6 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->flags);
     (void)hipFree(h->counters);
     (void)hipFree(h->part);
-    (void)hipFree(h->shift);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;

@@ -49,42 +49,45 @@ enum : uint32_t {
     F_OVERFLOW = 1u << MC_ERR_OVERFLOW,
 };
 
-// ---------------------------------------------------------- Philox4x32-10
-// Salmon, Moraes, Dror, Shaw (SC'11): ten rounds of the Philox S-P network,
-// multipliers 0xD2511F53 / 0xCD9E8D57, Weyl key increments 0x9E3779B9 /
-// 0xBB67AE85.
+// Philox4x32-10 output block.
 struct U4 {
     uint32_t x, y, z, w;
 };
 
-__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                       uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return U4{c0, c1, c2, c3};
-}
-
 // ---------------------------------------------------------- launch params
-struct WalkArgs {
+// What a task needs to know about its instance (matrix, horizon, weights).
+struct InstArgs {
     const RowRec *rows;
     const double *d64;
     const float *d32;
     const SlotRec *slots;
     const float2 *corr;        // non-null only for the tilted walk
-    const void *v;             // double* or float*
+    const void *v;             // double* (FP64 weights) or float* (FP32 weights)
+    double t;
+    double dt;                 // t / N
+    double inv_dt;             // N / t
+    int32_t ngrid;             // N
+    uint32_t key0, key1, inst, max_events;
+};
+
+// Per-walker record (parity checks only).
+struct TraceOut {
+    int32_t *x = nullptr;
+    uint32_t *ev = nullptr;
+    uint32_t *ju = nullptr;
+    double *f = nullptr;
+    int64_t base = 0;
+};
+
+// Statistics of one task, identical in every lane of the wave.
+struct TaskResult {
+    double n, mean, m2;        // count, mean and sum of squared deviations
+    unsigned long long events, jumps;
+    uint32_t err;
+};
+
+struct WalkArgs {
+    InstArgs P;
     const int64_t *idx;        // null: entry e is node e
     int64_t k;                 // entries
     int64_t n;
@@ -93,22 +96,12 @@ struct WalkArgs {
     uint32_t chunk;            // walkers per task
     int64_t chunks;            // tasks per entry
     int64_t ntasks;
-    double t;
-    double dt;                 // t / N
-    double inv_dt;             // N / t
-    int64_t ngrid;             // N
-    uint32_t key0, key1, inst, max_events;
     double *est;               // [k]   (chunks == 1) final results
     double *se;                // [k] or null
-    double *part;              // [k * chunks * 2] partial sums (chunks > 1)
-    double *shift;             // [k] per-entry shift (chunks > 1)
+    double *part;              // [k * chunks * 3] (count, mean, M2) per chunk
     unsigned long long *counters;  // [2]: events, jumps
     uint32_t *flags;
-    // trace outputs (per walker of one task)
-    int32_t *tr_x;
-    uint32_t *tr_ev;
-    uint32_t *tr_ju;
-    double *tr_f;
+    TraceOut trace;
 };
 
 // host-side launchers (walk.hip)

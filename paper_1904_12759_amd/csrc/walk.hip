@@ -5,19 +5,76 @@
 // ordinals c*chunk .. min(N, (c+1)*chunk)-1 started at node idx[e].  One
 // wavefront owns a task; its 64 lanes each run one walker and, when a walker
 // stops, take the next unstarted ordinal of the chunk (lane refill), so a long
-// path holds up one lane instead of the whole wave.  Each lane accumulates
-// sum(f - K) and sum((f - K)^2) in FP64, where K is the value of a walker that
-// never jumps (most walkers at the benchmark sizes), and the wave combines the
-// lane sums with cross-lane shuffles.  Paths depend only on the Philox counter
-// (event, ordinal, start node, instance), never on which lane ran them.
+// path holds up one lane instead of the whole wave.  Paths depend only on the
+// Philox counter (event, ordinal, start node, instance), never on the lane.
+//
+// Statistics.  Each lane keeps the count, the first value it saw (a shift)
+// and the shifted sums of f and f^2; the wave then merges lanes pairwise with
+// the Chan-Golub-LeVeque update of (count, mean, M2), and chunks are merged the
+// same way in chunk order.  A shift taken from the sample itself keeps the
+// shifted sums well conditioned even when the weights are heavy tailed.
 #include <math.h>
 
 #include "mc_internal.hpp"
 
 namespace mc {
+
+// ------------------------------------------------------------- primitives
 namespace {
 
 constexpr int WAVE = 64;
+
+// ln 2 split so that e * kLn2Hi is exact for |e| < 2^11 (low 21 bits zero).
+constexpr double kLn2Hi = 0x1.62e42fee00000p-1;
+constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
+
+// Natural logarithm of u in (0, 1].  With u = m 2^e, m in [1/sqrt2, sqrt2),
+// log u = e ln2 + 2 atanh(f), f = (m-1)/(m+1), |f| < 0.1716, and atanh(f)/f is
+// the Taylor series sum_k f^{2k}/(2k+1), kept to f^24 (truncation < 1e-19).
+// Within about 2 ulp of the correctly rounded logarithm.
+__device__ __forceinline__ double log_unit(double u) {
+    int e;
+    double m = frexp(u, &e);
+    if (m < 0.70710678118654752440) {
+        m = m + m;
+        e -= 1;
+    }
+    const double f = (m - 1.0) / (m + 1.0);
+    const double f2 = f * f;
+    double p = 1.0 / 25.0;
+    p = fma(p, f2, 1.0 / 23.0);
+    p = fma(p, f2, 1.0 / 21.0);
+    p = fma(p, f2, 1.0 / 19.0);
+    p = fma(p, f2, 1.0 / 17.0);
+    p = fma(p, f2, 1.0 / 15.0);
+    p = fma(p, f2, 1.0 / 13.0);
+    p = fma(p, f2, 1.0 / 11.0);
+    p = fma(p, f2, 1.0 / 9.0);
+    p = fma(p, f2, 1.0 / 7.0);
+    p = fma(p, f2, 1.0 / 5.0);
+    p = fma(p, f2, 1.0 / 3.0);
+    p = fma(p, f2, 1.0);
+    const double de = (double)e;
+    return fma(de, kLn2Hi, fma(de, kLn2Lo, 2.0 * f * p));
+}
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0;
+        c1 = (uint32_t)p1;
+        c2 = n2;
+        c3 = (uint32_t)p0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
 
 template <bool FP32>
 struct WeightT {
@@ -28,31 +85,19 @@ struct WeightT<true> {
     using T = float;
 };
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, WAVE);
-    return x;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, WAVE);
-    return x;
-}
-
 // Grid index K(s) = min(N, ceil(s * N / t)): the grid points k*dt with
 // K(s_a) <= k < K(s_b) lie in the holding interval [s_a, s_b).
-__device__ __forceinline__ int64_t grid_index(double s, double inv_dt, int64_t ngrid) {
+__device__ __forceinline__ int32_t grid_index(double s, double inv_dt, int32_t ngrid) {
     const double g = ceil(s * inv_dt);
-    return g >= (double)ngrid ? ngrid : (int64_t)g;
+    return g >= (double)ngrid ? ngrid : (int32_t)g;
 }
 
-// Sum of quadrature coefficients c_k over the grid points k in [ka, kb]
-// (kb >= ka - 1).  STRANG (trapezoid): c_0 = c_N = 1/2, else 1.  LIE (right
-// Riemann sum of Eq. (deff)): c_0 = 0, else 1.
+// Sum of quadrature coefficients c_k over the grid points ka..kb (kb >= ka-1).
+// STRANG (trapezoid): c_0 = c_N = 1/2, else 1.  LIE (right Riemann sum of
+// Eq. (deff)): c_0 = 0, else 1.
 template <int MODE>
-__device__ __forceinline__ double grid_coef_sum(int64_t ka, int64_t kb, int64_t ngrid) {
-    const int64_t count = kb - ka + 1;
+__device__ __forceinline__ double grid_coef_sum(int32_t ka, int32_t kb, int32_t ngrid) {
+    const int32_t count = kb - ka + 1;
     if (count <= 0) return 0.0;
     double c = (double)count;
     if (ka == 0) c -= (MODE == MC_STRANG) ? 0.5 : 1.0;
@@ -61,7 +106,7 @@ __device__ __forceinline__ double grid_coef_sum(int64_t ka, int64_t kb, int64_t 
 }
 
 template <bool FP32>
-__device__ __forceinline__ typename WeightT<FP32>::T load_v(const void *v, int64_t i) {
+__device__ __forceinline__ typename WeightT<FP32>::T load_v(const void *v, uint32_t i) {
     if constexpr (FP32)
         return static_cast<const float *>(v)[i];
     else
@@ -69,11 +114,11 @@ __device__ __forceinline__ typename WeightT<FP32>::T load_v(const void *v, int64
 }
 
 template <bool FP32>
-__device__ __forceinline__ typename WeightT<FP32>::T load_d(const WalkArgs &a, int64_t i) {
+__device__ __forceinline__ typename WeightT<FP32>::T load_d(const InstArgs &P, uint32_t i) {
     if constexpr (FP32)
-        return a.d32[i];
+        return P.d32[i];
     else
-        return a.d64[i];
+        return P.d64[i];
 }
 
 template <bool FP32>
@@ -84,32 +129,225 @@ __device__ __forceinline__ typename WeightT<FP32>::T wexp(typename WeightT<FP32>
         return exp(x);
 }
 
-// Log-weight of the last holding interval [s, t] in state x (weight exponent dx).
+// Log-weight of the last holding interval [s, t] in a state with exponent dx.
 template <int MODE, bool FP32>
-__device__ __forceinline__ typename WeightT<FP32>::T final_term(
-    typename WeightT<FP32>::T dx, double s, int64_t ka, const WalkArgs &a) {
+__device__ __forceinline__ typename WeightT<FP32>::T final_term(typename WeightT<FP32>::T dx,
+                                                                double s, int32_t ka,
+                                                                const InstArgs &P) {
     using WT = typename WeightT<FP32>::T;
     if constexpr (MODE == MC_EXACT) {
-        return dx * (WT)(a.t - s);
+        return dx * (WT)(P.t - s);
     } else {
-        const double c = grid_coef_sum<MODE>(ka, a.ngrid, a.ngrid);
-        return dx * (WT)(c * a.dt);
+        const double c = grid_coef_sum<MODE>(ka, P.ngrid, P.ngrid);
+        return dx * (WT)(c * P.dt);
     }
 }
 
+// Merge (nb, mb, qb) into (na, ma, qa): count, mean and sum of squared
+// deviations of the union (Chan, Golub, LeVeque 1979).
+__device__ __forceinline__ void chan_merge(double &na, double &ma, double &qa, double nb,
+                                           double mb, double qb) {
+    const double n = na + nb;
+    if (nb == 0.0) return;
+    if (na == 0.0) {
+        na = nb;
+        ma = mb;
+        qa = qb;
+        return;
+    }
+    const double delta = mb - ma;
+    const double w = nb / n;
+    ma = ma + delta * w;
+    qa = qa + qb + delta * delta * na * w;
+    na = n;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, WAVE);
+    return x;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------- one task
+// Runs walkers ord0 .. ord0+cnt-1 from `node` on the calling wavefront and
+// leaves, in every lane, the wave's (count, mean, M2) of W * v[X_t] plus the
+// event and jump totals.  All lanes of the wave must call it together.
 template <int MODE, bool FP32, bool PROP, bool TRACE>
-__global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
+__device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node, uint32_t ord0,
+                                               uint32_t cnt, const TraceOut &tr) {
     using WT = typename WeightT<FP32>::T;
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned long long lanemask_lt = (1ull << lane) - 1ull;
+    const double t = P.t;
+
+    // start row: the same for every walker of the task
+    const RowRec r0 = P.rows[node];
+    const WT d0 = load_d<FP32>(P, node);
+    const WT v0 = load_v<FP32>(P.v, node);
+    // K: the value of a walker that never leaves the start node
+    const double K = (double)(wexp<FP32>(final_term<MODE, FP32>(d0, 0.0, 0, P)) * v0);
+    // U below e0 means the first holding time certainly outlasts t: then
+    // -log(U)/r0 > t + 2^-40/r0, far beyond the rounding of the log-based test.
+    const double e0 = r0.deg ? exp(-t / r0.inv_r) * (1.0 - 0x1p-40) : 0.0;
+
+    uint32_t wl = (uint32_t)lane;
+    bool active = wl < cnt;
+    uint32_t x = node;
+    double s = 0.0;
+    WT logw = (WT)0;
+    uint32_t ev = 0, ju = 0;
+    int32_t ka = 0;
+    double inv_r = r0.inv_r;
+    uint32_t deg = r0.deg, begin = r0.begin;
+    WT dx = d0;
+
+    uint32_t nl = 0;
+    double kl = 0.0, s1 = 0.0, s2 = 0.0;
+    unsigned long long evs = 0, jus = 0;
+    uint32_t next = WAVE;
+    uint32_t err = 0;
+
+    while (__ballot(active) != 0ull) {
+        bool fin = false;
+        if (active) {
+            if (deg == 0) {
+                ++ev;                    // no exit rate: holds until t
+                fin = true;
+            } else if (ev >= P.max_events) {
+                err |= F_WALK_LIMIT;
+                fin = true;
+            } else {
+                const U4 o = philox(ev, ord0 + wl, node, P.inst, P.key0, P.key1);
+                ++ev;
+                const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
+                const double U = (double)(m + 1ull) * 0x1p-53;
+                bool jump = false;
+                double S = 0.0, sn = 0.0;
+                if (ju != 0 || U >= e0) {
+                    S = -log_unit(U) * inv_r;
+                    sn = s + S;
+                    jump = sn < t;
+                }
+                if (jump) {
+                    if constexpr (MODE == MC_EXACT) {
+                        logw = logw + dx * (WT)S;
+                    } else {
+                        const int32_t kb = grid_index(sn, P.inv_dt, P.ngrid);
+                        const double cs = grid_coef_sum<MODE>(ka, kb - 1, P.ngrid);
+                        logw = logw + dx * (WT)(cs * P.dt);
+                        ka = kb;
+                    }
+                    s = sn;
+                    const uint32_t sl = (uint32_t)(((uint64_t)o.z * (uint64_t)deg) >> 32);
+                    const SlotRec q = P.slots[begin + sl];
+                    const bool keep = o.w < q.thr;
+                    x = (uint32_t)(keep ? q.self : q.alias);
+                    if constexpr (PROP) {
+                        const float2 cr = P.corr[begin + sl];
+                        logw = logw + (WT)(keep ? cr.x : cr.y);
+                    }
+                    ++ju;
+                    const RowRec rr = P.rows[x];
+                    inv_r = rr.inv_r;
+                    deg = rr.deg;
+                    begin = rr.begin;
+                    dx = load_d<FP32>(P, x);
+                } else {
+                    fin = true;
+                }
+            }
+            if (fin) {
+                double f = K;            // never left the start node
+                if (ju != 0) {
+                    logw = logw + final_term<MODE, FP32>(dx, s, ka, P);
+                    f = (double)(wexp<FP32>(logw) * load_v<FP32>(P.v, x));
+                    if (!isfinite(f)) err |= F_OVERFLOW;
+                }
+                if (nl == 0) kl = f;
+                const double df = f - kl;
+                s1 += df;
+                s2 += df * df;
+                ++nl;
+                evs += ev;
+                jus += ju;
+                if constexpr (TRACE) {
+                    const int64_t ti = tr.base + wl;
+                    tr.x[ti] = (int32_t)x;
+                    tr.ev[ti] = ev;
+                    tr.ju[ti] = ju;
+                    tr.f[ti] = f;
+                }
+            }
+        }
+        const unsigned long long fmask = __ballot(fin);
+        if (fin) {
+            wl = next + (uint32_t)__popcll(fmask & lanemask_lt);
+            if (wl < cnt) {
+                x = node;
+                s = 0.0;
+                logw = (WT)0;
+                ev = 0;
+                ju = 0;
+                ka = 0;
+                inv_r = r0.inv_r;
+                deg = r0.deg;
+                begin = r0.begin;
+                dx = d0;
+            } else {
+                active = false;
+            }
+        }
+        next += (uint32_t)__popcll(fmask);
+    }
+
+    // lane -> (count, mean, M2), then pairwise across the wave
+    double n = (double)nl, mean = 0.0, q = 0.0;
+    if (nl) {
+        mean = kl + s1 / n;
+        q = s2 - s1 * (s1 / n);
+        if (q < 0.0) q = 0.0;
+    }
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const double nb = __shfl_xor(n, off, WAVE);
+        const double mb = __shfl_xor(mean, off, WAVE);
+        const double qb = __shfl_xor(q, off, WAVE);
+        // the lower lane of each pair keeps its own part first
+        if (lane & off) {
+            double n2 = nb, m2 = mb, q2 = qb;
+            chan_merge(n2, m2, q2, n, mean, q);
+            n = n2;
+            mean = m2;
+            q = q2;
+        } else {
+            chan_merge(n, mean, q, nb, mb, qb);
+        }
+    }
+    TaskResult res;
+    res.n = n;
+    res.mean = mean;
+    res.m2 = q;
+    res.events = wave_sum_u64(evs);
+    res.jumps = wave_sum_u64(jus);
+    res.err = err;
+    return res;
+}
+
+namespace {
+
+// Entries (or, with idx == null, every node) of one instance.
+template <int MODE, bool FP32, bool PROP, bool TRACE>
+__global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
+    const int lane = threadIdx.x & (WAVE - 1);
     const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
-    const double t = a.t;
-
     for (int64_t task = wave_id; task < a.ntasks; task += nwaves) {
         const int64_t e = task / a.chunks;
         const int64_t c = task - e * a.chunks;
         const int64_t node = a.idx ? a.idx[e] : e;
+        double *part = a.part + (e * a.chunks + c) * 3;
         if (node < 0 || node >= a.n) {
             if (lane == 0) {
                 atomicOr(a.flags, F_OUT_OF_RANGE);
@@ -117,9 +355,9 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
                     a.est[e] = NAN;
                     if (a.se) a.se[e] = NAN;
                 } else {
-                    a.part[(e * a.chunks + c) * 2] = NAN;
-                    a.part[(e * a.chunks + c) * 2 + 1] = NAN;
-                    if (c == 0) a.shift[e] = NAN;
+                    part[0] = 1.0;
+                    part[1] = NAN;
+                    part[2] = NAN;
                 }
             }
             continue;
@@ -127,163 +365,43 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
         const int64_t wbase = c * (int64_t)a.chunk;
         const int64_t rem = a.nwalk - wbase;
         const uint32_t cnt = (uint32_t)(rem < (int64_t)a.chunk ? rem : (int64_t)a.chunk);
-
-        // start row: the same for every walker of the task
-        const RowRec r0 = a.rows[node];
-        const WT d0 = load_d<FP32>(a, node);
-        const WT v0 = load_v<FP32>(a.v, node);
-        // K: the value returned by a walker that never leaves the start node
-        const WT lw0 = final_term<MODE, FP32>(d0, 0.0, 0, a);
-        const double K = (double)(wexp<FP32>(lw0) * v0);
-
-        // walker state
-        uint32_t wl = (uint32_t)lane;
-        bool active = wl < cnt;
-        uint32_t x = (uint32_t)node;
-        double s = 0.0;
-        WT logw = (WT)0;
-        uint32_t ev = 0, ju = 0;
-        int64_t ka = 0;
-        double inv_r = r0.inv_r;
-        uint32_t deg = r0.deg, begin = r0.begin;
-        WT dx = d0;
-
-        double acc1 = 0.0, acc2 = 0.0;
-        unsigned long long evs = 0, jus = 0;
-        uint32_t next = WAVE;
-        uint32_t err = 0;
-
-        while (__ballot(active) != 0ull) {
-            bool fin = false;
-            if (active) {
-                if (deg == 0) {
-                    ++ev;            // a state with no exit rate holds until t
-                    fin = true;
-                } else if (ev >= a.max_events) {
-                    err |= F_WALK_LIMIT;
-                    fin = true;
-                } else {
-                    const U4 o = philox10(ev, (uint32_t)(a.w0 + wbase + wl), (uint32_t)node,
-                                          a.inst, a.key0, a.key1);
-                    ++ev;
-                    const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
-                    const double U = (double)(m + 1ull) * 0x1p-53;
-                    const double S = -log(U) * inv_r;
-                    const double sn = s + S;
-                    if (sn < t) {
-                        if constexpr (MODE == MC_EXACT) {
-                            logw = logw + dx * (WT)S;
-                        } else {
-                            const int64_t kb = grid_index(sn, a.inv_dt, a.ngrid);
-                            const double cs = grid_coef_sum<MODE>(ka, kb - 1, a.ngrid);
-                            logw = logw + dx * (WT)(cs * a.dt);
-                            ka = kb;
-                        }
-                        s = sn;
-                        const uint32_t sl =
-                            (uint32_t)(((uint64_t)o.z * (uint64_t)deg) >> 32);
-                        const SlotRec q = a.slots[begin + sl];
-                        const bool keep = o.w < q.thr;
-                        x = (uint32_t)(keep ? q.self : q.alias);
-                        if constexpr (PROP) {
-                            const float2 cr = a.corr[begin + sl];
-                            logw = logw + (WT)(keep ? cr.x : cr.y);
-                        }
-                        ++ju;
-                        const RowRec rr = a.rows[x];
-                        inv_r = rr.inv_r;
-                        deg = rr.deg;
-                        begin = rr.begin;
-                        dx = load_d<FP32>(a, x);
-                    } else {
-                        fin = true;
-                    }
-                }
-                if (fin) {
-                    logw = logw + final_term<MODE, FP32>(dx, s, ka, a);
-                    const double f = (double)(wexp<FP32>(logw) * load_v<FP32>(a.v, x));
-                    if (!isfinite(f)) err |= F_OVERFLOW;
-                    const double df = f - K;
-                    acc1 += df;
-                    acc2 += df * df;
-                    evs += ev;
-                    jus += ju;
-                    if constexpr (TRACE) {
-                        const int64_t ti = wbase + wl;
-                        a.tr_x[ti] = (int32_t)x;
-                        a.tr_ev[ti] = ev;
-                        a.tr_ju[ti] = ju;
-                        a.tr_f[ti] = f;
-                    }
-                }
-            }
-            const unsigned long long fmask = __ballot(fin);
-            if (fin) {
-                wl = next + (uint32_t)__popcll(fmask & lanemask_lt);
-                if (wl < cnt) {
-                    x = (uint32_t)node;
-                    s = 0.0;
-                    logw = (WT)0;
-                    ev = 0;
-                    ju = 0;
-                    ka = 0;
-                    inv_r = r0.inv_r;
-                    deg = r0.deg;
-                    begin = r0.begin;
-                    dx = d0;
-                } else {
-                    active = false;
-                }
-            }
-            next += (uint32_t)__popcll(fmask);
-        }
-
-        acc1 = wave_sum(acc1);
-        acc2 = wave_sum(acc2);
-        evs = wave_sum_u64(evs);
-        jus = wave_sum_u64(jus);
-        const unsigned long long emask = __ballot(err != 0);
-        if (emask) {
-            if (err) atomicOr(a.flags, err);
-        }
+        TraceOut tr = a.trace;
+        tr.base = wbase;
+        const TaskResult r = run_task<MODE, FP32, PROP, TRACE>(
+            a.P, (uint32_t)node, (uint32_t)(a.w0 + wbase), cnt, tr);
+        if (r.err && lane == 0) atomicOr(a.flags, r.err);
         if (lane == 0) {
             if (a.chunks == 1) {
-                const double nw = (double)a.nwalk;
-                a.est[e] = K + acc1 / nw;
-                if (a.se) {
-                    double var = a.nwalk > 1 ? (acc2 - acc1 * acc1 / nw) / (nw - 1.0) : 0.0;
-                    a.se[e] = sqrt((var > 0.0 ? var : 0.0) / nw);
-                }
+                a.est[e] = r.mean;
+                if (a.se) a.se[e] = r.n > 1.0 ? sqrt(r.m2 / (r.n - 1.0) / r.n) : 0.0;
             } else {
-                a.part[(e * a.chunks + c) * 2] = acc1;
-                a.part[(e * a.chunks + c) * 2 + 1] = acc2;
-                if (c == 0) a.shift[e] = K;
+                part[0] = r.n;
+                part[1] = r.mean;
+                part[2] = r.m2;
             }
             if (a.counters) {
-                atomicAdd(&a.counters[0], evs);
-                atomicAdd(&a.counters[1], jus);
+                atomicAdd(&a.counters[0], r.events);
+                atomicAdd(&a.counters[1], r.jumps);
             }
         }
     }
 }
 
-// Combine the chunk partials of every entry in chunk order.
-__global__ void k_finalize(WalkArgs a) {
+}  // namespace
+
+// Merge the chunk partials of every entry in chunk order.
+__global__ void k_finalize(int64_t k, int64_t chunks, const double *__restrict__ part,
+                           double *__restrict__ est, double *__restrict__ se) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.k) return;
-    double s1 = 0.0, s2 = 0.0;
-    const double *p = a.part + e * a.chunks * 2;
-    for (int64_t c = 0; c < a.chunks; ++c) {
-        s1 += p[2 * c];
-        s2 += p[2 * c + 1];
-    }
-    const double nw = (double)a.nwalk;
-    a.est[e] = a.shift[e] + s1 / nw;
-    if (a.se) {
-        double var = a.nwalk > 1 ? (s2 - s1 * s1 / nw) / (nw - 1.0) : 0.0;
-        a.se[e] = sqrt((var > 0.0 ? var : 0.0) / nw);
-    }
+    if (e >= k) return;
+    const double *p = part + e * chunks * 3;
+    double n = 0.0, mean = 0.0, q = 0.0;
+    for (int64_t c = 0; c < chunks; ++c) chan_merge(n, mean, q, p[3 * c], p[3 * c + 1], p[3 * c + 2]);
+    est[e] = mean;
+    if (se) se[e] = n > 1.0 ? sqrt(q / (n - 1.0) / n) : 0.0;
 }
+
+namespace {
 
 template <int MODE, bool FP32, bool PROP, bool TRACE>
 hipError_t launch_t(const WalkArgs &a, int block, hipStream_t s) {
@@ -333,7 +451,8 @@ hipError_t launch_finalize(const WalkArgs &a, hipStream_t s) {
     if (a.chunks <= 1 || a.k == 0) return hipSuccess;
     const int block = 256;
     const int64_t grid = (a.k + block - 1) / block;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)grid), dim3(block), 0, s, a);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)grid), dim3(block), 0, s, a.k, a.chunks, a.part,
+                       a.est, a.se);
     return hipGetLastError();
 }
 
