@@ -34,6 +34,7 @@ struct mc_expmv_s {
     // last run
     bool ran = false;
     uint64_t last_walkers = 0;
+    int last_grid = 0;
     bool last_fp32 = false, last_prop = false;
 };
 
@@ -181,7 +182,6 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
         }
         a.part = h->part;
     }
-    HIP_TRY(hipMemsetAsync(h->counters, 0, 2 * sizeof(unsigned long long), h->stream));
     HIP_TRY(hipEventRecord(h->ev0, h->stream));
     HIP_TRY(launch_walk(a, h->opts.mode, fp32, prop, trace, (int)h->opts.walkers_per_block,
                         h->stream));
@@ -189,6 +189,7 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
     HIP_TRY(hipEventRecord(h->ev1, h->stream));
     h->ran = true;
     h->last_walkers = (uint64_t)k * (uint64_t)nwalk;
+    h->last_grid = a.ntasks > 0 ? launch_walk_grid(a.ntasks, (int)h->opts.walkers_per_block) : 0;
     h->last_fp32 = fp32;
     h->last_prop = prop;
     return MC_OK;
@@ -295,7 +296,7 @@ mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t
     CREATE_TRY(hipEventCreate(&h->ev0));
     CREATE_TRY(hipEventCreate(&h->ev1));
     CREATE_TRY(dalloc(&h->flags, 1));
-    CREATE_TRY(dalloc(&h->counters, 2));
+    CREATE_TRY(dalloc(&h->counters, 2 * (int64_t)kMaxWalkGrid));
     CREATE_TRY(hipMemsetAsync(h->flags, 0, sizeof(uint32_t), h->stream));
     CREATE_TRY(dalloc(&h->rowptr, n + 1));
     CREATE_TRY(dalloc(&h->col, nnz));
@@ -424,7 +425,15 @@ mc_status mc_expmv_stats(mc_expmv_t h, mc_expmv_run_stats *out) {
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
     unsigned long long c[2] = {0, 0};
-    HIP_TRY(hipMemcpy(c, h->counters, sizeof(c), hipMemcpyDeviceToHost));
+    if (h->last_grid > 0) {
+        std::vector<unsigned long long> pc((size_t)h->last_grid * 2);
+        HIP_TRY(hipMemcpy(pc.data(), h->counters, sizeof(unsigned long long) * pc.size(),
+                          hipMemcpyDeviceToHost));
+        for (int b = 0; b < h->last_grid; ++b) {
+            c[0] += pc[2 * (size_t)b];
+            c[1] += pc[2 * (size_t)b + 1];
+        }
+    }
     out->walkers = h->last_walkers;
     out->events = c[0];
     out->jumps = c[1];

@@ -99,12 +99,16 @@ struct WalkArgs {
     double *est;               // [k]   (chunks == 1) final results
     double *se;                // [k] or null
     double *part;              // [k * chunks * 3] (count, mean, M2) per chunk
-    unsigned long long *counters;  // [2]: events, jumps
+    unsigned long long *counters;  // [2 * grid]: events, jumps of every block
     uint32_t *flags;
     TraceOut trace;
 };
 
+// Largest walk grid (blocks); the per-block counter buffer has this many pairs.
+constexpr int kMaxWalkGrid = 1 << 16;
+
 // host-side launchers (walk.hip)
+int launch_walk_grid(int64_t ntasks, int block);
 hipError_t launch_walk(const WalkArgs &a, int mode, bool fp32, bool prop, bool trace,
                        int block, hipStream_t s);
 hipError_t launch_finalize(const WalkArgs &a, hipStream_t s);

@@ -337,12 +337,16 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
 
 namespace {
 
-// Entries (or, with idx == null, every node) of one instance.
+// Entries (or, with idx == null, every node) of one instance.  Event and
+// jump totals are reduced per block and written to counters[2*block] without
+// atomics (same-address atomics from every wave serialise across the chip).
 template <int MODE, bool FP32, bool PROP, bool TRACE>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
+    __shared__ unsigned long long sh_count[256 / WAVE][2];
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    unsigned long long my_events = 0, my_jumps = 0;
     for (int64_t task = wave_id; task < a.ntasks; task += nwaves) {
         const int64_t e = task / a.chunks;
         const int64_t c = task - e * a.chunks;
@@ -379,11 +383,24 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
                 part[1] = r.mean;
                 part[2] = r.m2;
             }
-            if (a.counters) {
-                atomicAdd(&a.counters[0], r.events);
-                atomicAdd(&a.counters[1], r.jumps);
-            }
         }
+        my_events += r.events;
+        my_jumps += r.jumps;
+    }
+    const int wave = threadIdx.x / WAVE;
+    if (lane == 0) {
+        sh_count[wave][0] = my_events;
+        sh_count[wave][1] = my_jumps;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long e = 0, j = 0;
+        for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) {
+            e += sh_count[w][0];
+            j += sh_count[w][1];
+        }
+        a.counters[2 * blockIdx.x] = e;
+        a.counters[2 * blockIdx.x + 1] = j;
     }
 }
 
@@ -403,15 +420,18 @@ __global__ void k_finalize(int64_t k, int64_t chunks, const double *__restrict__
 
 namespace {
 
+int walk_grid(int64_t ntasks, int block) {
+    const int64_t waves_per_block = block / WAVE;
+    int64_t grid = (ntasks + waves_per_block - 1) / waves_per_block;
+    if (grid > kMaxWalkGrid) grid = kMaxWalkGrid;
+    if (grid < 1) grid = 1;
+    return (int)grid;
+}
+
 template <int MODE, bool FP32, bool PROP, bool TRACE>
 hipError_t launch_t(const WalkArgs &a, int block, hipStream_t s) {
-    const int64_t waves_per_block = block / WAVE;
-    int64_t grid = (a.ntasks + waves_per_block - 1) / waves_per_block;
-    const int64_t max_grid = 1 << 16;
-    if (grid > max_grid) grid = max_grid;
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE>), dim3((unsigned)grid), dim3(block), 0, s,
-                       a);
+    hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE>), dim3((unsigned)walk_grid(a.ntasks, block)),
+                       dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
@@ -431,6 +451,8 @@ hipError_t launch_m(const WalkArgs &a, bool fp32, bool prop, bool trace, int blo
 }
 
 }  // namespace
+
+int launch_walk_grid(int64_t ntasks, int block) { return walk_grid(ntasks, block); }
 
 hipError_t launch_walk(const WalkArgs &a, int mode, bool fp32, bool prop, bool trace, int block,
                        hipStream_t s) {
