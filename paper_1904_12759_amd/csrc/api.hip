@@ -40,7 +40,7 @@ struct mc_expmv_s {
 
 namespace {
 
-constexpr uint32_t kChunk = 1024;   // walkers per task (fixes the summation order)
+constexpr uint32_t kChunk = kChunkMax;   // walkers per task (fixes the summation order)
 
 mc_status from_hip(hipError_t e) {
     if (e == hipSuccess) return MC_OK;

@@ -104,6 +104,9 @@ struct WalkArgs {
     TraceOut trace;
 };
 
+// Walkers per task: fixes the summation order of an entry's estimate.
+constexpr uint32_t kChunkMax = 1024;
+
 // Largest walk grid (blocks); the per-block counter buffer has this many pairs.
 constexpr int kMaxWalkGrid = 1 << 16;
 

@@ -174,9 +174,20 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
 // Runs walkers ord0 .. ord0+cnt-1 from `node` on the calling wavefront and
 // leaves, in every lane, the wave's (count, mean, M2) of W * v[X_t] plus the
 // event and jump totals.  All lanes of the wave must call it together.
+// `list` is this wave's LDS scratch of at least cnt words.
+//
+// Two phases.  When a walker's first holding time outlasts t with fair
+// probability (e^{-r t} >= 1/8), phase 1 draws only the first event of every
+// walker: those that stay return exactly K (the no-jump value), so they are
+// counted as one group (n0, K, 0); the ordinals of the others are compacted
+// into `list`.  Phase 2 runs the complete walk, with lane refill, on the
+// listed walkers only (their first event is drawn again from the same
+// counter), so the rarely needed logarithm, jump and exp code runs on lanes
+// that need it instead of masked lanes of a mostly idle wave.
 template <int MODE, bool FP32, bool PROP, bool TRACE>
 __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node, uint32_t ord0,
-                                               uint32_t cnt, const TraceOut &tr) {
+                                               uint32_t cnt, const TraceOut &tr,
+                                               uint32_t *list) {
     using WT = typename WeightT<FP32>::T;
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned long long lanemask_lt = (1ull << lane) - 1ull;
@@ -192,8 +203,62 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
     // -log(U)/r0 > t + 2^-40/r0, far beyond the rounding of the log-based test.
     const double e0 = r0.deg ? exp(-t / r0.inv_r) * (1.0 - 0x1p-40) : 0.0;
 
+    uint32_t n0 = 0;              // walkers that never jump (value K), wave-uniform
+    unsigned long long evs = 0, jus = 0;
+    uint32_t todo = cnt;          // walkers for phase 2
+    bool use_list = false;
+    if (r0.deg == 0) {
+        // no exit rate at the start: every walker holds until t
+        n0 = cnt;
+        todo = 0;
+        if (lane == 0) evs = cnt;
+        if constexpr (TRACE) {
+            for (uint32_t w = lane; w < cnt; w += WAVE) {
+                tr.x[tr.base + w] = (int32_t)node;
+                tr.ev[tr.base + w] = 1;
+                tr.ju[tr.base + w] = 0;
+                tr.f[tr.base + w] = K;
+            }
+        }
+    } else if (e0 >= 0.125) {
+        use_list = true;
+        uint32_t nlist = 0;
+        for (uint32_t b = 0; b < cnt; b += WAVE) {
+            const uint32_t w = b + (uint32_t)lane;
+            const bool valid = w < cnt;
+            bool go = false;
+            if (valid) {
+                const U4 o = philox(0u, ord0 + w, node, P.inst, P.key0, P.key1);
+                const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
+                const double U = (double)(m + 1ull) * 0x1p-53;
+                go = U >= e0;
+            }
+            const unsigned long long gmask = __ballot(go);
+            const unsigned long long smask = __ballot(valid && !go);
+            if (go) list[nlist + (uint32_t)__popcll(gmask & lanemask_lt)] = w;
+            nlist += (uint32_t)__popcll(gmask);
+            n0 += (uint32_t)__popcll(smask);
+            if constexpr (TRACE) {
+                if (valid && !go) {
+                    tr.x[tr.base + w] = (int32_t)node;
+                    tr.ev[tr.base + w] = 1;
+                    tr.ju[tr.base + w] = 0;
+                    tr.f[tr.base + w] = K;
+                }
+            }
+        }
+        if (lane == 0) evs = n0;
+        todo = nlist;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // ---- phase 2: full walks with lane refill over `todo` walkers
     uint32_t wl = (uint32_t)lane;
-    bool active = wl < cnt;
+    bool active = wl < todo;
+    uint32_t ow = 0;              // walker ordinal within the task
+    if (active) ow = use_list ? list[wl] : wl;
     uint32_t x = node;
     double s = 0.0;
     WT logw = (WT)0;
@@ -205,7 +270,6 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
 
     uint32_t nl = 0;
     double kl = 0.0, s1 = 0.0, s2 = 0.0;
-    unsigned long long evs = 0, jus = 0;
     uint32_t next = WAVE;
     uint32_t err = 0;
 
@@ -219,7 +283,7 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
                 err |= F_WALK_LIMIT;
                 fin = true;
             } else {
-                const U4 o = philox(ev, ord0 + wl, node, P.inst, P.key0, P.key1);
+                const U4 o = philox(ev, ord0 + ow, node, P.inst, P.key0, P.key1);
                 ++ev;
                 const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
                 const double U = (double)(m + 1ull) * 0x1p-53;
@@ -273,7 +337,7 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
                 evs += ev;
                 jus += ju;
                 if constexpr (TRACE) {
-                    const int64_t ti = tr.base + wl;
+                    const int64_t ti = tr.base + ow;
                     tr.x[ti] = (int32_t)x;
                     tr.ev[ti] = ev;
                     tr.ju[ti] = ju;
@@ -284,7 +348,8 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
         const unsigned long long fmask = __ballot(fin);
         if (fin) {
             wl = next + (uint32_t)__popcll(fmask & lanemask_lt);
-            if (wl < cnt) {
+            if (wl < todo) {
+                ow = use_list ? list[wl] : wl;
                 x = node;
                 s = 0.0;
                 logw = (WT)0;
@@ -314,7 +379,7 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
         const double nb = __shfl_xor(n, off, WAVE);
         const double mb = __shfl_xor(mean, off, WAVE);
         const double qb = __shfl_xor(q, off, WAVE);
-        // the lower lane of each pair keeps its own part first
+        // both lanes of a pair merge (lower, upper) in that order
         if (lane & off) {
             double n2 = nb, m2 = mb, q2 = qb;
             chan_merge(n2, m2, q2, n, mean, q);
@@ -325,10 +390,13 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
             chan_merge(n, mean, q, nb, mb, qb);
         }
     }
+    // the walkers that never jumped: n0 copies of K
+    double nn = (double)n0, mm = K, qq = 0.0;
+    chan_merge(nn, mm, qq, n, mean, q);
     TaskResult res;
-    res.n = n;
-    res.mean = mean;
-    res.m2 = q;
+    res.n = nn;
+    res.mean = mm;
+    res.m2 = qq;
     res.events = wave_sum_u64(evs);
     res.jumps = wave_sum_u64(jus);
     res.err = err;
@@ -343,6 +411,7 @@ namespace {
 template <int MODE, bool FP32, bool PROP, bool TRACE>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     __shared__ unsigned long long sh_count[256 / WAVE][2];
+    __shared__ uint32_t sh_list[256 / WAVE][kChunkMax];
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
@@ -372,7 +441,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
         TraceOut tr = a.trace;
         tr.base = wbase;
         const TaskResult r = run_task<MODE, FP32, PROP, TRACE>(
-            a.P, (uint32_t)node, (uint32_t)(a.w0 + wbase), cnt, tr);
+            a.P, (uint32_t)node, (uint32_t)(a.w0 + wbase), cnt, tr, sh_list[threadIdx.x / WAVE]);
         if (r.err && lane == 0) atomicOr(a.flags, r.err);
         if (lane == 0) {
             if (a.chunks == 1) {
