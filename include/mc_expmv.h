@@ -186,6 +186,82 @@ mc_status mc_expmv_info(mc_expmv_t h, int64_t *n, int64_t *nslots, int64_t *ngri
 /* Release everything the handle owns (synchronises its stream first). */
 void mc_expmv_destroy(mc_expmv_t h);
 
+/* ------------------------------------------------------------------ batches
+ * Many instances -- each its own matrix, horizon, weight mode, precision,
+ * vector and request (entries or the full vector) -- in one persistent launch
+ * replayed from a captured HIP graph.  Each instance's results equal those of
+ * a separate handle with the same settings and instance id (Algorithm 1 per
+ * instance); the schedule (block size, grid, task grabbing) never changes a
+ * result.  The paper runs one matrix at a time (Sec. 6); batching is this
+ * library's addition for many small problems.
+ */
+typedef struct mc_batch_s *mc_batch_t;
+
+typedef struct {
+    int64_t n, nnz;
+    const int64_t *rowptr;      /* device, as in mc_expmv_create */
+    const int32_t *col;         /* device */
+    const double *val;          /* device */
+    double t;                   /* horizon */
+    int32_t mode;               /* MC_EXACT, MC_STRANG or MC_LIE */
+    double dt;                  /* splitting step for STRANG / LIE */
+    int32_t weight_prec;        /* MC_FP64 or MC_FP32 (then v is float) */
+    uint32_t instance_id;       /* fourth Philox counter word */
+    const void *v;              /* device vector of n values */
+    const int64_t *idx;         /* device int64[k] entries, or NULL for the full vector */
+    int64_t k;                  /* number of entries (ignored when idx is NULL) */
+    int64_t n_walkers;          /* walkers per entry (per node for the full vector) */
+    double *est;                /* device double[k] (or [n]) */
+    double *stderr_;            /* device double[k] (or [n]), or NULL */
+} mc_instance_desc;
+
+typedef struct {
+    uint32_t struct_size;       /* sizeof(mc_batch_opts) */
+    uint32_t walkers_per_block; /* 64, 128 or 256; 0 = autotune */
+    uint32_t blocks_per_cu;     /* persistent grid = CUs * this (1..64); 0 = autotune */
+    uint32_t group;             /* tasks taken per grab from a global counter; 0 = static
+                                   stride over the task list */
+    int32_t use_graph;          /* 1 (default): capture the launch in a HIP graph */
+    uint32_t max_events;        /* walk-length cap per walker; 0 = 2^24 */
+    void *stream;               /* caller's hipStream_t, NULL = null stream: runs are
+                                   ordered after prior work on it and before later work */
+} mc_batch_opts;
+
+typedef struct {
+    uint32_t walkers_per_block, blocks_per_cu, group;
+    int64_t tasks;              /* (entry, chunk-of-1024-walkers) tasks per run */
+} mc_batch_schedule;
+
+/* Fill *opts with the defaults above. */
+void mc_batch_default_opts(mc_batch_opts *opts);
+
+/*
+ * Build every instance's tables (as mc_expmv_create), choose the schedule
+ * (given in opts, read from the file named by MC_EXPMV_TUNE_CACHE, or timed
+ * over a fixed candidate list and then appended to that file) and capture the
+ * run in a graph.  All instance buffers (v, idx, est, stderr_) must stay valid
+ * until mc_expmv_batch_destroy; A may be freed when this returns.
+ * Errors: those of mc_expmv_create for any instance, MC_ERR_INVALID_ARG for
+ * n_inst outside 1..1024 or bad options.  Synchronous.
+ */
+mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instance_desc *inst,
+                                uint64_t seed, const mc_batch_opts *opts);
+
+/* Replay the batch (asynchronous, ordered on the caller's stream). */
+mc_status mc_expmv_batch_run(mc_batch_t b);
+
+/* Wait for the batch; return (and clear) latched device errors. */
+mc_status mc_expmv_batch_sync(mc_batch_t b);
+
+/* Counters and device time of the last run, and the schedule in use (either may be NULL). */
+mc_status mc_expmv_batch_stats(mc_batch_t b, mc_expmv_run_stats *out, mc_batch_schedule *sched);
+
+/* Force a schedule (re-captures the graph).  Results are unchanged by it. */
+mc_status mc_expmv_batch_set_schedule(mc_batch_t b, const mc_batch_schedule *sched);
+
+/* Release the batch and every instance's tables. */
+void mc_expmv_batch_destroy(mc_batch_t b);
+
 #ifdef __cplusplus
 }
 #endif

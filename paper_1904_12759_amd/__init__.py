@@ -11,7 +11,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["MCExpmv", "MCError", "EXACT", "STRANG", "LIE", "FP64", "FP32", "lib", "load"]
+__all__ = ["MCExpmv", "MCBatch", "MCError", "EXACT", "STRANG", "LIE", "FP64", "FP32", "lib",
+           "load"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcexpmv.so")
@@ -62,6 +63,33 @@ class mc_expmv_run_stats(ctypes.Structure):
     ]
 
 
+class mc_instance_desc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+        ("t", ctypes.c_double), ("mode", ctypes.c_int32), ("dt", ctypes.c_double),
+        ("weight_prec", ctypes.c_int32), ("instance_id", ctypes.c_uint32),
+        ("v", ctypes.c_void_p), ("idx", ctypes.c_void_p), ("k", ctypes.c_int64),
+        ("n_walkers", ctypes.c_int64), ("est", ctypes.c_void_p), ("stderr_", ctypes.c_void_p),
+    ]
+
+
+class mc_batch_opts(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("walkers_per_block", ctypes.c_uint32),
+        ("blocks_per_cu", ctypes.c_uint32), ("group", ctypes.c_uint32),
+        ("use_graph", ctypes.c_int32), ("max_events", ctypes.c_uint32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class mc_batch_schedule(ctypes.Structure):
+    _fields_ = [
+        ("walkers_per_block", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+        ("group", ctypes.c_uint32), ("tasks", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 # exported C symbols and their signatures (also checked by the CPU tests)
@@ -87,6 +115,14 @@ _SIGS = {
     "mc_expmv_info": (ctypes.c_int, [ctypes.c_void_p] * 5),
     "mc_expmv_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_destroy": (None, [ctypes.c_void_p]),
+    "mc_batch_default_opts": (None, [ctypes.c_void_p]),
+    "mc_expmv_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.c_uint64, ctypes.c_void_p]),
+    "mc_expmv_batch_run": (ctypes.c_int, [ctypes.c_void_p]),
+    "mc_expmv_batch_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "mc_expmv_batch_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_expmv_batch_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_expmv_batch_destroy": (None, [ctypes.c_void_p]),
 }
 
 
@@ -280,3 +316,106 @@ class MCExpmv:
         for k in ("col", "thr", "alias"):
             out[k] = out[k][:ns]
         return out
+
+
+class MCBatch:
+    """Many instances in one persistent, graph-captured launch (``mc_expmv_batch_*``).
+
+    ``instances`` is a list of dicts with keys: rowptr, col, val (CSR, host or
+    device), t, v, and optionally idx (entries; None for the full vector),
+    n_walkers, mode, dt, fp32, instance_id.  Device copies of every buffer are
+    owned by this object; results land in ``est[i]`` / ``stderr[i]``."""
+
+    def __init__(self, instances, seed: int, walkers_per_block: int = 0,
+                 blocks_per_cu: int = 0, group: int = 0, use_graph: bool = True,
+                 max_events: int = 0, stream=None):
+        import torch
+        lib_ = load()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self._keep = []
+        self.est, self.stderr = [], []
+        descs = (mc_instance_desc * len(instances))()
+        for i, inst in enumerate(instances):
+            rp = torch.as_tensor(inst["rowptr"], dtype=torch.int64).to(dev).contiguous()
+            cl = torch.as_tensor(inst["col"], dtype=torch.int32).to(dev).contiguous()
+            vl = torch.as_tensor(inst["val"], dtype=torch.float64).to(dev).contiguous()
+            fp32 = bool(inst.get("fp32", False))
+            v = torch.as_tensor(inst["v"]).to(device=dev, dtype=torch.float32 if fp32 else
+                                               torch.float64).contiguous()
+            n = rp.numel() - 1
+            idx = inst.get("idx")
+            if idx is not None:
+                idx = torch.as_tensor(idx).to(device=dev, dtype=torch.int64).contiguous()
+                k = idx.numel()
+            else:
+                k = n
+            est = torch.empty(k, dtype=torch.float64, device=dev)
+            se = torch.empty(k, dtype=torch.float64, device=dev)
+            self._keep += [rp, cl, vl, v, idx]
+            self.est.append(est)
+            self.stderr.append(se)
+            d = descs[i]
+            d.n, d.nnz = n, cl.numel()
+            d.rowptr, d.col, d.val = rp.data_ptr(), cl.data_ptr(), vl.data_ptr()
+            d.t = float(inst["t"])
+            d.mode = int(inst.get("mode", EXACT))
+            d.dt = float(inst.get("dt", 0.03125))
+            d.weight_prec = FP32 if fp32 else FP64
+            d.instance_id = int(inst.get("instance_id", i))
+            d.v = v.data_ptr()
+            d.idx = idx.data_ptr() if idx is not None else None
+            d.k = k if idx is not None else 0
+            d.n_walkers = int(inst["n_walkers"])
+            d.est, d.stderr_ = est.data_ptr(), se.data_ptr()
+        o = mc_batch_opts()
+        lib_.mc_batch_default_opts(ctypes.byref(o))
+        o.walkers_per_block, o.blocks_per_cu, o.group = walkers_per_block, blocks_per_cu, group
+        o.use_graph = 1 if use_graph else 0
+        o.max_events = max_events
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        o.stream = stream
+        torch.cuda.current_stream().synchronize()
+        h = ctypes.c_void_p()
+        _check(lib_.mc_expmv_batch_create(ctypes.byref(h), len(instances), descs,
+                                          int(seed) & (2**64 - 1), ctypes.byref(o)),
+               "mc_expmv_batch_create")
+        self._h = h
+
+    def run(self, sync: bool = True):
+        _check(load().mc_expmv_batch_run(self._h), "mc_expmv_batch_run")
+        if sync:
+            self.sync()
+        return self.est, self.stderr
+
+    def sync(self):
+        _check(load().mc_expmv_batch_sync(self._h), "mc_expmv_batch_sync")
+
+    def schedule(self) -> dict:
+        sc = mc_batch_schedule()
+        _check(load().mc_expmv_batch_stats(self._h, None, ctypes.byref(sc)), "mc_expmv_batch_stats")
+        return dict(walkers_per_block=sc.walkers_per_block, blocks_per_cu=sc.blocks_per_cu,
+                    group=sc.group, tasks=sc.tasks)
+
+    def set_schedule(self, walkers_per_block: int, blocks_per_cu: int, group: int):
+        sc = mc_batch_schedule(walkers_per_block, blocks_per_cu, group, 0)
+        _check(load().mc_expmv_batch_set_schedule(self._h, ctypes.byref(sc)),
+               "mc_expmv_batch_set_schedule")
+
+    def stats(self) -> dict:
+        s = mc_expmv_run_stats()
+        _check(load().mc_expmv_batch_stats(self._h, ctypes.byref(s), None), "mc_expmv_batch_stats")
+        return dict(walkers=s.walkers, events=s.events, jumps=s.jumps, ms=s.ms,
+                    alg_bytes=s.alg_bytes)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mc_expmv_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -126,6 +126,24 @@ mc_status check_opts(const mc_expmv_opts &o) {
     return MC_OK;
 }
 
+void fill_inst(const mc_expmv_s *h, const void *v, bool prop, InstArgs &P) {
+    const Tables &tb = prop ? h->prop : h->plain;
+    P.rows = tb.rows;
+    P.d64 = tb.d64;
+    P.d32 = tb.d32;
+    P.slots = tb.slots;
+    P.corr = prop ? tb.corr : nullptr;
+    P.v = v;
+    P.t = h->t;
+    P.dt = h->dt;
+    P.inv_dt = h->inv_dt;
+    P.ngrid = (int32_t)h->ngrid;
+    P.key0 = (uint32_t)h->seed;
+    P.key1 = (uint32_t)(h->seed >> 32);
+    P.inst = h->opts.instance_id;
+    P.max_events = h->opts.max_events ? h->opts.max_events : (1u << 24);
+}
+
 // Run the walk kernel for k entries (idx == null: every node).
 mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, int64_t nwalk,
                    double *est, double *se, bool trace, int64_t w0, int32_t use_prop,
@@ -137,21 +155,7 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
     const bool fp32 = h->opts.weight_prec == MC_FP32;
     const int64_t chunks = (nwalk + kChunk - 1) / kChunk;
     WalkArgs a{};
-    const Tables &tb = prop ? h->prop : h->plain;
-    a.P.rows = tb.rows;
-    a.P.d64 = tb.d64;
-    a.P.d32 = tb.d32;
-    a.P.slots = tb.slots;
-    a.P.corr = prop ? tb.corr : nullptr;
-    a.P.v = v;
-    a.P.t = h->t;
-    a.P.dt = h->dt;
-    a.P.inv_dt = h->inv_dt;
-    a.P.ngrid = (int32_t)h->ngrid;
-    a.P.key0 = (uint32_t)h->seed;
-    a.P.key1 = (uint32_t)(h->seed >> 32);
-    a.P.inst = h->opts.instance_id;
-    a.P.max_events = h->opts.max_events ? h->opts.max_events : (1u << 24);
+    fill_inst(h, v, prop, a.P);
     a.idx = idx;
     a.k = k;
     a.n = h->n;
@@ -492,6 +496,410 @@ mc_status mc_expmv_info(mc_expmv_t h, int64_t *n, int64_t *nslots, int64_t *ngri
     if (nslots) *nslots = h->nslots;
     if (ngrid) *ngrid = h->ngrid;
     if (dt) *dt = h->dt;
+    return MC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <string>
+
+struct mc_batch_s {
+    int dev = 0;
+    int ncu = 0;
+    std::string devname;
+    hipStream_t user = nullptr;      // caller's stream
+    hipStream_t stream = nullptr;    // private stream (graph capture needs a non-null one)
+    uint64_t seed = 0;
+    std::vector<mc_expmv_t> handles; // table owners, one per instance
+    std::vector<BatchInst> inst;
+    std::vector<int64_t> fin_begin;
+    BatchInst *d_inst = nullptr;
+    int64_t *d_fin = nullptr;
+    double *part = nullptr;
+    unsigned long long *counters = nullptr;
+    unsigned long long *queue = nullptr;
+    uint32_t *flags = nullptr;
+    BatchArgs args{};
+    int block = 256, grid = 0;
+    uint32_t group = 0;
+    bool use_graph = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_user = nullptr, ev_done = nullptr;
+    uint64_t walkers = 0;
+    bool ran = false;
+};
+
+namespace {
+
+void batch_free(mc_batch_s *b) {
+    if (!b) return;
+    (void)hipSetDevice(b->dev);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (mc_expmv_t h : b->handles) mc_expmv_destroy(h);
+    (void)hipFree(b->d_inst);
+    (void)hipFree(b->d_fin);
+    (void)hipFree(b->part);
+    (void)hipFree(b->counters);
+    (void)hipFree(b->queue);
+    (void)hipFree(b->flags);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->ev_user) (void)hipEventDestroy(b->ev_user);
+    if (b->ev_done) (void)hipEventDestroy(b->ev_done);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+hipError_t batch_launch(mc_batch_s *b) {
+    b->args.group = b->group;
+    return launch_batch(b->args, b->block, b->grid, b->stream);
+}
+
+// (Re)build the graph for the current block / grid / group.
+hipError_t batch_capture(mc_batch_s *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    if (!b->use_graph) return hipSuccess;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = batch_launch(b);
+    e = hipStreamEndCapture(b->stream, &b->graph);
+    if (le != hipSuccess) return le;
+    if (e != hipSuccess) return e;
+    return hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+}
+
+// Candidate schedules for the autotuner; none of them changes any result.
+struct Sched {
+    int block, per_cu;
+    uint32_t group;
+};
+
+std::string tune_key(const mc_batch_s *b) {
+    char buf[256];
+    uint64_t tasks = (uint64_t)b->args.ntasks;
+    snprintf(buf, sizeof(buf), "%s|cu%d|inst%zu|tasks%llu|walkers%llu", b->devname.c_str(),
+             b->ncu, b->inst.size(), (unsigned long long)tasks,
+             (unsigned long long)b->walkers);
+    std::string k(buf);
+    for (char &c : k)
+        if (c == ' ') c = '_';
+    return k;
+}
+
+bool tune_cache_lookup(const mc_batch_s *b, Sched &out) {
+    const char *path = getenv("MC_EXPMV_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    const std::string key = tune_key(b);
+    char k[512];
+    int blk, pcu;
+    unsigned grp;
+    bool found = false;
+    while (fscanf(f, "%511s %d %d %u", k, &blk, &pcu, &grp) == 4) {
+        if (key == k && (blk == 64 || blk == 128 || blk == 256) && pcu > 0 && pcu <= 64) {
+            out = Sched{blk, pcu, grp};
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void tune_cache_store(const mc_batch_s *b, const Sched &s) {
+    const char *path = getenv("MC_EXPMV_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %u\n", tune_key(b).c_str(), s.block, s.per_cu, s.group);
+    fclose(f);
+}
+
+// Time each candidate schedule (one warm-up and two timed launches) and keep
+// the fastest.
+mc_status autotune(mc_batch_s *b, float *best_ms_out) {
+    static const Sched cands[] = {
+        {256, 4, 0},  {256, 8, 0},  {256, 16, 0}, {128, 8, 0},  {128, 16, 0},
+        {256, 8, 16}, {256, 8, 128}, {128, 16, 16}, {256, 16, 64},
+    };
+    float best = 1e30f;
+    Sched bs = cands[0];
+    for (const Sched &c : cands) {
+        b->block = c.block;
+        b->grid = b->ncu * c.per_cu;
+        b->group = c.group;
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIP_TRY(hipEventRecord(b->ev0, b->stream));
+            HIP_TRY(batch_launch(b));
+            HIP_TRY(hipEventRecord(b->ev1, b->stream));
+            HIP_TRY(hipEventSynchronize(b->ev1));
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+            if (rep > 0 && ms < tmin) tmin = ms;
+        }
+        if (tmin < best) {
+            best = tmin;
+            bs = c;
+        }
+    }
+    b->block = bs.block;
+    b->grid = b->ncu * bs.per_cu;
+    b->group = bs.group;
+    if (best_ms_out) *best_ms_out = best;
+    tune_cache_store(b, bs);
+    return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mc_batch_default_opts(mc_batch_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(mc_batch_opts);
+    o->walkers_per_block = 0;
+    o->blocks_per_cu = 0;
+    o->group = 0;
+    o->use_graph = 1;
+    o->max_events = 0;
+    o->stream = nullptr;
+}
+
+void mc_expmv_batch_destroy(mc_batch_t b) { batch_free(b); }
+
+mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instance_desc *desc,
+                                uint64_t seed, const mc_batch_opts *opts) {
+    if (!out) return MC_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n_inst < 1 || n_inst > kMaxBatch || !desc) return MC_ERR_INVALID_ARG;
+    mc_batch_opts o;
+    mc_batch_default_opts(&o);
+    if (opts) {
+        if (opts->struct_size != sizeof(mc_batch_opts)) return MC_ERR_INVALID_ARG;
+        o = *opts;
+    }
+    const uint32_t wpb = o.walkers_per_block;
+    if (wpb != 0 && wpb != 64 && wpb != 128 && wpb != 256) return MC_ERR_INVALID_ARG;
+    if (o.blocks_per_cu > 64) return MC_ERR_INVALID_ARG;
+    for (int i = 0; i < n_inst; ++i) {
+        const mc_instance_desc &d = desc[i];
+        if (!d.v || d.n_walkers < 1 || d.n_walkers > 0xFFFFFFFFll) return MC_ERR_INVALID_ARG;
+        if (d.idx && (d.k < 0 || (d.k > 0 && !d.est))) return MC_ERR_INVALID_ARG;
+        if (!d.idx && d.n > 0 && !d.est) return MC_ERR_INVALID_ARG;
+    }
+    mc_batch_s *b = new (std::nothrow) mc_batch_s();
+    if (!b) return MC_ERR_NO_MEMORY;
+    b->seed = seed;
+    b->user = (hipStream_t)o.stream;
+    b->use_graph = o.use_graph != 0;
+#define B_TRY(expr)                              \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) {                  \
+            mc_status s_ = from_hip(e_);         \
+            batch_free(b);                       \
+            return s_;                           \
+        }                                        \
+    } while (0)
+    B_TRY(hipGetDevice(&b->dev));
+    hipDeviceProp_t prop;
+    B_TRY(hipGetDeviceProperties(&prop, b->dev));
+    b->ncu = prop.multiProcessorCount;
+    b->devname = prop.gcnArchName;
+    B_TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    B_TRY(hipEventCreate(&b->ev0));
+    B_TRY(hipEventCreate(&b->ev1));
+    B_TRY(hipEventCreateWithFlags(&b->ev_user, hipEventDisableTiming));
+    B_TRY(hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
+    // the caller's stream may still be producing A, v or idx
+    B_TRY(hipEventRecord(b->ev_user, b->user));
+    B_TRY(hipStreamWaitEvent(b->stream, b->ev_user, 0));
+
+    int64_t ntasks = 0, part_doubles = 0, nfin = 0;
+    b->fin_begin.assign((size_t)n_inst + 1, 0);
+    for (int i = 0; i < n_inst; ++i) {
+        const mc_instance_desc &d = desc[i];
+        mc_expmv_opts io;
+        mc_expmv_default_opts(&io);
+        io.mode = d.mode;
+        io.dt = d.dt;
+        io.weight_prec = d.weight_prec;
+        io.instance_id = d.instance_id;
+        io.max_events = o.max_events;
+        io.stream = b->stream;
+        mc_expmv_t h = nullptr;
+        mc_status st = mc_expmv_create(&h, d.n, d.nnz, d.rowptr, d.col, d.val, d.t, seed, &io);
+        if (st != MC_OK) {
+            batch_free(b);
+            return st;
+        }
+        b->handles.push_back(h);
+        BatchInst I{};
+        fill_inst(h, d.v, false, I.P);
+        I.idx = d.idx;
+        I.k = d.idx ? d.k : d.n;
+        I.n = d.n;
+        I.nwalk = d.n_walkers;
+        I.chunks = (d.n_walkers + kChunk - 1) / kChunk;
+        I.task_begin = ntasks;
+        I.part_off = part_doubles;
+        I.est = d.est;
+        I.se = d.stderr_;
+        I.mode = d.mode;
+        I.fp32 = d.weight_prec == MC_FP32;
+        ntasks += I.k * I.chunks;
+        b->fin_begin[i] = nfin;
+        if (I.chunks > 1) {
+            part_doubles += I.k * I.chunks * 3;
+            nfin += I.k;
+        }
+        b->walkers += (uint64_t)I.k * (uint64_t)I.nwalk;
+        b->inst.push_back(I);
+    }
+    b->fin_begin[n_inst] = nfin;
+    B_TRY(dalloc(&b->d_inst, n_inst));
+    B_TRY(dalloc(&b->d_fin, n_inst + 1));
+    B_TRY(dalloc(&b->part, part_doubles));
+    B_TRY(dalloc(&b->counters, 2 * (int64_t)b->ncu * 64));
+    B_TRY(dalloc(&b->queue, 1));
+    B_TRY(dalloc(&b->flags, 1));
+    B_TRY(hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BatchInst) * (size_t)n_inst,
+                         hipMemcpyHostToDevice, b->stream));
+    B_TRY(hipMemcpyAsync(b->d_fin, b->fin_begin.data(), sizeof(int64_t) * (size_t)(n_inst + 1),
+                         hipMemcpyHostToDevice, b->stream));
+    B_TRY(hipMemsetAsync(b->flags, 0, sizeof(uint32_t), b->stream));
+    B_TRY(hipStreamSynchronize(b->stream));
+    BatchArgs &a = b->args;
+    a.inst = b->d_inst;
+    a.ninst = n_inst;
+    a.ntasks = ntasks;
+    a.part = b->part;
+    a.counters = b->counters;
+    a.flags = b->flags;
+    a.queue = b->queue;
+    a.fin_begin = b->d_fin;
+    a.nfin = nfin;
+
+    // schedule: given, cached, or tuned
+    Sched sc{256, 8, 0};
+    if (wpb != 0 && o.blocks_per_cu != 0) {
+        sc = Sched{(int)wpb, (int)o.blocks_per_cu, o.group};
+        b->block = sc.block;
+        b->grid = b->ncu * sc.per_cu;
+        b->group = sc.group;
+    } else if (tune_cache_lookup(b, sc)) {
+        b->block = sc.block;
+        b->grid = b->ncu * sc.per_cu;
+        b->group = sc.group;
+    } else {
+        mc_status st = autotune(b, nullptr);
+        if (st != MC_OK) {
+            batch_free(b);
+            return st;
+        }
+    }
+    B_TRY(hipStreamSynchronize(b->stream));
+    B_TRY(hipMemsetAsync(b->flags, 0, sizeof(uint32_t), b->stream));
+    B_TRY(batch_capture(b));
+    B_TRY(hipStreamSynchronize(b->stream));
+#undef B_TRY
+    *out = b;
+    return MC_OK;
+}
+
+mc_status mc_expmv_batch_run(mc_batch_t b) {
+    if (!b) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(b->dev));
+    HIP_TRY(hipEventRecord(b->ev_user, b->user));
+    HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_user, 0));
+    HIP_TRY(hipEventRecord(b->ev0, b->stream));
+    if (b->exec)
+        HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    else
+        HIP_TRY(batch_launch(b));
+    HIP_TRY(hipEventRecord(b->ev1, b->stream));
+    HIP_TRY(hipEventRecord(b->ev_done, b->stream));
+    HIP_TRY(hipStreamWaitEvent(b->user, b->ev_done, 0));
+    b->ran = true;
+    return MC_OK;
+}
+
+mc_status mc_expmv_batch_sync(mc_batch_t b) {
+    if (!b) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(b->dev));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    uint32_t f = 0;
+    HIP_TRY(hipMemcpy(&f, b->flags, sizeof(f), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(b->flags, 0, sizeof(uint32_t)));
+    return flags_to_status(f);
+}
+
+mc_status mc_expmv_batch_stats(mc_batch_t b, mc_expmv_run_stats *out, mc_batch_schedule *sched) {
+    if (!b) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(b->dev));
+    if (sched) {
+        sched->walkers_per_block = (uint32_t)b->block;
+        sched->blocks_per_cu = (uint32_t)(b->grid / (b->ncu > 0 ? b->ncu : 1));
+        sched->group = b->group;
+        sched->tasks = b->args.ntasks;
+    }
+    if (!out) return MC_OK;
+    memset(out, 0, sizeof(*out));
+    if (!b->ran) return MC_OK;
+    HIP_TRY(hipEventSynchronize(b->ev1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    std::vector<unsigned long long> pc((size_t)b->grid * 2);
+    HIP_TRY(hipMemcpy(pc.data(), b->counters, sizeof(unsigned long long) * pc.size(),
+                      hipMemcpyDeviceToHost));
+    unsigned long long ev = 0, ju = 0;
+    for (int i = 0; i < b->grid; ++i) {
+        ev += pc[2 * (size_t)i];
+        ju += pc[2 * (size_t)i + 1];
+    }
+    out->walkers = b->walkers;
+    out->events = ev;
+    out->jumps = ju;
+    out->ms = ms;
+    // algorithmic bytes as for a single instance, per instance precision
+    double bytes = 0.0;
+    double wsum64 = 0.0, wsum32 = 0.0;
+    for (const BatchInst &I : b->inst) {
+        const double w = (double)I.k * (double)I.nwalk;
+        if (I.fp32) wsum32 += w;
+        else wsum64 += w;
+    }
+    // events and jumps are not split by precision; attribute them in proportion
+    const double wt = wsum32 + wsum64 > 0 ? wsum32 / (wsum32 + wsum64) : 0.0;
+    const double row = 16.0 + 4.0 * wt + 8.0 * (1.0 - wt);
+    bytes = row * (double)ev + 12.0 * (double)ju + 4.0 * wsum32 + 8.0 * wsum64;
+    out->alg_bytes = bytes;
+    return MC_OK;
+}
+
+mc_status mc_expmv_batch_set_schedule(mc_batch_t b, const mc_batch_schedule *sched) {
+    if (!b || !sched) return MC_ERR_INVALID_ARG;
+    const uint32_t wpb = sched->walkers_per_block;
+    if (wpb != 64 && wpb != 128 && wpb != 256) return MC_ERR_INVALID_ARG;
+    if (sched->blocks_per_cu < 1 || sched->blocks_per_cu > 64) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(b->dev));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->block = (int)wpb;
+    b->grid = b->ncu * (int)sched->blocks_per_cu;
+    b->group = sched->group;
+    HIP_TRY(batch_capture(b));
     return MC_OK;
 }
 

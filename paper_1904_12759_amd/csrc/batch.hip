@@ -1,0 +1,175 @@
+// Batched walks: many instances (each its own matrix, horizon, weight mode,
+// precision, vector and request) in one persistent launch.
+//
+// The tasks of all instances form one index space (instance i owns tasks
+// task_begin[i] .. task_begin[i+1]-1, each an (entry, chunk) exactly as in the
+// single-instance kernel).  Waves either stride through it statically or take
+// `group` consecutive tasks at a time from a global counter; which one is
+// faster depends on the mix and is left to the autotuner.  Each task runs the
+// same run_task as the single-instance kernel and writes its own outputs, so
+// results do not depend on the schedule and equal separate per-instance runs.
+#include "walk_task.hpp"
+
+namespace mc {
+namespace {
+
+template <int MODE, bool FP32>
+__device__ __forceinline__ TaskResult run_one(const InstArgs &P, uint32_t node, uint32_t ord0,
+                                              uint32_t cnt, uint32_t *list) {
+    TraceOut none;
+    return run_task<MODE, FP32, false, false>(P, node, ord0, cnt, none, list);
+}
+
+__device__ __forceinline__ TaskResult dispatch(const BatchInst &I, uint32_t node, uint32_t ord0,
+                                               uint32_t cnt, uint32_t *list) {
+    switch (I.mode * 2 + (I.fp32 ? 1 : 0)) {
+        case MC_EXACT * 2: return run_one<MC_EXACT, false>(I.P, node, ord0, cnt, list);
+        case MC_EXACT * 2 + 1: return run_one<MC_EXACT, true>(I.P, node, ord0, cnt, list);
+        case MC_STRANG * 2: return run_one<MC_STRANG, false>(I.P, node, ord0, cnt, list);
+        case MC_STRANG * 2 + 1: return run_one<MC_STRANG, true>(I.P, node, ord0, cnt, list);
+        case MC_LIE * 2: return run_one<MC_LIE, false>(I.P, node, ord0, cnt, list);
+        default: return run_one<MC_LIE, true>(I.P, node, ord0, cnt, list);
+    }
+}
+
+// One task of the global index space.
+__device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, int64_t task,
+                                        uint32_t *list, unsigned long long &my_events,
+                                        unsigned long long &my_jumps) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    // instance owning this task: the last i with tb[i] <= task
+    int lo = 0, hi = a.ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tb[mid] <= task) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchInst &I = a.inst[lo];
+    const int64_t local = task - tb[lo];
+    const int64_t e = local / I.chunks;
+    const int64_t c = local - e * I.chunks;
+    const int64_t node = I.idx ? I.idx[e] : e;
+    double *part = a.part + I.part_off + (e * I.chunks + c) * 3;
+    if (node < 0 || node >= I.n) {
+        if (lane == 0) {
+            atomicOr(a.flags, F_OUT_OF_RANGE);
+            if (I.chunks == 1) {
+                I.est[e] = NAN;
+                if (I.se) I.se[e] = NAN;
+            } else {
+                part[0] = 1.0;
+                part[1] = NAN;
+                part[2] = NAN;
+            }
+        }
+        return;
+    }
+    const int64_t wbase = c * (int64_t)kChunkMax;
+    const int64_t rem = I.nwalk - wbase;
+    const uint32_t cnt = (uint32_t)(rem < (int64_t)kChunkMax ? rem : (int64_t)kChunkMax);
+    const TaskResult r = dispatch(I, (uint32_t)node, (uint32_t)wbase, cnt, list);
+    if (r.err && lane == 0) atomicOr(a.flags, r.err);
+    if (lane == 0) {
+        if (I.chunks == 1) {
+            I.est[e] = r.mean;
+            if (I.se) I.se[e] = r.n > 1.0 ? sqrt(r.m2 / (r.n - 1.0) / r.n) : 0.0;
+        } else {
+            part[0] = r.n;
+            part[1] = r.mean;
+            part[2] = r.m2;
+        }
+    }
+    my_events += r.events;
+    my_jumps += r.jumps;
+}
+
+__global__ __launch_bounds__(256) void k_walk_batched(BatchArgs a) {
+    __shared__ int64_t sh_tb[kMaxBatch];
+    __shared__ unsigned long long sh_count[256 / WAVE][2];
+    __shared__ uint32_t sh_list[256 / WAVE][kChunkMax];
+    for (int i = threadIdx.x; i < a.ninst; i += blockDim.x) sh_tb[i] = a.inst[i].task_begin;
+    __syncthreads();
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x / WAVE;
+    uint32_t *list = sh_list[wave];
+    unsigned long long my_events = 0, my_jumps = 0;
+    if (a.group == 0) {
+        const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+        const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+        for (int64_t task = wave_id; task < a.ntasks; task += nwaves)
+            do_task(a, sh_tb, task, list, my_events, my_jumps);
+    } else {
+        for (;;) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(a.queue, (unsigned long long)a.group);
+            base = __shfl(base, 0, WAVE);
+            if ((int64_t)base >= a.ntasks) break;
+            int64_t end = (int64_t)base + a.group;
+            if (end > a.ntasks) end = a.ntasks;
+            for (int64_t task = (int64_t)base; task < end; ++task)
+                do_task(a, sh_tb, task, list, my_events, my_jumps);
+        }
+    }
+    if (lane == 0) {
+        sh_count[wave][0] = my_events;
+        sh_count[wave][1] = my_jumps;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long ev = 0, ju = 0;
+        for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) {
+            ev += sh_count[w][0];
+            ju += sh_count[w][1];
+        }
+        a.counters[2 * blockIdx.x] = ev;
+        a.counters[2 * blockIdx.x + 1] = ju;
+    }
+}
+
+// Reset the task counter from inside a captured graph (a kernel node, not a
+// memset node).
+__global__ void k_reset_queue(unsigned long long *queue) { *queue = 0ull; }
+
+// Merge chunk partials of every entry that spans several chunks, for all
+// instances: item f belongs to instance i with fin_begin[i] <= f < fin_begin[i+1].
+__global__ void k_finalize_batched(BatchArgs a) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= a.nfin) return;
+    int lo = 0, hi = a.ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.fin_begin[mid] <= f) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchInst &I = a.inst[lo];
+    const int64_t e = f - a.fin_begin[lo];
+    const double *p = a.part + I.part_off + e * I.chunks * 3;
+    double n = 0.0, mean = 0.0, q = 0.0;
+    for (int64_t c = 0; c < I.chunks; ++c) chan_merge(n, mean, q, p[3 * c], p[3 * c + 1], p[3 * c + 2]);
+    I.est[e] = mean;
+    if (I.se) I.se[e] = n > 1.0 ? sqrt(q / (n - 1.0) / n) : 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchArgs &a, int block, int grid, hipStream_t s) {
+    if (a.group != 0) {
+        hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, a.queue);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (a.ntasks > 0) {
+        hipLaunchKernelGGL(k_walk_batched, dim3((unsigned)grid), dim3(block), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (a.nfin > 0) {
+        const int fb = 256;
+        hipLaunchKernelGGL(k_finalize_batched, dim3((unsigned)((a.nfin + fb - 1) / fb)), dim3(fb), 0,
+                           s, a);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+}  // namespace mc

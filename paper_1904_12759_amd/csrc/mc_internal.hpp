@@ -104,6 +104,33 @@ struct WalkArgs {
     TraceOut trace;
 };
 
+// One instance of a batched launch.
+struct BatchInst {
+    InstArgs P;
+    const int64_t *idx;        // null: full vector
+    int64_t k, n, nwalk, chunks;
+    int64_t task_begin;        // first task of this instance in the batch
+    int64_t part_off;          // offset (doubles) of its chunk partials
+    double *est, *se;
+    int32_t mode, fp32;
+};
+
+// Largest number of instances in one batch (their task offsets sit in LDS).
+constexpr int kMaxBatch = 1024;
+
+struct BatchArgs {
+    const BatchInst *inst;
+    int32_t ninst;
+    int64_t ntasks;
+    double *part;
+    unsigned long long *counters;  // [2 * grid]
+    uint32_t *flags;
+    unsigned long long *queue;     // dynamic schedule counter
+    uint32_t group;                // tasks per grab; 0 = static stride
+    const int64_t *fin_begin;      // [ninst + 1] prefix of entries with chunks > 1
+    int64_t nfin;
+};
+
 // Walkers per task: fixes the summation order of an entry's estimate.
 constexpr uint32_t kChunkMax = 1024;
 
@@ -115,6 +142,9 @@ int launch_walk_grid(int64_t ntasks, int block);
 hipError_t launch_walk(const WalkArgs &a, int mode, bool fp32, bool prop, bool trace,
                        int block, hipStream_t s);
 hipError_t launch_finalize(const WalkArgs &a, hipStream_t s);
+
+// batched launch (batch.hip): queue reset, persistent walk, finalize
+hipError_t launch_batch(const BatchArgs &a, int block, int grid, hipStream_t s);
 
 // setup kernels (setup.hip)
 hipError_t launch_check_rowptr(int64_t n, int64_t nnz, const int64_t *rowptr, uint32_t *flags,
