@@ -262,6 +262,71 @@ mc_status mc_expmv_batch_set_schedule(mc_batch_t b, const mc_batch_schedule *sch
 /* Release the batch and every instance's tables. */
 void mc_expmv_batch_destroy(mc_batch_t b);
 
+/* ------------------------------------------------------- learned proposal
+ * A small network predicts the tilt b_ij of every jump edge for
+ * mc_expmv_set_proposal.  Variance reduction is the remedy the paper names for
+ * the statistical error (Sec. 5, after Eq. (errortotal)); the tilted walk with
+ * its importance weights keeps the estimator unbiased whatever the network
+ * predicts, so the plain walk stays both the fallback and the judge of bias.
+ *
+ *   node features  f_i = [log1p deg_i, r_i, v_i, log1p(mean deg of i's jump
+ *                  targets)], each standardised over the nodes (population sd)
+ *   network        x = [f_i; f_j] -> 64 ReLU -> 64 ReLU -> y, b_ij = 8 tanh(y/8);
+ *                  bfloat16 weights, FP32 accumulation, the 64x64 layer on MFMA
+ *   training       minimise sum_e p_e (b_e - b*_e)^2 / sum_e p_e over the edges,
+ *                  p_e = a_ij / r_i, b*_e = log h_j - log h_i with h = sqrt of the
+ *                  per-node second moment of W v[X_t] from plain runs; Adam
+ *                  (beta 0.9 / 0.999, eps 1e-8) on FP32 master weights.
+ * Parameter vector (kMlpParams = 4801 floats): W1[64][8], b1[64], W2[64][64],
+ * b2[64], w3[64], b3.  Gradients are reduced in a fixed order (deterministic).
+ */
+typedef struct mc_mlp_s *mc_mlp_t;
+
+typedef struct {
+    uint32_t struct_size;       /* sizeof(mc_learn_opts) */
+    int64_t pilot_walkers;      /* plain walkers per node for the statistics (default 256) */
+    int32_t steps;              /* Adam steps (default 400) */
+    int64_t batch;              /* edge positions per step (default 65536) */
+    float lr;                   /* learning rate (default 3e-3) */
+    uint64_t seed;              /* weight initialisation */
+} mc_learn_opts;
+
+typedef struct {
+    float initial_loss, final_loss;
+    int32_t steps;
+    double pilot_ms, train_ms;  /* device time: pilot + features, training + inference */
+} mc_learn_report;
+
+/* Network with He-uniform initial weights drawn from Philox(seed); work on `stream`. */
+mc_status mc_mlp_create(mc_mlp_t *out, uint64_t seed, void *stream);
+void mc_mlp_destroy(mc_mlp_t m);
+/* Copy the FP32 master parameters to / from host float[4801] (set also resets Adam). */
+mc_status mc_mlp_get_params(mc_mlp_t m, float *host);
+mc_status mc_mlp_set_params(mc_mlp_t m, const float *host);
+/* Standardised node features of handle h's matrix and vector v: device float[n][4]. */
+mc_status mc_mlp_features(mc_expmv_t h, const void *v, float *feats);
+/* log h_i = 0.5 log(second moment) from a plain run's est/stderr (device double[n])
+ * with n_walkers walkers per node: device float[n]. */
+mc_status mc_mlp_log_h(mc_expmv_t h, const double *est, const double *stderr_, int64_t n_walkers,
+                       float *lh);
+/* b for every CSR position (0 off the jump edges): device float[nnz]. */
+mc_status mc_mlp_forward(mc_mlp_t m, mc_expmv_t h, const float *feats, float *bias);
+/* Gradient (device float[4801]) and loss (device float[1], may be NULL) of the
+ * weighted squared error over the jump edges at CSR positions [p0, p1). */
+mc_status mc_mlp_gradient(mc_mlp_t m, mc_expmv_t h, const float *feats, const float *lh,
+                          int64_t p0, int64_t p1, float *grad, float *loss);
+/* One Adam step with gradient `grad` (device float[4801]). */
+mc_status mc_mlp_adam_step(mc_mlp_t m, const float *grad, float lr);
+/* `steps` Adam steps on batches of `batch` positions spread over the matrix;
+ * loss_host (may be NULL): host float[steps].  Synchronous. */
+mc_status mc_mlp_train(mc_mlp_t m, mc_expmv_t h, const float *feats, const float *lh,
+                       int32_t steps, int64_t batch, float lr, float *loss_host);
+void mc_learn_default_opts(mc_learn_opts *opts);
+/* Pilot plain run on every node -> targets -> features -> training -> inference
+ * -> mc_expmv_set_proposal, all on the GPU.  MC_EXACT handles only.  Synchronous. */
+mc_status mc_expmv_learn_proposal(mc_expmv_t h, const void *v, const mc_learn_opts *opts,
+                                  mc_learn_report *rep);
+
 #ifdef __cplusplus
 }
 #endif

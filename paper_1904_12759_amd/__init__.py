@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["MCExpmv", "MCBatch", "MCError", "EXACT", "STRANG", "LIE", "FP64", "FP32", "lib",
+__all__ = ["MCExpmv", "MCBatch", "MLP", "MCError", "EXACT", "STRANG", "LIE", "FP64", "FP32", "lib",
            "load"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -90,6 +90,23 @@ class mc_batch_schedule(ctypes.Structure):
     ]
 
 
+class mc_learn_opts(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("pilot_walkers", ctypes.c_int64),
+        ("steps", ctypes.c_int32), ("batch", ctypes.c_int64), ("lr", ctypes.c_float),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class mc_learn_report(ctypes.Structure):
+    _fields_ = [
+        ("initial_loss", ctypes.c_float), ("final_loss", ctypes.c_float),
+        ("steps", ctypes.c_int32), ("pilot_ms", ctypes.c_double), ("train_ms", ctypes.c_double),
+    ]
+
+
+NPARAM = 4801
+
 _lib = None
 
 # exported C symbols and their signatures (also checked by the CPU tests)
@@ -123,6 +140,24 @@ _SIGS = {
     "mc_expmv_batch_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_batch_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_batch_destroy": (None, [ctypes.c_void_p]),
+    "mc_mlp_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "mc_mlp_destroy": (None, [ctypes.c_void_p]),
+    "mc_mlp_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_mlp_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_mlp_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_mlp_log_h": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int64, ctypes.c_void_p]),
+    "mc_mlp_forward": (ctypes.c_int, [ctypes.c_void_p] * 4),
+    "mc_mlp_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_mlp_adam_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float]),
+    "mc_mlp_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                    ctypes.c_float, ctypes.c_void_p]),
+    "mc_learn_default_opts": (None, [ctypes.c_void_p]),
+    "mc_expmv_learn_proposal": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -284,6 +319,34 @@ class MCExpmv:
     def sync(self):
         _check(load().mc_expmv_sync(self._h), "mc_expmv_sync")
 
+    def learn_proposal(self, v, pilot_walkers: int = 256, steps: int = 400, batch: int = 1 << 16,
+                       lr: float = 3e-3, seed: int = 1) -> dict:
+        """Train the proposal network on the GPU and install the tilted walk."""
+        v = self._v(v)
+        o = mc_learn_opts()
+        load().mc_learn_default_opts(ctypes.byref(o))
+        o.pilot_walkers, o.steps, o.batch, o.lr, o.seed = pilot_walkers, steps, batch, lr, seed
+        rep = mc_learn_report()
+        _check(load().mc_expmv_learn_proposal(self._h, _ptr(v), ctypes.byref(o), ctypes.byref(rep)),
+               "mc_expmv_learn_proposal")
+        return dict(initial_loss=rep.initial_loss, final_loss=rep.final_loss, steps=rep.steps,
+                    pilot_ms=rep.pilot_ms, train_ms=rep.train_ms)
+
+    def features(self, v):
+        import torch
+        v = self._v(v)
+        f = torch.empty(self.n, 4, dtype=torch.float32, device=self.device)
+        _check(load().mc_mlp_features(self._h, _ptr(v), _ptr(f)), "mc_mlp_features")
+        return f
+
+    def log_h(self, est, stderr, n_walkers: int):
+        import torch
+        lh = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        _check(load().mc_mlp_log_h(self._h, _ptr(est), _ptr(stderr), int(n_walkers), _ptr(lh)),
+               "mc_mlp_log_h")
+        self.sync()
+        return lh
+
     def stats(self) -> dict:
         s = mc_expmv_run_stats()
         _check(load().mc_expmv_stats(self._h, ctypes.byref(s)), "mc_expmv_stats")
@@ -419,3 +482,68 @@ class MCBatch:
             self.close()
         except Exception:
             pass
+
+
+class MLP:
+    """The proposal network (``mc_mlp_*``), bound to one MCExpmv handle's matrix."""
+
+    def __init__(self, handle: MCExpmv, seed: int = 1):
+        import torch
+        self.h = handle
+        m = ctypes.c_void_p()
+        _check(load().mc_mlp_create(ctypes.byref(m), int(seed), ctypes.c_void_p(handle.stream)),
+               "mc_mlp_create")
+        self._m = m
+        self.device = handle.device
+        self._grad = torch.empty(NPARAM, dtype=torch.float32, device=self.device)
+        self._loss = torch.empty(1, dtype=torch.float32, device=self.device)
+
+    def close(self):
+        if getattr(self, "_m", None):
+            load().mc_mlp_destroy(self._m)
+            self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        import numpy as np
+        out = np.zeros(NPARAM, np.float32)
+        _check(load().mc_mlp_get_params(self._m, out.ctypes.data_as(ctypes.c_void_p)),
+               "mc_mlp_get_params")
+        return out
+
+    def set_params(self, p):
+        import numpy as np
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.shape == (NPARAM,)
+        _check(load().mc_mlp_set_params(self._m, p.ctypes.data_as(ctypes.c_void_p)),
+               "mc_mlp_set_params")
+
+    def forward(self, feats):
+        import torch
+        b = torch.empty(self.h.nnz, dtype=torch.float32, device=self.device)
+        _check(load().mc_mlp_forward(self._m, self.h._h, _ptr(feats), _ptr(b)), "mc_mlp_forward")
+        self.h.sync()
+        return b
+
+    def gradient(self, feats, lh, p0: int, p1: int):
+        _check(load().mc_mlp_gradient(self._m, self.h._h, _ptr(feats), _ptr(lh), int(p0), int(p1),
+                                      _ptr(self._grad), _ptr(self._loss)), "mc_mlp_gradient")
+        self.h.sync()
+        return self._grad.clone(), float(self._loss.item())
+
+    def adam_step(self, grad, lr: float):
+        _check(load().mc_mlp_adam_step(self._m, _ptr(grad), float(lr)), "mc_mlp_adam_step")
+        self.h.sync()
+
+    def train(self, feats, lh, steps: int, batch: int, lr: float):
+        import numpy as np
+        loss = np.zeros(steps, np.float32)
+        _check(load().mc_mlp_train(self._m, self.h._h, _ptr(feats), _ptr(lh), int(steps),
+                                   int(batch), float(lr), loss.ctypes.data_as(ctypes.c_void_p)),
+               "mc_mlp_train")
+        return loss

@@ -35,6 +35,7 @@ struct mc_expmv_s {
     bool ran = false;
     uint64_t last_walkers = 0;
     int last_grid = 0;
+    int32_t *rowof = nullptr;            // row of each CSR position (learned proposal)
     bool last_fp32 = false, last_prop = false;
 };
 
@@ -247,6 +248,7 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->flags);
     (void)hipFree(h->counters);
     (void)hipFree(h->part);
+    (void)hipFree(h->rowof);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
@@ -901,6 +903,293 @@ mc_status mc_expmv_batch_set_schedule(mc_batch_t b, const mc_batch_schedule *sch
     b->group = sched->group;
     HIP_TRY(batch_capture(b));
     return MC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- learned proposal
+struct mc_mlp_s {
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    float *w = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *loss = nullptr;
+    uint16_t *wbf = nullptr;
+    float *gpart = nullptr;
+    int gpart_blocks = 0;
+    int step = 0;
+};
+
+namespace {
+
+hipError_t ensure_rowof(mc_expmv_s *h) {
+    if (h->rowof) return hipSuccess;
+    hipError_t e = dalloc(&h->rowof, h->nnz);
+    if (e != hipSuccess) return e;
+    return launch_rowof(h->n, h->rowptr, h->rowof, h->stream);
+}
+
+hipError_t ensure_gpart(mc_mlp_s *m, int blocks) {
+    if (blocks <= m->gpart_blocks) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) return e;
+    (void)hipFree(m->gpart);
+    m->gpart = nullptr;
+    m->gpart_blocks = 0;
+    e = dalloc(&m->gpart, (int64_t)blocks * 4 * mlp_grad_stride());
+    if (e == hipSuccess) m->gpart_blocks = blocks;
+    return e;
+}
+
+int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mc_mlp_destroy(mc_mlp_t m) {
+    if (!m) return;
+    (void)hipSetDevice(m->dev);
+    (void)hipStreamSynchronize(m->stream);
+    (void)hipFree(m->w);
+    (void)hipFree(m->m);
+    (void)hipFree(m->v);
+    (void)hipFree(m->grad);
+    (void)hipFree(m->loss);
+    (void)hipFree(m->wbf);
+    (void)hipFree(m->gpart);
+    delete m;
+}
+
+mc_status mc_mlp_create(mc_mlp_t *out, uint64_t seed, void *stream) {
+    if (!out) return MC_ERR_INVALID_ARG;
+    *out = nullptr;
+    mc_mlp_s *m = new (std::nothrow) mc_mlp_s();
+    if (!m) return MC_ERR_NO_MEMORY;
+    m->stream = (hipStream_t)stream;
+#define M_TRY(expr)                              \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) {                  \
+            mc_status s_ = from_hip(e_);         \
+            mc_mlp_destroy(m);                   \
+            return s_;                           \
+        }                                        \
+    } while (0)
+    M_TRY(hipGetDevice(&m->dev));
+    M_TRY(dalloc(&m->w, kMlpParams));
+    M_TRY(dalloc(&m->m, kMlpParams));
+    M_TRY(dalloc(&m->v, kMlpParams));
+    M_TRY(dalloc(&m->grad, kMlpParams));
+    M_TRY(dalloc(&m->loss, 1));
+    M_TRY(dalloc(&m->wbf, kMlpParams));
+    M_TRY(launch_mlp_init(m->w, m->m, m->v, m->wbf, seed, m->stream));
+    M_TRY(hipStreamSynchronize(m->stream));
+#undef M_TRY
+    *out = m;
+    return MC_OK;
+}
+
+mc_status mc_mlp_get_params(mc_mlp_t m, float *host) {
+    if (!m || !host) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(m->dev));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    HIP_TRY(hipMemcpy(host, m->w, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+    return MC_OK;
+}
+
+mc_status mc_mlp_set_params(mc_mlp_t m, const float *host) {
+    if (!m || !host) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(m->dev));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    HIP_TRY(hipMemcpy(m->w, host, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(m->m, 0, sizeof(float) * kMlpParams));
+    HIP_TRY(hipMemset(m->v, 0, sizeof(float) * kMlpParams));
+    HIP_TRY(launch_params_bf16(m->w, m->wbf, m->stream));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    m->step = 0;
+    return MC_OK;
+}
+
+mc_status mc_mlp_features(mc_expmv_t h, const void *v, float *feats) {
+    if (!h || !v || (h->n > 0 && !feats)) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    double *raw = nullptr, *stats = nullptr;
+    HIP_TRY(dalloc(&raw, 4 * h->n));
+    hipError_t e = dalloc(&stats, 8);
+    if (e == hipSuccess)
+        e = launch_features(h->n, h->rowptr, h->col, h->val, h->plain.rows, h->plain.r, v,
+                            h->opts.weight_prec == MC_FP32, raw, stats, feats, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(raw);
+    (void)hipFree(stats);
+    return from_hip(e);
+}
+
+mc_status mc_mlp_log_h(mc_expmv_t h, const double *est, const double *se, int64_t n_walkers,
+                       float *lh) {
+    if (!h || !est || !se || !lh || n_walkers < 2) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    HIP_TRY(launch_log_h(h->n, est, se, (double)n_walkers, lh, h->stream));
+    return MC_OK;
+}
+
+mc_status mc_mlp_forward(mc_mlp_t m, mc_expmv_t h, const float *feats, float *bias) {
+    if (!m || !h || !feats || (h->nnz > 0 && !bias)) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    HIP_TRY(ensure_rowof(h));
+    HIP_TRY(launch_net_forward(m->wbf, feats, h->rowof, h->col, h->val, h->plain.r, h->nnz, bias,
+                               h->stream));
+    return MC_OK;
+}
+
+mc_status mc_mlp_gradient(mc_mlp_t m, mc_expmv_t h, const float *feats, const float *lh,
+                          int64_t p0, int64_t p1, float *grad, float *loss) {
+    if (!m || !h || !feats || !lh || !grad) return MC_ERR_INVALID_ARG;
+    if (p0 < 0 || p1 > h->nnz || p1 <= p0) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    HIP_TRY(ensure_rowof(h));
+    const int64_t tile0 = p0 / 16;
+    const int64_t ntile = (p1 - tile0 * 16 + 15) / 16;
+    const int blocks = mlp_blocks(ntile, 1024);
+    HIP_TRY(ensure_gpart(m, blocks));
+    HIP_TRY(launch_net_gradient(m->wbf, feats, h->rowof, h->col, h->val, h->plain.r, lh, p0, p1,
+                                tile0, ntile, 1, (int64_t)1 << 62, blocks, m->gpart, grad, loss,
+                                h->stream));
+    return MC_OK;
+}
+
+mc_status mc_mlp_adam_step(mc_mlp_t m, const float *grad, float lr) {
+    if (!m || !grad || !(lr > 0.0f)) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(m->dev));
+    m->step += 1;
+    HIP_TRY(launch_adam(grad, m->w, m->m, m->v, m->wbf, lr, m->step, m->stream));
+    return MC_OK;
+}
+
+mc_status mc_mlp_train(mc_mlp_t m, mc_expmv_t h, const float *feats, const float *lh,
+                       int32_t steps, int64_t batch, float lr, float *loss_host) {
+    if (!m || !h || !feats || !lh || steps < 1 || batch < 16 || !(lr > 0.0f))
+        return MC_ERR_INVALID_ARG;
+    if (h->nnz == 0) return MC_OK;
+    HIP_TRY(hipSetDevice(h->dev));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    HIP_TRY(ensure_rowof(h));
+    const int64_t tmod = (h->nnz + 15) / 16;
+    int64_t ntile = (batch + 15) / 16;
+    if (ntile > tmod) ntile = tmod;
+    // visit tiles in the order T_k = (k * stride) mod tmod with stride coprime
+    // to tmod, so every batch spreads over the whole matrix
+    int64_t stride = (int64_t)(0.6180339887498949 * (double)tmod) | 1;
+    while (stride > 1 && gcd64(stride, tmod) != 1) stride += 2;
+    if (stride < 1 || stride >= tmod) stride = 1;
+    const int blocks = mlp_blocks(ntile, 1024);
+    HIP_TRY(ensure_gpart(m, blocks));
+    float *dloss = nullptr;
+    HIP_TRY(dalloc(&dloss, steps));
+    mc_status st = MC_OK;
+    for (int32_t s = 0; s < steps && st == MC_OK; ++s) {
+        const int64_t tile0 = ((int64_t)s * ntile % tmod) * stride % tmod;
+        hipError_t e = launch_net_gradient(m->wbf, feats, h->rowof, h->col, h->val, h->plain.r,
+                                           lh, 0, h->nnz, tile0, ntile, stride, tmod, blocks,
+                                           m->gpart, m->grad, dloss + s, h->stream);
+        if (e == hipSuccess) {
+            m->step += 1;
+            e = launch_adam(m->grad, m->w, m->m, m->v, m->wbf, lr, m->step, h->stream);
+        }
+        st = from_hip(e);
+    }
+    if (st == MC_OK && loss_host)
+        st = from_hip(hipMemcpy(loss_host, dloss, sizeof(float) * (size_t)steps,
+                                hipMemcpyDeviceToHost));
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(dloss);
+    return st;
+}
+
+void mc_learn_default_opts(mc_learn_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(mc_learn_opts);
+    o->pilot_walkers = 256;
+    o->steps = 400;
+    o->batch = 1 << 16;
+    o->lr = 3e-3f;
+    o->seed = 1;
+}
+
+mc_status mc_expmv_learn_proposal(mc_expmv_t h, const void *v, const mc_learn_opts *opts,
+                                  mc_learn_report *rep) {
+    if (!h || !v) return MC_ERR_INVALID_ARG;
+    mc_learn_opts o;
+    mc_learn_default_opts(&o);
+    if (opts) {
+        if (opts->struct_size != sizeof(mc_learn_opts)) return MC_ERR_INVALID_ARG;
+        o = *opts;
+    }
+    if (o.pilot_walkers < 2 || o.steps < 1 || o.batch < 16 || !(o.lr > 0.0f))
+        return MC_ERR_INVALID_ARG;
+    if (h->opts.mode != MC_EXACT) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    if (rep) memset(rep, 0, sizeof(*rep));
+    const int64_t n = h->n;
+    double *est = nullptr, *se = nullptr;
+    float *lh = nullptr, *feats = nullptr, *bias = nullptr;
+    mc_mlp_t net = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
+    std::vector<float> losses((size_t)o.steps);
+    mc_status st = from_hip(dalloc(&est, n));
+    if (st == MC_OK) st = from_hip(dalloc(&se, n));
+    if (st == MC_OK) st = from_hip(dalloc(&lh, n));
+    if (st == MC_OK) st = from_hip(dalloc(&feats, 4 * n));
+    if (st == MC_OK) st = from_hip(dalloc(&bias, h->nnz));
+    if (st == MC_OK) st = from_hip(hipEventCreate(&t0));
+    if (st == MC_OK) st = from_hip(hipEventCreate(&t1));
+    if (st == MC_OK) st = from_hip(hipEventCreate(&t2));
+    // 1. plain pilot over every node: per-node second moments
+    if (st == MC_OK) st = from_hip(hipEventRecord(t0, h->stream));
+    if (st == MC_OK)
+        st = run_walk(h, v, nullptr, n, o.pilot_walkers, est, se, false, 0, 0, nullptr, nullptr,
+                      nullptr, nullptr);
+    if (st == MC_OK) st = mc_expmv_sync(h);
+    if (st == MC_OK) st = mc_mlp_log_h(h, est, se, o.pilot_walkers, lh);
+    if (st == MC_OK) st = mc_mlp_features(h, v, feats);
+    if (st == MC_OK) st = from_hip(hipEventRecord(t1, h->stream));
+    // 2. train the network on the GPU
+    if (st == MC_OK) st = mc_mlp_create(&net, o.seed, h->stream);
+    if (st == MC_OK) st = mc_mlp_train(net, h, feats, lh, o.steps, o.batch, o.lr, losses.data());
+    // 3. inference over every edge, install the tilted tables
+    if (st == MC_OK) st = mc_mlp_forward(net, h, feats, bias);
+    if (st == MC_OK) st = from_hip(hipEventRecord(t2, h->stream));
+    if (st == MC_OK) st = from_hip(hipStreamSynchronize(h->stream));
+    if (st == MC_OK) st = mc_expmv_set_proposal(h, bias);
+    if (st == MC_OK && rep) {
+        float a = 0.0f, b = 0.0f;
+        (void)hipEventElapsedTime(&a, t0, t1);
+        (void)hipEventElapsedTime(&b, t1, t2);
+        rep->pilot_ms = a;
+        rep->train_ms = b;
+        rep->initial_loss = losses.front();
+        rep->final_loss = losses.back();
+        rep->steps = o.steps;
+    }
+    mc_mlp_destroy(net);
+    (void)hipFree(est);
+    (void)hipFree(se);
+    (void)hipFree(lh);
+    (void)hipFree(feats);
+    (void)hipFree(bias);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (t2) (void)hipEventDestroy(t2);
+    return st;
 }
 
 }  // extern "C"

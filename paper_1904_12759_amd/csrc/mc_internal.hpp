@@ -146,6 +146,31 @@ hipError_t launch_finalize(const WalkArgs &a, hipStream_t s);
 // batched launch (batch.hip): queue reset, persistent walk, finalize
 hipError_t launch_batch(const BatchArgs &a, int block, int grid, hipStream_t s);
 
+// learned proposal network (mlp.hip); parameter vector of kMlpParams floats:
+// W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3
+constexpr int kMlpParams = 64 * 8 + 64 + 64 * 64 + 64 + 64 + 1;
+int mlp_grad_stride();
+int mlp_blocks(int64_t ntile, int max_blocks);
+hipError_t launch_rowof(int64_t n, const int64_t *rowptr, int32_t *rowof, hipStream_t s);
+hipError_t launch_features(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                           const RowRec *rows, const double *r, const void *v, int v_fp32,
+                           double *raw, double *stats, float *feats, hipStream_t s);
+hipError_t launch_log_h(int64_t n, const double *est, const double *se, double nwalk, float *lh,
+                        hipStream_t s);
+hipError_t launch_net_forward(const uint16_t *wbf, const float *feats, const int32_t *rowof,
+                              const int32_t *col, const double *val, const double *r, int64_t nnz,
+                              float *out_b, hipStream_t s);
+hipError_t launch_net_gradient(const uint16_t *wbf, const float *feats, const int32_t *rowof,
+                               const int32_t *col, const double *val, const double *r,
+                               const float *lh, int64_t p0, int64_t p1, int64_t tile0,
+                               int64_t ntile, int64_t stride, int64_t tmod, int blocks,
+                               float *gpart, float *grad, float *loss, hipStream_t s);
+hipError_t launch_adam(const float *grad, float *w, float *m, float *v, uint16_t *wbf, float lr,
+                       int step, hipStream_t s);
+hipError_t launch_mlp_init(float *w, float *m, float *v, uint16_t *wbf, uint64_t seed,
+                           hipStream_t s);
+hipError_t launch_params_bf16(const float *w, uint16_t *wbf, hipStream_t s);
+
 // setup kernels (setup.hip)
 hipError_t launch_check_rowptr(int64_t n, int64_t nnz, const int64_t *rowptr, uint32_t *flags,
                                hipStream_t s);

@@ -101,3 +101,30 @@ def random_metzler(n: int, density: float, seed: int, symmetric: bool,
         off = off + off.T
     a = off + np.diag(rng.uniform(-1.0, 1.0, n) * diag_scale)
     return a
+
+
+def second_moment_exact(a, t: float, v: np.ndarray, bias=None) -> np.ndarray:
+    """E[f^2] per start node for the plain (bias None) or tilted walk, exactly.
+
+    Feynman-Kac with jump factors: for rates q_ij, a factor g_ij per jump and a
+    potential V, E[exp(int V) prod g  u(X_t)] = exp(t G) u with G_ij = q_ij g_ij,
+    G_ii = V_i - sum_j q_ij.  The squared estimator of the tilted walk has
+    q = a e^{b}, g = e^{-2b}, V = 2 d~, so G_ij = a_ij e^{-b_ij} and
+    G_ii = 2 d~_i - r~_i (d~ = d + r~ - r); b = 0 gives A + diag(d)."""
+    import scipy.sparse as sp
+    n = a.n
+    rows = np.repeat(np.arange(n), np.diff(a.rowptr))
+    off = (a.col != rows) & (a.val > 0)
+    diag = np.zeros(n)
+    np.add.at(diag, rows[a.col == rows], a.val[a.col == rows])
+    r = np.zeros(n)
+    np.add.at(r, rows[off], a.val[off])
+    d = diag + r
+    b = np.zeros(a.nnz) if bias is None else np.asarray(bias, np.float32).astype(np.float64)
+    at = a.val[off] * np.exp(b[off])
+    rt = np.zeros(n)
+    np.add.at(rt, rows[off], at)
+    dt = d + (rt - r)
+    g = sp.csr_matrix((a.val[off] * np.exp(-b[off]), (rows[off], a.col[off])), shape=(n, n))
+    g = g + sp.diags(2 * dt - rt)
+    return expm_multiply_v(g.tocsr(), t, np.asarray(v, np.float64) ** 2)

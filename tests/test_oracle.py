@@ -393,3 +393,27 @@ def test_random_bias_is_unbiased():
     est, se = o.estimate(v, None, 20_000, proposal=True, threads=4)
     ref = refs.expm_v(a, t, v)
     assert np.abs(_zscores(est, se, ref)).max() < 4.5
+
+
+@pytest.mark.parametrize("tilted", [False, True])
+def test_exact_second_moment_matches_oracle_samples(tilted):
+    """The exact second-moment formula (used to price walker-steps) against the
+    oracle's empirical mean of f^2 (var + mean^2) within statistical error."""
+    n = 25
+    a = refs.random_metzler(n, 0.25, 13, symmetric=False)
+    csr = wl.from_dense(a)
+    v = np.random.default_rng(1).uniform(0.2, 1.0, n)
+    t = 0.6
+    o = Oracle(csr.rowptr, csr.col, csr.val, t, 3)
+    bias = None
+    if tilted:
+        bias = np.random.default_rng(2).normal(0, 0.5, csr.nnz).astype(np.float32)
+        o.set_proposal(bias)
+    m2 = refs.second_moment_exact(csr, t, v, bias)
+    nw = 40_000
+    for i in (0, 7, 19):
+        _, _, _, f, _ = o.trace(v, i, 0, nw, proposal=tilted)
+        f2 = f * f
+        emp = f2.mean()
+        sd = f2.std() / np.sqrt(nw)
+        assert abs(emp - m2[i]) < 4.5 * sd, (i, emp, m2[i], sd)
