@@ -82,8 +82,11 @@ def test_gradient_matches_oracle(small, p0, p1):
                                 src[sel], dst[sel], pw[sel], tgt)
     gg = grad.cpu().numpy()
     assert abs(loss - lo) <= 1e-4 * max(1.0, abs(lo))
+    # dL/dz2 is rounded to bf16 on both sides, but from an FP32 value on the GPU and
+    # an FP64 one here: a value next to a rounding boundary may land one bf16 ulp
+    # (2^-8 relative) apart, which a single edge's outer product shows undiluted.
     scale = np.abs(go).max()
-    assert np.abs(gg - go).max() <= 2e-3 * scale, np.abs(gg - go).max() / scale
+    assert np.abs(gg - go).max() <= 2.0 ** -7 * scale, np.abs(gg - go).max() / scale
 
 
 def test_adam_step_matches_oracle(small):
