@@ -54,8 +54,9 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // three-input XOR in one v_bitop3_b32 (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c0 = n0;
         c1 = (uint32_t)p1;
         c2 = n2;
@@ -215,6 +216,8 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
     } else if (e0 >= 0.125) {
         use_list = true;
         uint32_t nlist = 0;
+        // U >= e0  <=>  m + 1 >= e0 * 2^53 (exact: U = (m+1) 2^-53), i.e. m + 1 >= ceil(e0 2^53)
+        const uint64_t m_thr = (uint64_t)ceil(e0 * 0x1p53);
         for (uint32_t b = 0; b < cnt; b += WAVE) {
             const uint32_t w = b + (uint32_t)lane;
             const bool valid = w < cnt;
@@ -222,8 +225,7 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
             if (valid) {
                 const U4 o = philox(0u, ord0 + w, node, P.inst, P.key0, P.key1);
                 const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
-                const double U = (double)(m + 1ull) * 0x1p-53;
-                go = U >= e0;
+                go = m + 1ull >= m_thr;
             }
             const unsigned long long gmask = __ballot(go);
             const unsigned long long smask = __ballot(valid && !go);
