@@ -31,6 +31,33 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "walk_ba_n1e5_fp32.txt")
+KERNEL_SOURCES = ["paper_1904_12759_amd/csrc/walk.hip", "paper_1904_12759_amd/csrc/walk_task.hpp",
+                  "paper_1904_12759_amd/csrc/mc_internal.hpp"]
+
+
+def measured_traffic():
+    """HBM bytes per walk launch from the committed rocprofv3 summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy), or None when the kernel sources have changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    fields = dict(ln.split(":", 1) for ln in text.splitlines()
+                  if ":" in ln and not ln.startswith(("#", " ")))
+    if fields.get("source_sha256", "").strip() != h.hexdigest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"].split()[0])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(w, seed, nthreads):
     """The oracle on the host: the same workload (every node, 1e3 walkers each)."""
     import oracle
@@ -47,12 +74,126 @@ def cpu_baseline(w, seed, nthreads):
                        f"{nthreads} threads")
 
 
+def entries_at_1e3(mc, h, v, idx, pilot: int, target: float = 1e-3, cap: int = 1 << 30):
+    """Two-pass entries/s at a relative standard error target: a pilot of `pilot`
+    walkers per entry estimates sigma_i / x_i, then every entry is re-run with
+    N_i = ceil((sigma_i / (target x_i))^2) walkers (entries grouped by N_i rounded
+    up to a power of two, one call per group).  Returns the production time."""
+    import torch
+    idx = np.asarray(idx, np.int64)
+    est, se = h.entries(v, idx, pilot)
+    x = est.cpu().numpy()
+    sig = se.cpu().numpy() * np.sqrt(pilot)
+    need = np.ceil((sig / (target * np.abs(x))) ** 2).astype(np.float64)
+    need = np.clip(need, 2, cap)
+    grp = np.exp2(np.ceil(np.log2(need))).astype(np.int64)
+    groups = {int(g): idx[grp == g] for g in np.unique(grp)}
+    dev = torch.device("cuda", torch.cuda.current_device())
+    tidx = {g: torch.as_tensor(ix, device=dev) for g, ix in groups.items()}
+    outs = {g: (torch.empty(len(ix), dtype=torch.float64, device=dev),
+                torch.empty(len(ix), dtype=torch.float64, device=dev)) for g, ix in groups.items()}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    walkers = 0
+    events = 0
+    for g in sorted(groups):
+        h.entries(v, tidx[g], g, est=outs[g][0], stderr=outs[g][1], sync=False)
+        h.sync()
+        st = h.stats()
+        walkers += st["walkers"]
+        events += st["events"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rel = np.concatenate([(outs[g][1] / outs[g][0].abs()).cpu().numpy() for g in sorted(groups)])
+    return dict(entries=len(idx), seconds=dt, entries_per_s=len(idx) / dt, walkers=walkers,
+                walker_steps=events, max_rel_stderr=float(rel.max()),
+                predicted_walkers=float(need.sum()))
+
+
+def bench_grid2d_entries(mc, seed):
+    """2-D Dirichlet Laplacian 32x32, t = 0.1, 16 entries, FP64: entries/s at 1e-3."""
+    from paper_1904_12759_amd import workloads as wl
+    w = wl.config_grid2d_entries()
+    h = mc.MCExpmv(w.a.rowptr, w.a.col, w.a.val, w.t, seed)
+    entries_at_1e3(mc, h, w.v, w.idx, 10_000)                       # warm-up
+    r = entries_at_1e3(mc, h, w.v, w.idx, 10_000)
+    r["workload"] = "grid2d 32x32 Dirichlet, t=0.1, 16 entries, FP64, two-pass (pilot 1e4)"
+    return r
+
+
+def bench_learned(mc, seed, n=1_000_000, m=4):
+    """BA(n=1e6, m=4, seed 1), A = (0.5/lambda_max) adjacency, t = 1, v ~ U[0,1] (seed 2);
+    1024 entries (256 highest degree + 768 uniform).  Walker-steps to 1e-3 relative
+    standard error for the plain and the learned walk from exact per-entry variances
+    (second moments by expm_multiply), and the learned walk's measured entries/s."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    from paper_1904_12759_amd import workloads as wl
+    t_gen = time.perf_counter()
+    g = wl.ba_graph(n, m, 1)
+    lam = wl.lambda_max(g)
+    a = wl.scaled(g, 0.5 / lam)
+    v = wl.uniform_v(a.n, 2)
+    deg = np.diff(a.rowptr)
+    rng = np.random.default_rng(3)
+    idx = np.unique(np.concatenate([np.argsort(-deg)[:256], rng.choice(a.n, 768, replace=False)]))
+    t_gen = time.perf_counter() - t_gen
+    h = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, seed)
+    out = dict(workload=f"BA n={n} m={m} seed 1, A=(0.5/lambda_max)*adjacency "
+                        f"(lambda_max={lam:.6g}), t=1, v~U[0,1], {len(idx)} entries "
+                        "(256 highest degree + uniform)", generation_s=t_gen)
+    # exact moments: x = exp(tA) v and E[f^2] = exp(tG) v^2 (Feynman-Kac with jump factors)
+    rows = np.repeat(np.arange(a.n), deg)
+    A = a.to_scipy()
+
+    def m2_exact(bias):
+        b = np.zeros(a.nnz) if bias is None else bias.astype(np.float64)
+        at = a.val * np.exp(b)
+        rt = np.bincount(rows, weights=at, minlength=a.n)
+        r = np.bincount(rows, weights=a.val, minlength=a.n)
+        gm = sp.csr_matrix((a.val * np.exp(-b), a.col, a.rowptr), shape=A.shape)
+        gm = gm + sp.diags(2 * (r + (rt - r)) - rt)         # d = r (no diagonal)
+        return sla.expm_multiply(gm.tocsr(), v * v)
+
+    x = sla.expm_multiply(A, v)
+    m2p = m2_exact(None)
+    h.entries(v, idx, 1 << 14)
+    st = h.stats()
+    ev_plain = st["events"] / st["walkers"]
+    rep = h.learn_proposal(v, pilot_walkers=256, steps=400, batch=1 << 16, lr=3e-3, seed=1)
+    bias = h.get_proposal()
+    h.entries(v, idx, 1 << 14)
+    st = h.stats()
+    ev_learn = st["events"] / st["walkers"]
+    m2l = m2_exact(bias.cpu().numpy())
+    xi = x[idx]
+    var_p = np.maximum(m2p[idx] - xi * xi, 0)
+    var_l = np.maximum(m2l[idx] - xi * xi, 0)
+    steps_p = float((var_p / (1e-3 * xi) ** 2).sum() * ev_plain)
+    steps_l = float((var_l / (1e-3 * xi) ** 2).sum() * ev_learn)
+    prod = entries_at_1e3(mc, h, v, idx, 10_000)
+    out.update(
+        walker_steps_to_1e3_plain_exact=steps_p,
+        walker_steps_to_1e3_learned_exact=steps_l,
+        gain_walker_steps=steps_p / steps_l if steps_l > 0 else None,
+        events_per_walker_plain=ev_plain, events_per_walker_learned=ev_learn,
+        learned_entries_per_s_at_1e3=prod["entries_per_s"],
+        learned_production_s=prod["seconds"],
+        learned_max_rel_stderr=prod["max_rel_stderr"],
+        train=dict(initial_loss=rep["initial_loss"], final_loss=rep["final_loss"],
+                   steps=rep["steps"], pilot_ms=rep["pilot_ms"], train_ms=rep["train_ms"]),
+    )
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the entries/s at 1e-3 and learned-vs-plain measurements")
     ap.add_argument("--seed", type=int, default=12759)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (steps times), "
@@ -153,9 +294,14 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
         },
     }
+    if not args.no_extras:
+        log("bench: entries/s at 1e-3 (grid2d)")
+        out["entries_at_1e3"] = bench_grid2d_entries(mc, args.seed)
+        log("bench: learned vs plain (BA n=1e6 m=4)")
+        out["learned_vs_plain"] = bench_learned(mc, args.seed)
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         try:

@@ -149,6 +149,10 @@ mc_status mc_expmv_full(mc_expmv_t h, const void *v, int64_t n_per_node, double 
  */
 mc_status mc_expmv_set_proposal(mc_expmv_t h, const float *edge_bias);
 
+/* Copy the installed proposal's biases (device float[nnz], CSR order) to edge_bias
+ * (device float[nnz]); MC_ERR_INVALID_ARG when the plain walk is in use.  Synchronous. */
+mc_status mc_expmv_get_proposal(mc_expmv_t h, float *edge_bias);
+
 /* Use `stream` (hipStream_t, NULL = null stream) for the handle's later work. */
 mc_status mc_expmv_set_stream(mc_expmv_t h, void *stream);
 

@@ -122,6 +122,7 @@ _SIGS = {
     "mc_expmv_full": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_set_proposal": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_expmv_get_proposal": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_sync": (ctypes.c_int, [ctypes.c_void_p]),
     "mc_expmv_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -315,6 +316,12 @@ class MCExpmv:
         if b.numel() != self.nnz:
             raise ValueError("edge_bias must have nnz entries (CSR order)")
         _check(load().mc_expmv_set_proposal(self._h, _ptr(b)), "mc_expmv_set_proposal")
+
+    def get_proposal(self):
+        import torch
+        b = torch.empty(self.nnz, dtype=torch.float32, device=self.device)
+        _check(load().mc_expmv_get_proposal(self._h, _ptr(b)), "mc_expmv_get_proposal")
+        return b
 
     def sync(self):
         _check(load().mc_expmv_sync(self._h), "mc_expmv_sync")

@@ -36,6 +36,7 @@ struct mc_expmv_s {
     uint64_t last_walkers = 0;
     int last_grid = 0;
     int32_t *rowof = nullptr;            // row of each CSR position (learned proposal)
+    float *bias = nullptr;               // copy of the installed proposal's edge biases
     bool last_fp32 = false, last_prop = false;
 };
 
@@ -249,6 +250,7 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->counters);
     (void)hipFree(h->part);
     (void)hipFree(h->rowof);
+    (void)hipFree(h->bias);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
@@ -401,7 +403,20 @@ mc_status mc_expmv_set_proposal(mc_expmv_t h, const float *edge_bias) {
         free_tables(h->prop);
         return st;
     }
+    if (!h->bias) HIP_TRY(dalloc(&h->bias, h->nnz));
+    HIP_TRY(hipMemcpyAsync(h->bias, edge_bias, sizeof(float) * (size_t)h->nnz,
+                           hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
     h->has_prop = true;
+    return MC_OK;
+}
+
+mc_status mc_expmv_get_proposal(mc_expmv_t h, float *edge_bias) {
+    if (!h || !edge_bias || !h->has_prop) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    HIP_TRY(hipMemcpyAsync(edge_bias, h->bias, sizeof(float) * (size_t)h->nnz,
+                           hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
     return MC_OK;
 }
 

@@ -123,6 +123,8 @@ def test_learned_proposal_is_unbiased():
     g = mc.MCExpmv(a.rowptr, a.col, a.val, t, 77)
     rep = g.learn_proposal(v, pilot_walkers=512, steps=100, batch=2048)
     assert np.isfinite(rep["final_loss"])
+    b = g.get_proposal().cpu().numpy()
+    assert np.isfinite(b).all() and np.abs(b).max() <= 8.0
     est, se = g.full(v, 20000)
     ref = refs.expm_v(a.to_dense(), t, v)
     z = (est.cpu().numpy() - ref) / se.cpu().numpy()
