@@ -120,35 +120,50 @@ def grid3d(m: int, seed: int, kmin: float = 0.1, kmax: float = 10.0) -> CSR:
     rng = np.random.default_rng(seed)
     kap = np.exp(rng.uniform(math.log(kmin), math.log(kmax), size=(m, m, m)))  # [z, y, x]
     n = m ** 3
-    cols = np.empty((n, 7), np.int64)
-    vals = np.zeros((n, 7), np.float64)
-    valid = np.zeros((n, 7), bool)
-    node = np.arange(n, dtype=np.int64).reshape(m, m, m)
+    # face coefficients along each axis between cell c and c+1: shape m-1 on that axis
+    faces = []
+    for ax in range(3):
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax] = slice(0, m - 1)
+        hi[ax] = slice(1, m)
+        ka, kb = kap[tuple(lo)], kap[tuple(hi)]
+        faces.append(2.0 * ka * kb / (ka + kb))
+    # per node: the seven entries in column order z-1, y-1, x-1, self, x+1, y+1, z+1
+    vals = np.zeros((m, m, m, 7))
+    valid = np.zeros((m, m, m, 7), bool)
     diag = np.zeros((m, m, m))
-    # neighbour order by column: z-1, y-1, x-1, self, x+1, y+1, z+1
-    offs = [(-1, 0, 0), (0, -1, 0), (0, 0, -1), None, (0, 0, 1), (0, 1, 0), (1, 0, 0)]
-    for k, off in enumerate(offs):
-        if off is None:
-            continue
-        dz, dy, dx = off
-        nb = np.roll(kap, shift=(-dz, -dy, -dx), axis=(0, 1, 2))
-        inside = np.ones((m, m, m), bool)
-        z, y, x = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
-        inside &= (z + dz >= 0) & (z + dz < m) & (y + dy >= 0) & (y + dy < m) & \
-                  (x + dx >= 0) & (x + dx < m)
-        face = np.where(inside, 2.0 * kap * nb / (kap + nb), kap)
-        diag -= face
-        cols[:, k] = (node + dz * m * m + dy * m + dx).reshape(-1)
-        vals[:, k] = np.where(inside, face, 0.0).reshape(-1)
-        valid[:, k] = inside.reshape(-1)
-        del nb, z, y, x, inside, face
-    cols[:, 3] = node.reshape(-1)
-    vals[:, 3] = diag.reshape(-1)
-    valid[:, 3] = True
+    slot = {(0, -1): 0, (1, -1): 1, (2, -1): 2, (2, 1): 4, (1, 1): 5, (0, 1): 6}
+    for ax in range(3):
+        f = faces[ax]
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax] = slice(0, m - 1)
+        hi[ax] = slice(1, m)
+        # neighbour at +1 along ax for cells 0..m-2, at -1 for cells 1..m-1
+        vals[tuple(lo) + (slot[(ax, 1)],)] = f
+        valid[tuple(lo) + (slot[(ax, 1)],)] = True
+        vals[tuple(hi) + (slot[(ax, -1)],)] = f
+        valid[tuple(hi) + (slot[(ax, -1)],)] = True
+        diag[tuple(lo)] -= f
+        diag[tuple(hi)] -= f
+        # boundary faces use the cell's own coefficient
+        first = [slice(None)] * 3
+        last = [slice(None)] * 3
+        first[ax] = slice(0, 1)
+        last[ax] = slice(m - 1, m)
+        diag[tuple(first)] -= kap[tuple(first)]
+        diag[tuple(last)] -= kap[tuple(last)]
+    vals[..., 3] = diag
+    valid[..., 3] = True
+    vals = vals.reshape(n, 7)
+    valid = valid.reshape(n, 7)
     counts = valid.sum(1)
     rowptr = np.zeros(n + 1, np.int64)
     np.cumsum(counts, out=rowptr[1:])
-    return CSR(rowptr, cols[valid].astype(np.int32), vals[valid])
+    offs = np.array([-m * m, -m, -1, 0, 1, m, m * m], np.int32)
+    cols = np.arange(n, dtype=np.int32)[:, None] + offs[None, :]
+    return CSR(rowptr, cols[valid], vals[valid])
 
 
 def er_graph(n: int, mean_deg: float, seed: int) -> CSR:

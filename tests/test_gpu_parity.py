@@ -338,3 +338,23 @@ def test_ba_config_full_size_sampled_parity():
     st = g.stats()
     assert st["walkers"] == w.a.n * w.nwalk
     assert st["events"] == st["walkers"] + st["jumps"]
+
+
+def test_grid3d_config_full_size_sampled_parity():
+    """3-D variable-coefficient diffusion, 256^3 (16.7M rows, 1.17e8 entries), t = 0.05,
+    full vector with 256 walkers/node in FP32 weights; sampled nodes by the oracle."""
+    w = wl.config_grid3d_full()
+    g = mc.MCExpmv(w.a.rowptr, w.a.col, w.a.val, w.t, 12759, fp32=True)
+    est, se = g.full(w.v, w.nwalk)
+    st = g.stats()
+    assert st["walkers"] == w.a.n * w.nwalk and st["events"] == st["walkers"] + st["jumps"]
+    est = est.cpu().numpy()
+    assert np.isfinite(est).all()
+    rng = np.random.default_rng(0)
+    m = 256
+    corner = [0, m - 1, m * m - 1, w.a.n - 1]
+    centre = [(m // 2) + m * ((m // 2) + m * (m // 2))]
+    sample = np.unique(np.concatenate([corner, centre, rng.choice(w.a.n, 300, replace=False)]))
+    o = Oracle(w.a.rowptr, w.a.col, w.a.val, w.t, 12759)
+    eo, _ = o.estimate(_v_for(w.v, True), sample, w.nwalk, threads=8)
+    assert _close(est[sample], eo, RTOL32)
