@@ -165,7 +165,8 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
     a.w0 = w0;
     a.chunk = kChunk;
     a.chunks = chunks;
-    a.ntasks = k * chunks;
+    a.group = trace ? 1u : group_size(nwalk);
+    a.ntasks = (k + a.group - 1) / a.group * chunks;
     a.est = est;
     a.se = se;
     a.counters = h->counters;
@@ -770,13 +771,14 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
         I.n = d.n;
         I.nwalk = d.n_walkers;
         I.chunks = (d.n_walkers + kChunk - 1) / kChunk;
+        I.group = group_size(d.n_walkers);
         I.task_begin = ntasks;
         I.part_off = part_doubles;
         I.est = d.est;
         I.se = d.stderr_;
         I.mode = d.mode;
         I.fp32 = d.weight_prec == MC_FP32;
-        ntasks += I.k * I.chunks;
+        ntasks += (I.k + I.group - 1) / I.group * I.chunks;
         b->fin_begin[i] = nfin;
         if (I.chunks > 1) {
             part_doubles += I.k * I.chunks * 3;

@@ -6,37 +6,17 @@
 // single-instance kernel).  Waves either stride through it statically or take
 // `group` consecutive tasks at a time from a global counter; which one is
 // faster depends on the mix and is left to the autotuner.  Each task runs the
-// same run_task as the single-instance kernel and writes its own outputs, so
+// same run_group as the single-instance kernel and writes its own outputs, so
 // results do not depend on the schedule and equal separate per-instance runs.
 #include "walk_task.hpp"
 
 namespace mc {
 namespace {
 
-template <int MODE, bool FP32>
-__device__ __forceinline__ TaskResult run_one(const InstArgs &P, uint32_t node, uint32_t ord0,
-                                              uint32_t cnt, uint32_t *list) {
-    TraceOut none;
-    return run_task<MODE, FP32, false, false>(P, node, ord0, cnt, none, list);
-}
-
-__device__ __forceinline__ TaskResult dispatch(const BatchInst &I, uint32_t node, uint32_t ord0,
-                                               uint32_t cnt, uint32_t *list) {
-    switch (I.mode * 2 + (I.fp32 ? 1 : 0)) {
-        case MC_EXACT * 2: return run_one<MC_EXACT, false>(I.P, node, ord0, cnt, list);
-        case MC_EXACT * 2 + 1: return run_one<MC_EXACT, true>(I.P, node, ord0, cnt, list);
-        case MC_STRANG * 2: return run_one<MC_STRANG, false>(I.P, node, ord0, cnt, list);
-        case MC_STRANG * 2 + 1: return run_one<MC_STRANG, true>(I.P, node, ord0, cnt, list);
-        case MC_LIE * 2: return run_one<MC_LIE, false>(I.P, node, ord0, cnt, list);
-        default: return run_one<MC_LIE, true>(I.P, node, ord0, cnt, list);
-    }
-}
-
-// One task of the global index space.
+// One task of the global index space: instance, then (entry group, chunk).
 __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, int64_t task,
-                                        uint32_t *list, unsigned long long &my_events,
-                                        unsigned long long &my_jumps) {
-    const int lane = threadIdx.x & (WAVE - 1);
+                                        unsigned char *lds, unsigned long long &my_events,
+                                        unsigned long long &my_jumps, uint32_t &err) {
     // instance owning this task: the last i with tb[i] <= task
     int lo = 0, hi = a.ninst - 1;
     while (lo < hi) {
@@ -46,58 +26,48 @@ __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, i
     }
     const BatchInst &I = a.inst[lo];
     const int64_t local = task - tb[lo];
-    const int64_t e = local / I.chunks;
-    const int64_t c = local - e * I.chunks;
-    const int64_t node = I.idx ? I.idx[e] : e;
-    double *part = a.part + I.part_off + (e * I.chunks + c) * 3;
-    if (node < 0 || node >= I.n) {
-        if (lane == 0) {
-            atomicOr(a.flags, F_OUT_OF_RANGE);
-            if (I.chunks == 1) {
-                I.est[e] = NAN;
-                if (I.se) I.se[e] = NAN;
-            } else {
-                part[0] = 1.0;
-                part[1] = NAN;
-                part[2] = NAN;
-            }
-        }
-        return;
-    }
+    const int64_t grp = local / I.chunks;
+    const int64_t c = local - grp * I.chunks;
+    const int64_t e_first = grp * (int64_t)I.group;
+    const int64_t left = I.k - e_first;
+    const uint32_t G = (uint32_t)(left < (int64_t)I.group ? left : (int64_t)I.group);
     const int64_t wbase = c * (int64_t)kChunkMax;
     const int64_t rem = I.nwalk - wbase;
     const uint32_t cnt = (uint32_t)(rem < (int64_t)kChunkMax ? rem : (int64_t)kChunkMax);
-    const TaskResult r = dispatch(I, (uint32_t)node, (uint32_t)wbase, cnt, list);
-    if (r.err && lane == 0) atomicOr(a.flags, r.err);
-    if (lane == 0) {
-        if (I.chunks == 1) {
-            I.est[e] = r.mean;
-            if (I.se) I.se[e] = r.n > 1.0 ? sqrt(r.m2 / (r.n - 1.0) / r.n) : 0.0;
-        } else {
-            part[0] = r.n;
-            part[1] = r.mean;
-            part[2] = r.m2;
-        }
+    const GroupOut out{I.est, I.se, a.part + I.part_off, e_first, I.chunks, c};
+    TraceOut none;
+#define MC_GROUP(MODE, FP32)                                                                     \
+    run_group<MODE, FP32, false, false>(I.P, I.idx, I.n, G, (uint32_t)wbase, cnt, none, out,     \
+                                        *reinterpret_cast<GroupLds<WeightT<FP32>::T> *>(lds),     \
+                                        my_events, my_jumps, err)
+    switch (I.mode * 2 + (I.fp32 ? 1 : 0)) {
+        case MC_EXACT * 2: MC_GROUP(MC_EXACT, false); break;
+        case MC_EXACT * 2 + 1: MC_GROUP(MC_EXACT, true); break;
+        case MC_STRANG * 2: MC_GROUP(MC_STRANG, false); break;
+        case MC_STRANG * 2 + 1: MC_GROUP(MC_STRANG, true); break;
+        case MC_LIE * 2: MC_GROUP(MC_LIE, false); break;
+        default: MC_GROUP(MC_LIE, true); break;
     }
-    my_events += r.events;
-    my_jumps += r.jumps;
+#undef MC_GROUP
 }
 
+// Dynamic LDS: one GroupLds<double> per wave (the float layout fits inside).
 __global__ __launch_bounds__(256) void k_walk_batched(BatchArgs a) {
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
     __shared__ int64_t sh_tb[kMaxBatch];
     __shared__ unsigned long long sh_count[256 / WAVE][2];
-    __shared__ uint32_t sh_list[256 / WAVE][kChunkMax];
     for (int i = threadIdx.x; i < a.ninst; i += blockDim.x) sh_tb[i] = a.inst[i].task_begin;
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x / WAVE;
-    uint32_t *list = sh_list[wave];
+    unsigned char *lds = dyn_lds + (size_t)wave * sizeof(GroupLds<double>);
     unsigned long long my_events = 0, my_jumps = 0;
+    uint32_t err = 0;
     if (a.group == 0) {
         const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
         const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
         for (int64_t task = wave_id; task < a.ntasks; task += nwaves)
-            do_task(a, sh_tb, task, list, my_events, my_jumps);
+            do_task(a, sh_tb, task, lds, my_events, my_jumps, err);
     } else {
         for (;;) {
             unsigned long long base = 0;
@@ -107,9 +77,11 @@ __global__ __launch_bounds__(256) void k_walk_batched(BatchArgs a) {
             int64_t end = (int64_t)base + a.group;
             if (end > a.ntasks) end = a.ntasks;
             for (int64_t task = (int64_t)base; task < end; ++task)
-                do_task(a, sh_tb, task, list, my_events, my_jumps);
+                do_task(a, sh_tb, task, lds, my_events, my_jumps, err);
         }
     }
+    for (int off = 1; off < WAVE; off <<= 1) err |= __shfl_xor(err, off, WAVE);
+    if (err && lane == 0) atomicOr(a.flags, err);
     if (lane == 0) {
         sh_count[wave][0] = my_events;
         sh_count[wave][1] = my_jumps;
@@ -159,7 +131,8 @@ hipError_t launch_batch(const BatchArgs &a, int block, int grid, hipStream_t s) 
         if (e != hipSuccess) return e;
     }
     if (a.ntasks > 0) {
-        hipLaunchKernelGGL(k_walk_batched, dim3((unsigned)grid), dim3(block), 0, s, a);
+        const size_t lds = (size_t)(block / WAVE) * sizeof(GroupLds<double>);
+        hipLaunchKernelGGL(k_walk_batched, dim3((unsigned)grid), dim3(block), lds, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

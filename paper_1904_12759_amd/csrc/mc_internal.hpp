@@ -94,8 +94,9 @@ struct WalkArgs {
     int64_t nwalk;             // walkers per entry
     int64_t w0;                // first walker ordinal (trace only)
     uint32_t chunk;            // walkers per task
-    int64_t chunks;            // tasks per entry
-    int64_t ntasks;
+    int64_t chunks;            // chunks per entry
+    uint32_t group;            // entries per task (1 when chunks > 1)
+    int64_t ntasks;            // ceil(k / group) * chunks
     double *est;               // [k]   (chunks == 1) final results
     double *se;                // [k] or null
     double *part;              // [k * chunks * 3] (count, mean, M2) per chunk
@@ -109,6 +110,7 @@ struct BatchInst {
     InstArgs P;
     const int64_t *idx;        // null: full vector
     int64_t k, n, nwalk, chunks;
+    uint32_t group;            // entries per task
     int64_t task_begin;        // first task of this instance in the batch
     int64_t part_off;          // offset (doubles) of its chunk partials
     double *est, *se;
@@ -131,8 +133,17 @@ struct BatchArgs {
     int64_t nfin;
 };
 
-// Walkers per task: fixes the summation order of an entry's estimate.
+// Walkers per task (an entry with more walkers is split into chunks merged in
+// chunk order), and the most entries one task may pack when they have fewer.
 constexpr uint32_t kChunkMax = 1024;
+constexpr uint32_t kGroupMax = 64;
+
+// Entries packed into one task when each has nwalk walkers.
+inline uint32_t group_size(int64_t nwalk) {
+    if (nwalk >= (int64_t)kChunkMax) return 1;
+    const int64_t g = (int64_t)kChunkMax / nwalk;
+    return (uint32_t)(g < (int64_t)kGroupMax ? g : (int64_t)kGroupMax);
+}
 
 // Largest walk grid (blocks); the per-block counter buffer has this many pairs.
 constexpr int kMaxWalkGrid = 1 << 16;

@@ -24,54 +24,35 @@ namespace {
 // Entries (or, with idx == null, every node) of one instance.  Event and
 // jump totals are reduced per block and written to counters[2*block] without
 // atomics (same-address atomics from every wave serialise across the chip).
+// Dynamic LDS: one GroupLds per wave.
 template <int MODE, bool FP32, bool PROP, bool TRACE>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
+    using WT = typename WeightT<FP32>::T;
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
     __shared__ unsigned long long sh_count[256 / WAVE][2];
-    __shared__ uint32_t sh_list[256 / WAVE][kChunkMax];
+    GroupLds<WT> &L = reinterpret_cast<GroupLds<WT> *>(dyn_lds)[threadIdx.x / WAVE];
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     unsigned long long my_events = 0, my_jumps = 0;
+    uint32_t err = 0;
     for (int64_t task = wave_id; task < a.ntasks; task += nwaves) {
-        const int64_t e = task / a.chunks;
-        const int64_t c = task - e * a.chunks;
-        const int64_t node = a.idx ? a.idx[e] : e;
-        double *part = a.part + (e * a.chunks + c) * 3;
-        if (node < 0 || node >= a.n) {
-            if (lane == 0) {
-                atomicOr(a.flags, F_OUT_OF_RANGE);
-                if (a.chunks == 1) {
-                    a.est[e] = NAN;
-                    if (a.se) a.se[e] = NAN;
-                } else {
-                    part[0] = 1.0;
-                    part[1] = NAN;
-                    part[2] = NAN;
-                }
-            }
-            continue;
-        }
+        const int64_t grp = task / a.chunks;
+        const int64_t c = task - grp * a.chunks;
+        const int64_t e_first = grp * (int64_t)a.group;
+        const int64_t left = a.k - e_first;
+        const uint32_t G = (uint32_t)(left < (int64_t)a.group ? left : (int64_t)a.group);
         const int64_t wbase = c * (int64_t)a.chunk;
         const int64_t rem = a.nwalk - wbase;
         const uint32_t cnt = (uint32_t)(rem < (int64_t)a.chunk ? rem : (int64_t)a.chunk);
         TraceOut tr = a.trace;
         tr.base = wbase;
-        const TaskResult r = run_task<MODE, FP32, PROP, TRACE>(
-            a.P, (uint32_t)node, (uint32_t)(a.w0 + wbase), cnt, tr, sh_list[threadIdx.x / WAVE]);
-        if (r.err && lane == 0) atomicOr(a.flags, r.err);
-        if (lane == 0) {
-            if (a.chunks == 1) {
-                a.est[e] = r.mean;
-                if (a.se) a.se[e] = r.n > 1.0 ? sqrt(r.m2 / (r.n - 1.0) / r.n) : 0.0;
-            } else {
-                part[0] = r.n;
-                part[1] = r.mean;
-                part[2] = r.m2;
-            }
-        }
-        my_events += r.events;
-        my_jumps += r.jumps;
+        const GroupOut out{a.est, a.se, a.part, e_first, a.chunks, c};
+        run_group<MODE, FP32, PROP, TRACE>(a.P, a.idx, a.n, G, (uint32_t)(a.w0 + wbase), cnt, tr,
+                                           out, L, my_events, my_jumps, err);
     }
+    for (int off = 1; off < WAVE; off <<= 1) err |= __shfl_xor(err, off, WAVE);
+    if (err && lane == 0) atomicOr(a.flags, err);
     const int wave = threadIdx.x / WAVE;
     if (lane == 0) {
         sh_count[wave][0] = my_events;
@@ -115,8 +96,9 @@ int walk_grid(int64_t ntasks, int block) {
 
 template <int MODE, bool FP32, bool PROP, bool TRACE>
 hipError_t launch_t(const WalkArgs &a, int block, hipStream_t s) {
+    const size_t lds = (size_t)(block / WAVE) * sizeof(GroupLds<typename WeightT<FP32>::T>);
     hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE>), dim3((unsigned)walk_grid(a.ntasks, block)),
-                       dim3(block), 0, s, a);
+                       dim3(block), lds, s, a);
     return hipGetLastError();
 }
 

@@ -164,60 +164,116 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
 using namespace detail;
 
 // ----------------------------------------------------------- one task
-// Runs walkers ord0 .. ord0+cnt-1 from `node` on the calling wavefront and
-// leaves, in every lane, the wave's (count, mean, M2) of W * v[X_t] plus the
-// event and jump totals.  All lanes of the wave must call it together.
-// `list` is this wave's LDS scratch of at least cnt words.
+// Per-wave LDS scratch of run_group.
+template <typename WT>
+struct GroupLds {
+    uint32_t list[kChunkMax];     // jumpers: (entry << 16) | ordinal, entry-major, ordinal order
+    WT fval[kChunkMax];           // W v[X_t] of list[i]
+    uint32_t node[kGroupMax];     // start node of each entry (UINT32_MAX: out of range)
+    uint32_t n0[kGroupMax];       // walkers of each entry that never jump
+    uint32_t seg[kGroupMax + 1];  // entry g's jumpers are list[seg[g] .. seg[g+1])
+    double K[kGroupMax];          // value of a walker that never leaves the start node
+};
+
+// Where a task's per-entry results go: entry e_first + g, chunk c of `chunks`.
+struct GroupOut {
+    double *est, *se, *part;
+    int64_t e_first, chunks, c;
+};
+
+__device__ __forceinline__ double wave_sum_f64(double x) {
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) x += __shfl_xor(x, off, WAVE);
+    return x;
+}
+
+// Runs walkers ord0 .. ord0+cnt-1 of G entries on the calling wavefront and
+// writes each entry's estimate (or its chunk's (count, mean, M2)).  All lanes
+// of the wave call it together; lds is this wave's scratch.
 //
-// Two phases.  When a walker's first holding time outlasts t with fair
-// probability (e^{-r t} >= 1/8), phase 1 draws only the first event of every
-// walker: those that stay return exactly K (the no-jump value), so they are
-// counted as one group (n0, K, 0); the ordinals of the others are compacted
-// into `list`.  Phase 2 runs the complete walk, with lane refill, on the
-// listed walkers only (their first event is drawn again from the same
-// counter), so the rarely needed logarithm, jump and exp code runs on lanes
-// that need it instead of masked lanes of a mostly idle wave.
+// Phase 1 draws only the first event of every walker of the entries whose
+// no-jump probability e^{-r t} is at least 1/8: a walker with U below
+// e^{-rt}(1 - 2^-40) certainly holds past t (-log(U)/r > t + 2^-40/r, far
+// beyond the logarithm's rounding) and returns exactly K, so only a count is
+// kept; the others are appended to a list, as are all walkers of the other
+// entries.  Phase 2 runs the complete walk for the listed walkers with lane
+// refill (their first event drawn again from the same counter), so the rarely
+// needed logarithm, jump and exp code runs on lanes that need it.  Every
+// finished walker writes its value to the slot of its list position, and each
+// entry's mean and M2 come from a two-pass reduction over its slots in a fixed
+// order plus its n0 copies of K: the result does not depend on which lane ran
+// which walker, nor on how many entries share the task.
 template <int MODE, bool FP32, bool PROP, bool TRACE>
-__device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node, uint32_t ord0,
-                                               uint32_t cnt, const TraceOut &tr,
-                                               uint32_t *list) {
+__device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx, int64_t n,
+                                          uint32_t G, uint32_t ord0, uint32_t cnt,
+                                          const TraceOut &tr, const GroupOut &out,
+                                          GroupLds<typename WeightT<FP32>::T> &L,
+                                          unsigned long long &my_events,
+                                          unsigned long long &my_jumps, uint32_t &err_out) {
     using WT = typename WeightT<FP32>::T;
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned long long lanemask_lt = (1ull << lane) - 1ull;
     const double t = P.t;
+    uint32_t err = 0;
 
-    // start row: the same for every walker of the task
-    const RowRec r0 = P.rows[node];
-    const WT d0 = load_d<FP32>(P, node);
-    const WT v0 = load_v<FP32>(P.v, node);
-    // K: the value of a walker that never leaves the start node
-    const double K = (double)(wexp<FP32>(final_term<MODE, FP32>(d0, 0.0, 0, P)) * v0);
-    // U below e0 means the first holding time certainly outlasts t: then
-    // -log(U)/r0 > t + 2^-40/r0, far beyond the rounding of the log-based test.
-    const double e0 = r0.deg ? exp(-t / r0.inv_r) * (1.0 - 0x1p-40) : 0.0;
-
-    uint32_t n0 = 0;              // walkers that never jump (value K), wave-uniform
-    unsigned long long evs = 0, jus = 0;
-    uint32_t todo = cnt;          // walkers for phase 2
-    bool use_list = false;
-    if (r0.deg == 0) {
-        // no exit rate at the start: every walker holds until t
-        n0 = cnt;
-        todo = 0;
-        if (lane == 0) evs = cnt;
-        if constexpr (TRACE) {
-            for (uint32_t w = lane; w < cnt; w += WAVE) {
-                tr.x[tr.base + w] = (int32_t)node;
-                tr.ev[tr.base + w] = 1;
-                tr.ju[tr.base + w] = 0;
-                tr.f[tr.base + w] = K;
-            }
+    // ---- per-entry setup, one lane per entry
+    double e0 = 0.0;
+    if (lane < (int)G) {
+        const int64_t e = out.e_first + lane;
+        const int64_t nd = idx ? idx[e] : e;
+        uint32_t node = 0xFFFFFFFFu;
+        double K = 0.0;
+        if (nd >= 0 && nd < n) {
+            node = (uint32_t)nd;
+            const RowRec r0 = P.rows[node];
+            const WT d0 = load_d<FP32>(P, node);
+            const WT v0 = load_v<FP32>(P.v, node);
+            K = (double)(wexp<FP32>(final_term<MODE, FP32>(d0, 0.0, 0, P)) * v0);
+            e0 = r0.deg ? exp(-t / r0.inv_r) * (1.0 - 0x1p-40) : 2.0;   // 2: never jumps
+        } else {
+            err |= F_OUT_OF_RANGE;
         }
-    } else if (e0 >= 0.125) {
-        use_list = true;
-        uint32_t nlist = 0;
-        // U >= e0  <=>  m + 1 >= e0 * 2^53 (exact: U = (m+1) 2^-53), i.e. m + 1 >= ceil(e0 2^53)
-        const uint64_t m_thr = (uint64_t)ceil(e0 * 0x1p53);
+        L.node[lane] = node;
+        L.K[lane] = K;
+        L.n0[lane] = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // ---- phase 1: first events, compaction of the walkers that may jump
+    uint32_t nlist = 0;
+    unsigned long long evs = 0, jus = 0;
+    for (uint32_t g = 0; g < G; ++g) {
+        const uint32_t node = L.node[g];
+        const double eg = __shfl(e0, (int)g, WAVE);
+        if (lane == 0) L.seg[g] = nlist;
+        if (node == 0xFFFFFFFFu) continue;
+        if (eg >= 1.5) {
+            // no exit rate: every walker holds until t, one holding interval each
+            if (lane == 0) {
+                L.n0[g] = cnt;
+                evs += cnt;
+            }
+            if constexpr (TRACE) {
+                for (uint32_t w = lane; w < cnt; w += WAVE) {
+                    tr.x[tr.base + w] = (int32_t)node;
+                    tr.ev[tr.base + w] = 1;
+                    tr.ju[tr.base + w] = 0;
+                    tr.f[tr.base + w] = L.K[g];
+                }
+            }
+            continue;
+        }
+        if (eg < 0.125) {
+            // most walkers leave: list them all
+            for (uint32_t w = lane; w < cnt; w += WAVE) L.list[nlist + w] = (g << 16) | w;
+            nlist += cnt;
+            continue;
+        }
+        // U >= e0  <=>  m + 1 >= e0 2^53 (U = (m+1) 2^-53 exactly), i.e. m + 1 >= ceil(e0 2^53)
+        const uint64_t m_thr = (uint64_t)ceil(eg * 0x1p53);
+        uint32_t stay = 0;
         for (uint32_t b = 0; b < cnt; b += WAVE) {
             const uint32_t w = b + (uint32_t)lane;
             const bool valid = w < cnt;
@@ -228,44 +284,49 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
                 go = m + 1ull >= m_thr;
             }
             const unsigned long long gmask = __ballot(go);
-            const unsigned long long smask = __ballot(valid && !go);
-            if (go) list[nlist + (uint32_t)__popcll(gmask & lanemask_lt)] = w;
+            if (go) L.list[nlist + (uint32_t)__popcll(gmask & lanemask_lt)] = (g << 16) | w;
             nlist += (uint32_t)__popcll(gmask);
-            n0 += (uint32_t)__popcll(smask);
+            stay += (uint32_t)__popcll(__ballot(valid && !go));
             if constexpr (TRACE) {
                 if (valid && !go) {
                     tr.x[tr.base + w] = (int32_t)node;
                     tr.ev[tr.base + w] = 1;
                     tr.ju[tr.base + w] = 0;
-                    tr.f[tr.base + w] = K;
+                    tr.f[tr.base + w] = L.K[g];
                 }
             }
         }
-        if (lane == 0) evs = n0;
-        todo = nlist;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane == 0) {
+            L.n0[g] = stay;
+            evs += stay;
+        }
     }
+    if (lane == 0) L.seg[G] = nlist;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // ---- phase 2: full walks with lane refill over `todo` walkers
+    // ---- phase 2: full walks with lane refill over the list
     uint32_t wl = (uint32_t)lane;
-    bool active = wl < todo;
-    uint32_t ow = 0;              // walker ordinal within the task
-    if (active) ow = use_list ? list[wl] : wl;
+    bool active = wl < nlist;
+    uint32_t code = active ? L.list[wl] : 0u;
+    uint32_t node = active ? L.node[code >> 16] : 0u;
     uint32_t x = node;
     double s = 0.0;
     WT logw = (WT)0;
     uint32_t ev = 0, ju = 0;
     int32_t ka = 0;
-    double inv_r = r0.inv_r;
-    uint32_t deg = r0.deg, begin = r0.begin;
-    WT dx = d0;
-
-    uint32_t nl = 0;
-    double kl = 0.0, s1 = 0.0, s2 = 0.0;
+    double inv_r = 0.0;
+    uint32_t deg = 0, begin = 0;
+    WT dx = (WT)0;
+    if (active) {
+        const RowRec rr = P.rows[x];
+        inv_r = rr.inv_r;
+        deg = rr.deg;
+        begin = rr.begin;
+        dx = load_d<FP32>(P, x);
+    }
     uint32_t next = WAVE;
-    uint32_t err = 0;
 
     while (__ballot(active) != 0ull) {
         bool fin = false;
@@ -277,18 +338,13 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
                 err |= F_WALK_LIMIT;
                 fin = true;
             } else {
-                const U4 o = philox(ev, ord0 + ow, node, P.inst, P.key0, P.key1);
+                const U4 o = philox(ev, ord0 + (code & 0xFFFFu), node, P.inst, P.key0, P.key1);
                 ++ev;
                 const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
                 const double U = (double)(m + 1ull) * 0x1p-53;
-                bool jump = false;
-                double S = 0.0, sn = 0.0;
-                if (ju != 0 || U >= e0) {
-                    S = -log_unit(U) * inv_r;
-                    sn = s + S;
-                    jump = sn < t;
-                }
-                if (jump) {
+                const double S = -log_unit(U) * inv_r;
+                const double sn = s + S;
+                if (sn < t) {
                     if constexpr (MODE == MC_EXACT) {
                         logw = logw + dx * (WT)S;
                     } else {
@@ -317,84 +373,97 @@ __device__ __forceinline__ TaskResult run_task(const InstArgs &P, uint32_t node,
                 }
             }
             if (fin) {
-                double f = K;            // never left the start node
-                if (ju != 0) {
+                WT f;
+                if (ju == 0) {
+                    f = (WT)L.K[code >> 16];         // never left the start node
+                } else {
                     logw = logw + final_term<MODE, FP32>(dx, s, ka, P);
-                    f = (double)(wexp<FP32>(logw) * load_v<FP32>(P.v, x));
-                    if (!isfinite(f)) err |= F_OVERFLOW;
+                    f = wexp<FP32>(logw) * load_v<FP32>(P.v, x);
+                    if (!isfinite((double)f)) err |= F_OVERFLOW;
                 }
-                if (nl == 0) kl = f;
-                const double df = f - kl;
-                s1 += df;
-                s2 += df * df;
-                ++nl;
+                L.fval[wl] = f;
                 evs += ev;
                 jus += ju;
                 if constexpr (TRACE) {
-                    const int64_t ti = tr.base + ow;
+                    const int64_t ti = tr.base + (code & 0xFFFFu);
                     tr.x[ti] = (int32_t)x;
                     tr.ev[ti] = ev;
                     tr.ju[ti] = ju;
-                    tr.f[ti] = f;
+                    tr.f[ti] = (double)f;
                 }
             }
         }
         const unsigned long long fmask = __ballot(fin);
         if (fin) {
             wl = next + (uint32_t)__popcll(fmask & lanemask_lt);
-            if (wl < todo) {
-                ow = use_list ? list[wl] : wl;
+            if (wl < nlist) {
+                code = L.list[wl];
+                node = L.node[code >> 16];
                 x = node;
                 s = 0.0;
                 logw = (WT)0;
                 ev = 0;
                 ju = 0;
                 ka = 0;
-                inv_r = r0.inv_r;
-                deg = r0.deg;
-                begin = r0.begin;
-                dx = d0;
+                const RowRec rr = P.rows[x];
+                inv_r = rr.inv_r;
+                deg = rr.deg;
+                begin = rr.begin;
+                dx = load_d<FP32>(P, x);
             } else {
                 active = false;
             }
         }
         next += (uint32_t)__popcll(fmask);
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // lane -> (count, mean, M2), then pairwise across the wave
-    double n = (double)nl, mean = 0.0, q = 0.0;
-    if (nl) {
-        mean = kl + s1 / n;
-        q = s2 - s1 * (s1 / n);
-        if (q < 0.0) q = 0.0;
-    }
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-        const double nb = __shfl_xor(n, off, WAVE);
-        const double mb = __shfl_xor(mean, off, WAVE);
-        const double qb = __shfl_xor(q, off, WAVE);
-        // both lanes of a pair merge (lower, upper) in that order
-        if (lane & off) {
-            double n2 = nb, m2 = mb, q2 = qb;
-            chan_merge(n2, m2, q2, n, mean, q);
-            n = n2;
-            mean = m2;
-            q = q2;
+    // ---- per-entry statistics: slots in a fixed order, plus n0 copies of K
+    for (uint32_t g = 0; g < G; ++g) {
+        const int64_t e = out.e_first + g;
+        const uint32_t b0 = L.seg[g], b1 = L.seg[g + 1];
+        double mean, m2, count;
+        if (L.node[g] == 0xFFFFFFFFu) {
+            mean = NAN;
+            m2 = NAN;
+            count = 1.0;
         } else {
-            chan_merge(n, mean, q, nb, mb, qb);
+            const double K = L.K[g];
+            const double nn0 = (double)L.n0[g];
+            count = (double)cnt;
+            // lanes stride from the segment start, so the summation tree depends only on
+            // the entry's own walkers
+            const uint32_t J = b1 - b0;
+            double s1 = 0.0;
+            for (uint32_t i = lane; i < J; i += WAVE) s1 += (double)L.fval[b0 + i];
+            s1 = wave_sum_f64(s1);
+            mean = (nn0 * K + s1) / count;
+            double s2 = 0.0;
+            for (uint32_t i = lane; i < J; i += WAVE) {
+                const double dv = (double)L.fval[b0 + i] - mean;
+                s2 += dv * dv;
+            }
+            s2 = wave_sum_f64(s2);
+            const double dk = K - mean;
+            m2 = s2 + nn0 * dk * dk;
+        }
+        if (lane == 0) {
+            if (out.chunks == 1) {
+                out.est[e] = mean;
+                if (out.se) out.se[e] = count > 1.0 ? sqrt(m2 / (count - 1.0) / count) : 0.0;
+            } else {
+                double *pp = out.part + (e * out.chunks + out.c) * 3;
+                pp[0] = count;
+                pp[1] = mean;
+                pp[2] = m2;
+            }
         }
     }
-    // the walkers that never jumped: n0 copies of K
-    double nn = (double)n0, mm = K, qq = 0.0;
-    chan_merge(nn, mm, qq, n, mean, q);
-    TaskResult res;
-    res.n = nn;
-    res.mean = mm;
-    res.m2 = qq;
-    res.events = wave_sum_u64(evs);
-    res.jumps = wave_sum_u64(jus);
-    res.err = err;
-    return res;
+    my_events += wave_sum_u64(evs);
+    my_jumps += wave_sum_u64(jus);
+    err_out |= err;
 }
 
 }  // namespace mc
