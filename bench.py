@@ -138,6 +138,33 @@ def bench_grid2d_entries(mc, seed):
     return r
 
 
+def bench_locality(mc, w, seed, steps=10):
+    """Kernel time of the benchmark workload with the rows in input order, relabelled
+    hot-first (descending exit rate), and relabelled with the hottest rows staged in
+    LDS.  All variants give bitwise identical results."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    v = torch.as_tensor(w.v, dtype=torch.float32, device=dev)
+    est = torch.empty(w.a.n, dtype=torch.float64, device=dev)
+    se = torch.empty(w.a.n, dtype=torch.float64, device=dev)
+    out = {}
+    ref = None
+    for name, relabel, lds in (("input_order", 0, 0), ("relabel", 1, 0),
+                               ("relabel_lds16k", 1, 16384), ("relabel_lds64k", 1, 65536)):
+        h = mc.MCExpmv(w.a.rowptr, w.a.col, w.a.val, w.t, seed, fp32=True, relabel=relabel,
+                       lds_budget=lds)
+        h.full(v, w.nwalk, est=est, stderr=se)
+        ms = []
+        for _ in range(steps):
+            h.full(v, w.nwalk, est=est, stderr=se)
+            ms.append(h.stats()["ms"])
+        if ref is None:
+            ref = est.clone()
+        out[name] = dict(kernel_ms=float(np.median(ms)), identical=bool(torch.equal(est, ref)))
+        del h
+    return out
+
+
 def bench_grid3d(mc, seed, m=256, steps=5):
     """3-D variable-coefficient diffusion 256^3, t = 0.05, full vector with 256
     walkers per node (4.3e9 walkers), FP32 weights: walker-steps/s and roofline."""
@@ -349,6 +376,8 @@ def main():
         },
     }
     if not args.no_extras:
+        log("bench: locality variants")
+        out["locality"] = bench_locality(mc, w, args.seed)
         log("bench: entries/s at 1e-3 (grid2d)")
         out["entries_at_1e3"] = bench_grid2d_entries(mc, args.seed)
         log("bench: learned vs plain (BA n=1e6 m=4)")

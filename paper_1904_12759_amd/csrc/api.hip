@@ -36,6 +36,9 @@ struct mc_expmv_s {
     uint64_t last_walkers = 0;
     int last_grid = 0;
     int32_t *rowof = nullptr;            // row of each CSR position (learned proposal)
+    uint32_t *perm = nullptr;            // relabel: original node -> walk id
+    uint32_t *inv = nullptr;             // relabel: walk id -> original node
+    uint32_t hot = 0;                    // walk ids staged in LDS (lds_budget)
     float *bias = nullptr;               // copy of the installed proposal's edge biases
     bool last_fp32 = false, last_prop = false;
 };
@@ -79,6 +82,9 @@ void free_tables(Tables &tb) {
     (void)hipFree(tb.r);
     (void)hipFree(tb.slots);
     (void)hipFree(tb.corr);
+    (void)hipFree(tb.wrows);
+    (void)hipFree(tb.wd64);
+    (void)hipFree(tb.wd32);
     tb = Tables{};
 }
 
@@ -91,6 +97,40 @@ hipError_t alloc_tables(Tables &tb, int64_t n, int64_t nnz, bool with_corr) {
     if ((e = dalloc(&tb.slots, nnz)) != hipSuccess) return e;
     if (with_corr && (e = dalloc(&tb.corr, nnz)) != hipSuccess) return e;
     return hipSuccess;
+}
+
+// Walk-order copies of a table set under the handle's permutation; with
+// build == true the permutation itself is computed first (descending r).
+mc_status relabel_tables(mc_expmv_s *h, Tables &tb, bool build) {
+    const int64_t n = h->n;
+    hipError_t e = dalloc(&tb.wrows, n);
+    if (e == hipSuccess) e = dalloc(&tb.wd64, n);
+    if (e == hipSuccess) e = dalloc(&tb.wd32, n);
+    if (e != hipSuccess) return from_hip(e);
+    if (build) {
+        unsigned long long *kin = nullptr, *kout = nullptr;
+        uint32_t *vin = nullptr;
+        void *tmp = nullptr;
+        size_t tmp_bytes = 0;
+        e = dalloc(&h->perm, n);
+        if (e == hipSuccess) e = dalloc(&h->inv, n);
+        if (e == hipSuccess) e = dalloc(&kin, n);
+        if (e == hipSuccess) e = dalloc(&kout, n);
+        if (e == hipSuccess) e = dalloc(&vin, n);
+        if (e == hipSuccess) e = launch_relabel_keys(n, tb.r, kin, vin, h->stream);
+        if (e == hipSuccess) e = sort_pairs_u64(nullptr, tmp_bytes, kin, kout, vin, h->inv, n, h->stream);
+        if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
+        if (e == hipSuccess) e = sort_pairs_u64(tmp, tmp_bytes, kin, kout, vin, h->inv, n, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        (void)hipFree(kin);
+        (void)hipFree(kout);
+        (void)hipFree(vin);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return from_hip(e);
+    }
+    e = launch_relabel_apply(n, h->rowptr, h->inv, h->perm, tb, build, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return from_hip(e);
 }
 
 // Build one table set from the handle's copy of A (bias == null: plain).
@@ -125,17 +165,24 @@ mc_status check_opts(const mc_expmv_opts &o) {
     if (b != 64 && b != 128 && b != 256) return MC_ERR_INVALID_ARG;
     if (o.resort_period != 0) return MC_ERR_INVALID_ARG;
     if (o.relabel != 0 && o.relabel != 1) return MC_ERR_INVALID_ARG;
+    if (o.lds_budget != 0 && (!o.relabel || o.lds_budget > kMaxHotBytes)) return MC_ERR_INVALID_ARG;
     return MC_OK;
 }
 
 void fill_inst(const mc_expmv_s *h, const void *v, bool prop, InstArgs &P) {
     const Tables &tb = prop ? h->prop : h->plain;
-    P.rows = tb.rows;
-    P.d64 = tb.d64;
-    P.d32 = tb.d32;
+    const bool rl = h->perm != nullptr;
+    P.rows = rl ? tb.wrows : tb.rows;
+    P.d64 = rl ? tb.wd64 : tb.d64;
+    P.d32 = rl ? tb.wd32 : tb.d32;
     P.slots = tb.slots;
     P.corr = prop ? tb.corr : nullptr;
     P.v = v;
+    P.perm = h->perm;
+    P.inv = h->inv;
+    P.hot = h->hot;
+    P.lrows = nullptr;
+    P.ld = nullptr;
     P.t = h->t;
     P.dt = h->dt;
     P.inv_dt = h->inv_dt;
@@ -252,6 +299,8 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->part);
     (void)hipFree(h->rowof);
     (void)hipFree(h->bias);
+    (void)hipFree(h->perm);
+    (void)hipFree(h->inv);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
@@ -329,9 +378,16 @@ mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t
     }
     CREATE_TRY(alloc_tables(h->plain, n, nnz, false));
     st = build_tables(h, nullptr, h->plain);
+    if (st == MC_OK && o.relabel) st = relabel_tables(h, h->plain, true);
     if (st != MC_OK) {
         mc_expmv_destroy(h);
         return st;
+    }
+    if (o.lds_budget) {
+        const uint32_t per_row = (uint32_t)sizeof(RowRec) +
+                                 (o.weight_prec == MC_FP32 ? (uint32_t)sizeof(float) : (uint32_t)sizeof(double));
+        const int64_t hot = o.lds_budget / per_row;
+        h->hot = (uint32_t)(hot < n ? hot : n);
     }
     // number of jump slots
     {
@@ -400,6 +456,7 @@ mc_status mc_expmv_set_proposal(mc_expmv_t h, const float *edge_bias) {
     if (h->opts.mode != MC_EXACT) return MC_ERR_INVALID_ARG;
     HIP_TRY(alloc_tables(h->prop, h->n, h->nnz, true));
     mc_status st = build_tables(h, edge_bias, h->prop);
+    if (st == MC_OK && h->perm) st = relabel_tables(h, h->prop, false);
     if (st != MC_OK) {
         free_tables(h->prop);
         return st;
@@ -490,6 +547,12 @@ mc_status mc_expmv_get_tables(mc_expmv_t h, int32_t use_proposal, double *r, dou
     if (h->nnz > 0)
         HIP_TRY(hipMemcpy(sl.data(), tb.slots, sizeof(SlotRec) * (size_t)h->nnz,
                           hipMemcpyDeviceToHost));
+    std::vector<uint32_t> inv;
+    if (h->inv) {
+        inv.resize(n);
+        HIP_TRY(hipMemcpy(inv.data(), h->inv, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+    }
+    auto orig = [&](int32_t c) { return h->inv ? (int32_t)inv[(size_t)c] : c; };
     int64_t pos = 0;
     for (size_t i = 0; i < n; ++i) {
         if (r) r[i] = rr[i];
@@ -499,9 +562,9 @@ mc_status mc_expmv_get_tables(mc_expmv_t h, int32_t use_proposal, double *r, dou
         if (begin) begin[i] = pos;
         for (uint32_t s = 0; s < rows[i].deg; ++s) {
             const SlotRec &q = sl[rows[i].begin + s];
-            if (col) col[pos] = q.self;
+            if (col) col[pos] = orig(q.self);
             if (thr) thr[pos] = q.thr;
-            if (alias) alias[pos] = q.alias;
+            if (alias) alias[pos] = orig(q.alias);
             ++pos;
         }
     }

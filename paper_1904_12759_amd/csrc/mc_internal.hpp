@@ -37,6 +37,11 @@ struct Tables {
     double *r = nullptr;       // [n] exit rate r_x (setup and export only)
     SlotRec *slots = nullptr;  // [nnz]: row x uses slots rowptr[x] .. rowptr[x]+deg-1
     float2 *corr = nullptr;    // [nnz] proposal only: (-b_self, -b_alias) per slot
+    // relabelled walk order (only with relabel): row/d of new id k = those of row
+    // inv[k]; slot columns then hold new ids
+    RowRec *wrows = nullptr;
+    double *wd64 = nullptr;
+    float *wd32 = nullptr;
 };
 
 // Error flags latched on the device (bit i = status code i).
@@ -63,6 +68,11 @@ struct InstArgs {
     const SlotRec *slots;
     const float2 *corr;        // non-null only for the tilted walk
     const void *v;             // double* (FP64 weights) or float* (FP32 weights)
+    const uint32_t *perm;      // relabel: original node -> walk id (null: identity)
+    const uint32_t *inv;       // relabel: walk id -> original node (null: identity)
+    uint32_t hot;              // walk ids < hot have their row and d staged in LDS
+    const RowRec *lrows;       // LDS copy of rows[0 .. hot) (set inside the kernel)
+    const void *ld;            // LDS copy of d[0 .. hot)
     double t;
     double dt;                 // t / N
     double inv_dt;             // N / t
@@ -137,6 +147,8 @@ struct BatchArgs {
 // chunk order), and the most entries one task may pack when they have fewer.
 constexpr uint32_t kChunkMax = 1024;
 constexpr uint32_t kGroupMax = 64;
+// Largest LDS budget for hot rows (bytes per block).
+constexpr uint32_t kMaxHotBytes = 65536;
 
 // Entries packed into one task when each has nwalk walkers.
 inline uint32_t group_size(int64_t nwalk) {
@@ -181,6 +193,15 @@ hipError_t launch_adam(const float *grad, float *w, float *m, float *v, uint16_t
 hipError_t launch_mlp_init(float *w, float *m, float *v, uint16_t *wbf, uint64_t seed,
                            hipStream_t s);
 hipError_t launch_params_bf16(const float *w, uint16_t *wbf, hipStream_t s);
+
+// relabelling (setup.hip): hot rows (largest exit rate) first
+hipError_t launch_relabel_keys(int64_t n, const double *r, unsigned long long *keys, uint32_t *vals,
+                               hipStream_t s);
+hipError_t launch_relabel_apply(int64_t n, const int64_t *rowptr, const uint32_t *inv,
+                                uint32_t *perm, Tables &tb, bool build_perm, hipStream_t s);
+hipError_t sort_pairs_u64(void *temp, size_t &temp_bytes, const unsigned long long *kin,
+                          unsigned long long *kout, const uint32_t *vin, uint32_t *vout, int64_t n,
+                          hipStream_t s);
 
 // setup kernels (setup.hip)
 hipError_t launch_check_rowptr(int64_t n, int64_t nnz, const int64_t *rowptr, uint32_t *flags,

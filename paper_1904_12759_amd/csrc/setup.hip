@@ -4,6 +4,8 @@
 // one gather instead of the row scan discussed in Sec. 4.
 #include <math.h>
 
+#include <hipcub/hipcub.hpp>
+
 #include "mc_internal.hpp"
 
 namespace mc {
@@ -131,7 +133,79 @@ __global__ void k_setup_rows(int64_t n, const int64_t *__restrict__ rowptr,
     }
 }
 
+// Relabelling: sort key ~bits(r_i) orders rows by descending exit rate (the
+// bit pattern of a non-negative double is monotone in its value); the radix
+// sort is stable, so equal rates keep index order.
+__global__ void k_relabel_keys(int64_t n, const double *__restrict__ r,
+                               unsigned long long *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = ~(unsigned long long)__double_as_longlong(r[i]);
+    vals[i] = (uint32_t)i;
+}
+
+__global__ void k_relabel_perm(int64_t n, const uint32_t *__restrict__ inv, uint32_t *__restrict__ perm) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) perm[inv[k]] = (uint32_t)k;
+}
+
+// Walk-order copies of the row records and weight exponents.
+__global__ void k_relabel_rows(int64_t n, const uint32_t *__restrict__ inv,
+                               const RowRec *__restrict__ rows, const double *__restrict__ d64,
+                               const float *__restrict__ d32, RowRec *__restrict__ wrows,
+                               double *__restrict__ wd64, float *__restrict__ wd32) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t i = inv[k];
+    wrows[k] = rows[i];
+    wd64[k] = d64[i];
+    wd32[k] = d32[i];
+}
+
+// Rename the columns held in row i's slots (one thread per original row; only
+// the deg slots in use are touched).
+__global__ void k_relabel_slots(int64_t n, const int64_t *__restrict__ rowptr,
+                                const RowRec *__restrict__ rows, const uint32_t *__restrict__ perm,
+                                SlotRec *__restrict__ slots) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t p0 = rowptr[i];
+    const uint32_t deg = rows[i].deg;
+    for (uint32_t s = 0; s < deg; ++s) {
+        SlotRec q = slots[p0 + s];
+        q.self = (int32_t)perm[q.self];
+        q.alias = (int32_t)perm[q.alias];
+        slots[p0 + s] = q;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_relabel_keys(int64_t n, const double *r, unsigned long long *keys, uint32_t *vals,
+                               hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_relabel_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, r, keys,
+                       vals);
+    return hipGetLastError();
+}
+
+hipError_t sort_pairs_u64(void *temp, size_t &temp_bytes, const unsigned long long *kin,
+                          unsigned long long *kout, const uint32_t *vin, uint32_t *vout, int64_t n,
+                          hipStream_t s) {
+    return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, kin, kout, vin, vout, (int)n, 0, 64,
+                                              s);
+}
+
+hipError_t launch_relabel_apply(int64_t n, const int64_t *rowptr, const uint32_t *inv,
+                                uint32_t *perm, Tables &tb, bool build_perm, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (build_perm) hipLaunchKernelGGL(k_relabel_perm, dim3(g), dim3(256), 0, s, n, inv, perm);
+    hipLaunchKernelGGL(k_relabel_rows, dim3(g), dim3(256), 0, s, n, inv, tb.rows, tb.d64, tb.d32,
+                       tb.wrows, tb.wd64, tb.wd32);
+    hipLaunchKernelGGL(k_relabel_slots, dim3(g), dim3(256), 0, s, n, rowptr, tb.rows, perm, tb.slots);
+    return hipGetLastError();
+}
 
 hipError_t launch_check_rowptr(int64_t n, int64_t nnz, const int64_t *rowptr, uint32_t *flags,
                                hipStream_t s) {

@@ -25,12 +25,27 @@ namespace {
 // jump totals are reduced per block and written to counters[2*block] without
 // atomics (same-address atomics from every wave serialise across the chip).
 // Dynamic LDS: one GroupLds per wave.
-template <int MODE, bool FP32, bool PROP, bool TRACE>
+template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     using WT = typename WeightT<FP32>::T;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     __shared__ unsigned long long sh_count[256 / WAVE][2];
+    const int nw = blockDim.x / WAVE;
     GroupLds<WT> &L = reinterpret_cast<GroupLds<WT> *>(dyn_lds)[threadIdx.x / WAVE];
+    // hot rows: LDS copies of rows[0 .. hot) and d[0 .. hot) after the wave scratch
+    InstArgs P = a.P;
+    if (LOC && P.hot) {
+        RowRec *lr = reinterpret_cast<RowRec *>(dyn_lds + nw * sizeof(GroupLds<WT>));
+        WT *ld = reinterpret_cast<WT *>(lr + P.hot);
+        const WT *gd = FP32 ? (const WT *)(const void *)a.P.d32 : (const WT *)(const void *)a.P.d64;
+        for (uint32_t k = threadIdx.x; k < P.hot; k += blockDim.x) {
+            lr[k] = a.P.rows[k];
+            ld[k] = gd[k];
+        }
+        __syncthreads();
+        P.lrows = lr;
+        P.ld = ld;
+    }
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
@@ -48,7 +63,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
         TraceOut tr = a.trace;
         tr.base = wbase;
         const GroupOut out{a.est, a.se, a.part, e_first, a.chunks, c};
-        run_group<MODE, FP32, PROP, TRACE>(a.P, a.idx, a.n, G, (uint32_t)(a.w0 + wbase), cnt, tr,
+        run_group<MODE, FP32, PROP, TRACE, LOC>(P, a.idx, a.n, G, (uint32_t)(a.w0 + wbase), cnt, tr,
                                            out, L, my_events, my_jumps, err);
     }
     for (int off = 1; off < WAVE; off <<= 1) err |= __shfl_xor(err, off, WAVE);
@@ -96,9 +111,14 @@ int walk_grid(int64_t ntasks, int block) {
 
 template <int MODE, bool FP32, bool PROP, bool TRACE>
 hipError_t launch_t(const WalkArgs &a, int block, hipStream_t s) {
-    const size_t lds = (size_t)(block / WAVE) * sizeof(GroupLds<typename WeightT<FP32>::T>);
-    hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE>), dim3((unsigned)walk_grid(a.ntasks, block)),
-                       dim3(block), lds, s, a);
+    using WT = typename WeightT<FP32>::T;
+    const size_t lds = (size_t)(block / WAVE) * sizeof(GroupLds<WT>) +
+                       (size_t)a.P.hot * (sizeof(RowRec) + sizeof(WT));
+    const dim3 grid((unsigned)walk_grid(a.ntasks, block));
+    if (a.P.perm)
+        hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true>), grid, dim3(block), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, false>), grid, dim3(block), lds, s, a);
     return hipGetLastError();
 }
 

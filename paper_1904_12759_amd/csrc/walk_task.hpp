@@ -112,6 +112,34 @@ __device__ __forceinline__ typename WeightT<FP32>::T load_d(const InstArgs &P, u
         return P.d64[i];
 }
 
+// Row record and weight exponent of walk id x.  With LOC (relabelled rows),
+// the hot rows x < P.hot come from their LDS copy.
+template <bool LOC>
+__device__ __forceinline__ RowRec row_at(const InstArgs &P, uint32_t x) {
+    if constexpr (LOC)
+        if (x < P.hot) return P.lrows[x];
+    return P.rows[x];
+}
+
+template <bool FP32, bool LOC>
+__device__ __forceinline__ typename WeightT<FP32>::T d_at(const InstArgs &P, uint32_t x) {
+    if constexpr (LOC)
+        if (x < P.hot) return static_cast<const typename WeightT<FP32>::T *>(P.ld)[x];
+    return load_d<FP32>(P, x);
+}
+
+// Walk id of an original node, and back (identity without relabelling).
+template <bool LOC>
+__device__ __forceinline__ uint32_t walk_id(const InstArgs &P, uint32_t node) {
+    if constexpr (LOC) return P.perm[node];
+    return node;
+}
+template <bool LOC>
+__device__ __forceinline__ uint32_t orig_id(const InstArgs &P, uint32_t x) {
+    if constexpr (LOC) return P.inv[x];
+    return x;
+}
+
 template <bool FP32>
 __device__ __forceinline__ typename WeightT<FP32>::T wexp(typename WeightT<FP32>::T x) {
     if constexpr (FP32)
@@ -164,9 +192,10 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
 using namespace detail;
 
 // ----------------------------------------------------------- one task
-// Per-wave LDS scratch of run_group.
+// Per-wave LDS scratch of run_group (16-byte aligned size: the hot-row copies
+// that may follow the wave scratch are read as 16-byte records).
 template <typename WT>
-struct GroupLds {
+struct alignas(16) GroupLds {
     uint32_t list[kChunkMax];     // jumpers: (entry << 16) | ordinal, entry-major, ordinal order
     WT fval[kChunkMax];           // W v[X_t] of list[i]
     uint32_t node[kGroupMax];     // start node of each entry (UINT32_MAX: out of range)
@@ -203,7 +232,7 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
 // entry's mean and M2 come from a two-pass reduction over its slots in a fixed
 // order plus its n0 copies of K: the result does not depend on which lane ran
 // which walker, nor on how many entries share the task.
-template <int MODE, bool FP32, bool PROP, bool TRACE>
+template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC>
 __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx, int64_t n,
                                           uint32_t G, uint32_t ord0, uint32_t cnt,
                                           const TraceOut &tr, const GroupOut &out,
@@ -225,8 +254,9 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         double K = 0.0;
         if (nd >= 0 && nd < n) {
             node = (uint32_t)nd;
-            const RowRec r0 = P.rows[node];
-            const WT d0 = load_d<FP32>(P, node);
+            const uint32_t x0 = walk_id<LOC>(P, node);
+            const RowRec r0 = row_at<LOC>(P, x0);
+            const WT d0 = d_at<FP32, LOC>(P, x0);
             const WT v0 = load_v<FP32>(P.v, node);
             K = (double)(wexp<FP32>(final_term<MODE, FP32>(d0, 0.0, 0, P)) * v0);
             e0 = r0.deg ? exp(-t / r0.inv_r) * (1.0 - 0x1p-40) : 2.0;   // 2: never jumps
@@ -310,8 +340,8 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
     uint32_t wl = (uint32_t)lane;
     bool active = wl < nlist;
     uint32_t code = active ? L.list[wl] : 0u;
-    uint32_t node = active ? L.node[code >> 16] : 0u;
-    uint32_t x = node;
+    uint32_t node = active ? L.node[code >> 16] : 0u;     // original id: RNG counter
+    uint32_t x = walk_id<LOC>(P, node);                      // walk id
     double s = 0.0;
     WT logw = (WT)0;
     uint32_t ev = 0, ju = 0;
@@ -320,11 +350,11 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
     uint32_t deg = 0, begin = 0;
     WT dx = (WT)0;
     if (active) {
-        const RowRec rr = P.rows[x];
+        const RowRec rr = row_at<LOC>(P, x);
         inv_r = rr.inv_r;
         deg = rr.deg;
         begin = rr.begin;
-        dx = load_d<FP32>(P, x);
+        dx = d_at<FP32, LOC>(P, x);
     }
     uint32_t next = WAVE;
 
@@ -363,11 +393,11 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                         logw = logw + (WT)(keep ? cr.x : cr.y);
                     }
                     ++ju;
-                    const RowRec rr = P.rows[x];
+                    const RowRec rr = row_at<LOC>(P, x);
                     inv_r = rr.inv_r;
                     deg = rr.deg;
                     begin = rr.begin;
-                    dx = load_d<FP32>(P, x);
+                    dx = d_at<FP32, LOC>(P, x);
                 } else {
                     fin = true;
                 }
@@ -378,7 +408,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     f = (WT)L.K[code >> 16];         // never left the start node
                 } else {
                     logw = logw + final_term<MODE, FP32>(dx, s, ka, P);
-                    f = wexp<FP32>(logw) * load_v<FP32>(P.v, x);
+                    f = wexp<FP32>(logw) * load_v<FP32>(P.v, orig_id<LOC>(P, x));
                     if (!isfinite((double)f)) err |= F_OVERFLOW;
                 }
                 L.fval[wl] = f;
@@ -386,7 +416,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 jus += ju;
                 if constexpr (TRACE) {
                     const int64_t ti = tr.base + (code & 0xFFFFu);
-                    tr.x[ti] = (int32_t)x;
+                    tr.x[ti] = (int32_t)orig_id<LOC>(P, x);
                     tr.ev[ti] = ev;
                     tr.ju[ti] = ju;
                     tr.f[ti] = (double)f;
@@ -399,17 +429,17 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             if (wl < nlist) {
                 code = L.list[wl];
                 node = L.node[code >> 16];
-                x = node;
+                x = walk_id<LOC>(P, node);
                 s = 0.0;
                 logw = (WT)0;
                 ev = 0;
                 ju = 0;
                 ka = 0;
-                const RowRec rr = P.rows[x];
+                const RowRec rr = row_at<LOC>(P, x);
                 inv_r = rr.inv_r;
                 deg = rr.deg;
                 begin = rr.begin;
-                dx = load_d<FP32>(P, x);
+                dx = d_at<FP32, LOC>(P, x);
             } else {
                 active = false;
             }

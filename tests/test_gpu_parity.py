@@ -358,3 +358,51 @@ def test_grid3d_config_full_size_sampled_parity():
     o = Oracle(w.a.rowptr, w.a.col, w.a.val, w.t, 12759)
     eo, _ = o.estimate(_v_for(w.v, True), sample, w.nwalk, threads=8)
     assert _close(est[sample], eo, RTOL32)
+
+
+# ------------------------------------------------------------ relabel / LDS
+@pytest.mark.parametrize("fp32", [False, True])
+def test_relabel_and_hot_rows_do_not_change_results(fp32):
+    """Rows stored hot-first (descending exit rate) and the hottest rows staged in LDS:
+    paths use original ids in the RNG counter and slot order is kept, so every result
+    is bitwise identical to the plain layout."""
+    w = wl.config_ba_full(n=20_000)
+    a = w.a
+    v = np.random.default_rng(3).uniform(0.5, 1.5, a.n)
+    base = mc.MCExpmv(a.rowptr, a.col, a.val, 2.0, 31, fp32=fp32)
+    e0, s0 = base.full(v, 300)
+    idx = np.array([0, 1, 5, 17, a.n - 1, 4000], np.int64)
+    ee0, _ = base.entries(v, idx, 3000)
+    t0 = base.trace(v, 3, 0, 2000)
+    for relabel, lds in ((1, 0), (1, 4096), (1, 32768)):
+        g = mc.MCExpmv(a.rowptr, a.col, a.val, 2.0, 31, fp32=fp32, relabel=relabel,
+                       lds_budget=lds)
+        e1, s1 = g.full(v, 300)
+        assert torch.equal(e0, e1) and torch.equal(s0, s1), (relabel, lds)
+        ee1, _ = g.entries(v, idx, 3000)
+        assert torch.equal(ee0, ee1)
+        t1 = g.trace(v, 3, 0, 2000)
+        for x, y in zip(t0, t1):
+            assert np.array_equal(x, y)
+        tg, tb = g.tables(), base.tables()
+        for key in ("r", "d", "inv_r", "deg", "begin", "col", "thr", "alias"):
+            assert np.array_equal(tg[key], tb[key]), key
+
+
+def test_relabel_with_proposal_matches_plain_layout():
+    a = MATS["nonsym48"]
+    bias = np.random.default_rng(4).normal(0, 0.6, a.nnz).astype(np.float32)
+    v = np.random.default_rng(5).uniform(0.3, 1.0, a.n)
+    g0 = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 55)
+    g1 = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 55, relabel=1, lds_budget=256)
+    g0.set_proposal(bias)
+    g1.set_proposal(bias)
+    e0, _ = g0.full(v, 2000)
+    e1, _ = g1.full(v, 2000)
+    assert torch.equal(e0, e1)
+
+
+def test_lds_budget_requires_relabel():
+    a = MATS["sym48"]
+    with pytest.raises(mc.MCError):
+        mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 1, lds_budget=1024)
