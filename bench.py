@@ -199,6 +199,70 @@ def bench_grid3d(mc, seed, m=256, steps=5):
                 setup_s=setup, generation_s=gen, median_rel_stderr=float(np.median(rel)))
 
 
+def bench_batched(mc, seed, runs=5):
+    """64 instances in one persistent launch (ER and power-law graphs, n log-uniform in
+    [1e3, 1e6], A = adjacency / lambda_max, t ~ U[0.05, 1], v ~ U[0,1]; 32 entries x 1e4
+    walkers or the full vector x 64 walkers per node), schedule from the autotuner,
+    against the same 64 instances run as separate launches."""
+    import torch
+    from paper_1904_12759_amd import workloads as wl
+    t0 = time.perf_counter()
+    ws = wl.batched_instances(count=64)
+    gen = time.perf_counter() - t0
+    insts = [dict(rowptr=w.a.rowptr, col=w.a.col, val=w.a.val, t=w.t, v=w.v, idx=w.idx,
+                  n_walkers=w.nwalk, instance_id=k) for k, w in enumerate(ws)]
+    os.environ.pop("MC_EXPMV_TUNE_CACHE", None)
+    t0 = time.perf_counter()
+    b = mc.MCBatch(insts, seed)
+    create_s = time.perf_counter() - t0
+    b.run()
+    ms = []
+    for _ in range(runs):
+        b.run()
+        ms.append(b.stats()["ms"])
+    st = b.stats()
+    kern = float(np.median(ms))
+    # the same instances as separate handles, one launch each
+    hs = [mc.MCExpmv(w.a.rowptr, w.a.col, w.a.val, w.t, seed, instance=k)
+          for k, w in enumerate(ws)]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    vs = [torch.as_tensor(w.v, device=dev) for w in ws]
+    outs = [torch.empty(len(w.idx) if w.idx is not None else w.a.n, dtype=torch.float64,
+                        device=dev) for w in ws]
+    idxs = [torch.as_tensor(w.idx, device=dev) if w.idx is not None else None for w in ws]
+
+    def separate():
+        for h, w, v, o, ix in zip(hs, ws, vs, outs, idxs):
+            if ix is None:
+                h.full(v, w.nwalk, est=o, sync=False)
+            else:
+                h.entries(v, ix, w.nwalk, est=o, sync=False)
+        torch.cuda.synchronize()
+
+    separate()
+    same = all(torch.equal(outs[k], b.est[k]) for k in range(len(ws)))
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        separate()
+    sep_ms = (time.perf_counter() - t0) * 1e3 / runs
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        b.run(sync=False)
+    torch.cuda.synchronize()
+    b.sync()
+    batch_wall_ms = (time.perf_counter() - t0) * 1e3 / runs
+    achieved = st["alg_bytes"] / (kern / 1e3) / 1e9
+    return dict(workload="64 instances: ER (mean degree 8) and Chung-Lu power-law (gamma 2.5) "
+                         "graphs, n log-uniform [1e3, 1e6], A = adjacency/lambda_max, "
+                         "t ~ U[0.05,1], 32 entries x 1e4 walkers or full vector x 64/node",
+                n_total=int(sum(w.a.n for w in ws)), nnz_total=int(sum(w.a.nnz for w in ws)),
+                walkers=st["walkers"], events=st["events"], jumps=st["jumps"],
+                kernel_ms=kern, walker_steps_per_s=st["events"] / (kern / 1e3),
+                roofline_frac=achieved / HBM_PEAK_GBS, schedule=b.schedule(),
+                batch_wall_ms=batch_wall_ms, separate_launches_wall_ms=sep_ms,
+                identical_to_separate=bool(same), create_s=create_s, generation_s=gen)
+
+
 def bench_learned(mc, seed, n=1_000_000, m=4):
     """BA(n=1e6, m=4, seed 1), A = (0.5/lambda_max) adjacency, t = 1, v ~ U[0,1] (seed 2);
     1024 entries (256 highest degree + 768 uniform).  Walker-steps to 1e-3 relative
@@ -384,6 +448,8 @@ def main():
         out["learned_vs_plain"] = bench_learned(mc, args.seed)
         log("bench: grid3d 256^3")
         out["grid3d_256"] = bench_grid3d(mc, args.seed)
+        log("bench: batched 64 instances")
+        out["batched_64"] = bench_batched(mc, args.seed)
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         try:
