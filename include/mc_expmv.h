@@ -77,7 +77,7 @@ typedef struct {
     uint32_t lds_budget;        /* bytes of LDS per block for hot rows (needs relabel);
                                    0 = off (default) */
     uint32_t resort_period;     /* reserved, must be 0 */
-    uint32_t walkers_per_block; /* threads per block: 64, 128 or 256 (default) */
+    uint32_t walkers_per_block; /* threads per block: 64 (default, one wave), 128 or 256 */
     uint32_t instance_id;       /* fourth Philox counter word. Default 0. */
     uint32_t max_events;        /* cap on holding intervals per walker; 0 = 2^24 */
     void *stream;               /* hipStream_t; NULL = null stream */

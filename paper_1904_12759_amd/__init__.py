@@ -218,7 +218,7 @@ class MCExpmv:
 
     def __init__(self, rowptr, col, val, t: float, seed: int, mode: int = EXACT,
                  dt: float = 0.03125, fp32: bool = False, instance: int = 0,
-                 max_events: int = 0, walkers_per_block: int = 256, relabel: int = 0,
+                 max_events: int = 0, walkers_per_block: int = 64, relabel: int = 0,
                  lds_budget: int = 0, stream=None):
         import torch
         lib_ = load()

@@ -45,7 +45,6 @@ struct mc_expmv_s {
 
 namespace {
 
-constexpr uint32_t kChunk = kChunkMax;   // walkers per task (fixes the summation order)
 
 mc_status from_hip(hipError_t e) {
     if (e == hipSuccess) return MC_OK;
@@ -202,7 +201,8 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
     if (k < 0) return MC_ERR_INVALID_ARG;
     const bool prop = use_prop != 0;
     const bool fp32 = h->opts.weight_prec == MC_FP32;
-    const int64_t chunks = (nwalk + kChunk - 1) / kChunk;
+    const int64_t chunk = chunk_walkers(fp32);   // fixes the summation order
+    const int64_t chunks = (nwalk + chunk - 1) / chunk;
     WalkArgs a{};
     fill_inst(h, v, prop, a.P);
     a.idx = idx;
@@ -210,9 +210,9 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
     a.n = h->n;
     a.nwalk = nwalk;
     a.w0 = w0;
-    a.chunk = kChunk;
+    a.chunk = (uint32_t)chunk;
     a.chunks = chunks;
-    a.group = trace ? 1u : group_size(nwalk);
+    a.group = trace ? 1u : group_size(nwalk, fp32);
     a.ntasks = (k + a.group - 1) / a.group * chunks;
     a.est = est;
     a.se = se;
@@ -263,7 +263,7 @@ void mc_expmv_default_opts(mc_expmv_opts *o) {
     o->relabel = 0;
     o->lds_budget = 0;
     o->resort_period = 0;
-    o->walkers_per_block = 256;
+    o->walkers_per_block = 64;
     o->instance_id = 0;
     o->max_events = 0;
     o->stream = nullptr;
@@ -710,8 +710,8 @@ void tune_cache_store(const mc_batch_s *b, const Sched &s) {
 // the fastest.
 mc_status autotune(mc_batch_s *b, float *best_ms_out) {
     static const Sched cands[] = {
-        {256, 4, 0},  {256, 8, 0},  {256, 16, 0}, {128, 8, 0},  {128, 16, 0},
-        {256, 8, 16}, {256, 8, 128}, {128, 16, 16}, {256, 16, 64},
+        {256, 4, 0},  {256, 8, 0},   {128, 8, 0},   {128, 16, 0}, {64, 16, 0},  {64, 32, 0},
+        {256, 8, 16}, {256, 8, 128}, {128, 16, 16}, {64, 32, 16}, {64, 32, 64}, {256, 16, 64},
     };
     float best = 1e30f;
     Sched bs = cands[0];
@@ -833,19 +833,21 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
         I.k = d.idx ? d.k : d.n;
         I.n = d.n;
         I.nwalk = d.n_walkers;
-        I.chunks = (d.n_walkers + kChunk - 1) / kChunk;
-        I.group = group_size(d.n_walkers);
+        const bool fp32 = d.weight_prec == MC_FP32;
+        const int64_t chunk = chunk_walkers(fp32);
+        I.chunks = (d.n_walkers + chunk - 1) / chunk;
+        I.group = group_size(d.n_walkers, fp32);
         I.task_begin = ntasks;
         I.part_off = part_doubles;
         I.est = d.est;
         I.se = d.stderr_;
         I.mode = d.mode;
-        I.fp32 = d.weight_prec == MC_FP32;
+        I.fp32 = fp32;
         ntasks += (I.k + I.group - 1) / I.group * I.chunks;
         b->fin_begin[i] = nfin;
         if (I.chunks > 1) {
             part_doubles += I.k * I.chunks * 3;
-            nfin += I.k;
+            nfin += (I.k * (int64_t)fin_lanes(I.chunks) + 63) / 64 * 64;
         }
         b->walkers += (uint64_t)I.k * (uint64_t)I.nwalk;
         b->inst.push_back(I);

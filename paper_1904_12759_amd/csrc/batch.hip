@@ -13,6 +13,10 @@
 namespace mc {
 namespace {
 
+constexpr size_t kBatchLdsPerWave = sizeof(GroupLds<float>) > sizeof(GroupLds<double>)
+                                        ? sizeof(GroupLds<float>)
+                                        : sizeof(GroupLds<double>);
+
 // One task of the global index space: instance, then (entry group, chunk).
 __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, int64_t task,
                                         unsigned char *lds, unsigned long long &my_events,
@@ -31,9 +35,10 @@ __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, i
     const int64_t e_first = grp * (int64_t)I.group;
     const int64_t left = I.k - e_first;
     const uint32_t G = (uint32_t)(left < (int64_t)I.group ? left : (int64_t)I.group);
-    const int64_t wbase = c * (int64_t)kChunkMax;
+    const int64_t chunk = chunk_walkers(I.fp32);
+    const int64_t wbase = c * chunk;
     const int64_t rem = I.nwalk - wbase;
-    const uint32_t cnt = (uint32_t)(rem < (int64_t)kChunkMax ? rem : (int64_t)kChunkMax);
+    const uint32_t cnt = (uint32_t)(rem < chunk ? rem : chunk);
     const GroupOut out{I.est, I.se, a.part + I.part_off, e_first, I.chunks, c};
     TraceOut none;
 #define MC_GROUP(MODE, FP32)                                                                     \
@@ -51,7 +56,7 @@ __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, i
 #undef MC_GROUP
 }
 
-// Dynamic LDS: one GroupLds<double> per wave (the float layout fits inside).
+// Dynamic LDS: one task scratch per wave, the larger of the two layouts.
 __global__ __launch_bounds__(256) void k_walk_batched(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     __shared__ int64_t sh_tb[kMaxBatch];
@@ -60,7 +65,7 @@ __global__ __launch_bounds__(256) void k_walk_batched(BatchArgs a) {
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x / WAVE;
-    unsigned char *lds = dyn_lds + (size_t)wave * sizeof(GroupLds<double>);
+    unsigned char *lds = dyn_lds + (size_t)wave * kBatchLdsPerWave;
     unsigned long long my_events = 0, my_jumps = 0;
     uint32_t err = 0;
     if (a.group == 0) {
@@ -103,23 +108,31 @@ __global__ __launch_bounds__(256) void k_walk_batched(BatchArgs a) {
 __global__ void k_reset_queue(unsigned long long *queue) { *queue = 0ull; }
 
 // Merge chunk partials of every entry that spans several chunks, for all
-// instances: item f belongs to instance i with fin_begin[i] <= f < fin_begin[i+1].
-__global__ void k_finalize_batched(BatchArgs a) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= a.nfin) return;
+// instances: instance i owns the finalize threads fin_begin[i] ..
+// fin_begin[i+1]-1 (a multiple of 64, so a wave never spans two instances),
+// fin_lanes(chunks) of them per entry, exactly as in k_finalize.
+__global__ __launch_bounds__(256) void k_finalize_batched(BatchArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.nfin) return;   // whole waves: nfin is a multiple of 64
     int lo = 0, hi = a.ninst - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (a.fin_begin[mid] <= f) lo = mid;
+        if (a.fin_begin[mid] <= t) lo = mid;
         else hi = mid - 1;
     }
     const BatchInst &I = a.inst[lo];
-    const int64_t e = f - a.fin_begin[lo];
-    const double *p = a.part + I.part_off + e * I.chunks * 3;
-    double n = 0.0, mean = 0.0, q = 0.0;
-    for (int64_t c = 0; c < I.chunks; ++c) chan_merge(n, mean, q, p[3 * c], p[3 * c + 1], p[3 * c + 2]);
-    I.est[e] = mean;
-    if (I.se) I.se[e] = n > 1.0 ? sqrt(q / (n - 1.0) / n) : 0.0;
+    const uint32_t L = fin_lanes(I.chunks);
+    const int64_t local = t - a.fin_begin[lo];
+    const int64_t e = local / L;
+    const uint32_t sub = (uint32_t)(local - e * L);
+    const bool valid = e < I.k;
+    double n, mean, m2;
+    fin_merge(valid ? a.part + I.part_off + e * I.chunks * 3 : nullptr, valid ? I.chunks : 0, L,
+              sub, n, mean, m2);
+    if (valid && sub == 0) {
+        I.est[e] = mean;
+        if (I.se) I.se[e] = n > 1.0 ? sqrt(m2 / (n - 1.0) / n) : 0.0;
+    }
 }
 
 }  // namespace
@@ -131,7 +144,7 @@ hipError_t launch_batch(const BatchArgs &a, int block, int grid, hipStream_t s) 
         if (e != hipSuccess) return e;
     }
     if (a.ntasks > 0) {
-        const size_t lds = (size_t)(block / WAVE) * sizeof(GroupLds<double>);
+        const size_t lds = (size_t)(block / WAVE) * kBatchLdsPerWave;
         hipLaunchKernelGGL(k_walk_batched, dim3((unsigned)grid), dim3(block), lds, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

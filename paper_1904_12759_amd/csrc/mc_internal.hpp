@@ -139,21 +139,33 @@ struct BatchArgs {
     uint32_t *flags;
     unsigned long long *queue;     // dynamic schedule counter
     uint32_t group;                // tasks per grab; 0 = static stride
-    const int64_t *fin_begin;      // [ninst + 1] prefix of entries with chunks > 1
-    int64_t nfin;
+    const int64_t *fin_begin;      // [ninst + 1] first finalize thread of each instance
+    int64_t nfin;                  // finalize threads (a multiple of 64)
 };
 
 // Walkers per task (an entry with more walkers is split into chunks merged in
 // chunk order), and the most entries one task may pack when they have fewer.
+// A task keeps one value per walker that may jump in LDS, so FP64 tasks are
+// half as long as FP32 ones: both then fit five waves per SIMD.
 constexpr uint32_t kChunkMax = 1024;
 constexpr uint32_t kGroupMax = 64;
+constexpr uint32_t chunk_walkers(bool fp32) { return fp32 ? kChunkMax : kChunkMax / 2; }
+// Lanes that merge one entry's chunk partials: one for up to 8 chunks, then
+// doubling up to a whole wave, so that no lane merges more than about eight
+// partials in sequence.
+__host__ __device__ constexpr uint32_t fin_lanes(int64_t chunks) {
+    uint32_t l = 1;
+    while (l < 64 && (int64_t)l * 8 < chunks) l <<= 1;
+    return l;
+}
 // Largest LDS budget for hot rows (bytes per block).
 constexpr uint32_t kMaxHotBytes = 65536;
 
 // Entries packed into one task when each has nwalk walkers.
-inline uint32_t group_size(int64_t nwalk) {
-    if (nwalk >= (int64_t)kChunkMax) return 1;
-    const int64_t g = (int64_t)kChunkMax / nwalk;
+inline uint32_t group_size(int64_t nwalk, bool fp32) {
+    const int64_t c = (int64_t)chunk_walkers(fp32);
+    if (nwalk >= c) return 1;
+    const int64_t g = c / nwalk;
     return (uint32_t)(g < (int64_t)kGroupMax ? g : (int64_t)kGroupMax);
 }
 

@@ -1,18 +1,21 @@
 // The walk: continuous-time Markov-chain paths through the indices of A and
 // the multiplicative functional of Theorem 1 (paper Sec. 2-3, Algorithm 1).
 //
-// Work decomposition.  A task is (entry e, chunk c): the walkers with
-// ordinals c*chunk .. min(N, (c+1)*chunk)-1 started at node idx[e].  One
-// wavefront owns a task; its 64 lanes each run one walker and, when a walker
-// stops, take the next unstarted ordinal of the chunk (lane refill), so a long
-// path holds up one lane instead of the whole wave.  Paths depend only on the
-// Philox counter (event, ordinal, start node, instance), never on the lane.
+// Work decomposition.  A task is (group of G consecutive entries, chunk c):
+// the walkers with ordinals c*C .. min(M, (c+1)*C)-1 of each entry, with
+// C = 1024 (FP32 weights) or 512 (FP64) and G = min(64, C/M) so that a task
+// holds about C walkers.  One wavefront
+// owns a task and runs it in two phases (run_group): the first event of every
+// walker, which for most start nodes already decides that the walker never
+// leaves, then complete walks with lane refill for the others.  Paths depend
+// only on the Philox counter (event, ordinal, start node, instance), never on
+// the lane or the task shape.
 //
-// Statistics.  Each lane keeps the count, the first value it saw (a shift)
-// and the shifted sums of f and f^2; the wave then merges lanes pairwise with
-// the Chan-Golub-LeVeque update of (count, mean, M2), and chunks are merged the
-// same way in chunk order.  A shift taken from the sample itself keeps the
-// shifted sums well conditioned even when the weights are heavy tailed.
+// Statistics.  Every finished walker's value goes to the LDS slot of its
+// position in the entry's ordinal-ordered list of jumpers; each entry's mean and sum of squared deviations come from a
+// two-pass sum over its slots in a fixed order plus the closed-form
+// contribution of its walkers that never jump, and entries spread over several
+// chunks are merged in chunk order (Chan, Golub, LeVeque).
 #include <math.h>
 
 #include "walk_task.hpp"
@@ -87,16 +90,22 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
 
 }  // namespace
 
-// Merge the chunk partials of every entry in chunk order.
-__global__ void k_finalize(int64_t k, int64_t chunks, const double *__restrict__ part,
-                           double *__restrict__ est, double *__restrict__ se) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= k) return;
-    const double *p = part + e * chunks * 3;
-    double n = 0.0, mean = 0.0, q = 0.0;
-    for (int64_t c = 0; c < chunks; ++c) chan_merge(n, mean, q, p[3 * c], p[3 * c + 1], p[3 * c + 2]);
-    est[e] = mean;
-    if (se) se[e] = n > 1.0 ? sqrt(q / (n - 1.0) / n) : 0.0;
+// Merge the chunk partials of every entry in chunk order: fin_lanes(chunks)
+// lanes per entry (the grid covers whole waves).
+__global__ __launch_bounds__(256) void k_finalize(int64_t k, int64_t chunks,
+                                                  const double *__restrict__ part,
+                                                  double *__restrict__ est, double *__restrict__ se) {
+    const uint32_t L = fin_lanes(chunks);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = t / L;
+    const uint32_t sub = (uint32_t)(t - e * L);
+    const bool valid = e < k;
+    double n, mean, m2;
+    fin_merge(valid ? part + e * chunks * 3 : nullptr, valid ? chunks : 0, L, sub, n, mean, m2);
+    if (valid && sub == 0) {
+        est[e] = mean;
+        if (se) se[e] = n > 1.0 ? sqrt(m2 / (n - 1.0) / n) : 0.0;
+    }
 }
 
 namespace {
@@ -112,6 +121,9 @@ int walk_grid(int64_t ntasks, int block) {
 template <int MODE, bool FP32, bool PROP, bool TRACE>
 hipError_t launch_t(const WalkArgs &a, int block, hipStream_t s) {
     using WT = typename WeightT<FP32>::T;
+    // a task's walkers must fit its LDS value slots
+    if (a.chunk != GroupLds<WT>::C || a.group == 0 || a.group > kGroupMax)
+        return hipErrorInvalidValue;
     const size_t lds = (size_t)(block / WAVE) * sizeof(GroupLds<WT>) +
                        (size_t)a.P.hot * (sizeof(RowRec) + sizeof(WT));
     const dim3 grid((unsigned)walk_grid(a.ntasks, block));
@@ -159,7 +171,8 @@ hipError_t launch_walk(const WalkArgs &a, int mode, bool fp32, bool prop, bool t
 hipError_t launch_finalize(const WalkArgs &a, hipStream_t s) {
     if (a.chunks <= 1 || a.k == 0) return hipSuccess;
     const int block = 256;
-    const int64_t grid = (a.k + block - 1) / block;
+    const int64_t threads = a.k * (int64_t)fin_lanes(a.chunks);
+    const int64_t grid = (threads + block - 1) / block;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)grid), dim3(block), 0, s, a.k, a.chunks, a.part,
                        a.est, a.se);
     return hipGetLastError();

@@ -1,6 +1,6 @@
 // Device code shared by the single-instance and batched walk kernels: the
 // Philox generator, the logarithm, weight quadratures, the Chan merge and the
-// per-task walker loop (run_task).  Included by walk.hip and batch.hip only.
+// per-task walker loop (run_group).  Included by walk.hip and batch.hip only.
 #pragma once
 
 #include <math.h>
@@ -18,6 +18,14 @@ constexpr int WAVE = 64;
 constexpr double kLn2Hi = 0x1.62e42fee00000p-1;
 constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
 
+// An FP64 constant materialised in a scalar register pair where it is used.
+// Without this the compiler keeps the logarithm's coefficients live in vector
+// registers across the whole walk loop, which costs a wave of occupancy.
+__device__ __forceinline__ double sconst(double c) {
+    asm volatile("" : "+s"(c));
+    return c;
+}
+
 // Natural logarithm of u in (0, 1].  With u = m 2^e, m in [1/sqrt2, sqrt2),
 // log u = e ln2 + 2 atanh(f), f = (m-1)/(m+1), |f| < 0.1716, and atanh(f)/f is
 // the Taylor series sum_k f^{2k}/(2k+1), kept to f^24 (truncation < 1e-19).
@@ -25,27 +33,54 @@ constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
 __device__ __forceinline__ double log_unit(double u) {
     int e;
     double m = frexp(u, &e);
-    if (m < 0.70710678118654752440) {
+    if (m < sconst(0.70710678118654752440)) {
         m = m + m;
         e -= 1;
     }
     const double f = (m - 1.0) / (m + 1.0);
     const double f2 = f * f;
-    double p = 1.0 / 25.0;
-    p = fma(p, f2, 1.0 / 23.0);
-    p = fma(p, f2, 1.0 / 21.0);
-    p = fma(p, f2, 1.0 / 19.0);
-    p = fma(p, f2, 1.0 / 17.0);
-    p = fma(p, f2, 1.0 / 15.0);
-    p = fma(p, f2, 1.0 / 13.0);
-    p = fma(p, f2, 1.0 / 11.0);
-    p = fma(p, f2, 1.0 / 9.0);
-    p = fma(p, f2, 1.0 / 7.0);
-    p = fma(p, f2, 1.0 / 5.0);
-    p = fma(p, f2, 1.0 / 3.0);
+    double p = sconst(1.0 / 25.0);
+    p = fma(p, f2, sconst(1.0 / 23.0));
+    p = fma(p, f2, sconst(1.0 / 21.0));
+    p = fma(p, f2, sconst(1.0 / 19.0));
+    p = fma(p, f2, sconst(1.0 / 17.0));
+    p = fma(p, f2, sconst(1.0 / 15.0));
+    p = fma(p, f2, sconst(1.0 / 13.0));
+    p = fma(p, f2, sconst(1.0 / 11.0));
+    p = fma(p, f2, sconst(1.0 / 9.0));
+    p = fma(p, f2, sconst(1.0 / 7.0));
+    p = fma(p, f2, sconst(1.0 / 5.0));
+    p = fma(p, f2, sconst(1.0 / 3.0));
     p = fma(p, f2, 1.0);
     const double de = (double)e;
-    return fma(de, kLn2Hi, fma(de, kLn2Lo, 2.0 * f * p));
+    return fma(de, sconst(kLn2Hi), fma(de, sconst(kLn2Lo), 2.0 * f * p));
+}
+
+// e^x in FP64: Cody-Waite reduction x = k ln2 + r, |r| <= ln2/2 (k ln2 taken
+// as k*kLn2Hi, exact for |k| < 2^11, plus k*kLn2Lo), the Taylor series of e^r
+// to r^13 (truncation below 2^-56 relative), then scaling by 2^k.  Within
+// about 2 ulp of the correctly rounded value; NaN stays NaN, x < -1100 gives
+// 0 and x > 1100 gives +inf.
+__device__ __forceinline__ double exp_f64(double x) {
+    if (!(x >= -1100.0)) return x != x ? x : 0.0;
+    if (x > 1100.0) return __longlong_as_double(0x7ff0000000000000ll);
+    const double k = rint(x * sconst(0x1.71547652b82fep+0));   // x log2(e)
+    const double r = fma(-k, sconst(kLn2Lo), fma(-k, sconst(kLn2Hi), x));
+    double p = sconst(1.0 / 6227020800.0);                       // 1/13!
+    p = fma(p, r, sconst(1.0 / 479001600.0));
+    p = fma(p, r, sconst(1.0 / 39916800.0));
+    p = fma(p, r, sconst(1.0 / 3628800.0));
+    p = fma(p, r, sconst(1.0 / 362880.0));
+    p = fma(p, r, sconst(1.0 / 40320.0));
+    p = fma(p, r, sconst(1.0 / 5040.0));
+    p = fma(p, r, sconst(1.0 / 720.0));
+    p = fma(p, r, sconst(1.0 / 120.0));
+    p = fma(p, r, sconst(1.0 / 24.0));
+    p = fma(p, r, sconst(1.0 / 6.0));
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)k);
 }
 
 __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -145,7 +180,7 @@ __device__ __forceinline__ typename WeightT<FP32>::T wexp(typename WeightT<FP32>
     if constexpr (FP32)
         return expf(x);
     else
-        return exp(x);
+        return exp_f64(x);
 }
 
 // Log-weight of the last holding interval [s, t] in a state with exponent dx.
@@ -181,10 +216,76 @@ __device__ __forceinline__ void chan_merge(double &na, double &ma, double &qa, d
     na = n;
 }
 
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, WAVE);
-    return x;
+// Cross-lane moves within a row of 16 lanes (DPP), on the two 32-bit halves of
+// a 64-bit value.  CTRL: 0xB1 swaps neighbouring lanes (quad_perm 1,0,3,2),
+// 0x4E swaps lane pairs (quad_perm 2,3,0,1), 0x141 mirrors each half row of 8,
+// 0x140 mirrors the row.  All lanes of the row must be active.
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t b) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Merge of one entry's chunk partials p[3c .. 3c+2] = (count, mean, M2),
+// c < chunks, by the L lanes sub = 0 .. L-1 of an aligned group: lane sub
+// merges a contiguous range of chunks in order, then lane sub takes in the
+// range of lane sub + off for off = 1, 2, 4, ..., so chunk order is kept at
+// every step.  The result is in sub-lane 0.  Every lane of the wave must call
+// it with the same L (p may be null when chunks is 0).
+__device__ __forceinline__ void fin_merge(const double *p, int64_t chunks, uint32_t L, uint32_t sub,
+                                          double &n, double &mean, double &m2) {
+    n = 0.0;
+    mean = 0.0;
+    m2 = 0.0;
+    const int64_t q = (chunks + L - 1) / L;
+    const int64_t c0 = (int64_t)sub * q;
+    const int64_t c1 = c0 + q < chunks ? c0 + q : chunks;
+    for (int64_t c = c0; c < c1; ++c) chan_merge(n, mean, m2, p[3 * c], p[3 * c + 1], p[3 * c + 2]);
+    for (uint32_t off = 1; off < L; off <<= 1) {
+        const double nb = __shfl_down(n, off, (int)L);
+        const double mb = __shfl_down(mean, off, (int)L);
+        const double qb = __shfl_down(m2, off, (int)L);
+        if ((sub & (2 * off - 1)) == 0) chan_merge(n, mean, m2, nb, mb, qb);
+    }
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t b, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    return __longlong_as_double((long long)readlane_u64((uint64_t)__double_as_longlong(x), l));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    return __longlong_as_double((long long)dpp_u64<CTRL>((uint64_t)__double_as_longlong(x)));
+}
+
+// Sum over the 64 lanes of a wavefront in a fixed tree: neighbours, pairs,
+// half rows and rows of 16 lanes by DPP (each step adds two equal partial sums
+// in both orders, which commutativity makes bitwise equal), then the four row
+// sums as (r0 + r1) + (r2 + r3).  The result is uniform.  Every lane of the
+// wave must be active.
+__device__ __forceinline__ double wave_sum_f64(double x) {
+    x = x + dpp_f64<0xB1>(x);
+    x = x + dpp_f64<0x4E>(x);
+    x = x + dpp_f64<0x141>(x);
+    x = x + dpp_f64<0x140>(x);
+    return (readlane_f64(x, 0) + readlane_f64(x, 16)) + (readlane_f64(x, 32) + readlane_f64(x, 48));
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+    uint64_t x = v;
+    x += dpp_u64<0xB1>(x);
+    x += dpp_u64<0x4E>(x);
+    x += dpp_u64<0x141>(x);
+    x += dpp_u64<0x140>(x);
+    return (readlane_u64(x, 0) + readlane_u64(x, 16)) + (readlane_u64(x, 32) + readlane_u64(x, 48));
 }
 
 }  // namespace detail
@@ -196,13 +297,15 @@ using namespace detail;
 // that may follow the wave scratch are read as 16-byte records).
 template <typename WT>
 struct alignas(16) GroupLds {
-    uint32_t list[kChunkMax];     // jumpers: (entry << 16) | ordinal, entry-major, ordinal order
-    WT fval[kChunkMax];           // W v[X_t] of list[i]
+    static constexpr uint32_t C = chunk_walkers(sizeof(WT) == sizeof(float));
+    WT fval[C];                   // W v[X_t] of list[i]
+    double K[kGroupMax];          // value of a walker that never leaves the start node
     uint32_t node[kGroupMax];     // start node of each entry (UINT32_MAX: out of range)
     uint32_t n0[kGroupMax];       // walkers of each entry that never jump
     uint32_t seg[kGroupMax + 1];  // entry g's jumpers are list[seg[g] .. seg[g+1])
-    double K[kGroupMax];          // value of a walker that never leaves the start node
+    uint16_t list[C];             // jumpers: (entry << 10) | ordinal, entry-major, ordinal order
 };
+static_assert(kGroupMax <= 64 && kChunkMax <= 1024, "list codes are 6 + 10 bits");
 
 // Where a task's per-entry results go: entry e_first + g, chunk c of `chunks`.
 struct GroupOut {
@@ -210,21 +313,16 @@ struct GroupOut {
     int64_t e_first, chunks, c;
 };
 
-__device__ __forceinline__ double wave_sum_f64(double x) {
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) x += __shfl_xor(x, off, WAVE);
-    return x;
-}
-
 // Runs walkers ord0 .. ord0+cnt-1 of G entries on the calling wavefront and
 // writes each entry's estimate (or its chunk's (count, mean, M2)).  All lanes
 // of the wave call it together; lds is this wave's scratch.
 //
 // Phase 1 draws only the first event of every walker of the entries whose
 // no-jump probability e^{-r t} is at least 1/8: a walker with U below
-// e^{-rt}(1 - 2^-40) certainly holds past t (-log(U)/r > t + 2^-40/r, far
-// beyond the logarithm's rounding) and returns exactly K, so only a count is
-// kept; the others are appended to a list, as are all walkers of the other
+// e0 = e^{-rt}(1 - 2^-16), evaluated in FP32 (error below 1e-6, so e0 stays
+// below e^{-rt}(1 - 2^-17)), certainly holds past t (-log(U)/r > t + 2^-17/r,
+// far beyond the logarithm's rounding) and returns exactly K, so only a count
+// is kept; the others are appended to a list, as are all walkers of the other
 // entries.  Phase 2 runs the complete walk for the listed walkers with lane
 // refill (their first event drawn again from the same counter), so the rarely
 // needed logarithm, jump and exp code runs on lanes that need it.  Every
@@ -259,7 +357,10 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             const WT d0 = d_at<FP32, LOC>(P, x0);
             const WT v0 = load_v<FP32>(P.v, node);
             K = (double)(wexp<FP32>(final_term<MODE, FP32>(d0, 0.0, 0, P)) * v0);
-            e0 = r0.deg ? exp(-t / r0.inv_r) * (1.0 - 0x1p-40) : 2.0;   // 2: never jumps
+            // e^{-rt} in FP32 (relative error below 1e-6 where e0 >= 1/8 matters),
+            // lowered by 2^-16; 2: never jumps
+            e0 = r0.deg ? (double)exp2f((float)(-t / r0.inv_r) * 1.44269504f) * (1.0 - 0x1p-16)
+                        : 2.0;
         } else {
             err |= F_OUT_OF_RANGE;
         }
@@ -276,7 +377,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
     unsigned long long evs = 0, jus = 0;
     for (uint32_t g = 0; g < G; ++g) {
         const uint32_t node = L.node[g];
-        const double eg = __shfl(e0, (int)g, WAVE);
+        const double eg = readlane_f64(e0, (int)g);
         if (lane == 0) L.seg[g] = nlist;
         if (node == 0xFFFFFFFFu) continue;
         if (eg >= 1.5) {
@@ -297,7 +398,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         }
         if (eg < 0.125) {
             // most walkers leave: list them all
-            for (uint32_t w = lane; w < cnt; w += WAVE) L.list[nlist + w] = (g << 16) | w;
+            for (uint32_t w = lane; w < cnt; w += WAVE) L.list[nlist + w] = (uint16_t)((g << 10) | w);
             nlist += cnt;
             continue;
         }
@@ -314,7 +415,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 go = m + 1ull >= m_thr;
             }
             const unsigned long long gmask = __ballot(go);
-            if (go) L.list[nlist + (uint32_t)__popcll(gmask & lanemask_lt)] = (g << 16) | w;
+            if (go) L.list[nlist + (uint32_t)__popcll(gmask & lanemask_lt)] = (uint16_t)((g << 10) | w);
             nlist += (uint32_t)__popcll(gmask);
             stay += (uint32_t)__popcll(__ballot(valid && !go));
             if constexpr (TRACE) {
@@ -340,7 +441,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
     uint32_t wl = (uint32_t)lane;
     bool active = wl < nlist;
     uint32_t code = active ? L.list[wl] : 0u;
-    uint32_t node = active ? L.node[code >> 16] : 0u;     // original id: RNG counter
+    uint32_t node = active ? L.node[code >> 10] : 0u;     // original id: RNG counter
     uint32_t x = walk_id<LOC>(P, node);                      // walk id
     double s = 0.0;
     WT logw = (WT)0;
@@ -368,7 +469,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 err |= F_WALK_LIMIT;
                 fin = true;
             } else {
-                const U4 o = philox(ev, ord0 + (code & 0xFFFFu), node, P.inst, P.key0, P.key1);
+                const U4 o = philox(ev, ord0 + (code & 1023u), node, P.inst, P.key0, P.key1);
                 ++ev;
                 const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
                 const double U = (double)(m + 1ull) * 0x1p-53;
@@ -405,7 +506,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             if (fin) {
                 WT f;
                 if (ju == 0) {
-                    f = (WT)L.K[code >> 16];         // never left the start node
+                    f = (WT)L.K[code >> 10];         // never left the start node
                 } else {
                     logw = logw + final_term<MODE, FP32>(dx, s, ka, P);
                     f = wexp<FP32>(logw) * load_v<FP32>(P.v, orig_id<LOC>(P, x));
@@ -415,7 +516,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 evs += ev;
                 jus += ju;
                 if constexpr (TRACE) {
-                    const int64_t ti = tr.base + (code & 0xFFFFu);
+                    const int64_t ti = tr.base + (code & 1023u);
                     tr.x[ti] = (int32_t)orig_id<LOC>(P, x);
                     tr.ev[ti] = ev;
                     tr.ju[ti] = ju;
@@ -428,7 +529,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             wl = next + (uint32_t)__popcll(fmask & lanemask_lt);
             if (wl < nlist) {
                 code = L.list[wl];
-                node = L.node[code >> 16];
+                node = L.node[code >> 10];
                 x = walk_id<LOC>(P, node);
                 s = 0.0;
                 logw = (WT)0;
