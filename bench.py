@@ -335,7 +335,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the entries/s at 1e-3 and learned-vs-plain measurements")
+                    help="skip every extra measurement (same as --extras none)")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated extra measurements after the main step: "
+                         "locality, entries, learned, grid3d, batched; 'all' or 'none'")
     ap.add_argument("--seed", type=int, default=12759)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (steps times), "
@@ -439,15 +442,26 @@ def main():
             "traffic": measured_traffic(),
         },
     }
-    if not args.no_extras:
+    names = ["locality", "entries", "learned", "grid3d", "batched"]
+    extras = [] if args.no_extras or args.extras == "none" else \
+        names if args.extras == "all" else [x for x in args.extras.split(",") if x]
+    unknown = [x for x in extras if x not in names]
+    if unknown:
+        print(f"bench.py: unknown extras {unknown}; choose from {names}", file=sys.stderr)
+        sys.exit(2)
+    if "locality" in extras:
         log("bench: locality variants")
         out["locality"] = bench_locality(mc, w, args.seed)
+    if "entries" in extras:
         log("bench: entries/s at 1e-3 (grid2d)")
         out["entries_at_1e3"] = bench_grid2d_entries(mc, args.seed)
+    if "learned" in extras:
         log("bench: learned vs plain (BA n=1e6 m=4)")
         out["learned_vs_plain"] = bench_learned(mc, args.seed)
+    if "grid3d" in extras:
         log("bench: grid3d 256^3")
         out["grid3d_256"] = bench_grid3d(mc, args.seed)
+    if "batched" in extras:
         log("bench: batched 64 instances")
         out["batched_64"] = bench_batched(mc, args.seed)
     if not args.no_cpu:
