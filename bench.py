@@ -36,21 +36,21 @@ KERNEL_SOURCES = ["paper_1904_12759_amd/csrc/walk.hip", "paper_1904_12759_amd/cs
                   "paper_1904_12759_amd/csrc/mc_internal.hpp"]
 
 
-def measured_traffic():
-    """HBM bytes per walk launch from the committed rocprofv3 summary (FETCH_SIZE and
+def measured_traffic(profile=PROFILE, sources=KERNEL_SOURCES):
+    """HBM bytes per launch from a committed rocprofv3 summary (FETCH_SIZE and
     WRITE_SIZE scaled by a plain copy), or None when the kernel sources have changed
     since the counters were taken."""
     import hashlib
     try:
-        text = open(PROFILE).read()
+        text = open(profile).read()
     except OSError:
         return None
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     fields = dict(ln.split(":", 1) for ln in text.splitlines()
                   if ":" in ln and not ln.startswith(("#", " ")))
-    if fields.get("source_sha256", "").strip() != h.hexdigest():
+    if fields.get("source_sha256", "").split(" ")[1:2] != [h.hexdigest()]:
         return None
     try:
         return float(fields["traffic_bytes_per_launch"].split()[0])
@@ -196,6 +196,7 @@ def bench_grid3d(mc, seed, m=256, steps=5):
                 n=w.a.n, nnz=w.a.nnz, walkers=st["walkers"], events=st["events"],
                 jumps=st["jumps"], kernel_ms=kern, walker_steps_per_s=st["events"] / (kern / 1e3),
                 roofline_frac=achieved / HBM_PEAK_GBS, achieved_gbs=achieved,
+                traffic=measured_traffic(os.path.join(ROOT, "profiles", "walk_grid3d_256_fp32.txt")),
                 setup_s=setup, generation_s=gen, median_rel_stderr=float(np.median(rel)))
 
 
@@ -259,6 +260,8 @@ def bench_batched(mc, seed, runs=5):
                 walkers=st["walkers"], events=st["events"], jumps=st["jumps"],
                 kernel_ms=kern, walker_steps_per_s=st["events"] / (kern / 1e3),
                 roofline_frac=achieved / HBM_PEAK_GBS, schedule=b.schedule(),
+                traffic=measured_traffic(os.path.join(ROOT, "profiles", "walk_batched_64.txt"),
+                                         KERNEL_SOURCES + ["paper_1904_12759_amd/csrc/batch.hip"]),
                 batch_wall_ms=batch_wall_ms, separate_launches_wall_ms=sep_ms,
                 identical_to_separate=bool(same), create_s=create_s, generation_s=gen)
 
