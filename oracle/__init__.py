@@ -59,8 +59,10 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
+        # ORACLE_LIB names another build of oracle.c to load instead (the
+        # planted-mistake tests load deliberately broken builds this way)
+        path = os.environ.get("ORACLE_LIB") or build()
+        lib = ctypes.CDLL(path)
         vp, i64, u64, u32, i32, dbl = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
                                        ctypes.c_uint32, ctypes.c_int, ctypes.c_double)
         lib.oracle_create.argtypes = [ctypes.POINTER(vp), i64, i64, vp, vp, vp, dbl, u64, i32,
