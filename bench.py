@@ -266,68 +266,99 @@ def bench_batched(mc, seed, runs=5):
                 identical_to_separate=bool(same), create_s=create_s, generation_s=gen)
 
 
-def bench_learned(mc, seed, n=1_000_000, m=4):
-    """BA(n=1e6, m=4, seed 1), A = (0.5/lambda_max) adjacency, t = 1, v ~ U[0,1] (seed 2);
-    1024 entries (256 highest degree + 768 uniform).  Walker-steps to 1e-3 relative
-    standard error for the plain and the learned walk from exact per-entry variances
-    (second moments by expm_multiply), and the learned walk's measured entries/s."""
-    import scipy.sparse as sp
-    import scipy.sparse.linalg as sla
+def _ba_learned_case(n, m, gseed):
+    """BA(n, m, gseed), A = (0.5/lambda_max) adjacency, v ~ U[0,1] (seed 2); 1024 entries
+    (the 256 highest-degree nodes and 768 uniform ones, seed 3)."""
     from paper_1904_12759_amd import workloads as wl
-    t_gen = time.perf_counter()
-    g = wl.ba_graph(n, m, 1)
+    g = wl.ba_graph(n, m, gseed)
     lam = wl.lambda_max(g)
     a = wl.scaled(g, 0.5 / lam)
     v = wl.uniform_v(a.n, 2)
     deg = np.diff(a.rowptr)
     rng = np.random.default_rng(3)
     idx = np.unique(np.concatenate([np.argsort(-deg)[:256], rng.choice(a.n, 768, replace=False)]))
+    return a, v, idx, lam
+
+
+def _steps_to_target(a, v, idx, bias, events_per_walker, t=1.0, target=1e-3):
+    """Walker-steps for a relative standard error of `target` at every entry, from the
+    exact per-entry variance: x = exp(tA) v and, by Feynman-Kac with the jump factors
+    e^{-b}, E[f^2] = exp(tG) v^2 with G_ij = a_ij e^{-b_ij}, G_ii = 2 d~_i - r~_i."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    deg = np.diff(a.rowptr)
+    rows = np.repeat(np.arange(a.n), deg)
+    b = np.zeros(a.nnz) if bias is None else np.asarray(bias, np.float64)
+    at = a.val * np.exp(b)
+    rt = np.bincount(rows, weights=at, minlength=a.n)
+    r = np.bincount(rows, weights=a.val, minlength=a.n)
+    gm = sp.csr_matrix((a.val * np.exp(-b), a.col, a.rowptr), shape=(a.n, a.n))
+    gm = gm + sp.diags(2 * (r + (rt - r)) - rt)         # d = r (no diagonal in A)
+    m2 = sla.expm_multiply((t * gm).tocsr(), v * v)
+    x = sla.expm_multiply((t * a.to_scipy()).tocsr(), v)
+    xi = x[idx]
+    var = np.maximum(m2[idx] - xi * xi, 0)
+    return float((var / (target * xi) ** 2).sum() * events_per_walker)
+
+
+def bench_learned(mc, seed, n=1_000_000, m=4):
+    """Learned vs plain proposal on BA(n=1e6, m=4), t = 1: walker-steps to 1e-3 relative
+    standard error for the plain and the learned walk from exact per-entry variances, and
+    the learned walk's measured entries/s.  The network is trained on the graph of seed 1
+    and also applied, unchanged, to a held-out graph of seed 2 (features computed there)."""
+    import torch
+    t_gen = time.perf_counter()
+    a, v, idx, lam = _ba_learned_case(n, m, 1)
     t_gen = time.perf_counter() - t_gen
+
+    def events_per_walker(h, vv, ii):
+        h.entries(vv, ii, 1 << 14)      # plain, or tilted once a proposal is installed
+        st = h.stats()
+        return st["events"] / st["walkers"]
+
     h = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, seed)
+    ev_plain = events_per_walker(h, v, idx)
+    rep = h.learn_proposal(v, pilot_walkers=256, steps=400, batch=1 << 16, lr=3e-3, seed=1)
+    bias = h.get_proposal().cpu().numpy()
+    ev_learn = events_per_walker(h, v, idx)
+    steps_p = _steps_to_target(a, v, idx, None, ev_plain)
+    steps_l = _steps_to_target(a, v, idx, bias, ev_learn)
+    prod = entries_at_1e3(mc, h, v, idx, 10_000)
     out = dict(workload=f"BA n={n} m={m} seed 1, A=(0.5/lambda_max)*adjacency "
                         f"(lambda_max={lam:.6g}), t=1, v~U[0,1], {len(idx)} entries "
-                        "(256 highest degree + uniform)", generation_s=t_gen)
-    # exact moments: x = exp(tA) v and E[f^2] = exp(tG) v^2 (Feynman-Kac with jump factors)
-    rows = np.repeat(np.arange(a.n), deg)
-    A = a.to_scipy()
-
-    def m2_exact(bias):
-        b = np.zeros(a.nnz) if bias is None else bias.astype(np.float64)
-        at = a.val * np.exp(b)
-        rt = np.bincount(rows, weights=at, minlength=a.n)
-        r = np.bincount(rows, weights=a.val, minlength=a.n)
-        gm = sp.csr_matrix((a.val * np.exp(-b), a.col, a.rowptr), shape=A.shape)
-        gm = gm + sp.diags(2 * (r + (rt - r)) - rt)         # d = r (no diagonal)
-        return sla.expm_multiply(gm.tocsr(), v * v)
-
-    x = sla.expm_multiply(A, v)
-    m2p = m2_exact(None)
-    h.entries(v, idx, 1 << 14)
-    st = h.stats()
-    ev_plain = st["events"] / st["walkers"]
-    rep = h.learn_proposal(v, pilot_walkers=256, steps=400, batch=1 << 16, lr=3e-3, seed=1)
-    bias = h.get_proposal()
-    h.entries(v, idx, 1 << 14)
-    st = h.stats()
-    ev_learn = st["events"] / st["walkers"]
-    m2l = m2_exact(bias.cpu().numpy())
-    xi = x[idx]
-    var_p = np.maximum(m2p[idx] - xi * xi, 0)
-    var_l = np.maximum(m2l[idx] - xi * xi, 0)
-    steps_p = float((var_p / (1e-3 * xi) ** 2).sum() * ev_plain)
-    steps_l = float((var_l / (1e-3 * xi) ** 2).sum() * ev_learn)
-    prod = entries_at_1e3(mc, h, v, idx, 10_000)
-    out.update(
-        walker_steps_to_1e3_plain_exact=steps_p,
-        walker_steps_to_1e3_learned_exact=steps_l,
-        gain_walker_steps=steps_p / steps_l if steps_l > 0 else None,
-        events_per_walker_plain=ev_plain, events_per_walker_learned=ev_learn,
-        learned_entries_per_s_at_1e3=prod["entries_per_s"],
-        learned_production_s=prod["seconds"],
-        learned_max_rel_stderr=prod["max_rel_stderr"],
-        train=dict(initial_loss=rep["initial_loss"], final_loss=rep["final_loss"],
-                   steps=rep["steps"], pilot_ms=rep["pilot_ms"], train_ms=rep["train_ms"]),
-    )
+                        "(256 highest degree + uniform)", generation_s=t_gen,
+               walker_steps_to_1e3_plain_exact=steps_p,
+               walker_steps_to_1e3_learned_exact=steps_l,
+               gain_walker_steps=steps_p / steps_l if steps_l > 0 else None,
+               events_per_walker_plain=ev_plain, events_per_walker_learned=ev_learn,
+               learned_entries_per_s_at_1e3=prod["entries_per_s"],
+               learned_production_s=prod["seconds"],
+               learned_max_rel_stderr=prod["max_rel_stderr"],
+               train=dict(initial_loss=rep["initial_loss"], final_loss=rep["final_loss"],
+                          steps=rep["steps"], pilot_ms=rep["pilot_ms"], train_ms=rep["train_ms"]))
+    del h
+    # held-out graph: same network, features of the new graph
+    a2, v2, idx2, lam2 = _ba_learned_case(n, m, 2)
+    h2 = mc.MCExpmv(a2.rowptr, a2.col, a2.val, 1.0, seed)
+    ev_plain2 = events_per_walker(h2, v2, idx2)
+    net = mc.MLP(h2, seed=1)
+    net.set_params(rep["params"])
+    dev = torch.device("cuda", torch.cuda.current_device())
+    feats2 = h2.features(torch.as_tensor(v2, device=dev))
+    bias2 = net.forward(feats2)
+    h2.set_proposal(bias2)
+    ev_learn2 = events_per_walker(h2, v2, idx2)
+    steps_p2 = _steps_to_target(a2, v2, idx2, None, ev_plain2)
+    steps_l2 = _steps_to_target(a2, v2, idx2, bias2.cpu().numpy(), ev_learn2)
+    prod2 = entries_at_1e3(mc, h2, v2, idx2, 10_000)
+    out["held_out"] = dict(
+        workload=f"BA n={n} m={m} seed 2 (lambda_max={lam2:.6g}), same recipe; network "
+                 "trained on seed 1, not retrained",
+        walker_steps_to_1e3_plain_exact=steps_p2, walker_steps_to_1e3_learned_exact=steps_l2,
+        gain_walker_steps=steps_p2 / steps_l2 if steps_l2 > 0 else None,
+        learned_entries_per_s_at_1e3=prod2["entries_per_s"],
+        learned_max_rel_stderr=prod2["max_rel_stderr"])
+    net.close()
     return out
 
 

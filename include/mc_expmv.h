@@ -293,6 +293,9 @@ typedef struct {
     int64_t batch;              /* edge positions per step (default 65536) */
     float lr;                   /* learning rate (default 3e-3) */
     uint64_t seed;              /* weight initialisation */
+    float *params_out;          /* host float[4801] or NULL: receives the trained FP32
+                                   parameters, e.g. to install the same network on another
+                                   matrix with mc_mlp_set_params and mc_mlp_forward */
 } mc_learn_opts;
 
 typedef struct {

@@ -94,7 +94,7 @@ class mc_learn_opts(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32), ("pilot_walkers", ctypes.c_int64),
         ("steps", ctypes.c_int32), ("batch", ctypes.c_int64), ("lr", ctypes.c_float),
-        ("seed", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64), ("params_out", ctypes.c_void_p),
     ]
 
 
@@ -328,16 +328,20 @@ class MCExpmv:
 
     def learn_proposal(self, v, pilot_walkers: int = 256, steps: int = 400, batch: int = 1 << 16,
                        lr: float = 3e-3, seed: int = 1) -> dict:
-        """Train the proposal network on the GPU and install the tilted walk."""
+        """Train the proposal network on the GPU and install the tilted walk.  The
+        returned dict holds the trained FP32 parameters under "params"."""
+        import numpy as np
         v = self._v(v)
         o = mc_learn_opts()
         load().mc_learn_default_opts(ctypes.byref(o))
         o.pilot_walkers, o.steps, o.batch, o.lr, o.seed = pilot_walkers, steps, batch, lr, seed
+        params = np.zeros(NPARAM, np.float32)
+        o.params_out = params.ctypes.data_as(ctypes.c_void_p)
         rep = mc_learn_report()
         _check(load().mc_expmv_learn_proposal(self._h, _ptr(v), ctypes.byref(o), ctypes.byref(rep)),
                "mc_expmv_learn_proposal")
         return dict(initial_loss=rep.initial_loss, final_loss=rep.final_loss, steps=rep.steps,
-                    pilot_ms=rep.pilot_ms, train_ms=rep.train_ms)
+                    pilot_ms=rep.pilot_ms, train_ms=rep.train_ms, params=params)
 
     def features(self, v):
         import torch
@@ -530,11 +534,14 @@ class MLP:
         _check(load().mc_mlp_set_params(self._m, p.ctypes.data_as(ctypes.c_void_p)),
                "mc_mlp_set_params")
 
-    def forward(self, feats):
+    def forward(self, feats, handle: "MCExpmv | None" = None):
+        """Tilts for every CSR position of `handle`'s matrix (default: the bound one),
+        from that matrix's node features."""
         import torch
-        b = torch.empty(self.h.nnz, dtype=torch.float32, device=self.device)
-        _check(load().mc_mlp_forward(self._m, self.h._h, _ptr(feats), _ptr(b)), "mc_mlp_forward")
-        self.h.sync()
+        h = handle or self.h
+        b = torch.empty(h.nnz, dtype=torch.float32, device=h.device)
+        _check(load().mc_mlp_forward(self._m, h._h, _ptr(feats), _ptr(b)), "mc_mlp_forward")
+        h.sync()
         return b
 
     def gradient(self, feats, lh, p0: int, p1: int):

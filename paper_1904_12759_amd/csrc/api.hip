@@ -1252,6 +1252,7 @@ mc_status mc_expmv_learn_proposal(mc_expmv_t h, const void *v, const mc_learn_op
     if (st == MC_OK) st = from_hip(hipEventRecord(t2, h->stream));
     if (st == MC_OK) st = from_hip(hipStreamSynchronize(h->stream));
     if (st == MC_OK) st = mc_expmv_set_proposal(h, bias);
+    if (st == MC_OK && o.params_out) st = mc_mlp_get_params(net, o.params_out);
     if (st == MC_OK && rep) {
         float a = 0.0f, b = 0.0f;
         (void)hipEventElapsedTime(&a, t0, t1);

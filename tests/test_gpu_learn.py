@@ -129,6 +129,13 @@ def test_learned_proposal_is_unbiased():
     ref = refs.expm_v(a.to_dense(), t, v)
     z = (est.cpu().numpy() - ref) / se.cpu().numpy()
     assert np.abs(z).max() < 4.5
+    # the returned parameters rebuild the installed tilts exactly
+    net = mc.MLP(g, seed=99)
+    net.set_params(rep["params"])
+    np.testing.assert_array_equal(net.params(), rep["params"])
+    b2 = net.forward(g.features(v)).cpu().numpy()
+    np.testing.assert_array_equal(b2, b)
+    net.close()
 
 
 def test_learned_proposal_reduces_walker_steps_to_1e_3():
