@@ -84,6 +84,8 @@ def _load():
         lib.oracle_dt.restype = dbl
         lib.oracle_get_tables.argtypes = [vp, i32] + [vp] * 9
         lib.oracle_get_tables.restype = i32
+        lib.oracle_forward.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.oracle_forward.restype = i32
         lib.oracle_philox4x32_10.argtypes = [vp, vp, vp]
         lib.oracle_philox4x32_10.restype = None
         _lib = lib
@@ -189,6 +191,24 @@ class Oracle:
         if counts:
             return est, se, ev, ju
         return est, se
+
+    def forward(self, v, nwalk: int, walkers: bool = False):
+        """Forward estimator (Lemma 2, Theorem 2): per-node mean and standard error, the
+        mean of the walker values Y and its standard error, and with walkers=True the
+        per-walker (start, end, events, jumps, Y)."""
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        n = self.n
+        est = np.zeros(n)
+        se = np.zeros(n)
+        tot = np.zeros(2)
+        per = (np.zeros(nwalk, np.int32), np.zeros(nwalk, np.int32), np.zeros(nwalk, np.uint32),
+               np.zeros(nwalk, np.uint32), np.zeros(nwalk)) if walkers else (None,) * 5
+        st = _load().oracle_forward(self._h, _p(v), int(nwalk), 0, _p(est), _p(se), _p(tot[0:1]),
+                                    _p(tot[1:2]), *[_p(a) for a in per])
+        if st != 0:
+            raise OracleError(st)
+        out = (est, se, float(tot[0]), float(tot[1]))
+        return out + (per,) if walkers else out
 
     def tables(self, proposal: bool = False) -> dict:
         n, ns = self.n, self.nslots

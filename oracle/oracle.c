@@ -393,12 +393,18 @@ static double grid_coef(const oracle_t *o, int64_t k)
     return k == 0 ? 0.0 : 1.0;
 }
 
+/* Philox counter word that marks a forward walk in place of the start node. */
+#define FORWARD_MARK 0xFFFFFFFFu
+
 /* One walker started at node `start`, ordinal w.  The path is recorded as
  * the sequence of visited states and entry times, then the weight is formed
- * from the recorded path. */
-static void walk_one(const oracle_t *o, int64_t start, uint32_t w, const double *v,
-                     int use_prop, int64_t *path_x, double *path_s, double *path_c,
-                     walk_out *res)
+ * from the recorded path.  Backward walks (Algorithm 1) use the counters
+ * (k, w, start, instance), k = 0, 1, ...; forward walks (Algorithm 2) use
+ * (k, w, FORWARD_MARK, instance), k = 1, 2, ... (k = 0 drew the start) and
+ * read the grid coefficients in reverse time order, c_{N-k}. */
+static void walk_path(const oracle_t *o, int64_t start, uint32_t w, const double *v,
+                      int use_prop, int forward, int64_t *path_x, double *path_s,
+                      double *path_c, walk_out *res)
 {
     const table_set *ts = use_prop ? &o->prop : &o->plain;
     uint32_t key[2] = { (uint32_t)o->seed, (uint32_t)(o->seed >> 32) };
@@ -411,7 +417,8 @@ static void walk_one(const oracle_t *o, int64_t start, uint32_t w, const double 
     for (;;) {
         if (ts->deg[x] == 0) { ++events; break; }         /* rate 0: stays until t */
         if (events >= o->max_events) { res->status = OR_ERR_WALK_LIMIT; break; }
-        uint32_t ctr[4] = { events, w, (uint32_t)start, o->instance };
+        uint32_t ctr[4] = { forward ? events + 1u : events, w,
+                            forward ? FORWARD_MARK : (uint32_t)start, o->instance };
         uint32_t rnd[4];
         oracle_philox4x32_10(ctr, key, rnd);
         ++events;
@@ -453,7 +460,7 @@ static void walk_one(const oracle_t *o, int64_t start, uint32_t w, const double 
         int64_t m = 0;
         for (int64_t k = 0; k <= o->ngrid; ++k) {
             while (m < len && grid_index(o, path_s[m + 1]) <= k) ++m;
-            acc += grid_coef(o, k) * ts->d[path_x[m]];
+            acc += grid_coef(o, forward ? o->ngrid - k : k) * ts->d[path_x[m]];
         }
         logw = acc * o->dt;
     }
@@ -463,6 +470,13 @@ static void walk_one(const oracle_t *o, int64_t start, uint32_t w, const double 
     res->x_end = (int32_t)x;
     res->events = events;
     res->jumps = jumps;
+}
+
+static void walk_one(const oracle_t *o, int64_t start, uint32_t w, const double *v,
+                     int use_prop, int64_t *path_x, double *path_s, double *path_c,
+                     walk_out *res)
+{
+    walk_path(o, start, w, v, use_prop, 0, path_x, path_s, path_c, res);
 }
 
 /* Per-walker trace for parity checks: walkers w0 .. w0+count-1 from `start`. */
@@ -586,6 +600,113 @@ int oracle_estimate(const oracle_t *o, const double *v, const int64_t *idx, int6
     for (int tI = 0; tI < nthreads; ++tI)
         if (jobs[tI].status != OR_OK && st == OR_OK) st = jobs[tI].status;
     free(jobs); free(th);
+    return st;
+}
+
+/* ---------------------------------------------------- forward estimator */
+/* Full vector by forward walks (Lemma 2 and Theorem 2; Algorithm 2 with its
+ * update applied to the state where the walk ends).  Walker w (w = 0..M-1)
+ * draws its start j with probability |v_j| / V, V = sum_l |v_l|: with U from
+ * the counter (0, w, FORWARD_MARK, instance), j is the first node whose
+ * cumulative sum |v_0| + ... + |v_j| (taken in node order) reaches U V.  It
+ * then walks forward for time t and contributes Y = V sign(v_j) W to the entry
+ * of its end state X_t (the indicator of the terminal state in Theorem 2).
+ * E[Y 1{X_t = i}] = sum_j v_j (e^{tA})_{ji} = (e^{tA^T} v)_i, which is
+ * (e^{tA} v)_i for the symmetric A of the paper.  For v >= 0 this is Lemma 2's
+ * sampling; a sign carries negative entries.
+ * Outputs: est_i = (1/M) sum_w Y_w 1{end_w = i}; se_i = sqrt(s_i^2 / M) with s_i^2
+ * the sample variance of Y_w 1{end_w = i} over the M walkers; *sum, *sum_se =
+ * mean and standard error of Y (an estimate of sum_i x_i).  Per-walker
+ * arrays (nullable): start, end state, events, jumps, Y. */
+int oracle_forward(const oracle_t *o, const double *v, int64_t nwalk, int use_prop,
+                   double *est, double *se, double *sum, double *sum_se,
+                   int32_t *w_start, int32_t *w_end, uint32_t *w_events, uint32_t *w_jumps,
+                   double *w_y)
+{
+    if (nwalk <= 0 || nwalk > 0xFFFFFFFFll) return OR_ERR_INVALID_ARG;
+    if (use_prop) return OR_ERR_INVALID_ARG;
+    int64_t n = o->n;
+    double *cdf = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *s1 = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *c1 = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *s2 = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *c2 = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *ys = (double *)malloc(sizeof(double) * (size_t)nwalk);
+    size_t cap = (size_t)o->max_events + 2;
+    int64_t *px = (int64_t *)malloc(sizeof(int64_t) * cap);
+    double *ps = (double *)malloc(sizeof(double) * cap);
+    double *pc = (double *)malloc(sizeof(double) * cap);
+    int st = OR_OK;
+    if (!cdf || !s1 || !c1 || !s2 || !c2 || !ys || !px || !ps || !pc) { st = OR_ERR_NO_MEMORY; goto out; }
+    double V = 0.0;
+    for (int64_t j = 0; j < n; ++j) { V = V + fabs(v[j]); cdf[j] = V; }
+    uint32_t key[2] = { (uint32_t)o->seed, (uint32_t)(o->seed >> 32) };
+    for (int64_t w = 0; w < nwalk; ++w) {
+        double y = 0.0;
+        int32_t j = -1, x_end = -1;
+        walk_out r = { 0.0, 0.0, -1, 0, 0, OR_OK };
+        if (V > 0.0) {
+            uint32_t ctr[4] = { 0u, (uint32_t)w, FORWARD_MARK, o->instance };
+            uint32_t rnd[4];
+            oracle_philox4x32_10(ctr, key, rnd);
+            double target = uniform_open0(rnd[0], rnd[1]) * V;
+            int64_t lo = 0, hi = n - 1;             /* first j with cdf[j] >= target */
+            while (lo < hi) {
+                int64_t mid = lo + (hi - lo) / 2;
+                if (cdf[mid] >= target) hi = mid; else lo = mid + 1;
+            }
+            j = (int32_t)lo;
+            walk_path(o, lo, (uint32_t)w, v, 0, 1, px, ps, pc, &r);
+            if (r.status != OR_OK && st == OR_OK) st = r.status;
+            /* r.f = W v[X_t]; the forward value uses W alone */
+            y = V * (v[lo] > 0.0 ? 1.0 : -1.0) * exp(r.logw);
+            if (!isfinite(y) && st == OR_OK) st = OR_ERR_OVERFLOW;
+            x_end = r.x_end;
+            /* per-node compensated sums of Y and Y^2 (Neumaier) */
+            double *pairs[2][2] = { { s1, c1 }, { s2, c2 } };
+            double add[2] = { y, y * y };
+            for (int q = 0; q < 2; ++q) {
+                double *sq = pairs[q][0], *cq = pairs[q][1];
+                double a = sq[x_end], b = add[q], tt = a + b;
+                if (fabs(a) >= fabs(b)) cq[x_end] += (a - tt) + b;
+                else cq[x_end] += (b - tt) + a;
+                sq[x_end] = tt;
+            }
+        }
+        ys[w] = y;
+        if (w_start) w_start[w] = j;
+        if (w_end) w_end[w] = x_end;
+        if (w_events) w_events[w] = r.events;
+        if (w_jumps) w_jumps[w] = r.jumps;
+        if (w_y) w_y[w] = y;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double sy = s1[i] + c1[i], syy = s2[i] + c2[i];
+        double mean = sy / (double)nwalk;
+        if (est) est[i] = mean;
+        if (se) {
+            if (nwalk > 1) {
+                double var = (syy - (double)nwalk * mean * mean) / (double)(nwalk - 1);
+                se[i] = sqrt((var > 0.0 ? var : 0.0) / (double)nwalk);
+            } else {
+                se[i] = 0.0;
+            }
+        }
+    }
+    {
+        double mean = neumaier_sum(ys, nwalk) / (double)nwalk;
+        if (sum) *sum = mean;
+        if (sum_se) {
+            if (nwalk > 1) {
+                for (int64_t w = 0; w < nwalk; ++w) ys[w] = (ys[w] - mean) * (ys[w] - mean);
+                *sum_se = sqrt(neumaier_sum(ys, nwalk) / (double)(nwalk - 1) / (double)nwalk);
+            } else {
+                *sum_se = 0.0;
+            }
+        }
+    }
+out:
+    free(cdf); free(s1); free(c1); free(s2); free(c2); free(ys); free(px); free(ps); free(pc);
     return st;
 }
 

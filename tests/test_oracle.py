@@ -417,3 +417,99 @@ def test_exact_second_moment_matches_oracle_samples(tilted):
         emp = f2.mean()
         sd = f2.std() / np.sqrt(nw)
         assert abs(emp - m2[i]) < 4.5 * sd, (i, emp, m2[i], sd)
+
+
+# --------------------------------------------------- forward estimator
+# Lemma 2 / Theorem 2 / Algorithm 2: starts drawn with probability |v_j|/V, the
+# value V sign(v_j) W credited to the state where the walk ends.
+def test_forward_cycle_total_is_exact():
+    """On a cycle with weight beta, d = 2 beta everywhere, so every walker carries
+    exactly V e^{2 beta t}: the mean of Y is n e^{2 beta t} = (1, e^{tA} 1) with zero
+    variance, and the per-node estimates add up to it."""
+    n, beta, t = 12, 0.3, 1.3
+    c = wl.cycle_graph(n, beta)
+    o = Oracle(c.rowptr, c.col, c.val, t, 5)
+    est, se, tot, tse = o.forward(np.ones(n), 5000)
+    exact = n * np.exp(2 * beta * t)
+    assert tot == pytest.approx(exact, rel=1e-14) and tse < 1e-12 * exact
+    assert est.sum() == pytest.approx(exact, rel=1e-13)
+    ref = refs.cycle_expm_v(n, beta, 0.0, t, np.ones(n))
+    assert np.abs((est - ref) / se).max() < 4.5
+
+
+def test_forward_matches_dense_expm_symmetric():
+    n = 40
+    a = refs.random_metzler(n, 0.2, 11, symmetric=True, off_scale=1.0)
+    t = 0.8
+    v = np.random.default_rng(12).uniform(-1, 2, n)       # negative entries carry a sign
+    csr = wl.from_dense(a)
+    o = Oracle(csr.rowptr, csr.col, csr.val, t, 31)
+    est, se, tot, tse = o.forward(v, 400_000)
+    ref = refs.expm_v(a, t, v)
+    z = _zscores(est, se, ref)
+    assert np.abs(z).max() < 4.5 and abs(np.mean(z ** 2) - 1) < 0.5
+    assert abs(tot - ref.sum()) < 4.5 * tse
+
+
+def test_forward_estimates_transpose_action():
+    """Without symmetry the forward walks estimate e^{tA^T} v (Kolmogorov forward
+    equation); for this matrix e^{tA} v is many standard errors away."""
+    n = 30
+    a = refs.random_metzler(n, 0.3, 21, symmetric=False, off_scale=1.5)
+    t = 1.0
+    v = np.random.default_rng(22).uniform(0.2, 1.0, n)
+    csr = wl.from_dense(a)
+    o = Oracle(csr.rowptr, csr.col, csr.val, t, 32)
+    est, se, _, _ = o.forward(v, 400_000)
+    zt = _zscores(est, se, refs.expm_v(a.T, t, v))
+    assert np.abs(zt).max() < 4.5
+    assert np.mean(_zscores(est, se, refs.expm_v(a, t, v)) ** 2) > 25.0
+
+
+def test_forward_start_law():
+    """Starts follow |v_j| / V (chi-square), nodes with v_j = 0 are never drawn, and with
+    t = 0 every walker stays at its start, so each Y is exactly V sign(v_start)."""
+    n = 16
+    a = refs.random_metzler(n, 0.3, 5, symmetric=True)
+    csr = wl.from_dense(a)
+    v = np.random.default_rng(6).uniform(-1, 1, n)
+    v[[3, 9]] = 0.0
+    V = np.abs(v).sum()
+    m = 200_000
+    o = Oracle(csr.rowptr, csr.col, csr.val, 0.0, 7)
+    est, se, tot, tse, (st, en, ev, ju, y) = o.forward(v, m, walkers=True)
+    assert np.array_equal(st, en) and (ju == 0).all()
+    np.testing.assert_allclose(y, V * np.sign(v[st]), rtol=1e-14)
+    assert len(np.unique(y)) <= 2
+    counts = np.bincount(st, minlength=n)
+    assert counts[3] == 0 and counts[9] == 0
+    p = np.abs(v) / V
+    keep = p > 0
+    chi2 = (((counts - m * p) ** 2)[keep] / (m * p[keep])).sum()
+    assert chi2 < 45.0        # 13 degrees of freedom: P(chi2 > 45) < 1e-4
+    z = _zscores(est, np.where(se > 0, se, 1.0), v)
+    assert np.abs(z).max() < 4.5
+
+
+@pytest.mark.parametrize("mode,nsteps", [(STRANG, 4), (LIE, 4), (LIE, 3)])
+def test_forward_split_modes_match_split_products(mode, nsteps):
+    """With the grid coefficients read in reverse time order, the forward STRANG/LIE
+    estimators are unbiased for the same split products as the backward ones (symmetric A)."""
+    n = 24
+    a = refs.random_metzler(n, 0.25, 7, symmetric=True, off_scale=1.5, diag_scale=2.0)
+    t = 1.0
+    v = np.random.default_rng(8).uniform(0.5, 1.5, n)
+    csr = wl.from_dense(a)
+    o = Oracle(csr.rowptr, csr.col, csr.val, t, 78, mode=mode, dt=t / nsteps)
+    est, se, _, _ = o.forward(v, 600_000)
+    ref = (refs.strang_v if mode == STRANG else refs.lie_v)(a, t, nsteps, v)
+    z = _zscores(est, se, ref)
+    assert np.abs(z).max() < 4.5
+    assert np.mean(_zscores(est, se, refs.expm_v(a, t, v)) ** 2) > 5.0
+
+
+def test_forward_zero_vector():
+    csr = wl.cycle_graph(6, 1.0)
+    o = Oracle(csr.rowptr, csr.col, csr.val, 1.0, 1)
+    est, se, tot, tse = o.forward(np.zeros(6), 100)
+    assert not est.any() and not se.any() and tot == 0.0 and tse == 0.0

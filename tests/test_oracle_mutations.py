@@ -65,6 +65,13 @@ MUTANTS = [
      "dev[w] = fs[w] * fs[w];"),
     ("negative rates accepted", "else if (col[p] != i && val[p] < 0.0) bad_sign = 1;",
      "else if (col[p] != i && val[p] < -1.0) bad_sign = 1;"),
+    ("forward starts weighted by v, not |v|", "V = V + fabs(v[j]);", "V = V + v[j];"),
+    ("forward value without the sign", "y = V * (v[lo] > 0.0 ? 1.0 : -1.0) * exp(r.logw);",
+     "y = V * exp(r.logw);"),
+    ("forward value credited to the start", "x_end = r.x_end;", "x_end = (int32_t)lo;"),
+    ("forward grid not reversed",
+     "acc += grid_coef(o, forward ? o->ngrid - k : k) * ts->d[path_x[m]];",
+     "acc += grid_coef(o, k) * ts->d[path_x[m]];"),
 ]
 
 
