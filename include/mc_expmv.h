@@ -52,7 +52,7 @@ typedef enum {
     MC_ERR_NOT_METZLER = 2,   /* an off-diagonal entry is negative (not a jump rate) */
     MC_ERR_NONFINITE = 3,     /* NaN or Inf in A, t, dt or a proposal bias */
     MC_ERR_OUT_OF_RANGE = 4,  /* a requested entry index is outside [0, n) */
-    MC_ERR_NOT_SYMMETRIC = 5, /* reserved for the forward (Algorithm 2) estimator */
+    MC_ERR_NOT_SYMMETRIC = 5, /* the forward (Algorithm 2) estimator needs A == A^T */
     MC_ERR_NO_MEMORY = 6,     /* a device or host allocation failed */
     MC_ERR_DEVICE = 7,        /* a HIP runtime call failed */
     MC_ERR_WALK_LIMIT = 8,    /* a walker reached opts.max_events holding intervals */
@@ -137,6 +137,38 @@ mc_status mc_expmv_entries(mc_expmv_t h, const void *v, const int64_t *idx, int6
  */
 mc_status mc_expmv_full(mc_expmv_t h, const void *v, int64_t n_per_node, double *est,
                         double *stderr_);
+
+/*
+ * The full vector by forward walks (Lemma 2 and Theorem 2, Algorithm 2, with
+ * the update credited to the state where each walk ends): n_walkers walkers
+ * w = 0 .. M-1 draw their start j with probability |v_j| / V, V = sum_l |v_l|
+ * (the first node whose cumulative sum of |v| in node order reaches U V, U
+ * from the Philox counter (0, w, 0xFFFFFFFF, instance id)), walk forward with
+ * counters (k, w, 0xFFFFFFFF, instance id), k = 1, 2, ..., and contribute
+ * Y = V sign(v_j) W to the entry of their state at t.  The STRANG and LIE
+ * grid coefficients are read in reverse time order, so every mode estimates
+ * the same vector as the backward estimator.  A must be symmetric (checked on
+ * the first call of a handle, synchronously; MC_ERR_NOT_SYMMETRIC otherwise):
+ * then the forward and backward chains coincide, as the paper notes before
+ * Lemma 2.  The tilted proposal, if installed, is not used.
+ *   v        device double[n] (float[n] with MC_FP32 weights), any signs
+ *   est      device double[n]: (1/M) sum_w Y_w 1{X_t = i}
+ *   stderr_  device double[n] or NULL: sqrt(s_i^2 / M), s_i^2 the sample
+ *            variance of Y_w 1{X_t = i} over the M walkers
+ *   sum_out  device double[2] or NULL: mean of Y (an estimate of sum_i x_i, the
+ *            total communicability (1, e^A 1) when t = 1 and v = 1, Eq. (TC))
+ *            and its standard error
+ * Per-node sums use FP64 atomics: two runs agree to rounding, not bitwise;
+ * sum_out is bitwise reproducible.  Device errors as for the other entry points.
+ */
+mc_status mc_expmv_forward(mc_expmv_t h, const void *v, int64_t n_walkers, double *est,
+                           double *stderr_, double *sum_out);
+
+/* Per-walker record of forward walkers w0 .. w0+count-1 (parity checks): start
+ * node, end node, holding intervals, jumps and Y, each a device array[count]. */
+mc_status mc_expmv_forward_trace(mc_expmv_t h, const void *v, int64_t w0, int64_t count,
+                                 int32_t *start, int32_t *end, uint32_t *events, uint32_t *jumps,
+                                 double *y);
 
 /*
  * Install a tilted proposal (importance sampling; variance reduction is the

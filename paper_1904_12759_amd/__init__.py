@@ -121,6 +121,10 @@ _SIGS = {
                                         ctypes.c_void_p]),
     "mc_expmv_full": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_expmv_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_expmv_forward_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                              ctypes.c_int64] + [ctypes.c_void_p] * 5),
     "mc_expmv_set_proposal": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_get_proposal": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_sync": (ctypes.c_int, [ctypes.c_void_p]),
@@ -306,6 +310,42 @@ class MCExpmv:
         if sync:
             self.sync()
         return est, stderr
+
+    def forward(self, v, n_walkers: int, est=None, stderr=None, total=None, sync: bool = True):
+        """Forward estimator (Lemma 2, Theorem 2, Algorithm 2; A must be symmetric):
+        per-node mean and standard error, and a device double[2] with the mean of the
+        walker values (an estimate of sum_i x_i) and its standard error."""
+        import torch
+        v = self._v(v)
+        if est is None:
+            est = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        if stderr is None:
+            stderr = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        if total is None:
+            total = torch.empty(2, dtype=torch.float64, device=self.device)
+        _require_cuda(v, est, stderr, total)
+        _check(load().mc_expmv_forward(self._h, _ptr(v), int(n_walkers), _ptr(est), _ptr(stderr),
+                                       _ptr(total)), "mc_expmv_forward")
+        if sync:
+            self.sync()
+        return est, stderr, total
+
+    def forward_trace(self, v, w0: int, count: int):
+        """Per-walker (start, end, events, jumps, Y) of forward walkers w0..w0+count-1."""
+        import torch
+        v = self._v(v)
+        d = self.device
+        st = torch.empty(count, dtype=torch.int32, device=d)
+        en = torch.empty(count, dtype=torch.int32, device=d)
+        ev = torch.empty(count, dtype=torch.int32, device=d)
+        ju = torch.empty(count, dtype=torch.int32, device=d)
+        y = torch.empty(count, dtype=torch.float64, device=d)
+        _check(load().mc_expmv_forward_trace(self._h, _ptr(v), int(w0), int(count), _ptr(st),
+                                             _ptr(en), _ptr(ev), _ptr(ju), _ptr(y)),
+               "mc_expmv_forward_trace")
+        self.sync()
+        return (st.cpu().numpy(), en.cpu().numpy(), ev.cpu().numpy().view("uint32"),
+                ju.cpu().numpy().view("uint32"), y.cpu().numpy())
 
     def set_proposal(self, edge_bias):
         import torch

@@ -41,6 +41,15 @@ struct mc_expmv_s {
     uint32_t hot = 0;                    // walk ids staged in LDS (lds_budget)
     float *bias = nullptr;               // copy of the installed proposal's edge biases
     bool last_fp32 = false, last_prop = false;
+    // forward estimator
+    int sym_state = -1;                  // A == A^T: -1 not checked yet, 0 no, 1 yes
+    double *fwd_abs = nullptr, *fwd_cdf = nullptr;   // [n] |v| and its cumulative sums
+    void *fwd_temp = nullptr;            // scan scratch
+    size_t fwd_temp_bytes = 0;
+    double *fwd_part = nullptr;          // chunk partials of Y
+    int64_t fwd_part_cap = 0;
+    double *fwd_acc = nullptr;           // [n] sums for trace runs
+    bool last_fwd = false;
 };
 
 namespace {
@@ -246,6 +255,7 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
     h->last_grid = a.ntasks > 0 ? launch_walk_grid(a.ntasks, (int)h->opts.walkers_per_block) : 0;
     h->last_fp32 = fp32;
     h->last_prop = prop;
+    h->last_fwd = false;
     return MC_OK;
 }
 
@@ -301,6 +311,11 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->bias);
     (void)hipFree(h->perm);
     (void)hipFree(h->inv);
+    (void)hipFree(h->fwd_abs);
+    (void)hipFree(h->fwd_cdf);
+    (void)hipFree(h->fwd_temp);
+    (void)hipFree(h->fwd_part);
+    (void)hipFree(h->fwd_acc);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
@@ -524,6 +539,12 @@ mc_status mc_expmv_stats(mc_expmv_t h, mc_expmv_run_stats *out) {
     const double row = 16.0 + dbytes;
     const double slot = 12.0 + (h->last_prop ? 8.0 : 0.0);
     out->alg_bytes = row * (double)(c[0]) + slot * (double)c[1] + dbytes * (double)h->last_walkers;
+    if (h->last_fwd) {
+        // forward walks: per walker also the binary search over the cumulative
+        // sums (8 B per step) and two FP64 read-modify-writes at the end node
+        const double steps = h->n > 1 ? ceil(log2((double)h->n)) : 0.0;
+        out->alg_bytes += (8.0 * steps + 32.0) * (double)h->last_walkers;
+    }
     return MC_OK;
 }
 
@@ -1273,6 +1294,111 @@ mc_status mc_expmv_learn_proposal(mc_expmv_t h, const void *v, const mc_learn_op
     if (t1) (void)hipEventDestroy(t1);
     if (t2) (void)hipEventDestroy(t2);
     return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ forward estimator
+namespace {
+
+// A == A^T (summed duplicates compared exactly), checked once per handle.
+mc_status check_symmetric(mc_expmv_s *h) {
+    if (h->sym_state >= 0) return h->sym_state ? MC_OK : MC_ERR_NOT_SYMMETRIC;
+    HIP_TRY(ensure_rowof(h));
+    uint32_t *flag = nullptr;
+    HIP_TRY(dalloc(&flag, 1));
+    uint32_t f = 0;
+    hipError_t e = hipMemcpyAsync(flag, &f, sizeof(f), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = launch_check_symmetric(h->nnz, h->rowptr, h->rowof, h->col, h->val, flag, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&f, flag, sizeof(f), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(flag);
+    HIP_TRY(e);
+    h->sym_state = f ? 0 : 1;
+    return f ? MC_ERR_NOT_SYMMETRIC : MC_OK;
+}
+
+mc_status run_forward(mc_expmv_s *h, const void *v, int64_t w0, int64_t nwalk, double *acc1,
+                      double *acc2, double *sum_out, bool trace, int32_t *ts, int32_t *te,
+                      uint32_t *tev, uint32_t *tju, double *ty) {
+    if (!v || !acc1 || nwalk < 1 || nwalk > 0xFFFFFFFFll || w0 < 0 ||
+        w0 + nwalk > 0x100000000ll)
+        return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    mc_status st = check_symmetric(h);
+    if (st != MC_OK) return st;
+    const bool fp32 = h->opts.weight_prec == MC_FP32;
+    const int64_t n = h->n;
+    if (n > 0 && !h->fwd_cdf) {
+        HIP_TRY(dalloc(&h->fwd_abs, n));
+        HIP_TRY(dalloc(&h->fwd_cdf, n));
+        size_t bytes = 0;
+        HIP_TRY(launch_fwd_cdf(n, v, fp32, h->fwd_abs, h->fwd_cdf, nullptr, bytes, h->stream));
+        HIP_TRY(hipMalloc(&h->fwd_temp, bytes > 0 ? bytes : 1));
+        h->fwd_temp_bytes = bytes;
+    }
+    const int64_t chunks = (nwalk + kFwdChunk - 1) / kFwdChunk;
+    if (chunks * 3 > h->fwd_part_cap) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        (void)hipFree(h->fwd_part);
+        h->fwd_part = nullptr;
+        h->fwd_part_cap = 0;
+        HIP_TRY(dalloc(&h->fwd_part, chunks * 3));
+        h->fwd_part_cap = chunks * 3;
+    }
+    HIP_TRY(hipEventRecord(h->ev0, h->stream));
+    if (n > 0) {
+        size_t bytes = h->fwd_temp_bytes;
+        HIP_TRY(launch_fwd_cdf(n, v, fp32, h->fwd_abs, h->fwd_cdf, h->fwd_temp, bytes, h->stream));
+    }
+    FwdArgs a{};
+    fill_inst(h, v, false, a.P);
+    a.P.hot = 0;
+    a.n = n;
+    a.nwalk = nwalk;
+    a.w0 = w0;
+    a.chunks = chunks;
+    a.cdf = h->fwd_cdf;
+    a.acc1 = acc1;
+    a.acc2 = acc2;
+    a.part = h->fwd_part;
+    a.counters = h->counters;
+    a.flags = h->flags;
+    a.t_start = ts;
+    a.t_end = te;
+    a.t_ev = tev;
+    a.t_ju = tju;
+    a.t_y = ty;
+    HIP_TRY(launch_forward(a, h->opts.mode, fp32, trace, sum_out, h->stream));
+    HIP_TRY(hipEventRecord(h->ev1, h->stream));
+    h->ran = true;
+    h->last_walkers = (uint64_t)nwalk;
+    h->last_grid = forward_grid(chunks);
+    h->last_fp32 = fp32;
+    h->last_prop = false;
+    h->last_fwd = true;
+    return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mc_status mc_expmv_forward(mc_expmv_t h, const void *v, int64_t n_walkers, double *est,
+                           double *stderr_, double *sum_out) {
+    if (!h || !est) return MC_ERR_INVALID_ARG;
+    return run_forward(h, v, 0, n_walkers, est, stderr_, sum_out, false, nullptr, nullptr,
+                       nullptr, nullptr, nullptr);
+}
+
+mc_status mc_expmv_forward_trace(mc_expmv_t h, const void *v, int64_t w0, int64_t count,
+                                 int32_t *start, int32_t *end, uint32_t *events, uint32_t *jumps,
+                                 double *y) {
+    if (!h || !start || !end || !events || !jumps || !y) return MC_ERR_INVALID_ARG;
+    if (!h->fwd_acc && h->n > 0) HIP_TRY(dalloc(&h->fwd_acc, h->n));
+    return run_forward(h, v, w0, count, h->fwd_acc, nullptr, nullptr, true, start, end, events,
+                       jumps, y);
 }
 
 }  // extern "C"

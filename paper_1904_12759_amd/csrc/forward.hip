@@ -1,0 +1,339 @@
+// The forward estimator of the full vector (paper Lemma 2, Theorem 2 and
+// Algorithm 2): walkers start at node j with probability |v_j| / V,
+// V = sum_l |v_l|, evolve forward in time under the same jump law (the
+// generator is symmetric, so forward and backward chains coincide), and add
+// V sign(v_j) W to the entry of the state where they stop at t.  The value
+// credited to node i is then an unbiased estimate of (e^{tA^T} v)_i, which is
+// (e^{tA} v)_i for the symmetric A the paper assumes (the library checks it).
+//
+// Random numbers: walker w draws its start from the Philox counter
+// (0, w, 0xFFFFFFFF, instance) and its k-th holding interval (k = 1, 2, ...)
+// from (k, w, 0xFFFFFFFF, instance); 0xFFFFFFFF is never a node id, so these
+// streams are disjoint from every backward walk.
+//
+// Work decomposition: a task is a chunk of kFwdChunk consecutive walker
+// ordinals, one wavefront per task, one walker per lane with lane refill.
+// Each finished walker adds Y and Y^2 to its end node with FP64 atomics (so
+// per-node sums are exact up to the order of the additions) and writes Y to
+// the LDS slot of its ordinal; the chunk's (count, mean, M2) of Y comes from a
+// fixed-order two-pass sum and the chunks merge in order, so the estimate of
+// sum_i x_i is bitwise reproducible.
+#include <math.h>
+
+#include <hipcub/hipcub.hpp>
+
+#include "walk_task.hpp"
+
+namespace mc {
+
+namespace {
+
+constexpr uint32_t kFwdMark = 0xFFFFFFFFu;
+
+// Sum of the grid coefficients c_{N-k} over ka <= k <= kb: the backward
+// coefficients read in reverse time order.
+template <int MODE>
+__device__ __forceinline__ double grid_coef_sum_rev(int32_t ka, int32_t kb, int32_t ngrid) {
+    if (kb < ka) return 0.0;
+    return grid_coef_sum<MODE>(ngrid - kb, ngrid - ka, ngrid);
+}
+
+// Start node of walker w: the first j with cdf[j] >= U V (binary search).
+__device__ __forceinline__ uint32_t draw_start(const FwdArgs &a, uint32_t w, double V) {
+    const U4 o = philox(0u, w, kFwdMark, a.P.inst, a.P.key0, a.P.key1);
+    const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
+    const double target = (double)(m + 1ull) * 0x1p-53 * V;
+    int64_t lo = 0, hi = a.n - 1;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (a.cdf[mid] >= target) hi = mid;
+        else lo = mid + 1;
+    }
+    return (uint32_t)lo;
+}
+
+template <int MODE, bool FP32, bool TRACE>
+__global__ __launch_bounds__(64) void k_forward(FwdArgs a) {
+    using WT = typename WeightT<FP32>::T;
+    __shared__ double ys[kFwdChunk];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned long long lanemask_lt = (1ull << lane) - 1ull;
+    const InstArgs &P = a.P;
+    const double t = P.t;
+    const double V = a.n > 0 ? a.cdf[a.n - 1] : 0.0;
+    unsigned long long evs = 0, jus = 0;
+    uint32_t err = 0;
+    for (int64_t c = blockIdx.x; c < a.chunks; c += gridDim.x) {
+        const int64_t wbase = c * (int64_t)kFwdChunk;
+        const int64_t rem = a.nwalk - wbase;
+        const uint32_t cnt = (uint32_t)(rem < (int64_t)kFwdChunk ? rem : (int64_t)kFwdChunk);
+        const uint32_t ord0 = (uint32_t)(a.w0 + wbase);
+        if (!(V > 0.0)) {
+            // v = 0: every walker contributes 0
+            for (uint32_t i = lane; i < cnt; i += WAVE) {
+                ys[i] = 0.0;
+                if constexpr (TRACE) {
+                    a.t_start[wbase + i] = -1;
+                    a.t_end[wbase + i] = -1;
+                    a.t_ev[wbase + i] = 0;
+                    a.t_ju[wbase + i] = 0;
+                    a.t_y[wbase + i] = 0.0;
+                }
+            }
+        } else {
+            // walker state of this lane
+            uint32_t wl = (uint32_t)lane;
+            bool active = wl < cnt;
+            uint32_t j = 0, x = 0, ev = 0, ju = 0, deg = 0, begin = 0;
+            double s = 0.0, inv_r = 0.0, sgn = 1.0;
+            int32_t ka = 0;
+            WT logw = (WT)0, dx = (WT)0;
+            auto start = [&](uint32_t i) {
+                j = draw_start(a, ord0 + i, V);
+                sgn = (double)load_v<FP32>(P.v, j) > 0.0 ? 1.0 : -1.0;
+                x = P.perm ? P.perm[j] : j;
+                const RowRec rr = P.rows[x];
+                inv_r = rr.inv_r;
+                deg = rr.deg;
+                begin = rr.begin;
+                dx = load_d<FP32>(P, x);
+                s = 0.0;
+                logw = (WT)0;
+                ev = 0;
+                ju = 0;
+                ka = 0;
+            };
+            if (active) start(wl);
+            uint32_t next = WAVE;
+            while (__ballot(active) != 0ull) {
+                bool fin = false;
+                if (active) {
+                    if (deg == 0) {
+                        ++ev;
+                        fin = true;
+                    } else if (ev >= P.max_events) {
+                        err |= F_WALK_LIMIT;
+                        fin = true;
+                    } else {
+                        const U4 o = philox(ev + 1u, ord0 + wl, kFwdMark, P.inst, P.key0, P.key1);
+                        ++ev;
+                        const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
+                        const double U = (double)(m + 1ull) * 0x1p-53;
+                        const double S = -log_unit(U) * inv_r;
+                        const double sn = s + S;
+                        if (sn < t) {
+                            if constexpr (MODE == MC_EXACT) {
+                                logw = logw + dx * (WT)S;
+                            } else {
+                                const int32_t kb = grid_index(sn, P.inv_dt, P.ngrid);
+                                const double cs = grid_coef_sum_rev<MODE>(ka, kb - 1, P.ngrid);
+                                logw = logw + dx * (WT)(cs * P.dt);
+                                ka = kb;
+                            }
+                            s = sn;
+                            const uint32_t sl = (uint32_t)(((uint64_t)o.z * (uint64_t)deg) >> 32);
+                            const SlotRec q = P.slots[begin + sl];
+                            x = (uint32_t)(o.w < q.thr ? q.self : q.alias);
+                            ++ju;
+                            const RowRec rr = P.rows[x];
+                            inv_r = rr.inv_r;
+                            deg = rr.deg;
+                            begin = rr.begin;
+                            dx = load_d<FP32>(P, x);
+                        } else {
+                            fin = true;
+                        }
+                    }
+                    if (fin) {
+                        if constexpr (MODE == MC_EXACT) {
+                            logw = logw + dx * (WT)(t - s);
+                        } else {
+                            const double cs = grid_coef_sum_rev<MODE>(ka, P.ngrid, P.ngrid);
+                            logw = logw + dx * (WT)(cs * P.dt);
+                        }
+                        const double y = V * sgn * (double)wexp<FP32>(logw);
+                        if (!isfinite(y)) err |= F_OVERFLOW;
+                        const uint32_t xe = P.inv ? P.inv[x] : x;
+                        unsafeAtomicAdd(a.acc1 + xe, y);
+                        if (a.acc2) unsafeAtomicAdd(a.acc2 + xe, y * y);
+                        ys[wl] = y;
+                        evs += ev;
+                        jus += ju;
+                        if constexpr (TRACE) {
+                            a.t_start[wbase + wl] = (int32_t)j;
+                            a.t_end[wbase + wl] = (int32_t)xe;
+                            a.t_ev[wbase + wl] = ev;
+                            a.t_ju[wbase + wl] = ju;
+                            a.t_y[wbase + wl] = y;
+                        }
+                    }
+                }
+                const unsigned long long fmask = __ballot(fin);
+                if (fin) {
+                    wl = next + (uint32_t)__popcll(fmask & lanemask_lt);
+                    if (wl < cnt) start(wl);
+                    else active = false;
+                }
+                next += (uint32_t)__popcll(fmask);
+            }
+        }
+        __syncthreads();
+        // chunk statistics of Y in ordinal order: two passes, fixed DPP tree
+        double s1 = 0.0;
+        for (uint32_t i = lane; i < cnt; i += WAVE) s1 += ys[i];
+        const double mean = wave_sum_f64(s1) / (double)cnt;
+        double s2 = 0.0;
+        for (uint32_t i = lane; i < cnt; i += WAVE) {
+            const double dv = ys[i] - mean;
+            s2 += dv * dv;
+        }
+        const double m2 = wave_sum_f64(s2);
+        if (lane == 0) {
+            a.part[3 * c] = (double)cnt;
+            a.part[3 * c + 1] = mean;
+            a.part[3 * c + 2] = m2;
+        }
+        __syncthreads();
+    }
+    for (int off = 1; off < WAVE; off <<= 1) err |= __shfl_xor(err, off, WAVE);
+    if (err && lane == 0) atomicOr(a.flags, err);
+    const unsigned long long e = wave_sum_u64(evs), jn = wave_sum_u64(jus);
+    if (lane == 0) {
+        a.counters[2 * blockIdx.x] = e;
+        a.counters[2 * blockIdx.x + 1] = jn;
+    }
+}
+
+// acc1 = acc2 = 0 (a kernel, so the sequence can be captured in a graph).
+__global__ void k_fwd_zero(int64_t n, double *acc1, double *acc2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    acc1[i] = 0.0;
+    if (acc2) acc2[i] = 0.0;
+}
+
+// |v| in FP64, the input of the cumulative sums.
+template <bool FP32>
+__global__ void k_fwd_absv(int64_t n, const void *v, double *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = fabs((double)load_v<FP32>(v, (uint32_t)i));
+}
+
+// Per-node mean and standard error from the sums of Y and Y^2, in place.
+__global__ void k_fwd_finish(int64_t n, int64_t m, double *acc1, double *acc2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double mean = acc1[i] / (double)m;
+    acc1[i] = mean;
+    if (acc2) {
+        if (m > 1) {
+            const double var = (acc2[i] - (double)m * mean * mean) / (double)(m - 1);
+            acc2[i] = sqrt((var > 0.0 ? var : 0.0) / (double)m);
+        } else {
+            acc2[i] = 0.0;
+        }
+    }
+}
+
+// Mean and standard error of Y over all walkers: fin_lanes(chunks) lanes merge
+// the chunk partials in order (one wave).
+__global__ __launch_bounds__(64) void k_fwd_total(int64_t chunks, const double *part,
+                                                  double *sum_out) {
+    const uint32_t L = fin_lanes(chunks);
+    const uint32_t sub = threadIdx.x;
+    double n, mean, m2;
+    // lanes beyond the first group merge nothing but take part in the shuffles
+    fin_merge(sub < L ? part : nullptr, sub < L ? chunks : 0, L, sub % L, n, mean, m2);
+    if (sub == 0) {
+        sum_out[0] = mean;
+        sum_out[1] = n > 1.0 ? sqrt(m2 / (n - 1.0) / n) : 0.0;
+    }
+}
+
+// A == A^T: for every stored off-diagonal position (i, j), the sum of the
+// stored entries (i, j) equals the sum of the stored entries (j, i).
+__global__ void k_check_symmetric(int64_t nnz, const int64_t *__restrict__ rowptr,
+                                  const int32_t *__restrict__ rowof,
+                                  const int32_t *__restrict__ col, const double *__restrict__ val,
+                                  uint32_t *flag) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    const int32_t i = rowof[p], j = col[p];
+    if (i == j) return;
+    double sij = 0.0, sji = 0.0;
+    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q)
+        if (col[q] == j) sij += val[q];
+    for (int64_t q = rowptr[j]; q < rowptr[j + 1]; ++q)
+        if (col[q] == i) sji += val[q];
+    if (!(sij == sji)) atomicOr(flag, 1u);
+}
+
+}  // namespace
+
+hipError_t launch_check_symmetric(int64_t nnz, const int64_t *rowptr, const int32_t *rowof,
+                                  const int32_t *col, const double *val, uint32_t *flag,
+                                  hipStream_t s) {
+    if (nnz == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_symmetric, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz,
+                       rowptr, rowof, col, val, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_cdf(int64_t n, const void *v, bool fp32, double *absv, double *cdf,
+                          void *temp, size_t &temp_bytes, hipStream_t s) {
+    if (!temp) return hipcub::DeviceScan::InclusiveSum(nullptr, temp_bytes, absv, cdf, (int)n, s);
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (fp32) hipLaunchKernelGGL(k_fwd_absv<true>, dim3(g), dim3(256), 0, s, n, v, absv);
+    else hipLaunchKernelGGL(k_fwd_absv<false>, dim3(g), dim3(256), 0, s, n, v, absv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipcub::DeviceScan::InclusiveSum(temp, temp_bytes, absv, cdf, (int)n, s);
+}
+
+int forward_grid(int64_t chunks) {
+    int64_t g = chunks < (int64_t)kMaxWalkGrid ? chunks : (int64_t)kMaxWalkGrid;
+    return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_forward(const FwdArgs &a, int mode, bool fp32, bool trace, double *sum_out,
+                          hipStream_t s) {
+    const unsigned gz = (unsigned)((a.n + 255) / 256);
+    if (a.n > 0) {
+        hipLaunchKernelGGL(k_fwd_zero, dim3(gz), dim3(256), 0, s, a.n, a.acc1, a.acc2);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid((unsigned)forward_grid(a.chunks)), block(64);
+#define MC_FWD(M, F, T) hipLaunchKernelGGL((k_forward<M, F, T>), grid, block, 0, s, a)
+    switch (mode * 4 + (fp32 ? 2 : 0) + (trace ? 1 : 0)) {
+        case MC_EXACT * 4 + 0: MC_FWD(MC_EXACT, false, false); break;
+        case MC_EXACT * 4 + 1: MC_FWD(MC_EXACT, false, true); break;
+        case MC_EXACT * 4 + 2: MC_FWD(MC_EXACT, true, false); break;
+        case MC_EXACT * 4 + 3: MC_FWD(MC_EXACT, true, true); break;
+        case MC_STRANG * 4 + 0: MC_FWD(MC_STRANG, false, false); break;
+        case MC_STRANG * 4 + 1: MC_FWD(MC_STRANG, false, true); break;
+        case MC_STRANG * 4 + 2: MC_FWD(MC_STRANG, true, false); break;
+        case MC_STRANG * 4 + 3: MC_FWD(MC_STRANG, true, true); break;
+        case MC_LIE * 4 + 0: MC_FWD(MC_LIE, false, false); break;
+        case MC_LIE * 4 + 1: MC_FWD(MC_LIE, false, true); break;
+        case MC_LIE * 4 + 2: MC_FWD(MC_LIE, true, false); break;
+        case MC_LIE * 4 + 3: MC_FWD(MC_LIE, true, true); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef MC_FWD
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (a.n > 0) {
+        hipLaunchKernelGGL(k_fwd_finish, dim3(gz), dim3(256), 0, s, a.n, a.nwalk, a.acc1, a.acc2);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (sum_out) {
+        hipLaunchKernelGGL(k_fwd_total, dim3(1), dim3(64), 0, s, a.chunks, a.part, sum_out);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace mc

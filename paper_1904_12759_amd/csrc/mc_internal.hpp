@@ -115,6 +115,24 @@ struct WalkArgs {
     TraceOut trace;
 };
 
+// Forward (Algorithm 2) walks: one wave per chunk of kFwdChunk walker ordinals.
+constexpr uint32_t kFwdChunk = 512;
+struct FwdArgs {
+    InstArgs P;                // plain tables; P.hot must be 0
+    int64_t n;
+    int64_t nwalk;             // M
+    int64_t w0;                // first walker ordinal (trace only)
+    int64_t chunks;            // ceil(M / kFwdChunk)
+    const double *cdf;         // [n] cumulative sums of |v| in node order
+    double *acc1, *acc2;       // [n] sums of Y and Y^2 per end node (acc2 may be null)
+    double *part;              // [chunks * 3] (count, mean, M2) of Y per chunk
+    unsigned long long *counters;  // [2 * grid]
+    uint32_t *flags;
+    int32_t *t_start, *t_end;  // per-walker trace (parity checks only)
+    uint32_t *t_ev, *t_ju;
+    double *t_y;
+};
+
 // One instance of a batched launch.
 struct BatchInst {
     InstArgs P;
@@ -171,6 +189,16 @@ inline uint32_t group_size(int64_t nwalk, bool fp32) {
 
 // Largest walk grid (blocks); the per-block counter buffer has this many pairs.
 constexpr int kMaxWalkGrid = 1 << 16;
+
+// host-side launchers (forward.hip)
+hipError_t launch_check_symmetric(int64_t nnz, const int64_t *rowptr, const int32_t *rowof,
+                                  const int32_t *col, const double *val, uint32_t *flag,
+                                  hipStream_t s);
+hipError_t launch_fwd_cdf(int64_t n, const void *v, bool fp32, double *absv, double *cdf,
+                          void *temp, size_t &temp_bytes, hipStream_t s);
+int forward_grid(int64_t chunks);
+hipError_t launch_forward(const FwdArgs &a, int mode, bool fp32, bool trace, double *sum_out,
+                          hipStream_t s);
 
 // host-side launchers (walk.hip)
 int launch_walk_grid(int64_t ntasks, int block);
