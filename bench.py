@@ -362,6 +362,44 @@ def bench_learned(mc, seed, n=1_000_000, m=4):
     return out
 
 
+def bench_forward_tc(mc, seed, n=1_000_000, m=1_000_000, steps=5):
+    """Total communicability TC = (1, e^A 1) (Eq. (TC)) of a small-world network
+    (Newman-Watts ring with shortcuts, mean degree 2.4, n = 1e6) by forward walks
+    (Theorem 2, Algorithm 2) with M = 1e6 walkers, in STRANG mode with the paper's
+    dt = 0.03125 (the setting of its Tables 0 and 00) and in EXACT mode; against the
+    exact TC from expm_multiply."""
+    import torch
+    import scipy.sparse.linalg as sla
+    from paper_1904_12759_amd import workloads as wl
+    t0 = time.perf_counter()
+    a = wl.small_world(n, 0.2, 1)
+    gen = time.perf_counter() - t0
+    exact = float(sla.expm_multiply(a.to_scipy().tocsr(), np.ones(a.n)).sum())
+    dev = torch.device("cuda", torch.cuda.current_device())
+    v = torch.ones(a.n, dtype=torch.float64, device=dev)
+    out = dict(workload=f"small world (Newman-Watts, p=0.2) n={n}, mean degree "
+                        f"{a.nnz / a.n:.3f}, A = adjacency, t = 1, v = 1, M = {m} walkers",
+               tc_exact=exact, generation_s=gen)
+    for name, mode in (("strang_dt_0.03125", mc.STRANG), ("exact", mc.EXACT)):
+        h = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, seed, mode=mode, dt=0.03125)
+        tot = torch.empty(2, dtype=torch.float64, device=dev)
+        t0 = time.perf_counter()
+        h.forward(v, m, total=tot, total_only=True)        # includes the symmetry check
+        first = time.perf_counter() - t0
+        ms = []
+        for _ in range(steps):
+            h.forward(v, m, total=tot, total_only=True)
+            ms.append(h.stats()["ms"])
+        st = h.stats()
+        tc, tse = tot.cpu().numpy().tolist()
+        out[name] = dict(ms_per_tc=float(np.median(ms)), first_call_s=first, tc=tc,
+                         rel_stderr=tse / abs(tc), rel_err_vs_exact=(tc - exact) / exact,
+                         events=st["events"], jumps=st["jumps"],
+                         walker_steps_per_s=st["events"] / (float(np.median(ms)) / 1e3))
+        del h
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -372,7 +410,7 @@ def main():
                     help="skip every extra measurement (same as --extras none)")
     ap.add_argument("--extras", default="all",
                     help="comma-separated extra measurements after the main step: "
-                         "locality, entries, learned, grid3d, batched; 'all' or 'none'")
+                         "locality, entries, learned, grid3d, batched, forward; 'all' or 'none'")
     ap.add_argument("--seed", type=int, default=12759)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (steps times), "
@@ -476,7 +514,7 @@ def main():
             "traffic": measured_traffic(),
         },
     }
-    names = ["locality", "entries", "learned", "grid3d", "batched"]
+    names = ["locality", "entries", "learned", "grid3d", "batched", "forward"]
     extras = [] if args.no_extras or args.extras == "none" else \
         names if args.extras == "all" else [x for x in args.extras.split(",") if x]
     unknown = [x for x in extras if x not in names]
@@ -498,6 +536,9 @@ def main():
     if "batched" in extras:
         log("bench: batched 64 instances")
         out["batched_64"] = bench_batched(mc, args.seed)
+    if "forward" in extras:
+        log("bench: forward total communicability (small world n=1e6)")
+        out["forward_tc"] = bench_forward_tc(mc, args.seed)
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         try:

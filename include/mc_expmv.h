@@ -152,9 +152,10 @@ mc_status mc_expmv_full(mc_expmv_t h, const void *v, int64_t n_per_node, double 
  * then the forward and backward chains coincide, as the paper notes before
  * Lemma 2.  The tilted proposal, if installed, is not used.
  *   v        device double[n] (float[n] with MC_FP32 weights), any signs
- *   est      device double[n]: (1/M) sum_w Y_w 1{X_t = i}
- *   stderr_  device double[n] or NULL: sqrt(s_i^2 / M), s_i^2 the sample
- *            variance of Y_w 1{X_t = i} over the M walkers
+ *   est      device double[n]: (1/M) sum_w Y_w 1{X_t = i}; may be NULL when
+ *            sum_out is given (then no per-node work is done)
+ *   stderr_  device double[n] or NULL (NULL when est is): sqrt(s_i^2 / M), s_i^2
+ *            the sample variance of Y_w 1{X_t = i} over the M walkers
  *   sum_out  device double[2] or NULL: mean of Y (an estimate of sum_i x_i, the
  *            total communicability (1, e^A 1) when t = 1 and v = 1, Eq. (TC))
  *            and its standard error

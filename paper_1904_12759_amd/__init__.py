@@ -311,19 +311,21 @@ class MCExpmv:
             self.sync()
         return est, stderr
 
-    def forward(self, v, n_walkers: int, est=None, stderr=None, total=None, sync: bool = True):
+    def forward(self, v, n_walkers: int, est=None, stderr=None, total=None, sync: bool = True,
+                total_only: bool = False):
         """Forward estimator (Lemma 2, Theorem 2, Algorithm 2; A must be symmetric):
         per-node mean and standard error, and a device double[2] with the mean of the
-        walker values (an estimate of sum_i x_i) and its standard error."""
+        walker values (an estimate of sum_i x_i) and its standard error.  With
+        total_only=True only the latter is computed (est and stderr are None)."""
         import torch
         v = self._v(v)
-        if est is None:
+        if est is None and not total_only:
             est = torch.empty(self.n, dtype=torch.float64, device=self.device)
-        if stderr is None:
+        if stderr is None and not total_only:
             stderr = torch.empty(self.n, dtype=torch.float64, device=self.device)
         if total is None:
             total = torch.empty(2, dtype=torch.float64, device=self.device)
-        _require_cuda(v, est, stderr, total)
+        _require_cuda(*[x for x in (v, est, stderr, total) if x is not None])
         _check(load().mc_expmv_forward(self._h, _ptr(v), int(n_walkers), _ptr(est), _ptr(stderr),
                                        _ptr(total)), "mc_expmv_forward")
         if sync:

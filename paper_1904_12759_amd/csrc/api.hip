@@ -44,6 +44,7 @@ struct mc_expmv_s {
     // forward estimator
     int sym_state = -1;                  // A == A^T: -1 not checked yet, 0 no, 1 yes
     double *fwd_abs = nullptr, *fwd_cdf = nullptr;   // [n] |v| and its cumulative sums
+    int32_t *fwd_guide = nullptr;        // guide table over fwd_cdf
     void *fwd_temp = nullptr;            // scan scratch
     size_t fwd_temp_bytes = 0;
     double *fwd_part = nullptr;          // chunk partials of Y
@@ -313,6 +314,7 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->inv);
     (void)hipFree(h->fwd_abs);
     (void)hipFree(h->fwd_cdf);
+    (void)hipFree(h->fwd_guide);
     (void)hipFree(h->fwd_temp);
     (void)hipFree(h->fwd_part);
     (void)hipFree(h->fwd_acc);
@@ -1322,8 +1324,8 @@ mc_status check_symmetric(mc_expmv_s *h) {
 mc_status run_forward(mc_expmv_s *h, const void *v, int64_t w0, int64_t nwalk, double *acc1,
                       double *acc2, double *sum_out, bool trace, int32_t *ts, int32_t *te,
                       uint32_t *tev, uint32_t *tju, double *ty) {
-    if (!v || !acc1 || nwalk < 1 || nwalk > 0xFFFFFFFFll || w0 < 0 ||
-        w0 + nwalk > 0x100000000ll)
+    if (!v || (!acc1 && !sum_out) || (!acc1 && acc2) || nwalk < 1 || nwalk > 0xFFFFFFFFll ||
+        w0 < 0 || w0 + nwalk > 0x100000000ll)
         return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
     mc_status st = check_symmetric(h);
@@ -1333,8 +1335,10 @@ mc_status run_forward(mc_expmv_s *h, const void *v, int64_t w0, int64_t nwalk, d
     if (n > 0 && !h->fwd_cdf) {
         HIP_TRY(dalloc(&h->fwd_abs, n));
         HIP_TRY(dalloc(&h->fwd_cdf, n));
+        HIP_TRY(dalloc(&h->fwd_guide, guide_cells(n) + 1));
         size_t bytes = 0;
-        HIP_TRY(launch_fwd_cdf(n, v, fp32, h->fwd_abs, h->fwd_cdf, nullptr, bytes, h->stream));
+        HIP_TRY(launch_fwd_cdf(n, v, fp32, h->fwd_abs, h->fwd_cdf, h->fwd_guide, nullptr, bytes,
+                               h->stream));
         HIP_TRY(hipMalloc(&h->fwd_temp, bytes > 0 ? bytes : 1));
         h->fwd_temp_bytes = bytes;
     }
@@ -1350,7 +1354,8 @@ mc_status run_forward(mc_expmv_s *h, const void *v, int64_t w0, int64_t nwalk, d
     HIP_TRY(hipEventRecord(h->ev0, h->stream));
     if (n > 0) {
         size_t bytes = h->fwd_temp_bytes;
-        HIP_TRY(launch_fwd_cdf(n, v, fp32, h->fwd_abs, h->fwd_cdf, h->fwd_temp, bytes, h->stream));
+        HIP_TRY(launch_fwd_cdf(n, v, fp32, h->fwd_abs, h->fwd_cdf, h->fwd_guide, h->fwd_temp, bytes,
+                               h->stream));
     }
     FwdArgs a{};
     fill_inst(h, v, false, a.P);
@@ -1360,6 +1365,9 @@ mc_status run_forward(mc_expmv_s *h, const void *v, int64_t w0, int64_t nwalk, d
     a.w0 = w0;
     a.chunks = chunks;
     a.cdf = h->fwd_cdf;
+    a.absv = h->fwd_abs;
+    a.guide = h->fwd_guide;
+    a.gcells = guide_cells(n);
     a.acc1 = acc1;
     a.acc2 = acc2;
     a.part = h->fwd_part;
@@ -1387,7 +1395,7 @@ extern "C" {
 
 mc_status mc_expmv_forward(mc_expmv_t h, const void *v, int64_t n_walkers, double *est,
                            double *stderr_, double *sum_out) {
-    if (!h || !est) return MC_ERR_INVALID_ARG;
+    if (!h) return MC_ERR_INVALID_ARG;
     return run_forward(h, v, 0, n_walkers, est, stderr_, sum_out, false, nullptr, nullptr,
                        nullptr, nullptr, nullptr);
 }

@@ -38,18 +38,34 @@ __device__ __forceinline__ double grid_coef_sum_rev(int32_t ka, int32_t kb, int3
     return grid_coef_sum<MODE>(ngrid - kb, ngrid - ka, ngrid);
 }
 
-// Start node of walker w: the first j with cdf[j] >= U V (binary search).
-__device__ __forceinline__ uint32_t draw_start(const FwdArgs &a, uint32_t w, double V) {
+// Guide-table cell of a cumulative value c: min(G, floor(c G / V)), non-decreasing
+// in c (all the lookup relies on).
+__device__ __forceinline__ int64_t guide_cell(double c, double scale, int64_t G) {
+    const double k = floor(c * scale);
+    return k >= (double)G ? G : (int64_t)k;
+}
+
+// Start node of walker w: the first j with cdf[j] >= U V.  The guide table
+// (Chen and Asau, 1974) holds for every cell k the first node j whose cell is
+// >= k; the answer's cell is >= the target's, so the search walks forward from
+// guide[cell(target)], over about n / G nodes (one or two cache lines).  cdf is
+// the device's parallel prefix sum; should its rounding ever make a node of
+// zero weight the answer, the next node of non-zero weight is taken instead.
+__device__ __forceinline__ uint32_t draw_start(const FwdArgs &a, uint32_t w, double V,
+                                               double scale) {
     const U4 o = philox(0u, w, kFwdMark, a.P.inst, a.P.key0, a.P.key1);
     const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
     const double target = (double)(m + 1ull) * 0x1p-53 * V;
-    int64_t lo = 0, hi = a.n - 1;
-    while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (a.cdf[mid] >= target) hi = mid;
-        else lo = mid + 1;
+    int64_t j = a.guide[guide_cell(target, scale, a.gcells)];
+    while (a.cdf[j] < target) ++j;          // stops at n - 1 at the latest: cdf[n-1] = V
+    if (a.absv[j] == 0.0) {
+        int64_t k = j;
+        while (k < a.n - 1 && a.absv[k] == 0.0) ++k;
+        if (a.absv[k] == 0.0)
+            while (k > 0 && a.absv[k] == 0.0) --k;
+        j = k;
     }
-    return (uint32_t)lo;
+    return (uint32_t)j;
 }
 
 template <int MODE, bool FP32, bool TRACE>
@@ -61,6 +77,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs a) {
     const InstArgs &P = a.P;
     const double t = P.t;
     const double V = a.n > 0 ? a.cdf[a.n - 1] : 0.0;
+    const double gscale = (double)a.gcells / V;
     unsigned long long evs = 0, jus = 0;
     uint32_t err = 0;
     for (int64_t c = blockIdx.x; c < a.chunks; c += gridDim.x) {
@@ -89,7 +106,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs a) {
             int32_t ka = 0;
             WT logw = (WT)0, dx = (WT)0;
             auto start = [&](uint32_t i) {
-                j = draw_start(a, ord0 + i, V);
+                j = draw_start(a, ord0 + i, V, gscale);
                 sgn = (double)load_v<FP32>(P.v, j) > 0.0 ? 1.0 : -1.0;
                 x = P.perm ? P.perm[j] : j;
                 const RowRec rr = P.rows[x];
@@ -154,7 +171,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs a) {
                         const double y = V * sgn * (double)wexp<FP32>(logw);
                         if (!isfinite(y)) err |= F_OVERFLOW;
                         const uint32_t xe = P.inv ? P.inv[x] : x;
-                        unsafeAtomicAdd(a.acc1 + xe, y);
+                        if (a.acc1) unsafeAtomicAdd(a.acc1 + xe, y);
                         if (a.acc2) unsafeAtomicAdd(a.acc2 + xe, y * y);
                         ys[wl] = y;
                         evs += ev;
@@ -204,6 +221,24 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs a) {
     }
 }
 
+// Guide table: for every cell k = 0..G, the first node j with cell(cdf[j]) >= k
+// (binary search; n - 1 when there is none).  One thread per cell, no races.
+__global__ void k_fwd_guide(int64_t n, int64_t G, const double *__restrict__ cdf,
+                            int32_t *__restrict__ guide) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > G) return;
+    const double V = cdf[n - 1];
+    if (!(V > 0.0)) return;
+    const double scale = (double)G / V;
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (guide_cell(cdf[mid], scale, G) >= k) hi = mid;
+        else lo = mid + 1;
+    }
+    guide[k] = (int32_t)lo;
+}
+
 // acc1 = acc2 = 0 (a kernel, so the sequence can be captured in a graph).
 __global__ void k_fwd_zero(int64_t n, double *acc1, double *acc2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -236,18 +271,35 @@ __global__ void k_fwd_finish(int64_t n, int64_t m, double *acc1, double *acc2) {
     }
 }
 
-// Mean and standard error of Y over all walkers: fin_lanes(chunks) lanes merge
-// the chunk partials in order (one wave).
-__global__ __launch_bounds__(64) void k_fwd_total(int64_t chunks, const double *part,
-                                                  double *sum_out) {
-    const uint32_t L = fin_lanes(chunks);
-    const uint32_t sub = threadIdx.x;
-    double n, mean, m2;
-    // lanes beyond the first group merge nothing but take part in the shuffles
-    fin_merge(sub < L ? part : nullptr, sub < L ? chunks : 0, L, sub % L, n, mean, m2);
-    if (sub == 0) {
-        sum_out[0] = mean;
-        sum_out[1] = n > 1.0 ? sqrt(m2 / (n - 1.0) / n) : 0.0;
+// Mean and standard error of Y over all walkers: 1024 threads each merge a
+// contiguous range of chunk partials in order, then neighbouring ranges merge
+// pairwise in LDS (thread i takes in thread i + off), keeping chunk order.
+__global__ __launch_bounds__(1024) void k_fwd_total(int64_t chunks, const double *part,
+                                                    double *sum_out) {
+    __shared__ double sn[1024], sm[1024], sq[1024];
+    const int64_t T = blockDim.x;
+    const int64_t i = threadIdx.x;
+    const int64_t q = (chunks + T - 1) / T;
+    const int64_t c0 = i * q, c1 = c0 + q < chunks ? c0 + q : chunks;
+    double n = 0.0, mean = 0.0, m2 = 0.0;
+    for (int64_t c = c0; c < c1; ++c) chan_merge(n, mean, m2, part[3 * c], part[3 * c + 1], part[3 * c + 2]);
+    sn[i] = n;
+    sm[i] = mean;
+    sq[i] = m2;
+    __syncthreads();
+    for (int64_t off = 1; off < T; off <<= 1) {
+        if ((i & (2 * off - 1)) == 0 && i + off < T) {
+            double a = sn[i], b = sm[i], c = sq[i];
+            chan_merge(a, b, c, sn[i + off], sm[i + off], sq[i + off]);
+            sn[i] = a;
+            sm[i] = b;
+            sq[i] = c;
+        }
+        __syncthreads();
+    }
+    if (i == 0) {
+        sum_out[0] = sm[0];
+        sum_out[1] = sn[0] > 1.0 ? sqrt(sq[0] / (sn[0] - 1.0) / sn[0]) : 0.0;
     }
 }
 
@@ -281,14 +333,19 @@ hipError_t launch_check_symmetric(int64_t nnz, const int64_t *rowptr, const int3
 }
 
 hipError_t launch_fwd_cdf(int64_t n, const void *v, bool fp32, double *absv, double *cdf,
-                          void *temp, size_t &temp_bytes, hipStream_t s) {
+                          int32_t *guide, void *temp, size_t &temp_bytes, hipStream_t s) {
     if (!temp) return hipcub::DeviceScan::InclusiveSum(nullptr, temp_bytes, absv, cdf, (int)n, s);
     const unsigned g = (unsigned)((n + 255) / 256);
     if (fp32) hipLaunchKernelGGL(k_fwd_absv<true>, dim3(g), dim3(256), 0, s, n, v, absv);
     else hipLaunchKernelGGL(k_fwd_absv<false>, dim3(g), dim3(256), 0, s, n, v, absv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return hipcub::DeviceScan::InclusiveSum(temp, temp_bytes, absv, cdf, (int)n, s);
+    e = hipcub::DeviceScan::InclusiveSum(temp, temp_bytes, absv, cdf, (int)n, s);
+    if (e != hipSuccess) return e;
+    const int64_t G = guide_cells(n);
+    hipLaunchKernelGGL(k_fwd_guide, dim3((unsigned)((G + 256) / 256)), dim3(256), 0, s, n, G, cdf,
+                       guide);
+    return hipGetLastError();
 }
 
 int forward_grid(int64_t chunks) {
@@ -299,7 +356,7 @@ int forward_grid(int64_t chunks) {
 hipError_t launch_forward(const FwdArgs &a, int mode, bool fp32, bool trace, double *sum_out,
                           hipStream_t s) {
     const unsigned gz = (unsigned)((a.n + 255) / 256);
-    if (a.n > 0) {
+    if (a.n > 0 && a.acc1) {
         hipLaunchKernelGGL(k_fwd_zero, dim3(gz), dim3(256), 0, s, a.n, a.acc1, a.acc2);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -324,13 +381,13 @@ hipError_t launch_forward(const FwdArgs &a, int mode, bool fp32, bool trace, dou
 #undef MC_FWD
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (a.n > 0) {
+    if (a.n > 0 && a.acc1) {
         hipLaunchKernelGGL(k_fwd_finish, dim3(gz), dim3(256), 0, s, a.n, a.nwalk, a.acc1, a.acc2);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (sum_out) {
-        hipLaunchKernelGGL(k_fwd_total, dim3(1), dim3(64), 0, s, a.chunks, a.part, sum_out);
+        hipLaunchKernelGGL(k_fwd_total, dim3(1), dim3(1024), 0, s, a.chunks, a.part, sum_out);
         e = hipGetLastError();
     }
     return e;

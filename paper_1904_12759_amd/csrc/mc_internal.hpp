@@ -116,7 +116,9 @@ struct WalkArgs {
 };
 
 // Forward (Algorithm 2) walks: one wave per chunk of kFwdChunk walker ordinals.
-constexpr uint32_t kFwdChunk = 512;
+constexpr uint32_t kFwdChunk = 128;
+// Guide-table cells for n nodes: about eight nodes per cell.
+inline int64_t guide_cells(int64_t n) { return n > 8 ? (n + 7) / 8 : 1; }
 struct FwdArgs {
     InstArgs P;                // plain tables; P.hot must be 0
     int64_t n;
@@ -124,6 +126,9 @@ struct FwdArgs {
     int64_t w0;                // first walker ordinal (trace only)
     int64_t chunks;            // ceil(M / kFwdChunk)
     const double *cdf;         // [n] cumulative sums of |v| in node order
+    const double *absv;        // [n] |v|
+    const int32_t *guide;      // [gcells + 1] guide table over cdf
+    int64_t gcells;            // G = guide_cells(n)
     double *acc1, *acc2;       // [n] sums of Y and Y^2 per end node (acc2 may be null)
     double *part;              // [chunks * 3] (count, mean, M2) of Y per chunk
     unsigned long long *counters;  // [2 * grid]
@@ -195,7 +200,7 @@ hipError_t launch_check_symmetric(int64_t nnz, const int64_t *rowptr, const int3
                                   const int32_t *col, const double *val, uint32_t *flag,
                                   hipStream_t s);
 hipError_t launch_fwd_cdf(int64_t n, const void *v, bool fp32, double *absv, double *cdf,
-                          void *temp, size_t &temp_bytes, hipStream_t s);
+                          int32_t *guide, void *temp, size_t &temp_bytes, hipStream_t s);
 int forward_grid(int64_t chunks);
 hipError_t launch_forward(const FwdArgs &a, int mode, bool fp32, bool trace, double *sum_out,
                           hipStream_t s);

@@ -15,6 +15,8 @@ and Wikipedia networks) are not available here:
 * ``grid3d``  3-D 7-point variable-coefficient diffusion operator (method of
               lines), harmonic-mean face coefficients, Dirichlet boundary.
 * ``er`` / ``chung_lu``  Erdos-Renyi and power-law (Chung-Lu) random graphs.
+* ``small_world``  Newman-Watts ring with random shortcuts (mean degree 2.4),
+              standing in for the paper's small-world networks (Sec. 6, Tables 0, 00).
 """
 from __future__ import annotations
 
@@ -164,6 +166,19 @@ def grid3d(m: int, seed: int, kmin: float = 0.1, kmax: float = 10.0) -> CSR:
     offs = np.array([-m * m, -m, -1, 0, 1, m, m * m], np.int32)
     cols = np.arange(n, dtype=np.int32)[:, None] + offs[None, :]
     return CSR(rowptr, cols[valid], vals[valid])
+
+
+def small_world(n: int, p: float, seed: int) -> CSR:
+    """Newman-Watts small world: a ring (each node joined to its neighbour on either
+    side) plus, from every node, a shortcut to a uniform random node with probability
+    p; loops and repeated edges dropped.  Mean degree about 2 + 2p (2.4 for p = 0.2)."""
+    rng = np.random.default_rng(seed)
+    u = np.arange(n, dtype=np.int64)
+    ring_w = (u + 1) % n
+    has = rng.random(n) < p
+    su = u[has]
+    sw = rng.integers(0, n, size=len(su))
+    return _edges_to_adjacency(n, np.concatenate([u, su]), np.concatenate([ring_w, sw]))
 
 
 def er_graph(n: int, mean_deg: float, seed: int) -> CSR:

@@ -104,7 +104,8 @@ def test_forward_total_is_reproducible_and_relabel_invariant():
     e1, t1 = e1.clone(), t1.clone()
     e2, s2, t2 = g.forward(v, 30_000)
     e3, s3, t3 = r.forward(v, 30_000)
-    assert torch.equal(t1, t2) and torch.equal(t1, t3)
+    _, _, t4 = g.forward(v, 30_000, total_only=True)
+    assert torch.equal(t1, t2) and torch.equal(t1, t3) and torch.equal(t1, t4)
     assert _rel(e2.cpu().numpy(), e1.cpu().numpy()) <= 1e-13
     assert _rel(e3.cpu().numpy(), e1.cpu().numpy()) <= 1e-13
 

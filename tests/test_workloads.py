@@ -44,3 +44,12 @@ def test_grid2d_and_graphs():
     assert 7.0 < deg.mean() < 9.0
     pl = wl.chung_lu_graph(5000, 8.0, 2.5, 3)
     assert pl.to_scipy().max() == 1.0 and np.diff(pl.rowptr).max() > 50
+
+
+def test_small_world_shape():
+    a = wl.small_world(10_000, 0.2, 1)
+    dense_check = a.to_scipy()
+    assert (dense_check != dense_check.T).nnz == 0          # symmetric
+    assert dense_check.diagonal().sum() == 0                 # no loops
+    deg = np.diff(a.rowptr)
+    assert deg.min() >= 2 and 2.3 < deg.mean() < 2.5
