@@ -28,6 +28,9 @@ __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, i
         if (tb[mid] <= task) lo = mid;
         else hi = mid - 1;
     }
+    // the instance is the same for the whole wave: make that visible to the
+    // compiler so its record is read with scalar loads into scalar registers
+    lo = __builtin_amdgcn_readfirstlane(lo);
     const BatchInst &I = a.inst[lo];
     const int64_t local = task - tb[lo];
     const int64_t grp = local / I.chunks;
@@ -68,22 +71,24 @@ __global__ __launch_bounds__(256) void k_walk_batched(BatchArgs a) {
     unsigned char *lds = dyn_lds + (size_t)wave * kBatchLdsPerWave;
     unsigned long long my_events = 0, my_jumps = 0;
     uint32_t err = 0;
-    if (a.group == 0) {
-        const int64_t wave_id = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-        const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
-        for (int64_t task = wave_id; task < a.ntasks; task += nwaves)
-            do_task(a, sh_tb, task, lds, my_events, my_jumps, err);
-    } else {
-        for (;;) {
+    // one call site of do_task for both schedules (two inlined copies cost
+    // registers): static stride over the tasks, or grabs of `group` tasks
+    const bool dynamic = a.group != 0;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    int64_t task = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE));
+    int64_t end = task;               // dynamic: end of the current grab
+    for (;;) {
+        if (dynamic && task >= end) {
             unsigned long long base = 0;
             if (lane == 0) base = atomicAdd(a.queue, (unsigned long long)a.group);
-            base = __shfl(base, 0, WAVE);
-            if ((int64_t)base >= a.ntasks) break;
-            int64_t end = (int64_t)base + a.group;
-            if (end > a.ntasks) end = a.ntasks;
-            for (int64_t task = (int64_t)base; task < end; ++task)
-                do_task(a, sh_tb, task, lds, my_events, my_jumps, err);
+            task = (int64_t)((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base) |
+                             ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(base >> 32))
+                              << 32));
+            end = task + a.group < a.ntasks ? task + a.group : a.ntasks;
         }
+        if (task >= a.ntasks) break;
+        do_task(a, sh_tb, task, lds, my_events, my_jumps, err);
+        task += dynamic ? 1 : nwaves;
     }
     for (int off = 1; off < WAVE; off <<= 1) err |= __shfl_xor(err, off, WAVE);
     if (err && lane == 0) atomicOr(a.flags, err);
