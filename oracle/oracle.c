@@ -97,6 +97,13 @@ static double uniform_open0(uint32_t o0, uint32_t o1)
     return (double)(m + 1u) * 0x1p-53;
 }
 
+/* U in [0,1) from the same 53 bits. */
+static double uniform_open1(uint32_t o0, uint32_t o1)
+{
+    uint64_t m = ((uint64_t)o0 << 21) | ((uint64_t)o1 >> 11);
+    return (double)m * 0x1p-53;
+}
+
 /* ------------------------------------------------------------------ model */
 typedef struct {
     /* per row */
@@ -125,6 +132,7 @@ typedef struct {
     table_set plain;
     int has_proposal;
     table_set prop;
+    int cond;                     /* condition backward walks on a first jump before t */
     int64_t *slot_of_csr;         /* CSR position -> slot index, -1 if none */
 } oracle_t;
 
@@ -402,10 +410,20 @@ static double grid_coef(const oracle_t *o, int64_t k)
  * (k, w, start, instance), k = 0, 1, ...; forward walks (Algorithm 2) use
  * (k, w, FORWARD_MARK, instance), k = 1, 2, ... (k = 0 drew the start) and
  * read the grid coefficients in reverse time order, c_{N-k}. */
+/* With cond set (backward walks only), the first holding time is drawn
+ * conditioned on a jump before t: with q = 1 - e^{-r t}, S = -log(1 - U q) / r
+ * for U in [0,1) (the inverse of the exponential law truncated to [0, t)), and
+ * the walker jumps whatever S.  The value returned is then
+ *     e^{-r t} K + q W v[X_t],
+ * K the value of a walker that never leaves the start node: the no-jump event,
+ * of probability e^{-r t}, is integrated exactly and only the jump event is
+ * sampled, so the mean is unchanged and the variance of the start node's
+ * jump/no-jump choice is removed. */
 static void walk_path(const oracle_t *o, int64_t start, uint32_t w, const double *v,
                       int use_prop, int forward, int64_t *path_x, double *path_s,
                       double *path_c, walk_out *res)
 {
+    const int cond = o->cond && !forward;
     const table_set *ts = use_prop ? &o->prop : &o->plain;
     uint32_t key[2] = { (uint32_t)o->seed, (uint32_t)(o->seed >> 32) };
     int64_t x = start;
@@ -422,9 +440,17 @@ static void walk_path(const oracle_t *o, int64_t start, uint32_t w, const double
         uint32_t rnd[4];
         oracle_philox4x32_10(ctr, key, rnd);
         ++events;
-        double U = uniform_open0(rnd[0], rnd[1]);
-        double S = -log(U) * ts->inv_r[x];
-        if (s + S < o->t) {
+        double S;
+        int jump;
+        if (cond && events == 1) {
+            double q = -expm1(-ts->r[x] * o->t);
+            S = -log(1.0 - uniform_open1(rnd[0], rnd[1]) * q) * ts->inv_r[x];
+            jump = 1;
+        } else {
+            S = -log(uniform_open0(rnd[0], rnd[1])) * ts->inv_r[x];
+            jump = s + S < o->t;
+        }
+        if (jump) {
             s = s + S;
             int64_t slot = (int64_t)(((uint64_t)rnd[2] * (uint64_t)ts->deg[x]) >> 32);
             int64_t q = ts->begin[x] + slot;
@@ -466,6 +492,19 @@ static void walk_path(const oracle_t *o, int64_t start, uint32_t w, const double
     }
     res->logw = logw;
     res->f = exp(logw) * v[x];
+    if (cond && ts->deg[start] > 0) {
+        /* no-jump value K of the start node (its weight over the whole horizon) */
+        double logk = 0.0;
+        if (o->mode == OR_EXACT) {
+            logk = ts->d[start] * o->t;
+        } else if (o->t > 0.0) {
+            double acc = 0.0;
+            for (int64_t k = 0; k <= o->ngrid; ++k) acc += grid_coef(o, k) * ts->d[start];
+            logk = acc * o->dt;
+        }
+        double rt = ts->r[start] * o->t;
+        res->f = exp(-rt) * (exp(logk) * v[start]) + (-expm1(-rt)) * res->f;
+    }
     if (!isfinite(res->f) && res->status == OR_OK) res->status = OR_ERR_OVERFLOW;
     res->x_end = (int32_t)x;
     res->events = events;
@@ -601,6 +640,13 @@ int oracle_estimate(const oracle_t *o, const double *v, const int64_t *idx, int6
         if (jobs[tI].status != OR_OK && st == OR_OK) st = jobs[tI].status;
     free(jobs); free(th);
     return st;
+}
+
+/* Switch the first-jump conditioning of backward walks on or off. */
+int oracle_set_conditioning(oracle_t *o, int on)
+{
+    o->cond = on ? 1 : 0;
+    return OR_OK;
 }
 
 /* ---------------------------------------------------- forward estimator */

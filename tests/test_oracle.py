@@ -513,3 +513,93 @@ def test_forward_zero_vector():
     o = Oracle(csr.rowptr, csr.col, csr.val, 1.0, 1)
     est, se, tot, tse = o.forward(np.zeros(6), 100)
     assert not est.any() and not se.any() and tot == 0.0 and tse == 0.0
+
+
+# ------------------------------------------- first-jump conditioning (cond)
+# The no-jump event of the start node (probability e^{-rt}) is integrated
+# exactly; only walks that jump before t are sampled.
+def _rate_and_d(a):
+    off = a - np.diag(np.diag(a))
+    r = off.sum(1)
+    return r, np.diag(a) + r
+
+
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_conditioned_matches_dense_expm(symmetric):
+    n = 40
+    a = refs.random_metzler(n, 0.15, 41, symmetric=symmetric, off_scale=1.0)
+    t = 0.7
+    v = np.random.default_rng(42).uniform(-1, 2, n)
+    csr = wl.from_dense(a)
+    o = Oracle(csr.rowptr, csr.col, csr.val, t, 43, cond=True)
+    est, se = o.estimate(v, nwalk=20_000, threads=4)
+    ref = refs.expm_v(a, t, v)
+    # rows without jumps are deterministic: exact up to rounding
+    det = se <= 1e-13 * np.abs(ref)
+    np.testing.assert_allclose(est[det], ref[det], rtol=1e-13)
+    z = _zscores(est[~det], se[~det], ref[~det])
+    assert np.abs(z).max() < 4.5 and abs(np.mean(z ** 2) - 1) < 0.5
+
+
+@pytest.mark.parametrize("mode,nsteps", [(STRANG, 4), (LIE, 3)])
+def test_conditioned_split_modes(mode, nsteps):
+    n = 24
+    a = refs.random_metzler(n, 0.25, 7, symmetric=True, off_scale=1.5, diag_scale=2.0)
+    t = 1.0
+    v = np.random.default_rng(8).uniform(0.5, 1.5, n)
+    csr = wl.from_dense(a)
+    o = Oracle(csr.rowptr, csr.col, csr.val, t, 79, mode=mode, dt=t / nsteps, cond=True)
+    est, se = o.estimate(v, nwalk=40_000, threads=4)
+    ref = (refs.strang_v if mode == STRANG else refs.lie_v)(a, t, nsteps, v)
+    assert np.abs(_zscores(est, se, ref)).max() < 4.5
+
+
+def test_conditioned_second_moment_is_exact():
+    """E[f_c] = x and E[f_c^2] = p0^2 K^2 + 2 p0 K (x - p0 K) + q (m2 - p0 K^2), with
+    p0 = e^{-rt}, q = 1 - p0, K = e^{dt} v_i, x = (e^{tA}v)_i and m2 the plain walk's
+    exact second moment: the sampled values of the conditioned walker match both."""
+    n = 25
+    a = refs.random_metzler(n, 0.25, 13, symmetric=False)
+    csr = wl.from_dense(a)
+    v = np.random.default_rng(1).uniform(0.2, 1.0, n)
+    t = 0.6
+    o = Oracle(csr.rowptr, csr.col, csr.val, t, 3, cond=True)
+    x = refs.expm_v(a, t, v)
+    m2 = refs.second_moment_exact(csr, t, v)
+    r, d = _rate_and_d(a)
+    nw = 40_000
+    for i in (0, 7, 19):
+        p0 = np.exp(-r[i] * t)
+        q = 1 - p0
+        k = np.exp(d[i] * t) * v[i]
+        m2c = p0 ** 2 * k ** 2 + 2 * p0 * k * (x[i] - p0 * k) + q * (m2[i] - p0 * k ** 2)
+        _, _, ju, f, _ = o.trace(v, i, 0, nw)
+        assert (ju >= 1).all()                       # every sampled walk jumps
+        assert abs(f.mean() - x[i]) < 4.5 * f.std() / np.sqrt(nw)
+        f2 = f * f
+        assert abs(f2.mean() - m2c) < 4.5 * f2.std() / np.sqrt(nw), (i, f2.mean(), m2c)
+
+
+def test_conditioned_reduces_variance_on_low_rate_nodes():
+    """Where the start node rarely leaves (e^{-rt} near 1) the jump/no-jump choice
+    dominates the plain variance; conditioning removes it."""
+    g = wl.ba_graph(2000, 3, 5)
+    a = wl.scaled(g, 0.5 / wl.lambda_max(g))
+    v = np.random.default_rng(6).random(a.n)
+    deg = np.diff(a.rowptr)
+    idx = np.where(deg == 3)[0][:20]
+    plain = Oracle(a.rowptr, a.col, a.val, 1.0, 7)
+    cond = Oracle(a.rowptr, a.col, a.val, 1.0, 7, cond=True)
+    _, se_p = plain.estimate(v, idx, 20_000, threads=4)
+    _, se_c = cond.estimate(v, idx, 20_000, threads=4)
+    assert np.median(se_p / se_c) > 2.0
+
+
+def test_conditioned_diagonal_and_rate_zero_rows():
+    a = np.diag([-0.5, 0.3, 1.0])
+    csr = wl.from_dense(a)
+    v = np.array([1.0, 2.0, -1.0])
+    o = Oracle(csr.rowptr, csr.col, csr.val, 1.5, 1, cond=True)
+    est, se = o.estimate(v, nwalk=10)
+    np.testing.assert_allclose(est, np.exp(1.5 * np.diag(a)) * v, rtol=1e-15)
+    assert not se.any()

@@ -69,6 +69,15 @@ MUTANTS = [
     ("forward value without the sign", "y = V * (v[lo] > 0.0 ? 1.0 : -1.0) * exp(r.logw);",
      "y = V * exp(r.logw);"),
     ("forward value credited to the start", "x_end = r.x_end;", "x_end = (int32_t)lo;"),
+    ("conditioned first time not truncated",
+     "S = -log(1.0 - uniform_open1(rnd[0], rnd[1]) * q) * ts->inv_r[x];",
+     "S = -log(uniform_open0(rnd[0], rnd[1])) * ts->inv_r[x];"),
+    ("conditioned value without the no-jump term",
+     "res->f = exp(-rt) * (exp(logk) * v[start]) + (-expm1(-rt)) * res->f;",
+     "res->f = (-expm1(-rt)) * res->f;"),
+    ("conditioned value without the jump probability",
+     "res->f = exp(-rt) * (exp(logk) * v[start]) + (-expm1(-rt)) * res->f;",
+     "res->f = exp(-rt) * (exp(logk) * v[start]) + res->f;"),
     ("forward grid not reversed",
      "acc += grid_coef(o, forward ? o->ngrid - k : k) * ts->d[path_x[m]];",
      "acc += grid_coef(o, k) * ts->d[path_x[m]];"),
