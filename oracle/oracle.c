@@ -90,18 +90,21 @@ void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], ui
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* U in (0,1] from the first two output words. */
-static double uniform_open0(uint32_t o0, uint32_t o1)
+/* 53 random bits from the first two output words. */
+static uint64_t bits53(uint32_t o0, uint32_t o1)
 {
-    uint64_t m = ((uint64_t)o0 << 21) | ((uint64_t)o1 >> 11);
-    return (double)(m + 1u) * 0x1p-53;
+    return ((uint64_t)o0 << 21) | ((uint64_t)o1 >> 11);
 }
 
-/* U in [0,1) from the same 53 bits. */
+/* U in (0,1] and in [0,1) from those bits. */
+static double uniform_open0(uint32_t o0, uint32_t o1)
+{
+    return (double)(bits53(o0, o1) + 1u) * 0x1p-53;
+}
+
 static double uniform_open1(uint32_t o0, uint32_t o1)
 {
-    uint64_t m = ((uint64_t)o0 << 21) | ((uint64_t)o1 >> 11);
-    return (double)m * 0x1p-53;
+    return (double)bits53(o0, o1) * 0x1p-53;
 }
 
 /* ------------------------------------------------------------------ model */

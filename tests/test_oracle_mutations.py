@@ -27,11 +27,11 @@ MUTANTS = [
      "uint64_t p0 = (uint64_t)0xD2511F52u * (uint64_t)c0;"),
     ("philox key increment", "k1 += 0xBB67AE85u;", "k1 += 0xBB67AE84u;"),
     ("philox output order", "out[0] = c0; out[1] = c1;", "out[0] = c1; out[1] = c0;"),
-    ("uniform from the low word only", "uint64_t m = ((uint64_t)o0 << 21) | ((uint64_t)o1 >> 11);",
-     "uint64_t m = ((uint64_t)o1 >> 11);"),
-    ("holding time scaled by the rate", "double S = -log(U) * ts->inv_r[x];",
-     "double S = -log(U) * ts->r[x];"),
-    ("jump test forgets elapsed time", "if (s + S < o->t) {", "if (S < o->t) {"),
+    ("uniform from the low word only", "return ((uint64_t)o0 << 21) | ((uint64_t)o1 >> 11);",
+     "return ((uint64_t)o1 >> 11);"),
+    ("holding time scaled by the rate", "S = -log(uniform_open0(rnd[0], rnd[1])) * ts->inv_r[x];",
+     "S = -log(uniform_open0(rnd[0], rnd[1])) * ts->r[x];"),
+    ("jump test forgets elapsed time", "jump = s + S < o->t;", "jump = S < o->t;"),
     ("slot index misses the last slot",
      "(((uint64_t)rnd[2] * (uint64_t)ts->deg[x]) >> 32)",
      "(((uint64_t)rnd[2] * (uint64_t)(ts->deg[x] - 1)) >> 32)"),
