@@ -81,6 +81,15 @@ typedef struct {
     uint32_t instance_id;       /* fourth Philox counter word. Default 0. */
     uint32_t max_events;        /* cap on holding intervals per walker; 0 = 2^24 */
     void *stream;               /* hipStream_t; NULL = null stream */
+    int32_t cond_first_jump;    /* 1: variance reduction by conditioning (a remedy of the
+                                   kind Sec. 5 names): every backward walker from a node
+                                   with exits is drawn given a jump before t (first
+                                   holding time from the exponential law truncated to
+                                   [0, t), U in [0,1) from the same 53 bits), and returns
+                                   e^{-rt} K + (1 - e^{-rt}) W v[X_t], K the value of a
+                                   walker that never leaves; the no-jump event is
+                                   integrated exactly, the mean is unchanged.  Backward
+                                   estimators only.  Default 0. */
 } mc_expmv_opts;
 
 typedef struct {

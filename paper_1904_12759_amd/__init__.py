@@ -50,6 +50,7 @@ class mc_expmv_opts(ctypes.Structure):
         ("instance_id", ctypes.c_uint32),
         ("max_events", ctypes.c_uint32),
         ("stream", ctypes.c_void_p),
+        ("cond_first_jump", ctypes.c_int32),
     ]
 
 
@@ -223,7 +224,7 @@ class MCExpmv:
     def __init__(self, rowptr, col, val, t: float, seed: int, mode: int = EXACT,
                  dt: float = 0.03125, fp32: bool = False, instance: int = 0,
                  max_events: int = 0, walkers_per_block: int = 64, relabel: int = 0,
-                 lds_budget: int = 0, stream=None):
+                 lds_budget: int = 0, stream=None, cond: bool = False):
         import torch
         lib_ = load()
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -237,7 +238,7 @@ class MCExpmv:
         opts = default_opts(mode=mode, dt=dt, weight_prec=FP32 if fp32 else FP64,
                             instance_id=instance, max_events=max_events,
                             walkers_per_block=walkers_per_block, relabel=relabel,
-                            lds_budget=lds_budget, stream=stream)
+                            lds_budget=lds_budget, stream=stream, cond_first_jump=int(cond))
         h = ctypes.c_void_p()
         torch.cuda.current_stream().synchronize()
         _check(lib_.mc_expmv_create(ctypes.byref(h), rp.numel() - 1, cl.numel(), _ptr(rp),

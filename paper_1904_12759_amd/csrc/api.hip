@@ -175,6 +175,7 @@ mc_status check_opts(const mc_expmv_opts &o) {
     if (o.resort_period != 0) return MC_ERR_INVALID_ARG;
     if (o.relabel != 0 && o.relabel != 1) return MC_ERR_INVALID_ARG;
     if (o.lds_budget != 0 && (!o.relabel || o.lds_budget > kMaxHotBytes)) return MC_ERR_INVALID_ARG;
+    if (o.cond_first_jump != 0 && o.cond_first_jump != 1) return MC_ERR_INVALID_ARG;
     return MC_OK;
 }
 
@@ -223,6 +224,7 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
     a.chunk = (uint32_t)chunk;
     a.chunks = chunks;
     a.group = trace ? 1u : group_size(nwalk, fp32);
+    a.cond = h->opts.cond_first_jump != 0;
     a.ntasks = (k + a.group - 1) / a.group * chunks;
     a.est = est;
     a.se = se;
@@ -1258,11 +1260,15 @@ mc_status mc_expmv_learn_proposal(mc_expmv_t h, const void *v, const mc_learn_op
     if (st == MC_OK) st = from_hip(hipEventCreate(&t0));
     if (st == MC_OK) st = from_hip(hipEventCreate(&t1));
     if (st == MC_OK) st = from_hip(hipEventCreate(&t2));
-    // 1. plain pilot over every node: per-node second moments
+    // 1. plain pilot over every node: per-node second moments of the plain walk
+    //    (without first-jump conditioning, whose second moments differ)
+    const int32_t cond = h->opts.cond_first_jump;
+    h->opts.cond_first_jump = 0;
     if (st == MC_OK) st = from_hip(hipEventRecord(t0, h->stream));
     if (st == MC_OK)
         st = run_walk(h, v, nullptr, n, o.pilot_walkers, est, se, false, 0, 0, nullptr, nullptr,
                       nullptr, nullptr);
+    h->opts.cond_first_jump = cond;
     if (st == MC_OK) st = mc_expmv_sync(h);
     if (st == MC_OK) st = mc_mlp_log_h(h, est, se, o.pilot_walkers, lh);
     if (st == MC_OK) st = mc_mlp_features(h, v, feats);

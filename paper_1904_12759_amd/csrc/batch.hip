@@ -45,7 +45,7 @@ __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, i
     const GroupOut out{I.est, I.se, a.part + I.part_off, e_first, I.chunks, c};
     TraceOut none;
 #define MC_GROUP(MODE, FP32)                                                                     \
-    run_group<MODE, FP32, false, false, false>(I.P, I.idx, I.n, G, (uint32_t)wbase, cnt, none, out,     \
+    run_group<MODE, FP32, false, false, false, false>(I.P, I.idx, I.n, G, (uint32_t)wbase, cnt, none, out,     \
                                         *reinterpret_cast<GroupLds<WeightT<FP32>::T> *>(lds),     \
                                         my_events, my_jumps, err)
     switch (I.mode * 2 + (I.fp32 ? 1 : 0)) {

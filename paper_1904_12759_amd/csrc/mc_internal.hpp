@@ -113,6 +113,7 @@ struct WalkArgs {
     unsigned long long *counters;  // [2 * grid]: events, jumps of every block
     uint32_t *flags;
     TraceOut trace;
+    bool cond;                 // first-jump conditioning
 };
 
 // Forward (Algorithm 2) walks: one wave per chunk of kFwdChunk walker ordinals.

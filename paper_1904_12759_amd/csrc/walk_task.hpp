@@ -83,6 +83,30 @@ __device__ __forceinline__ double exp_f64(double x) {
     return ldexp(p, (int)k);
 }
 
+// 1 - e^{-y} for y >= 0 without cancellation: for y below ln2/2 the series
+// y (1 - y/2! + y^2/3! - ...) to y^14 (truncation below 2^-56 relative),
+// otherwise 1 - e^{-y} with exp_f64 (e^{-y} <= 0.71, so the difference loses
+// no more than a bit).
+__device__ __forceinline__ double one_minus_exp_neg(double y) {
+    if (y >= sconst(0.34657359027997264)) return 1.0 - exp_f64(-y);
+    const double r = -y;
+    double p = sconst(1.0 / 87178291200.0);                      // 1/14!
+    p = fma(p, r, sconst(1.0 / 6227020800.0));
+    p = fma(p, r, sconst(1.0 / 479001600.0));
+    p = fma(p, r, sconst(1.0 / 39916800.0));
+    p = fma(p, r, sconst(1.0 / 3628800.0));
+    p = fma(p, r, sconst(1.0 / 362880.0));
+    p = fma(p, r, sconst(1.0 / 40320.0));
+    p = fma(p, r, sconst(1.0 / 5040.0));
+    p = fma(p, r, sconst(1.0 / 720.0));
+    p = fma(p, r, sconst(1.0 / 120.0));
+    p = fma(p, r, sconst(1.0 / 24.0));
+    p = fma(p, r, sconst(1.0 / 6.0));
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    return y * p;                                                // -(r P(r)) = -expm1(r)
+}
+
 __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                      uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -300,6 +324,8 @@ struct alignas(16) GroupLds {
     static constexpr uint32_t C = chunk_walkers(sizeof(WT) == sizeof(float));
     WT fval[C];                   // W v[X_t] of list[i]
     double K[kGroupMax];          // value of a walker that never leaves the start node
+                                  // (first-jump conditioning: e^{-rt} times that value)
+    double q[kGroupMax];          // first-jump conditioning: 1 - e^{-rt} of the start node
     uint32_t node[kGroupMax];     // start node of each entry (UINT32_MAX: out of range)
     uint32_t n0[kGroupMax];       // walkers of each entry that never jump
     uint32_t seg[kGroupMax + 1];  // entry g's jumpers are list[seg[g] .. seg[g+1])
@@ -330,7 +356,7 @@ struct GroupOut {
 // entry's mean and M2 come from a two-pass reduction over its slots in a fixed
 // order plus its n0 copies of K: the result does not depend on which lane ran
 // which walker, nor on how many entries share the task.
-template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC>
+template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND>
 __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx, int64_t n,
                                           uint32_t G, uint32_t ord0, uint32_t cnt,
                                           const TraceOut &tr, const GroupOut &out,
@@ -357,10 +383,23 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             const WT d0 = d_at<FP32, LOC>(P, x0);
             const WT v0 = load_v<FP32>(P.v, node);
             K = (double)(wexp<FP32>(final_term<MODE, FP32>(d0, 0.0, 0, P)) * v0);
-            // e^{-rt} in FP32 (relative error below 1e-6 where e0 >= 1/8 matters),
-            // lowered by 2^-16; 2: never jumps
-            e0 = r0.deg ? (double)exp2f((float)(-t / r0.inv_r) * 1.44269504f) * (1.0 - 0x1p-16)
-                        : 2.0;
+            if constexpr (COND) {
+                // every walker of a row with exits is sampled given a jump before t;
+                // the no-jump event enters as e^{-rt} K
+                double q = 0.0;
+                if (r0.deg) {
+                    const double rt = t / r0.inv_r;
+                    K = exp_f64(-rt) * K;
+                    q = one_minus_exp_neg(rt);
+                }
+                L.q[lane] = q;
+                e0 = r0.deg ? 0.0 : 2.0;
+            } else {
+                // e^{-rt} in FP32 (relative error below 1e-6 where e0 >= 1/8 matters),
+                // lowered by 2^-16; 2: never jumps
+                e0 = r0.deg ? (double)exp2f((float)(-t / r0.inv_r) * 1.44269504f) * (1.0 - 0x1p-16)
+                            : 2.0;
+            }
         } else {
             err |= F_OUT_OF_RANGE;
         }
@@ -470,12 +509,21 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 fin = true;
             } else {
                 const U4 o = philox(ev, ord0 + (code & 1023u), node, P.inst, P.key0, P.key1);
-                ++ev;
                 const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
-                const double U = (double)(m + 1ull) * 0x1p-53;
-                const double S = -log_unit(U) * inv_r;
+                double S;
+                if (COND && ev == 0) {
+                    // first holding time given a jump before t: inverse of the
+                    // exponential law truncated to [0, t), U in [0, 1)
+                    const double U = (double)m * 0x1p-53;
+                    S = -log_unit(1.0 - U * L.q[code >> 10]) * inv_r;
+                } else {
+                    const double U = (double)(m + 1ull) * 0x1p-53;
+                    S = -log_unit(U) * inv_r;
+                }
                 const double sn = s + S;
-                if (sn < t) {
+                const bool jump = (COND && ev == 0) || sn < t;
+                ++ev;
+                if (jump) {
                     if constexpr (MODE == MC_EXACT) {
                         logw = logw + dx * (WT)S;
                     } else {
@@ -510,6 +558,10 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 } else {
                     logw = logw + final_term<MODE, FP32>(dx, s, ka, P);
                     f = wexp<FP32>(logw) * load_v<FP32>(P.v, orig_id<LOC>(P, x));
+                    if constexpr (COND) {
+                        const uint32_t e = code >> 10;
+                        f = (WT)(L.K[e] + L.q[e] * (double)f);
+                    }
                     if (!isfinite((double)f)) err |= F_OVERFLOW;
                 }
                 L.fval[wl] = f;
