@@ -400,6 +400,64 @@ def bench_forward_tc(mc, seed, n=1_000_000, m=1_000_000, steps=5):
     return out
 
 
+# first-jump conditioning only where the start node keeps its walkers with
+# probability >= 1/2 (r t <= ln 2)
+HYBRID_RT = 0.6931471805599453
+
+
+def bench_conditioning(mc, seed, steps=10):
+    """First-jump conditioning against the plain walk: on the main BA n=1e5 workload
+    (full vector, 1000 walkers per node, FP32) the kernel time and the per-node
+    variance, combined as the work-normalised gain (var_plain t_plain) /
+    (var_cond t_cond), median over nodes; and entries/s at 1e-3 on the grid2d
+    32x32 entries workload (FP64), both walks."""
+    import torch
+    from paper_1904_12759_amd import workloads as wl
+    out = {}
+    w = wl.config_ba_full()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    v = torch.as_tensor(w.v, dtype=torch.float32, device=dev)
+    res = {}
+    for name, cond, theta in (("plain", False, np.inf), ("cond", True, np.inf),
+                              ("hybrid", True, HYBRID_RT)):
+        h = mc.MCExpmv(w.a.rowptr, w.a.col, w.a.val, w.t, seed, fp32=True, cond=cond,
+                       cond_max_rt=theta)
+        est = torch.empty(w.a.n, dtype=torch.float64, device=dev)
+        se = torch.empty(w.a.n, dtype=torch.float64, device=dev)
+        h.full(v, w.nwalk, est=est, stderr=se)
+        ms = []
+        for _ in range(steps):
+            h.full(v, w.nwalk, est=est, stderr=se)
+            ms.append(h.stats()["ms"])
+        st = h.stats()
+        res[name] = (float(np.median(ms)), (se * se).cpu().numpy(), st["events"])
+        del h
+    deg = np.diff(w.a.rowptr)
+    out["ba_full"] = dict(
+        workload="BA n=1e5 m=3, full vector, 1000 walkers/node, FP32 weights",
+        hybrid_cond_max_rt=HYBRID_RT)
+    for name in ("cond", "hybrid"):
+        gain = (res["plain"][1] * res["plain"][0]) / np.maximum(res[name][1] * res[name][0], 1e-300)
+        # total work to bring every node to the same standard error: sum of variances x time
+        total = (res["plain"][1].sum() * res["plain"][0]) / (res[name][1].sum() * res[name][0])
+        out["ba_full"][name] = dict(
+            kernel_ms=res[name][0], events=res[name][2],
+            median_work_normalised_gain=float(np.median(gain)),
+            median_gain_degree_3=float(np.median(gain[deg == 3])),
+            median_gain_top_1pct_degree=float(np.median(gain[deg >= np.quantile(deg, 0.99)])),
+            total_work_gain=float(total))
+    out["ba_full"]["kernel_ms_plain"] = res["plain"][0]
+    g2 = wl.config_grid2d_entries()
+    for name, cond in (("plain", False), ("cond", True)):
+        h = mc.MCExpmv(g2.a.rowptr, g2.a.col, g2.a.val, g2.t, seed, cond=cond)
+        entries_at_1e3(mc, h, g2.v, g2.idx, 10_000)                       # warm-up
+        r = entries_at_1e3(mc, h, g2.v, g2.idx, 10_000)
+        out[f"grid2d_entries_at_1e3_{name}"] = dict(entries_per_s=r["entries_per_s"],
+                                                    walkers=r["walkers"],
+                                                    max_rel_stderr=r["max_rel_stderr"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -410,7 +468,7 @@ def main():
                     help="skip every extra measurement (same as --extras none)")
     ap.add_argument("--extras", default="all",
                     help="comma-separated extra measurements after the main step: "
-                         "locality, entries, learned, grid3d, batched, forward; 'all' or 'none'")
+                         "locality, entries, learned, grid3d, batched, forward, cond; 'all' or 'none'")
     ap.add_argument("--seed", type=int, default=12759)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (steps times), "
@@ -514,7 +572,7 @@ def main():
             "traffic": measured_traffic(),
         },
     }
-    names = ["locality", "entries", "learned", "grid3d", "batched", "forward"]
+    names = ["locality", "entries", "learned", "grid3d", "batched", "forward", "cond"]
     extras = [] if args.no_extras or args.extras == "none" else \
         names if args.extras == "all" else [x for x in args.extras.split(",") if x]
     unknown = [x for x in extras if x not in names]
@@ -539,6 +597,9 @@ def main():
     if "forward" in extras:
         log("bench: forward total communicability (small world n=1e6)")
         out["forward_tc"] = bench_forward_tc(mc, args.seed)
+    if "cond" in extras:
+        log("bench: first-jump conditioning vs plain")
+        out["conditioning"] = bench_conditioning(mc, args.seed)
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         try:

@@ -90,6 +90,10 @@ typedef struct {
                                    walker that never leaves; the no-jump event is
                                    integrated exactly, the mean is unchanged.  Backward
                                    estimators only.  Default 0. */
+    double cond_max_rt;         /* conditioning applies to start nodes with exits and
+                                   r t <= cond_max_rt, decided in FP64 as
+                                   t <= cond_max_rt * (1/r); others walk plainly.
+                                   Default +inf (every node with exits). */
 } mc_expmv_opts;
 
 typedef struct {

@@ -84,7 +84,7 @@ def _load():
         lib.oracle_dt.restype = dbl
         lib.oracle_get_tables.argtypes = [vp, i32] + [vp] * 9
         lib.oracle_get_tables.restype = i32
-        lib.oracle_set_conditioning.argtypes = [vp, i32]
+        lib.oracle_set_conditioning.argtypes = [vp, i32, dbl]
         lib.oracle_set_conditioning.restype = i32
         lib.oracle_forward.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.oracle_forward.restype = i32
@@ -113,7 +113,7 @@ class Oracle:
 
     def __init__(self, rowptr, col, val, t: float, seed: int, mode: int = EXACT,
                  dt: float = 0.03125, instance: int = 0, max_events: int = 0,
-                 cond: bool = False):
+                 cond: bool = False, cond_max_rt: float = float("inf")):
         lib = _load()
         self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
         self._col = np.ascontiguousarray(col, dtype=np.int32)
@@ -134,7 +134,7 @@ class Oracle:
         self.dt = float(lib.oracle_dt(h))
         self.has_proposal = False
         self.cond = bool(cond)
-        lib.oracle_set_conditioning(h, int(self.cond))
+        lib.oracle_set_conditioning(h, int(self.cond), float(cond_max_rt))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -136,6 +136,7 @@ typedef struct {
     int has_proposal;
     table_set prop;
     int cond;                     /* condition backward walks on a first jump before t */
+    double cond_max_rt;           /* ... from start nodes with t <= cond_max_rt / r */
     int64_t *slot_of_csr;         /* CSR position -> slot index, -1 if none */
 } oracle_t;
 
@@ -421,13 +422,15 @@ static double grid_coef(const oracle_t *o, int64_t k)
  * K the value of a walker that never leaves the start node: the no-jump event,
  * of probability e^{-r t}, is integrated exactly and only the jump event is
  * sampled, so the mean is unchanged and the variance of the start node's
- * jump/no-jump choice is removed. */
+ * jump/no-jump choice is removed.  It applies to start nodes with exits and
+ * r t <= cond_max_rt (decided as t <= cond_max_rt * (1/r), the stored 1/r). */
 static void walk_path(const oracle_t *o, int64_t start, uint32_t w, const double *v,
                       int use_prop, int forward, int64_t *path_x, double *path_s,
                       double *path_c, walk_out *res)
 {
-    const int cond = o->cond && !forward;
     const table_set *ts = use_prop ? &o->prop : &o->plain;
+    const int cond = o->cond && !forward && ts->deg[start] > 0 &&
+                     o->t <= o->cond_max_rt * ts->inv_r[start];
     uint32_t key[2] = { (uint32_t)o->seed, (uint32_t)(o->seed >> 32) };
     int64_t x = start;
     double s = 0.0;
@@ -495,7 +498,7 @@ static void walk_path(const oracle_t *o, int64_t start, uint32_t w, const double
     }
     res->logw = logw;
     res->f = exp(logw) * v[x];
-    if (cond && ts->deg[start] > 0) {
+    if (cond) {
         /* no-jump value K of the start node (its weight over the whole horizon) */
         double logk = 0.0;
         if (o->mode == OR_EXACT) {
@@ -645,10 +648,12 @@ int oracle_estimate(const oracle_t *o, const double *v, const int64_t *idx, int6
     return st;
 }
 
-/* Switch the first-jump conditioning of backward walks on or off. */
-int oracle_set_conditioning(oracle_t *o, int on)
+/* Switch the first-jump conditioning of backward walks on or off; it applies
+ * to start nodes with exits and r t <= max_rt, decided as t <= max_rt (1/r). */
+int oracle_set_conditioning(oracle_t *o, int on, double max_rt)
 {
     o->cond = on ? 1 : 0;
+    o->cond_max_rt = max_rt;
     return OR_OK;
 }
 

@@ -51,6 +51,7 @@ class mc_expmv_opts(ctypes.Structure):
         ("max_events", ctypes.c_uint32),
         ("stream", ctypes.c_void_p),
         ("cond_first_jump", ctypes.c_int32),
+        ("cond_max_rt", ctypes.c_double),
     ]
 
 
@@ -224,7 +225,8 @@ class MCExpmv:
     def __init__(self, rowptr, col, val, t: float, seed: int, mode: int = EXACT,
                  dt: float = 0.03125, fp32: bool = False, instance: int = 0,
                  max_events: int = 0, walkers_per_block: int = 64, relabel: int = 0,
-                 lds_budget: int = 0, stream=None, cond: bool = False):
+                 lds_budget: int = 0, stream=None, cond: bool = False,
+                 cond_max_rt: float = float("inf")):
         import torch
         lib_ = load()
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -238,7 +240,8 @@ class MCExpmv:
         opts = default_opts(mode=mode, dt=dt, weight_prec=FP32 if fp32 else FP64,
                             instance_id=instance, max_events=max_events,
                             walkers_per_block=walkers_per_block, relabel=relabel,
-                            lds_budget=lds_budget, stream=stream, cond_first_jump=int(cond))
+                            lds_budget=lds_budget, stream=stream, cond_first_jump=int(cond),
+                            cond_max_rt=float(cond_max_rt))
         h = ctypes.c_void_p()
         torch.cuda.current_stream().synchronize()
         _check(lib_.mc_expmv_create(ctypes.byref(h), rp.numel() - 1, cl.numel(), _ptr(rp),

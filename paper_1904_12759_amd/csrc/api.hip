@@ -176,6 +176,7 @@ mc_status check_opts(const mc_expmv_opts &o) {
     if (o.relabel != 0 && o.relabel != 1) return MC_ERR_INVALID_ARG;
     if (o.lds_budget != 0 && (!o.relabel || o.lds_budget > kMaxHotBytes)) return MC_ERR_INVALID_ARG;
     if (o.cond_first_jump != 0 && o.cond_first_jump != 1) return MC_ERR_INVALID_ARG;
+    if (!(o.cond_max_rt >= 0.0)) return MC_ERR_INVALID_ARG;
     return MC_OK;
 }
 
@@ -201,6 +202,7 @@ void fill_inst(const mc_expmv_s *h, const void *v, bool prop, InstArgs &P) {
     P.key1 = (uint32_t)(h->seed >> 32);
     P.inst = h->opts.instance_id;
     P.max_events = h->opts.max_events ? h->opts.max_events : (1u << 24);
+    P.cond_max_rt = h->opts.cond_max_rt;
 }
 
 // Run the walk kernel for k entries (idx == null: every node).
@@ -280,6 +282,8 @@ void mc_expmv_default_opts(mc_expmv_opts *o) {
     o->instance_id = 0;
     o->max_events = 0;
     o->stream = nullptr;
+    o->cond_first_jump = 0;
+    o->cond_max_rt = INFINITY;
 }
 
 const char *mc_expmv_status_string(mc_status s) {

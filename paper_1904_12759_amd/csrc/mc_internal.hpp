@@ -78,6 +78,7 @@ struct InstArgs {
     double inv_dt;             // N / t
     int32_t ngrid;             // N
     uint32_t key0, key1, inst, max_events;
+    double cond_max_rt;        // first-jump conditioning for start nodes with t <= this / r
 };
 
 // Per-walker record (parity checks only).

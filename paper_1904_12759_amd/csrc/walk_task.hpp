@@ -383,17 +383,18 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             const WT d0 = d_at<FP32, LOC>(P, x0);
             const WT v0 = load_v<FP32>(P.v, node);
             K = (double)(wexp<FP32>(final_term<MODE, FP32>(d0, 0.0, 0, P)) * v0);
-            if constexpr (COND) {
-                // every walker of a row with exits is sampled given a jump before t;
-                // the no-jump event enters as e^{-rt} K
-                double q = 0.0;
-                if (r0.deg) {
-                    const double rt = t / r0.inv_r;
-                    K = exp_f64(-rt) * K;
-                    q = one_minus_exp_neg(rt);
-                }
-                L.q[lane] = q;
-                e0 = r0.deg ? 0.0 : 2.0;
+            // first-jump conditioning (start nodes with exits and r t <= cond_max_rt):
+            // every walker is sampled given a jump before t and the no-jump event
+            // enters as e^{-rt} K; q = 1 - e^{-rt} > 0 marks such an entry
+            double q = 0.0;
+            if (COND && r0.deg && t <= P.cond_max_rt * r0.inv_r) {
+                const double rt = t / r0.inv_r;
+                q = one_minus_exp_neg(rt);
+            }
+            if (COND) L.q[lane] = q;
+            if (q > 0.0) {
+                K = exp_f64(-t / r0.inv_r) * K;
+                e0 = 0.0;                 // list every walker
             } else {
                 // e^{-rt} in FP32 (relative error below 1e-6 where e0 >= 1/8 matters),
                 // lowered by 2^-16; 2: never jumps
@@ -511,17 +512,18 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 const U4 o = philox(ev, ord0 + (code & 1023u), node, P.inst, P.key0, P.key1);
                 const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
                 double S;
-                if (COND && ev == 0) {
+                const double qe = (COND && ev == 0) ? L.q[code >> 10] : 0.0;
+                if (qe > 0.0) {
                     // first holding time given a jump before t: inverse of the
                     // exponential law truncated to [0, t), U in [0, 1)
                     const double U = (double)m * 0x1p-53;
-                    S = -log_unit(1.0 - U * L.q[code >> 10]) * inv_r;
+                    S = -log_unit(1.0 - U * qe) * inv_r;
                 } else {
                     const double U = (double)(m + 1ull) * 0x1p-53;
                     S = -log_unit(U) * inv_r;
                 }
                 const double sn = s + S;
-                const bool jump = (COND && ev == 0) || sn < t;
+                const bool jump = qe > 0.0 || sn < t;
                 ++ev;
                 if (jump) {
                     if constexpr (MODE == MC_EXACT) {
@@ -560,7 +562,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     f = wexp<FP32>(logw) * load_v<FP32>(P.v, orig_id<LOC>(P, x));
                     if constexpr (COND) {
                         const uint32_t e = code >> 10;
-                        f = (WT)(L.K[e] + L.q[e] * (double)f);
+                        if (L.q[e] > 0.0) f = (WT)(L.K[e] + L.q[e] * (double)f);
                     }
                     if (!isfinite((double)f)) err |= F_OVERFLOW;
                 }

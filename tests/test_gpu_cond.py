@@ -125,3 +125,25 @@ def test_conditioned_ba_sampled_and_variance_reduction():
     low = np.where(deg == 3)[0][:2000]
     ratio = pse.cpu().numpy()[low] / se.cpu().numpy()[low]
     assert np.median(ratio) > 2.0
+
+
+def test_conditioning_threshold_matches_oracle():
+    g0 = wl.ba_graph(400, 2, 9)
+    a = wl.scaled(g0, 0.8 / wl.lambda_max(g0))
+    v = np.random.default_rng(10).random(a.n)
+    r = np.zeros(a.n)
+    np.add.at(r, np.repeat(np.arange(a.n), np.diff(a.rowptr)), a.val)
+    theta = float(np.quantile(r, 0.7))
+    g = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 11, cond=True, cond_max_rt=theta)
+    o = Oracle(a.rowptr, a.col, a.val, 1.0, 11, cond=True, cond_max_rt=theta)
+    low = int(np.where(r < 0.99 * theta)[0][0])
+    high = int(np.where(r > 1.01 * theta)[0][0])
+    for i in (low, high):
+        xg, eg, jg, fg = g.trace(v, i, 0, 1500)
+        xo, eo, jo, fo, _ = o.trace(v, i, 0, 1500)
+        assert np.array_equal(xg, xo) and np.array_equal(eg, eo) and np.array_equal(jg, jo)
+        assert _rel(fg, fo) <= 1e-12
+    idx = np.arange(0, a.n, 7)
+    est, se = g.entries(v, idx, 900)
+    eo, so = o.estimate(v, idx, 900)
+    assert _rel(est.cpu().numpy(), eo) <= 1e-12

@@ -603,3 +603,25 @@ def test_conditioned_diagonal_and_rate_zero_rows():
     est, se = o.estimate(v, nwalk=10)
     np.testing.assert_allclose(est, np.exp(1.5 * np.diag(a)) * v, rtol=1e-15)
     assert not se.any()
+
+
+def test_conditioning_threshold_selects_nodes():
+    """With cond_max_rt = theta, start nodes with r t <= theta take the conditioned
+    walk and the others the plain one, walker for walker."""
+    g = wl.ba_graph(300, 2, 9)
+    a = wl.scaled(g, 0.8 / wl.lambda_max(g))
+    v = np.random.default_rng(10).random(a.n)
+    t = 1.0
+    r = np.zeros(a.n)
+    np.add.at(r, np.repeat(np.arange(a.n), np.diff(a.rowptr)), a.val)
+    theta = float(np.quantile(r * t, 0.7))
+    mixed = Oracle(a.rowptr, a.col, a.val, t, 11, cond=True, cond_max_rt=theta)
+    allc = Oracle(a.rowptr, a.col, a.val, t, 11, cond=True)
+    plain = Oracle(a.rowptr, a.col, a.val, t, 11)
+    low = np.where(r * t < 0.99 * theta)[0][:5]
+    high = np.where(r * t > 1.01 * theta)[0][:5]
+    assert len(low) and len(high)
+    for i in low:
+        assert np.array_equal(mixed.trace(v, i, 0, 200)[3], allc.trace(v, i, 0, 200)[3])
+    for i in high:
+        assert np.array_equal(mixed.trace(v, i, 0, 200)[3], plain.trace(v, i, 0, 200)[3])
