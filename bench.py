@@ -400,6 +400,76 @@ def bench_forward_tc(mc, seed, n=1_000_000, m=1_000_000, steps=5):
     return out
 
 
+def bench_splitting(mc, seed, m_total=4_000_000, m_entry=1_000_000):
+    """Splitting study (Sec. 5, Figs. 2-3): small-world networks n = 100 and 1000
+    (Newman-Watts, mean degree 2.4), A = adjacency, t = 1, v = 1, dt = 1/2 .. 1/64.  Per
+    dt the exact errors of the Strang and Lie products (dense) for the total
+    communicability and for entry 0, the errors of the GPU estimates in STRANG and LIE
+    mode (forward walks for the total, M = 4e6; backward walks for entry 0, 1e6 walkers)
+    with their standard errors, and the leading Strang term |(1, D L D 1)| dt^2."""
+    import torch
+    import scipy.linalg as sla
+    from paper_1904_12759_amd import workloads as wl
+
+    def split_parts(a):
+        off = a - np.diag(np.diag(a))
+        return np.diag(a) + off.sum(1), np.diag(off.sum(1)) - off     # d, L
+
+    def strang(a, nsteps, x):        # (e^{dt D/2} e^{-dt L} e^{dt D/2})^N x
+        d, lap = split_parts(a)
+        dt = 1.0 / nsteps
+        h = np.exp(dt * d / 2)
+        step = h[:, None] * sla.expm(-dt * lap) * h[None, :]
+        for _ in range(nsteps):
+            x = step @ x
+        return x
+
+    def lie(a, nsteps, x):           # (e^{-dt L} e^{dt D})^N x
+        d, lap = split_parts(a)
+        dt = 1.0 / nsteps
+        step = sla.expm(-dt * lap) * np.exp(dt * d)[None, :]
+        for _ in range(nsteps):
+            x = step @ x
+        return x
+
+    dev = torch.device("cuda", torch.cuda.current_device())
+    dts = [0.5, 0.25, 0.125, 0.0625, 0.03125, 0.015625]
+    out = dict(dts=dts)
+    for n in (100, 1000):
+        w = wl.small_world(n, 0.2, 3)
+        a = w.to_dense()
+        one = np.ones(n)
+        exact = sla.expm(a) @ one
+        dvec, lap = split_parts(a)
+        lead = abs(one @ (dvec * (lap @ (dvec * one))))
+        rec = dict(tc_exact=float(exact.sum()), x0_exact=float(exact[0]),
+                   strang_lead_coef=float(lead))
+        v = torch.ones(n, dtype=torch.float64, device=dev)
+        for name, mode, prod in (("strang", mc.STRANG, strang), ("lie", mc.LIE, lie)):
+            r = dict(tc_split_err=[], x0_split_err=[], tc_mc_err=[], tc_mc_se=[], x0_mc_err=[],
+                     x0_mc_se=[])
+            for dt in dts:
+                nsteps = int(round(1 / dt))
+                p = prod(a, nsteps, one)
+                r["tc_split_err"].append(float(p.sum() - exact.sum()))
+                r["x0_split_err"].append(float(p[0] - exact[0]))
+                h = mc.MCExpmv(w.rowptr, w.col, w.val, 1.0, seed, mode=mode, dt=dt)
+                _, _, tot = h.forward(v, m_total, total_only=True)
+                tc, tse = tot.cpu().numpy().tolist()
+                e, se = h.entries(v, [0], m_entry)
+                r["tc_mc_err"].append(tc - float(exact.sum()))
+                r["tc_mc_se"].append(tse)
+                r["x0_mc_err"].append(e.item() - float(exact[0]))
+                r["x0_mc_se"].append(se.item())
+                del h
+            fit = lambda errs: float(np.polyfit(np.log(dts), np.log(np.abs(errs)), 1)[0])
+            r["tc_split_order"] = fit(r["tc_split_err"])
+            r["x0_split_order"] = fit(r["x0_split_err"])
+            rec[name] = r
+        out[f"n{n}"] = rec
+    return out
+
+
 # first-jump conditioning only where the start node keeps its walkers with
 # probability >= 1/2 (r t <= ln 2)
 HYBRID_RT = 0.6931471805599453
@@ -468,7 +538,8 @@ def main():
                     help="skip every extra measurement (same as --extras none)")
     ap.add_argument("--extras", default="all",
                     help="comma-separated extra measurements after the main step: "
-                         "locality, entries, learned, grid3d, batched, forward, cond; 'all' or 'none'")
+                         "locality, entries, learned, grid3d, batched, forward, cond, splitting; "
+                         "'all' or 'none'")
     ap.add_argument("--seed", type=int, default=12759)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (steps times), "
@@ -572,7 +643,7 @@ def main():
             "traffic": measured_traffic(),
         },
     }
-    names = ["locality", "entries", "learned", "grid3d", "batched", "forward", "cond"]
+    names = ["locality", "entries", "learned", "grid3d", "batched", "forward", "cond", "splitting"]
     extras = [] if args.no_extras or args.extras == "none" else \
         names if args.extras == "all" else [x for x in args.extras.split(",") if x]
     unknown = [x for x in extras if x not in names]
@@ -600,6 +671,9 @@ def main():
     if "cond" in extras:
         log("bench: first-jump conditioning vs plain")
         out["conditioning"] = bench_conditioning(mc, args.seed)
+    if "splitting" in extras:
+        log("bench: splitting study (small world n=100, 1000)")
+        out["splitting"] = bench_splitting(mc, args.seed)
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         try:
