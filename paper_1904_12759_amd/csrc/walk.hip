@@ -34,11 +34,11 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     __shared__ unsigned long long sh_count[256 / WAVE][2];
     const int nw = blockDim.x / WAVE;
-    GroupLds<WT> &L = reinterpret_cast<GroupLds<WT> *>(dyn_lds)[threadIdx.x / WAVE];
+    GroupLds<WT, COND> &L = reinterpret_cast<GroupLds<WT, COND> *>(dyn_lds)[threadIdx.x / WAVE];
     // hot rows: LDS copies of rows[0 .. hot) and d[0 .. hot) after the wave scratch
     InstArgs P = a.P;
     if (LOC && P.hot) {
-        RowRec *lr = reinterpret_cast<RowRec *>(dyn_lds + nw * sizeof(GroupLds<WT>));
+        RowRec *lr = reinterpret_cast<RowRec *>(dyn_lds + nw * sizeof(GroupLds<WT, COND>));
         WT *ld = reinterpret_cast<WT *>(lr + P.hot);
         const WT *gd = FP32 ? (const WT *)(const void *)a.P.d32 : (const WT *)(const void *)a.P.d64;
         for (uint32_t k = threadIdx.x; k < P.hot; k += blockDim.x) {
@@ -124,7 +124,8 @@ hipError_t launch_t(const WalkArgs &a, int block, hipStream_t s) {
     // a task's walkers must fit its LDS value slots
     if (a.chunk != GroupLds<WT>::C || a.group == 0 || a.group > kGroupMax)
         return hipErrorInvalidValue;
-    const size_t lds = (size_t)(block / WAVE) * sizeof(GroupLds<WT>) +
+    const size_t task_lds = a.cond ? sizeof(GroupLds<WT, true>) : sizeof(GroupLds<WT, false>);
+    const size_t lds = (size_t)(block / WAVE) * task_lds +
                        (size_t)a.P.hot * (sizeof(RowRec) + sizeof(WT));
     const dim3 grid((unsigned)walk_grid(a.ntasks, block));
     if (a.P.perm) {

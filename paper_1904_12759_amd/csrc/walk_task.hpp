@@ -319,17 +319,17 @@ using namespace detail;
 // ----------------------------------------------------------- one task
 // Per-wave LDS scratch of run_group (16-byte aligned size: the hot-row copies
 // that may follow the wave scratch are read as 16-byte records).
-template <typename WT>
+template <typename WT, bool COND = false>
 struct alignas(16) GroupLds {
     static constexpr uint32_t C = chunk_walkers(sizeof(WT) == sizeof(float));
     WT fval[C];                   // W v[X_t] of list[i]
     double K[kGroupMax];          // value of a walker that never leaves the start node
                                   // (first-jump conditioning: e^{-rt} times that value)
-    double q[kGroupMax];          // first-jump conditioning: 1 - e^{-rt} of the start node
     uint32_t node[kGroupMax];     // start node of each entry (UINT32_MAX: out of range)
     uint32_t n0[kGroupMax];       // walkers of each entry that never jump
     uint32_t seg[kGroupMax + 1];  // entry g's jumpers are list[seg[g] .. seg[g+1])
     uint16_t list[C];             // jumpers: (entry << 10) | ordinal, entry-major, ordinal order
+    double q[COND ? kGroupMax : 1];  // first-jump conditioning: 1 - e^{-rt} of the start node
 };
 static_assert(kGroupMax <= 64 && kChunkMax <= 1024, "list codes are 6 + 10 bits");
 
@@ -360,7 +360,7 @@ template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND>
 __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx, int64_t n,
                                           uint32_t G, uint32_t ord0, uint32_t cnt,
                                           const TraceOut &tr, const GroupOut &out,
-                                          GroupLds<typename WeightT<FP32>::T> &L,
+                                          GroupLds<typename WeightT<FP32>::T, COND> &L,
                                           unsigned long long &my_events,
                                           unsigned long long &my_jumps, uint32_t &err_out) {
     using WT = typename WeightT<FP32>::T;
@@ -391,7 +391,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 const double rt = t / r0.inv_r;
                 q = one_minus_exp_neg(rt);
             }
-            if (COND) L.q[lane] = q;
+            if constexpr (COND) L.q[lane] = q;
             if (q > 0.0) {
                 K = exp_f64(-t / r0.inv_r) * K;
                 e0 = 0.0;                 // list every walker
@@ -510,22 +510,27 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 fin = true;
             } else {
                 const U4 o = philox(ev, ord0 + (code & 1023u), node, P.inst, P.key0, P.key1);
+                ++ev;
                 const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
                 double S;
-                const double qe = (COND && ev == 0) ? L.q[code >> 10] : 0.0;
-                if (qe > 0.0) {
-                    // first holding time given a jump before t: inverse of the
-                    // exponential law truncated to [0, t), U in [0, 1)
-                    const double U = (double)m * 0x1p-53;
-                    S = -log_unit(1.0 - U * qe) * inv_r;
+                bool forced = false;
+                if constexpr (COND) {
+                    const double qe = ev == 1 ? L.q[code >> 10] : 0.0;
+                    if (qe > 0.0) {
+                        // first holding time given a jump before t: inverse of the
+                        // exponential law truncated to [0, t), U in [0, 1)
+                        const double U = (double)m * 0x1p-53;
+                        S = -log_unit(1.0 - U * qe) * inv_r;
+                        forced = true;
+                    } else {
+                        S = -log_unit((double)(m + 1ull) * 0x1p-53) * inv_r;
+                    }
                 } else {
                     const double U = (double)(m + 1ull) * 0x1p-53;
                     S = -log_unit(U) * inv_r;
                 }
                 const double sn = s + S;
-                const bool jump = qe > 0.0 || sn < t;
-                ++ev;
-                if (jump) {
+                if (forced || sn < t) {
                     if constexpr (MODE == MC_EXACT) {
                         logw = logw + dx * (WT)S;
                     } else {
