@@ -2,6 +2,8 @@
 // device allocations, kernel launches on the caller's stream, latched device
 // errors and run statistics.  No C++ exception leaves this file.
 #include <math.h>
+
+#include <algorithm>
 #include <string.h>
 
 #include <new>
@@ -625,7 +627,8 @@ struct mc_batch_s {
     hipStream_t stream = nullptr;    // private stream (graph capture needs a non-null one)
     uint64_t seed = 0;
     std::vector<mc_expmv_t> handles; // table owners, one per instance
-    std::vector<BatchInst> inst;
+    std::vector<BatchInst> inst;         // grouped by class (weight mode, precision)
+    std::vector<BatchClass> classes;
     std::vector<int64_t> fin_begin;
     BatchInst *d_inst = nullptr;
     int64_t *d_fin = nullptr;
@@ -669,7 +672,8 @@ void batch_free(mc_batch_s *b) {
 
 hipError_t batch_launch(mc_batch_s *b) {
     b->args.group = b->group;
-    return launch_batch(b->args, b->block, b->grid, b->stream);
+    return launch_batch(b->args, b->classes.data(), (int)b->classes.size(), b->block, b->grid,
+                        b->stream);
 }
 
 // (Re)build the graph for the current block / grid / group.
@@ -839,8 +843,17 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
 
     int64_t ntasks = 0, part_doubles = 0, nfin = 0;
     b->fin_begin.assign((size_t)n_inst + 1, 0);
-    for (int i = 0; i < n_inst; ++i) {
+    // instances grouped by class (weight mode, precision), each class one
+    // specialised persistent launch; order within a class as given
+    std::vector<int> order((size_t)n_inst);
+    for (int i = 0; i < n_inst; ++i) order[(size_t)i] = i;
+    auto cls = [&](int i) { return desc[i].mode * 2 + (desc[i].weight_prec == MC_FP32 ? 1 : 0); };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cls(x) < cls(y); });
+    for (int oi = 0; oi < n_inst; ++oi) {
+        const int i = order[(size_t)oi];
         const mc_instance_desc &d = desc[i];
+        if (b->classes.empty() || b->classes.back().mode * 2 + (b->classes.back().fp32 ? 1 : 0) != cls(i))
+            b->classes.push_back(BatchClass{d.mode, d.weight_prec == MC_FP32, oi, 0, ntasks, 0});
         mc_expmv_opts io;
         mc_expmv_default_opts(&io);
         io.mode = d.mode;
@@ -872,8 +885,11 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
         I.se = d.stderr_;
         I.mode = d.mode;
         I.fp32 = fp32;
-        ntasks += (I.k + I.group - 1) / I.group * I.chunks;
-        b->fin_begin[i] = nfin;
+        const int64_t itasks = (I.k + I.group - 1) / I.group * I.chunks;
+        ntasks += itasks;
+        b->classes.back().ninst += 1;
+        b->classes.back().ntasks += itasks;
+        b->fin_begin[(size_t)oi] = nfin;
         if (I.chunks > 1) {
             part_doubles += I.k * I.chunks * 3;
             nfin += (I.k * (int64_t)fin_lanes(I.chunks) + 63) / 64 * 64;
@@ -885,7 +901,7 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
     B_TRY(dalloc(&b->d_inst, n_inst));
     B_TRY(dalloc(&b->d_fin, n_inst + 1));
     B_TRY(dalloc(&b->part, part_doubles));
-    B_TRY(dalloc(&b->counters, 2 * (int64_t)b->ncu * 64));
+    B_TRY(dalloc(&b->counters, 2 * (int64_t)b->ncu * 64 * (int64_t)b->classes.size()));
     B_TRY(dalloc(&b->queue, 1));
     B_TRY(dalloc(&b->flags, 1));
     B_TRY(hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BatchInst) * (size_t)n_inst,
@@ -974,13 +990,17 @@ mc_status mc_expmv_batch_stats(mc_batch_t b, mc_expmv_run_stats *out, mc_batch_s
     HIP_TRY(hipEventSynchronize(b->ev1));
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
-    std::vector<unsigned long long> pc((size_t)b->grid * 2);
+    // one counter block per class launch (classes without tasks leave theirs unused)
+    std::vector<unsigned long long> pc((size_t)b->grid * 2 * b->classes.size());
     HIP_TRY(hipMemcpy(pc.data(), b->counters, sizeof(unsigned long long) * pc.size(),
                       hipMemcpyDeviceToHost));
     unsigned long long ev = 0, ju = 0;
-    for (int i = 0; i < b->grid; ++i) {
-        ev += pc[2 * (size_t)i];
-        ju += pc[2 * (size_t)i + 1];
+    for (size_t c = 0; c < b->classes.size(); ++c) {
+        if (b->classes[c].ntasks == 0) continue;
+        for (int i = 0; i < b->grid; ++i) {
+            ev += pc[2 * ((size_t)b->grid * c + (size_t)i)];
+            ju += pc[2 * ((size_t)b->grid * c + (size_t)i) + 1];
+        }
     }
     out->walkers = b->walkers;
     out->events = ev;

@@ -13,11 +13,9 @@
 namespace mc {
 namespace {
 
-constexpr size_t kBatchLdsPerWave = sizeof(GroupLds<float>) > sizeof(GroupLds<double>)
-                                        ? sizeof(GroupLds<float>)
-                                        : sizeof(GroupLds<double>);
 
-// One task of the global index space: instance, then (entry group, chunk).
+// One task of a class's index space: instance, then (entry group, chunk).
+template <int MODE, bool FP32>
 __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, int64_t task,
                                         unsigned char *lds, unsigned long long &my_events,
                                         unsigned long long &my_jumps, uint32_t &err) {
@@ -38,37 +36,29 @@ __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, i
     const int64_t e_first = grp * (int64_t)I.group;
     const int64_t left = I.k - e_first;
     const uint32_t G = (uint32_t)(left < (int64_t)I.group ? left : (int64_t)I.group);
-    const int64_t chunk = chunk_walkers(I.fp32);
+    const int64_t chunk = chunk_walkers(FP32);
     const int64_t wbase = c * chunk;
     const int64_t rem = I.nwalk - wbase;
     const uint32_t cnt = (uint32_t)(rem < chunk ? rem : chunk);
     const GroupOut out{I.est, I.se, a.part + I.part_off, e_first, I.chunks, c};
     TraceOut none;
-#define MC_GROUP(MODE, FP32)                                                                     \
-    run_group<MODE, FP32, false, false, false, false>(I.P, I.idx, I.n, G, (uint32_t)wbase, cnt, none, out,     \
-                                        *reinterpret_cast<GroupLds<WeightT<FP32>::T> *>(lds),     \
-                                        my_events, my_jumps, err)
-    switch (I.mode * 2 + (I.fp32 ? 1 : 0)) {
-        case MC_EXACT * 2: MC_GROUP(MC_EXACT, false); break;
-        case MC_EXACT * 2 + 1: MC_GROUP(MC_EXACT, true); break;
-        case MC_STRANG * 2: MC_GROUP(MC_STRANG, false); break;
-        case MC_STRANG * 2 + 1: MC_GROUP(MC_STRANG, true); break;
-        case MC_LIE * 2: MC_GROUP(MC_LIE, false); break;
-        default: MC_GROUP(MC_LIE, true); break;
-    }
-#undef MC_GROUP
+    run_group<MODE, FP32, false, false, false, false>(
+        I.P, I.idx, I.n, G, (uint32_t)wbase, cnt, none, out,
+        *reinterpret_cast<GroupLds<typename WeightT<FP32>::T> *>(lds), my_events, my_jumps, err);
 }
 
-// Dynamic LDS: one task scratch per wave, the larger of the two layouts.
+// Persistent kernel over the tasks of one class.  Dynamic LDS: one task
+// scratch per wave.
+template <int MODE, bool FP32>
 __global__ __launch_bounds__(256) void k_walk_batched(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     __shared__ int64_t sh_tb[kMaxBatch];
     __shared__ unsigned long long sh_count[256 / WAVE][2];
-    for (int i = threadIdx.x; i < a.ninst; i += blockDim.x) sh_tb[i] = a.inst[i].task_begin;
+    for (int i = threadIdx.x; i < a.ninst; i += blockDim.x) sh_tb[i] = a.inst[i].task_begin - a.task0;
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x / WAVE;
-    unsigned char *lds = dyn_lds + (size_t)wave * kBatchLdsPerWave;
+    unsigned char *lds = dyn_lds + (size_t)wave * sizeof(GroupLds<typename WeightT<FP32>::T>);
     unsigned long long my_events = 0, my_jumps = 0;
     uint32_t err = 0;
     // one call site of do_task for both schedules (two inlined copies cost
@@ -87,7 +77,7 @@ __global__ __launch_bounds__(256) void k_walk_batched(BatchArgs a) {
             end = task + a.group < a.ntasks ? task + a.group : a.ntasks;
         }
         if (task >= a.ntasks) break;
-        do_task(a, sh_tb, task, lds, my_events, my_jumps, err);
+        do_task<MODE, FP32>(a, sh_tb, task, lds, my_events, my_jumps, err);
         task += dynamic ? 1 : nwaves;
     }
     for (int off = 1; off < WAVE; off <<= 1) err |= __shfl_xor(err, off, WAVE);
@@ -142,22 +132,42 @@ __global__ __launch_bounds__(256) void k_finalize_batched(BatchArgs a) {
 
 }  // namespace
 
-hipError_t launch_batch(const BatchArgs &a, int block, int grid, hipStream_t s) {
-    if (a.group != 0) {
-        hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, a.queue);
+hipError_t launch_batch(const BatchArgs &base, const BatchClass *classes, int nclass, int block,
+                        int grid, hipStream_t s) {
+    for (int c = 0; c < nclass; ++c) {
+        const BatchClass &C = classes[c];
+        if (C.ntasks == 0) continue;
+        BatchArgs a = base;
+        a.inst = base.inst + C.inst0;
+        a.ninst = C.ninst;
+        a.ntasks = C.ntasks;
+        a.task0 = C.task0;
+        a.counters = base.counters + 2 * (size_t)grid * (size_t)c;
+        if (a.group != 0) {
+            hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, a.queue);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        const size_t lds =
+            (size_t)(block / WAVE) * (C.fp32 ? sizeof(GroupLds<float>) : sizeof(GroupLds<double>));
+#define MC_BATCH(M, F) hipLaunchKernelGGL((k_walk_batched<M, F>), dim3((unsigned)grid), dim3(block), lds, s, a)
+        switch (C.mode * 2 + (C.fp32 ? 1 : 0)) {
+            case MC_EXACT * 2: MC_BATCH(MC_EXACT, false); break;
+            case MC_EXACT * 2 + 1: MC_BATCH(MC_EXACT, true); break;
+            case MC_STRANG * 2: MC_BATCH(MC_STRANG, false); break;
+            case MC_STRANG * 2 + 1: MC_BATCH(MC_STRANG, true); break;
+            case MC_LIE * 2: MC_BATCH(MC_LIE, false); break;
+            case MC_LIE * 2 + 1: MC_BATCH(MC_LIE, true); break;
+            default: return hipErrorInvalidValue;
+        }
+#undef MC_BATCH
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (a.ntasks > 0) {
-        const size_t lds = (size_t)(block / WAVE) * kBatchLdsPerWave;
-        hipLaunchKernelGGL(k_walk_batched, dim3((unsigned)grid), dim3(block), lds, s, a);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (a.nfin > 0) {
+    if (base.nfin > 0) {
         const int fb = 256;
-        hipLaunchKernelGGL(k_finalize_batched, dim3((unsigned)((a.nfin + fb - 1) / fb)), dim3(fb), 0,
-                           s, a);
+        hipLaunchKernelGGL(k_finalize_batched, dim3((unsigned)((base.nfin + fb - 1) / fb)), dim3(fb),
+                           0, s, base);
         return hipGetLastError();
     }
     return hipSuccess;

@@ -156,9 +156,10 @@ struct BatchInst {
 constexpr int kMaxBatch = 1024;
 
 struct BatchArgs {
-    const BatchInst *inst;
+    const BatchInst *inst;     // the instances of one class (weight mode, precision)
     int32_t ninst;
-    int64_t ntasks;
+    int64_t ntasks;            // tasks of those instances
+    int64_t task0;             // their first task in the batch's task numbering
     double *part;
     unsigned long long *counters;  // [2 * grid]
     uint32_t *flags;
@@ -214,7 +215,17 @@ hipError_t launch_walk(const WalkArgs &a, int mode, bool fp32, bool prop, bool t
 hipError_t launch_finalize(const WalkArgs &a, hipStream_t s);
 
 // batched launch (batch.hip): queue reset, persistent walk, finalize
-hipError_t launch_batch(const BatchArgs &a, int block, int grid, hipStream_t s);
+// Instances of one weight mode and precision, contiguous in the batch.
+struct BatchClass {
+    int32_t mode;
+    bool fp32;
+    int32_t inst0, ninst;      // instances inst0 .. inst0+ninst-1
+    int64_t task0, ntasks;     // their tasks task0 .. task0+ntasks-1
+};
+// One persistent walk launch per class (counters for class c at counters +
+// 2 * grid * c), then one finalize launch for every instance.
+hipError_t launch_batch(const BatchArgs &a, const BatchClass *classes, int nclass, int block,
+                        int grid, hipStream_t s);
 
 // learned proposal network (mlp.hip); parameter vector of kMlpParams floats:
 // W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3
