@@ -58,20 +58,28 @@ def measured_traffic(profile=PROFILE, sources=KERNEL_SOURCES):
         return None
 
 
-def cpu_baseline(w, seed, nthreads):
-    """The oracle on the host: the same workload (every node, 1e3 walkers each)."""
+def cpu_baseline(w, seed, nthreads, min_seconds=10.0):
+    """The oracle on the host over the same workload (every node, 1e3 walkers each),
+    repeated until at least min_seconds of wall time so the rate is not dominated by
+    thread start-up; walker-steps per second over all passes."""
     import oracle
     from oracle import Oracle
     oracle.build()
     o = Oracle(w.a.rowptr, w.a.col, w.a.val, w.t, seed)
     v = np.asarray(w.v, np.float32).astype(np.float64)
+    events = 0
+    passes = 0
     t0 = time.perf_counter()
-    _, _, ev, _ = o.estimate(v, None, w.nwalk, threads=nthreads, counts=True)
-    dt = time.perf_counter() - t0
-    return dict(value=float(ev.sum()) / dt, unit="walker-steps/s", cores=nthreads,
-                kind="oracle",
-                sample=f"whole workload: {w.a.n} nodes x {w.nwalk} walkers, {dt:.2f} s, "
-                       f"{nthreads} threads")
+    while True:
+        _, _, ev, _ = o.estimate(v, None, w.nwalk, threads=nthreads, counts=True)
+        events += int(ev.sum())
+        passes += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
+    return dict(value=events / dt, unit="walker-steps/s", cores=nthreads, kind="oracle",
+                sample=f"whole workload ({w.a.n} nodes x {w.nwalk} walkers) {passes} times, "
+                       f"{dt:.1f} s, {nthreads} threads")
 
 
 def entries_at_1e3(mc, h, v, idx, pilot: int, target: float = 1e-3, cap: int = 1 << 31,
