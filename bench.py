@@ -83,21 +83,23 @@ def cpu_baseline(w, seed, nthreads, min_seconds=10.0):
 
 
 def entries_at_1e3(mc, h, v, idx, pilot: int, target: float = 1e-3, cap: int = 1 << 31,
-                   max_passes: int = 4):
+                   max_passes: int = 4, margin: float = 1.2):
     """Entries/s at a relative standard error target.  A pilot of `pilot` walkers per
     entry estimates sigma_i / x_i; every entry is then run with
-    N_i = ceil((sigma_i / (target x_i))^2) walkers (grouped by N_i rounded up to a power
-    of two, one asynchronous call per group, one synchronisation).  Entries whose
-    measured relative error still exceeds the target (a pilot underestimates heavy
-    tails) are re-run with N scaled by (error / target)^2 * 1.25, up to max_passes.
-    The time covers every production pass; the pilot is not counted."""
+    N_i = ceil(margin (sigma_i / (target x_i))^2) walkers (the margin covers the pilot's
+    own error on sigma_i, so that one pass usually suffices), all entries in one launch
+    (mc_expmv_entries_multi).  Entries whose measured relative error still exceeds the
+    target (a pilot underestimates heavy tails) are re-run with N scaled by
+    (error / target)^2 * 1.25, up to max_passes.  The time covers every production
+    pass; the pilot is not counted."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
     idx = np.asarray(idx, np.int64)
+    v = h._v(v)                      # device copy once, outside the timed passes
     est, se = h.entries(v, idx, pilot)
     x = est.cpu().numpy()
     sig = se.cpu().numpy() * np.sqrt(pilot)
-    need = np.clip(np.ceil((sig / (target * np.abs(x))) ** 2), 2, cap)
+    need = np.clip(np.ceil(margin * (sig / (target * np.abs(x))) ** 2), 2, cap)
     todo = np.arange(len(idx))
     final_rel = np.zeros(len(idx))
     final_n = np.zeros(len(idx))
@@ -106,29 +108,22 @@ def entries_at_1e3(mc, h, v, idx, pilot: int, target: float = 1e-3, cap: int = 1
     passes = 0
     while len(todo) and passes < max_passes:
         passes += 1
-        grp = np.minimum(np.exp2(np.ceil(np.log2(need[todo]))), cap).astype(np.int64)
-        groups = {int(g): todo[grp == g] for g in np.unique(grp)}
-        outs = {}
+        counts = np.minimum(need[todo], cap).astype(np.int64)
+        ti = torch.as_tensor(idx[todo], device=dev)
+        e = torch.empty(len(todo), dtype=torch.float64, device=dev)
+        s_ = torch.empty(len(todo), dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for g, sel in groups.items():
-            ti = torch.as_tensor(idx[sel], device=dev)
-            e = torch.empty(len(sel), dtype=torch.float64, device=dev)
-            s_ = torch.empty(len(sel), dtype=torch.float64, device=dev)
-            h.entries(v, ti, g, est=e, stderr=s_, sync=False)
-            outs[g] = (sel, e, s_)
+        h.entries_multi(v, ti, counts, est=e, stderr=s_, sync=False)
         h.sync()
         seconds += time.perf_counter() - t0
-        nxt = []
-        for g, (sel, e, s_) in outs.items():
-            rel = (s_ / e.abs()).cpu().numpy()
-            final_rel[sel] = rel
-            final_n[sel] = g
-            walkers += g * len(sel)
-            bad = rel > target
-            need[sel[bad]] = np.minimum(np.ceil(g * (rel[bad] / target) ** 2 * 1.25), cap)
-            nxt.append(sel[bad])
-        todo = np.concatenate(nxt) if nxt else np.zeros(0, np.int64)
+        rel = (s_ / e.abs()).cpu().numpy()
+        final_rel[todo] = rel
+        final_n[todo] = counts
+        walkers += int(counts.sum())
+        bad = rel > target
+        need[todo[bad]] = np.minimum(np.ceil(counts[bad] * (rel[bad] / target) ** 2 * 1.25), cap)
+        todo = todo[bad]
     return dict(entries=len(idx), seconds=seconds, entries_per_s=len(idx) / seconds,
                 walkers=int(walkers), passes=passes, max_rel_stderr=float(final_rel.max()),
                 entries_above_target=int((final_rel > target).sum()),

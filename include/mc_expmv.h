@@ -144,6 +144,16 @@ mc_status mc_expmv_entries(mc_expmv_t h, const void *v, const int64_t *idx, int6
                            int64_t n_walkers, double *est, double *stderr_);
 
 /*
+ * As mc_expmv_entries, with its own walker count for every entry (e.g. the
+ * production pass of a two-pass run to a target error, Sec. 5): n_walkers is a
+ * HOST int64_t[k] (each in 1 .. 2^32-1); all entries go into one launch.  Entry
+ * e's estimate and standard error are bitwise those mc_expmv_entries returns
+ * for that entry with n_walkers[e] walkers.
+ */
+mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
+                                 const int64_t *n_walkers, double *est, double *stderr_);
+
+/*
  * Every entry of exp(tA) v with n_per_node walkers started at each node
  * (Algorithm 1 applied at every node; equal to mc_expmv_entries with
  * idx = 0..n-1).  est, stderr_: device double[n] (stderr_ may be NULL).

@@ -123,6 +123,9 @@ _SIGS = {
                                         ctypes.c_void_p]),
     "mc_expmv_full": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_expmv_entries_multi": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
     "mc_expmv_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_forward_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -297,6 +300,28 @@ class MCExpmv:
         _require_cuda(v, idx, est, stderr)
         _check(load().mc_expmv_entries(self._h, _ptr(v), _ptr(idx), k, int(n_walkers),
                                        _ptr(est), _ptr(stderr)), "mc_expmv_entries")
+        if sync:
+            self.sync()
+        return est, stderr
+
+    def entries_multi(self, v, idx, n_walkers, est=None, stderr=None, sync: bool = True):
+        """Entries idx with their own walker counts n_walkers (one launch)."""
+        import numpy as np
+        import torch
+        v = self._v(v)
+        idx = torch.as_tensor(idx).to(device=self.device, dtype=torch.int64).contiguous()
+        k = idx.numel()
+        counts = np.ascontiguousarray(n_walkers, dtype=np.int64)
+        if counts.shape != (k,):
+            raise ValueError("n_walkers must have one count per entry")
+        if est is None:
+            est = torch.empty(k, dtype=torch.float64, device=self.device)
+        if stderr is None:
+            stderr = torch.empty(k, dtype=torch.float64, device=self.device)
+        _require_cuda(v, idx, est, stderr)
+        _check(load().mc_expmv_entries_multi(self._h, _ptr(v), _ptr(idx), k,
+                                             counts.ctypes.data_as(ctypes.c_void_p), _ptr(est),
+                                             _ptr(stderr)), "mc_expmv_entries_multi")
         if sync:
             self.sync()
         return est, stderr

@@ -53,6 +53,11 @@ struct mc_expmv_s {
     int64_t fwd_part_cap = 0;
     double *fwd_acc = nullptr;           // [n] sums for trace runs
     bool last_fwd = false;
+    // entries with their own walker counts
+    int64_t *var_dev = nullptr;          // [2k + 1]: task offsets (k + 1), then counts (k)
+    int64_t *var_host = nullptr;         // pinned staging of the same
+    int64_t var_cap = 0;                 // int64 slots in both
+    hipEvent_t var_ev = nullptr;         // staging copy done
 };
 
 namespace {
@@ -326,6 +331,9 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->fwd_temp);
     (void)hipFree(h->fwd_part);
     (void)hipFree(h->fwd_acc);
+    (void)hipFree(h->var_dev);
+    if (h->var_host) (void)hipHostFree(h->var_host);
+    if (h->var_ev) (void)hipEventDestroy(h->var_ev);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
@@ -436,6 +444,84 @@ mc_status mc_expmv_entries(mc_expmv_t h, const void *v, const int64_t *idx, int6
     HIP_TRY(hipSetDevice(h->dev));
     return run_walk(h, v, idx, k, n_walkers, est, stderr_, false, 0, h->has_prop ? 1 : 0,
                     nullptr, nullptr, nullptr, nullptr);
+}
+
+mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
+                                 const int64_t *n_walkers, double *est, double *stderr_) {
+    if (!h || !v || k < 0) return MC_ERR_INVALID_ARG;
+    if (k > 0 && (!idx || !est || !n_walkers)) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    if (k == 0) return MC_OK;
+    const bool fp32 = h->opts.weight_prec == MC_FP32;
+    const int64_t chunk = chunk_walkers(fp32);
+    const int64_t need = 2 * k + 1;
+    if (need > h->var_cap) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        (void)hipFree(h->var_dev);
+        if (h->var_host) (void)hipHostFree(h->var_host);
+        h->var_dev = nullptr;
+        h->var_host = nullptr;
+        h->var_cap = 0;
+        HIP_TRY(dalloc(&h->var_dev, need));
+        HIP_TRY(hipHostMalloc((void **)&h->var_host, sizeof(int64_t) * (size_t)need, 0));
+        h->var_cap = need;
+    }
+    if (!h->var_ev) HIP_TRY(hipEventCreateWithFlags(&h->var_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventSynchronize(h->var_ev));   // the previous call's copy has left the staging
+    int64_t *offs = h->var_host, *cnts = h->var_host + k + 1;
+    uint64_t walkers = 0;
+    offs[0] = 0;
+    for (int64_t e = 0; e < k; ++e) {
+        const int64_t m = n_walkers[e];
+        if (m < 1 || m > 0xFFFFFFFFll) return MC_ERR_INVALID_ARG;
+        cnts[e] = m;
+        offs[e + 1] = offs[e] + (m + chunk - 1) / chunk;
+        walkers += (uint64_t)m;
+    }
+    const int64_t ntasks = offs[k];
+    if (ntasks * 3 > h->part_cap) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        (void)hipFree(h->part);
+        h->part = nullptr;
+        h->part_cap = 0;
+        HIP_TRY(dalloc(&h->part, ntasks * 3));
+        h->part_cap = ntasks * 3;
+    }
+    HIP_TRY(hipMemcpyAsync(h->var_dev, h->var_host, sizeof(int64_t) * (size_t)need,
+                           hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipEventRecord(h->var_ev, h->stream));
+    const bool prop = h->has_prop;
+    WalkArgs a{};
+    fill_inst(h, v, prop, a.P);
+    a.idx = idx;
+    a.k = k;
+    a.n = h->n;
+    a.nwalk = 0;
+    a.w0 = 0;
+    a.chunk = (uint32_t)chunk;
+    a.chunks = 1;
+    a.group = 1;
+    a.ntasks = ntasks;
+    a.est = est;
+    a.se = stderr_;
+    a.part = h->part;
+    a.counters = h->counters;
+    a.flags = h->flags;
+    a.cond = h->opts.cond_first_jump != 0;
+    a.var_task = h->var_dev;
+    a.var_nwalk = h->var_dev + k + 1;
+    HIP_TRY(hipEventRecord(h->ev0, h->stream));
+    HIP_TRY(launch_walk(a, h->opts.mode, fp32, prop, false, (int)h->opts.walkers_per_block,
+                        h->stream));
+    HIP_TRY(launch_finalize(a, h->stream));
+    HIP_TRY(hipEventRecord(h->ev1, h->stream));
+    h->ran = true;
+    h->last_walkers = walkers;
+    h->last_grid = launch_walk_grid(ntasks, (int)h->opts.walkers_per_block);
+    h->last_fp32 = fp32;
+    h->last_prop = prop;
+    h->last_fwd = false;
+    return MC_OK;
 }
 
 mc_status mc_expmv_full(mc_expmv_t h, const void *v, int64_t n_per_node, double *est,

@@ -115,6 +115,10 @@ struct WalkArgs {
     uint32_t *flags;
     TraceOut trace;
     bool cond;                 // first-jump conditioning
+    // entries with their own walker counts (null otherwise): entry e owns tasks
+    // var_task[e] .. var_task[e+1]-1 (one entry per task) and var_nwalk[e] walkers
+    const int64_t *var_task;
+    const int64_t *var_nwalk;
 };
 
 // Forward (Algorithm 2) walks: one wave per chunk of kFwdChunk walker ordinals.

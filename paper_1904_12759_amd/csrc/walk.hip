@@ -55,17 +55,39 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     unsigned long long my_events = 0, my_jumps = 0;
     uint32_t err = 0;
     for (int64_t task = wave_id; task < a.ntasks; task += nwaves) {
-        const int64_t grp = task / a.chunks;
-        const int64_t c = task - grp * a.chunks;
-        const int64_t e_first = grp * (int64_t)a.group;
-        const int64_t left = a.k - e_first;
-        const uint32_t G = (uint32_t)(left < (int64_t)a.group ? left : (int64_t)a.group);
+        int64_t e_first, c, chunks, nwalk, pbase;
+        uint32_t G;
+        if (a.var_task) {
+            // entries with their own walker counts: one entry per task, entry e owns
+            // tasks var_task[e] .. var_task[e+1]-1 (the last e with var_task[e] <= task)
+            int64_t lo = 0, hi = a.k - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (a.var_task[mid] <= task) lo = mid;
+                else hi = mid - 1;
+            }
+            e_first = lo;
+            c = task - a.var_task[lo];
+            chunks = a.var_task[lo + 1] - a.var_task[lo];
+            nwalk = a.var_nwalk[lo];
+            pbase = task;
+            G = 1;
+        } else {
+            const int64_t grp = task / a.chunks;
+            c = task - grp * a.chunks;
+            e_first = grp * (int64_t)a.group;
+            const int64_t left = a.k - e_first;
+            G = (uint32_t)(left < (int64_t)a.group ? left : (int64_t)a.group);
+            chunks = a.chunks;
+            nwalk = a.nwalk;
+            pbase = e_first * chunks + c;
+        }
         const int64_t wbase = c * (int64_t)a.chunk;
-        const int64_t rem = a.nwalk - wbase;
+        const int64_t rem = nwalk - wbase;
         const uint32_t cnt = (uint32_t)(rem < (int64_t)a.chunk ? rem : (int64_t)a.chunk);
         TraceOut tr = a.trace;
         tr.base = wbase;
-        const GroupOut out{a.est, a.se, a.part, e_first, a.chunks, c};
+        const GroupOut out{a.est, a.se, a.part, e_first, chunks, c, pbase};
         run_group<MODE, FP32, PROP, TRACE, LOC, COND>(P, a.idx, a.n, G, (uint32_t)(a.w0 + wbase), cnt, tr,
                                            out, L, my_events, my_jumps, err);
     }
@@ -103,6 +125,27 @@ __global__ __launch_bounds__(256) void k_finalize(int64_t k, int64_t chunks,
     double n, mean, m2;
     fin_merge(valid ? part + e * chunks * 3 : nullptr, valid ? chunks : 0, L, sub, n, mean, m2);
     if (valid && sub == 0) {
+        est[e] = mean;
+        if (se) se[e] = n > 1.0 ? sqrt(m2 / (n - 1.0) / n) : 0.0;
+    }
+}
+
+// Chunk partials of entries with their own walker counts: one wave per entry,
+// fin_lanes(chunks of the entry) of its lanes merging exactly as k_finalize does
+// (so results equal those of a run with that walker count for every entry).
+__global__ __launch_bounds__(256) void k_finalize_var(int64_t k, const int64_t *__restrict__ var_task,
+                                                      const double *__restrict__ part,
+                                                      double *__restrict__ est, double *__restrict__ se) {
+    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const uint32_t lane = threadIdx.x & (WAVE - 1);
+    if (e >= k) return;                      // whole waves
+    const int64_t chunks = var_task[e + 1] - var_task[e];
+    if (chunks <= 1) return;                 // written by the walk itself
+    const uint32_t L = fin_lanes(chunks);
+    double n, mean, m2;
+    fin_merge(lane < L ? part + 3 * var_task[e] : nullptr, lane < L ? chunks : 0, L, lane % L, n,
+              mean, m2);
+    if (lane == 0) {
         est[e] = mean;
         if (se) se[e] = n > 1.0 ? sqrt(m2 / (n - 1.0) / n) : 0.0;
     }
@@ -173,6 +216,12 @@ hipError_t launch_walk(const WalkArgs &a, int mode, bool fp32, bool prop, bool t
 }
 
 hipError_t launch_finalize(const WalkArgs &a, hipStream_t s) {
+    if (a.var_task) {
+        if (a.k == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_finalize_var, dim3((unsigned)((a.k * WAVE + 255) / 256)), dim3(256), 0, s,
+                           a.k, a.var_task, a.part, a.est, a.se);
+        return hipGetLastError();
+    }
     if (a.chunks <= 1 || a.k == 0) return hipSuccess;
     const int block = 256;
     const int64_t threads = a.k * (int64_t)fin_lanes(a.chunks);

@@ -337,6 +337,7 @@ static_assert(kGroupMax <= 64 && kChunkMax <= 1024, "list codes are 6 + 10 bits"
 struct GroupOut {
     double *est, *se, *part;
     int64_t e_first, chunks, c;
+    int64_t pbase;             // partial of entry e_first + g at this chunk: pbase + g * chunks
 };
 
 // Runs walkers ord0 .. ord0+cnt-1 of G entries on the calling wavefront and
@@ -644,7 +645,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 out.est[e] = mean;
                 if (out.se) out.se[e] = count > 1.0 ? sqrt(m2 / (count - 1.0) / count) : 0.0;
             } else {
-                double *pp = out.part + (e * out.chunks + out.c) * 3;
+                double *pp = out.part + (out.pbase + (int64_t)g * out.chunks) * 3;
                 pp[0] = count;
                 pp[1] = mean;
                 pp[2] = m2;

@@ -406,3 +406,22 @@ def test_lds_budget_requires_relabel():
     a = MATS["sym48"]
     with pytest.raises(mc.MCError):
         mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 1, lds_budget=1024)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_entries_multi_equals_per_count_runs(fp32):
+    """One launch with a walker count per entry gives, entry by entry, bitwise what a
+    run with that count gives (single chunk, several chunks, ragged tails)."""
+    a = MATS["special40"]
+    g = mc.MCExpmv(a.rowptr, a.col, a.val, 0.9, 77, fp32=fp32)
+    v = np.random.default_rng(3).uniform(-1.0, 2.0, a.n)
+    idx = np.array([0, 5, 7, 11, 39, 3, 5], np.int64)
+    counts = np.array([1, 37, 512, 1025, 5000, 70_000, 2], np.int64)
+    est, se = g.entries_multi(v, idx, counts)
+    for j, (i, m) in enumerate(zip(idx, counts)):
+        e1, s1 = g.entries(v, [int(i)], int(m))
+        assert est[j].item() == e1.item() and se[j].item() == s1.item(), (j, int(m))
+    o = Oracle(a.rowptr, a.col, a.val, 0.9, 77)
+    eo, so = o.estimate(_v_for(v, fp32), idx[:4], 1025)
+    e4, _ = g.entries_multi(v, idx[:4], np.full(4, 1025))
+    assert _close(e4.cpu().numpy(), eo, RTOL32 if fp32 else RTOL64)
