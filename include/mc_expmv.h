@@ -94,6 +94,14 @@ typedef struct {
                                    r t <= cond_max_rt, decided in FP64 as
                                    t <= cond_max_rt * (1/r); others walk plainly.
                                    Default +inf (every node with exits). */
+    uint32_t task_walkers;      /* walkers of consecutive entries packed into one task of
+                                   the backward walk kernel, which runs them through its
+                                   LDS list in as many passes as their jumping walkers
+                                   need; entries with fewer walkers share a task up to
+                                   this many (at most 64 entries).  0 (default):
+                                   automatic, from 1024 to 8192 walkers aiming at
+                                   20480 tasks per run.  A tuning knob only: estimates
+                                   do not depend on it, bit for bit. */
 } mc_expmv_opts;
 
 typedef struct {

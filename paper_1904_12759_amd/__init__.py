@@ -52,6 +52,7 @@ class mc_expmv_opts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("cond_first_jump", ctypes.c_int32),
         ("cond_max_rt", ctypes.c_double),
+        ("task_walkers", ctypes.c_uint32),
     ]
 
 
@@ -229,7 +230,7 @@ class MCExpmv:
                  dt: float = 0.03125, fp32: bool = False, instance: int = 0,
                  max_events: int = 0, walkers_per_block: int = 64, relabel: int = 0,
                  lds_budget: int = 0, stream=None, cond: bool = False,
-                 cond_max_rt: float = float("inf")):
+                 cond_max_rt: float = float("inf"), task_walkers: int = 0):
         import torch
         lib_ = load()
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -244,7 +245,7 @@ class MCExpmv:
                             instance_id=instance, max_events=max_events,
                             walkers_per_block=walkers_per_block, relabel=relabel,
                             lds_budget=lds_budget, stream=stream, cond_first_jump=int(cond),
-                            cond_max_rt=float(cond_max_rt))
+                            cond_max_rt=float(cond_max_rt), task_walkers=int(task_walkers))
         h = ctypes.c_void_p()
         torch.cuda.current_stream().synchronize()
         _check(lib_.mc_expmv_create(ctypes.byref(h), rp.numel() - 1, cl.numel(), _ptr(rp),

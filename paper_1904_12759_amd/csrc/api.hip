@@ -232,7 +232,7 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
     a.w0 = w0;
     a.chunk = (uint32_t)chunk;
     a.chunks = chunks;
-    a.group = trace ? 1u : group_size(nwalk, fp32);
+    a.group = trace ? 1u : group_size(nwalk, k, h->opts.task_walkers);
     a.cond = h->opts.cond_first_jump != 0;
     a.ntasks = (k + a.group - 1) / a.group * chunks;
     a.est = est;
@@ -291,6 +291,7 @@ void mc_expmv_default_opts(mc_expmv_opts *o) {
     o->stream = nullptr;
     o->cond_first_jump = 0;
     o->cond_max_rt = INFINITY;
+    o->task_walkers = 0;
 }
 
 const char *mc_expmv_status_string(mc_status s) {
@@ -964,7 +965,7 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
         const bool fp32 = d.weight_prec == MC_FP32;
         const int64_t chunk = chunk_walkers(fp32);
         I.chunks = (d.n_walkers + chunk - 1) / chunk;
-        I.group = group_size(d.n_walkers, fp32);
+        I.group = group_size(d.n_walkers, I.k, 0);
         I.task_begin = ntasks;
         I.part_off = part_doubles;
         I.est = d.est;

@@ -191,12 +191,26 @@ __host__ __device__ constexpr uint32_t fin_lanes(int64_t chunks) {
 // Largest LDS budget for hot rows (bytes per block).
 constexpr uint32_t kMaxHotBytes = 65536;
 
-// Entries packed into one task when each has nwalk walkers.
-inline uint32_t group_size(int64_t nwalk, bool fp32) {
-    const int64_t c = (int64_t)chunk_walkers(fp32);
-    if (nwalk >= c) return 1;
-    const int64_t g = c / nwalk;
-    return (uint32_t)(g < (int64_t)kGroupMax ? g : (int64_t)kGroupMax);
+// Entries packed into one task when each of k entries has nwalk walkers.  A task
+// runs its entries in LDS sessions of up to chunk_walkers() listed walkers, so
+// packing keeps the lanes of the full-walk phase busy.  task_walkers > 0 asks
+// for about that many walkers per task.  0 aims at kMinTasks tasks (four waves
+// per SIMD slot at five waves per SIMD on 256 CUs, so that the last waves do
+// not run alone) with between kTaskWalkersMin and kTaskWalkersMax walkers each.
+constexpr int64_t kTaskWalkersMin = 1024;
+constexpr int64_t kTaskWalkersMax = 8192;
+constexpr int64_t kMinTasks = 20480;
+inline uint32_t group_size(int64_t nwalk, int64_t k, uint32_t task_walkers) {
+    int64_t g;
+    if (task_walkers) {
+        g = (int64_t)task_walkers / nwalk;
+    } else {
+        g = k / kMinTasks;
+        if (g < kTaskWalkersMin / nwalk) g = kTaskWalkersMin / nwalk;
+        if (g > kTaskWalkersMax / nwalk) g = kTaskWalkersMax / nwalk;
+    }
+    if (g > (int64_t)kGroupMax) g = kGroupMax;
+    return (uint32_t)(g < 1 ? 1 : g);
 }
 
 // Largest walk grid (blocks); the per-block counter buffer has this many pairs.

@@ -413,244 +413,276 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // ---- phase 1: first events, compaction of the walkers that may jump
-    uint32_t nlist = 0;
+    // ---- sessions: phase 1 appends the possibly-jumping walkers of consecutive
+    // entries to the LDS pool while they fit; a full pool is flushed (phase 2 and
+    // the statistics of its entries) and the entry that did not fit is redone in
+    // an empty pool, where it always fits (cnt <= C).  An entry's values and its
+    // reduction do not depend on which session it falls in.
+    constexpr uint32_t C = GroupLds<WT, COND>::C;
+    uint32_t nlist = 0, g_begin = 0;
     unsigned long long evs = 0, jus = 0;
-    for (uint32_t g = 0; g < G; ++g) {
-        const uint32_t node = L.node[g];
-        const double eg = readlane_f64(e0, (int)g);
-        if (lane == 0) L.seg[g] = nlist;
-        if (node == 0xFFFFFFFFu) continue;
-        if (eg >= 1.5) {
-            // no exit rate: every walker holds until t, one holding interval each
-            if (lane == 0) {
-                L.n0[g] = cnt;
-                evs += cnt;
+    uint32_t g = 0;
+    for (;;) {
+        for (; g < G;) {
+            const uint32_t node = L.node[g];
+            const double eg = readlane_f64(e0, (int)g);
+            const uint32_t start = nlist;
+            if (lane == 0) L.seg[g] = start;
+            if (node == 0xFFFFFFFFu) {
+                ++g;
+                continue;
             }
-            if constexpr (TRACE) {
-                for (uint32_t w = lane; w < cnt; w += WAVE) {
-                    tr.x[tr.base + w] = (int32_t)node;
-                    tr.ev[tr.base + w] = 1;
-                    tr.ju[tr.base + w] = 0;
-                    tr.f[tr.base + w] = L.K[g];
+            if (eg >= 1.5) {
+                // no exit rate: every walker holds until t, one holding interval each
+                if (lane == 0) {
+                    L.n0[g] = cnt;
+                    evs += cnt;
                 }
-            }
-            continue;
-        }
-        if (eg < 0.125) {
-            // most walkers leave: list them all
-            for (uint32_t w = lane; w < cnt; w += WAVE) L.list[nlist + w] = (uint16_t)((g << 10) | w);
-            nlist += cnt;
-            continue;
-        }
-        // U >= e0  <=>  m + 1 >= e0 2^53 (U = (m+1) 2^-53 exactly), i.e. m + 1 >= ceil(e0 2^53)
-        const uint64_t m_thr = (uint64_t)ceil(eg * 0x1p53);
-        uint32_t stay = 0;
-        for (uint32_t b = 0; b < cnt; b += WAVE) {
-            const uint32_t w = b + (uint32_t)lane;
-            const bool valid = w < cnt;
-            bool go = false;
-            if (valid) {
-                const U4 o = philox(0u, ord0 + w, node, P.inst, P.key0, P.key1);
-                const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
-                go = m + 1ull >= m_thr;
-            }
-            const unsigned long long gmask = __ballot(go);
-            if (go) L.list[nlist + (uint32_t)__popcll(gmask & lanemask_lt)] = (uint16_t)((g << 10) | w);
-            nlist += (uint32_t)__popcll(gmask);
-            stay += (uint32_t)__popcll(__ballot(valid && !go));
-            if constexpr (TRACE) {
-                if (valid && !go) {
-                    tr.x[tr.base + w] = (int32_t)node;
-                    tr.ev[tr.base + w] = 1;
-                    tr.ju[tr.base + w] = 0;
-                    tr.f[tr.base + w] = L.K[g];
-                }
-            }
-        }
-        if (lane == 0) {
-            L.n0[g] = stay;
-            evs += stay;
-        }
-    }
-    if (lane == 0) L.seg[G] = nlist;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-    // ---- phase 2: full walks with lane refill over the list
-    uint32_t wl = (uint32_t)lane;
-    bool active = wl < nlist;
-    uint32_t code = active ? L.list[wl] : 0u;
-    uint32_t node = active ? L.node[code >> 10] : 0u;     // original id: RNG counter
-    uint32_t x = walk_id<LOC>(P, node);                      // walk id
-    double s = 0.0;
-    WT logw = (WT)0;
-    uint32_t ev = 0, ju = 0;
-    int32_t ka = 0;
-    double inv_r = 0.0;
-    uint32_t deg = 0, begin = 0;
-    WT dx = (WT)0;
-    if (active) {
-        const RowRec rr = row_at<LOC>(P, x);
-        inv_r = rr.inv_r;
-        deg = rr.deg;
-        begin = rr.begin;
-        dx = d_at<FP32, LOC>(P, x);
-    }
-    uint32_t next = WAVE;
-
-    while (__ballot(active) != 0ull) {
-        bool fin = false;
-        if (active) {
-            if (deg == 0) {
-                ++ev;                    // no exit rate: holds until t
-                fin = true;
-            } else if (ev >= P.max_events) {
-                err |= F_WALK_LIMIT;
-                fin = true;
-            } else {
-                const U4 o = philox(ev, ord0 + (code & 1023u), node, P.inst, P.key0, P.key1);
-                ++ev;
-                const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
-                double S;
-                bool forced = false;
-                if constexpr (COND) {
-                    const double qe = ev == 1 ? L.q[code >> 10] : 0.0;
-                    if (qe > 0.0) {
-                        // first holding time given a jump before t: inverse of the
-                        // exponential law truncated to [0, t), U in [0, 1)
-                        const double U = (double)m * 0x1p-53;
-                        S = -log_unit(1.0 - U * qe) * inv_r;
-                        forced = true;
-                    } else {
-                        S = -log_unit((double)(m + 1ull) * 0x1p-53) * inv_r;
+                if constexpr (TRACE) {
+                    for (uint32_t w = lane; w < cnt; w += WAVE) {
+                        tr.x[tr.base + w] = (int32_t)node;
+                        tr.ev[tr.base + w] = 1;
+                        tr.ju[tr.base + w] = 0;
+                        tr.f[tr.base + w] = L.K[g];
                     }
+                }
+                ++g;
+                continue;
+            }
+            bool fits = true;
+            uint32_t stay = 0;
+            if (eg < 0.125) {
+                // most walkers leave: list them all
+                if (nlist + cnt > C) {
+                    fits = false;
                 } else {
-                    const double U = (double)(m + 1ull) * 0x1p-53;
-                    S = -log_unit(U) * inv_r;
+                    for (uint32_t w = lane; w < cnt; w += WAVE) L.list[nlist + w] = (uint16_t)((g << 10) | w);
+                    nlist += cnt;
                 }
-                const double sn = s + S;
-                if (forced || sn < t) {
-                    if constexpr (MODE == MC_EXACT) {
-                        logw = logw + dx * (WT)S;
+            } else {
+                // U >= e0  <=>  m + 1 >= e0 2^53 (U = (m+1) 2^-53 exactly), i.e. m + 1 >= ceil(e0 2^53)
+                const uint64_t m_thr = (uint64_t)ceil(eg * 0x1p53);
+                for (uint32_t b = 0; b < cnt; b += WAVE) {
+                    if (nlist + WAVE > C) {
+                        fits = false;
+                        break;
+                    }
+                    const uint32_t w = b + (uint32_t)lane;
+                    const bool valid = w < cnt;
+                    bool go = false;
+                    if (valid) {
+                        const U4 o = philox(0u, ord0 + w, node, P.inst, P.key0, P.key1);
+                        const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
+                        go = m + 1ull >= m_thr;
+                    }
+                    const unsigned long long gmask = __ballot(go);
+                    if (go) L.list[nlist + (uint32_t)__popcll(gmask & lanemask_lt)] = (uint16_t)((g << 10) | w);
+                    nlist += (uint32_t)__popcll(gmask);
+                    stay += (uint32_t)__popcll(__ballot(valid && !go));
+                    if constexpr (TRACE) {
+                        if (valid && !go) {
+                            tr.x[tr.base + w] = (int32_t)node;
+                            tr.ev[tr.base + w] = 1;
+                            tr.ju[tr.base + w] = 0;
+                            tr.f[tr.base + w] = L.K[g];
+                        }
+                    }
+                }
+            }
+            if (!fits) {
+                nlist = start;            // roll back entry g: it opens the next session
+                break;
+            }
+            if (lane == 0) {
+                L.n0[g] = stay;
+                evs += stay;
+            }
+            ++g;
+        }
+        const uint32_t g_end = g;
+        if (lane == 0) L.seg[g_end] = nlist;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // ---- phase 2: full walks with lane refill over the list
+        uint32_t wl = (uint32_t)lane;
+        bool active = wl < nlist;
+        uint32_t code = active ? L.list[wl] : 0u;
+        uint32_t node = active ? L.node[code >> 10] : 0u;     // original id: RNG counter
+        uint32_t x = walk_id<LOC>(P, node);                      // walk id
+        double s = 0.0;
+        WT logw = (WT)0;
+        uint32_t ev = 0, ju = 0;
+        int32_t ka = 0;
+        double inv_r = 0.0;
+        uint32_t deg = 0, begin = 0;
+        WT dx = (WT)0;
+        if (active) {
+            const RowRec rr = row_at<LOC>(P, x);
+            inv_r = rr.inv_r;
+            deg = rr.deg;
+            begin = rr.begin;
+            dx = d_at<FP32, LOC>(P, x);
+        }
+        uint32_t next = WAVE;
+
+        while (__ballot(active) != 0ull) {
+            bool fin = false;
+            if (active) {
+                if (deg == 0) {
+                    ++ev;                    // no exit rate: holds until t
+                    fin = true;
+                } else if (ev >= P.max_events) {
+                    err |= F_WALK_LIMIT;
+                    fin = true;
+                } else {
+                    const U4 o = philox(ev, ord0 + (code & 1023u), node, P.inst, P.key0, P.key1);
+                    ++ev;
+                    const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
+                    double S;
+                    bool forced = false;
+                    if constexpr (COND) {
+                        const double qe = ev == 1 ? L.q[code >> 10] : 0.0;
+                        if (qe > 0.0) {
+                            // first holding time given a jump before t: inverse of the
+                            // exponential law truncated to [0, t), U in [0, 1)
+                            const double U = (double)m * 0x1p-53;
+                            S = -log_unit(1.0 - U * qe) * inv_r;
+                            forced = true;
+                        } else {
+                            S = -log_unit((double)(m + 1ull) * 0x1p-53) * inv_r;
+                        }
                     } else {
-                        const int32_t kb = grid_index(sn, P.inv_dt, P.ngrid);
-                        const double cs = grid_coef_sum<MODE>(ka, kb - 1, P.ngrid);
-                        logw = logw + dx * (WT)(cs * P.dt);
-                        ka = kb;
+                        const double U = (double)(m + 1ull) * 0x1p-53;
+                        S = -log_unit(U) * inv_r;
                     }
-                    s = sn;
-                    const uint32_t sl = (uint32_t)(((uint64_t)o.z * (uint64_t)deg) >> 32);
-                    const SlotRec q = P.slots[begin + sl];
-                    const bool keep = o.w < q.thr;
-                    x = (uint32_t)(keep ? q.self : q.alias);
-                    if constexpr (PROP) {
-                        const float2 cr = P.corr[begin + sl];
-                        logw = logw + (WT)(keep ? cr.x : cr.y);
+                    const double sn = s + S;
+                    if (forced || sn < t) {
+                        if constexpr (MODE == MC_EXACT) {
+                            logw = logw + dx * (WT)S;
+                        } else {
+                            const int32_t kb = grid_index(sn, P.inv_dt, P.ngrid);
+                            const double cs = grid_coef_sum<MODE>(ka, kb - 1, P.ngrid);
+                            logw = logw + dx * (WT)(cs * P.dt);
+                            ka = kb;
+                        }
+                        s = sn;
+                        const uint32_t sl = (uint32_t)(((uint64_t)o.z * (uint64_t)deg) >> 32);
+                        const SlotRec q = P.slots[begin + sl];
+                        const bool keep = o.w < q.thr;
+                        x = (uint32_t)(keep ? q.self : q.alias);
+                        if constexpr (PROP) {
+                            const float2 cr = P.corr[begin + sl];
+                            logw = logw + (WT)(keep ? cr.x : cr.y);
+                        }
+                        ++ju;
+                        const RowRec rr = row_at<LOC>(P, x);
+                        inv_r = rr.inv_r;
+                        deg = rr.deg;
+                        begin = rr.begin;
+                        dx = d_at<FP32, LOC>(P, x);
+                    } else {
+                        fin = true;
                     }
-                    ++ju;
+                }
+                if (fin) {
+                    WT f;
+                    if (ju == 0) {
+                        f = (WT)L.K[code >> 10];         // never left the start node
+                    } else {
+                        logw = logw + final_term<MODE, FP32>(dx, s, ka, P);
+                        f = wexp<FP32>(logw) * load_v<FP32>(P.v, orig_id<LOC>(P, x));
+                        if constexpr (COND) {
+                            const uint32_t e = code >> 10;
+                            if (L.q[e] > 0.0) f = (WT)(L.K[e] + L.q[e] * (double)f);
+                        }
+                        if (!isfinite((double)f)) err |= F_OVERFLOW;
+                    }
+                    L.fval[wl] = f;
+                    evs += ev;
+                    jus += ju;
+                    if constexpr (TRACE) {
+                        const int64_t ti = tr.base + (code & 1023u);
+                        tr.x[ti] = (int32_t)orig_id<LOC>(P, x);
+                        tr.ev[ti] = ev;
+                        tr.ju[ti] = ju;
+                        tr.f[ti] = (double)f;
+                    }
+                }
+            }
+            const unsigned long long fmask = __ballot(fin);
+            if (fin) {
+                wl = next + (uint32_t)__popcll(fmask & lanemask_lt);
+                if (wl < nlist) {
+                    code = L.list[wl];
+                    node = L.node[code >> 10];
+                    x = walk_id<LOC>(P, node);
+                    s = 0.0;
+                    logw = (WT)0;
+                    ev = 0;
+                    ju = 0;
+                    ka = 0;
                     const RowRec rr = row_at<LOC>(P, x);
                     inv_r = rr.inv_r;
                     deg = rr.deg;
                     begin = rr.begin;
                     dx = d_at<FP32, LOC>(P, x);
                 } else {
-                    fin = true;
+                    active = false;
                 }
             }
-            if (fin) {
-                WT f;
-                if (ju == 0) {
-                    f = (WT)L.K[code >> 10];         // never left the start node
+            next += (uint32_t)__popcll(fmask);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // ---- per-entry statistics: slots in a fixed order, plus n0 copies of K
+        for (uint32_t g = g_begin; g < g_end; ++g) {
+            const int64_t e = out.e_first + g;
+            const uint32_t b0 = L.seg[g], b1 = L.seg[g + 1];
+            double mean, m2, count;
+            if (L.node[g] == 0xFFFFFFFFu) {
+                mean = NAN;
+                m2 = NAN;
+                count = 1.0;
+            } else {
+                const double K = L.K[g];
+                const double nn0 = (double)L.n0[g];
+                count = (double)cnt;
+                // lanes stride from the segment start, so the summation tree depends only on
+                // the entry's own walkers
+                const uint32_t J = b1 - b0;
+                double s1 = 0.0;
+                for (uint32_t i = lane; i < J; i += WAVE) s1 += (double)L.fval[b0 + i];
+                s1 = wave_sum_f64(s1);
+                mean = (nn0 * K + s1) / count;
+                double s2 = 0.0;
+                for (uint32_t i = lane; i < J; i += WAVE) {
+                    const double dv = (double)L.fval[b0 + i] - mean;
+                    s2 += dv * dv;
+                }
+                s2 = wave_sum_f64(s2);
+                const double dk = K - mean;
+                m2 = s2 + nn0 * dk * dk;
+            }
+            if (lane == 0) {
+                if (out.chunks == 1) {
+                    out.est[e] = mean;
+                    if (out.se) out.se[e] = count > 1.0 ? sqrt(m2 / (count - 1.0) / count) : 0.0;
                 } else {
-                    logw = logw + final_term<MODE, FP32>(dx, s, ka, P);
-                    f = wexp<FP32>(logw) * load_v<FP32>(P.v, orig_id<LOC>(P, x));
-                    if constexpr (COND) {
-                        const uint32_t e = code >> 10;
-                        if (L.q[e] > 0.0) f = (WT)(L.K[e] + L.q[e] * (double)f);
-                    }
-                    if (!isfinite((double)f)) err |= F_OVERFLOW;
-                }
-                L.fval[wl] = f;
-                evs += ev;
-                jus += ju;
-                if constexpr (TRACE) {
-                    const int64_t ti = tr.base + (code & 1023u);
-                    tr.x[ti] = (int32_t)orig_id<LOC>(P, x);
-                    tr.ev[ti] = ev;
-                    tr.ju[ti] = ju;
-                    tr.f[ti] = (double)f;
+                    double *pp = out.part + (out.pbase + (int64_t)g * out.chunks) * 3;
+                    pp[0] = count;
+                    pp[1] = mean;
+                    pp[2] = m2;
                 }
             }
         }
-        const unsigned long long fmask = __ballot(fin);
-        if (fin) {
-            wl = next + (uint32_t)__popcll(fmask & lanemask_lt);
-            if (wl < nlist) {
-                code = L.list[wl];
-                node = L.node[code >> 10];
-                x = walk_id<LOC>(P, node);
-                s = 0.0;
-                logw = (WT)0;
-                ev = 0;
-                ju = 0;
-                ka = 0;
-                const RowRec rr = row_at<LOC>(P, x);
-                inv_r = rr.inv_r;
-                deg = rr.deg;
-                begin = rr.begin;
-                dx = d_at<FP32, LOC>(P, x);
-            } else {
-                active = false;
-            }
-        }
-        next += (uint32_t)__popcll(fmask);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-    // ---- per-entry statistics: slots in a fixed order, plus n0 copies of K
-    for (uint32_t g = 0; g < G; ++g) {
-        const int64_t e = out.e_first + g;
-        const uint32_t b0 = L.seg[g], b1 = L.seg[g + 1];
-        double mean, m2, count;
-        if (L.node[g] == 0xFFFFFFFFu) {
-            mean = NAN;
-            m2 = NAN;
-            count = 1.0;
-        } else {
-            const double K = L.K[g];
-            const double nn0 = (double)L.n0[g];
-            count = (double)cnt;
-            // lanes stride from the segment start, so the summation tree depends only on
-            // the entry's own walkers
-            const uint32_t J = b1 - b0;
-            double s1 = 0.0;
-            for (uint32_t i = lane; i < J; i += WAVE) s1 += (double)L.fval[b0 + i];
-            s1 = wave_sum_f64(s1);
-            mean = (nn0 * K + s1) / count;
-            double s2 = 0.0;
-            for (uint32_t i = lane; i < J; i += WAVE) {
-                const double dv = (double)L.fval[b0 + i] - mean;
-                s2 += dv * dv;
-            }
-            s2 = wave_sum_f64(s2);
-            const double dk = K - mean;
-            m2 = s2 + nn0 * dk * dk;
-        }
-        if (lane == 0) {
-            if (out.chunks == 1) {
-                out.est[e] = mean;
-                if (out.se) out.se[e] = count > 1.0 ? sqrt(m2 / (count - 1.0) / count) : 0.0;
-            } else {
-                double *pp = out.part + (out.pbase + (int64_t)g * out.chunks) * 3;
-                pp[0] = count;
-                pp[1] = mean;
-                pp[2] = m2;
-            }
-        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (g_end >= G) break;
+        nlist = 0;
+        g_begin = g_end;
     }
     my_events += wave_sum_u64(evs);
     my_jumps += wave_sum_u64(jus);

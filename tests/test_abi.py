@@ -46,6 +46,7 @@ def test_status_strings_and_default_opts():
     o = pkg.default_opts()
     assert o.struct_size == ctypes.sizeof(pkg.mc_expmv_opts)
     assert o.mode == pkg.EXACT and o.walkers_per_block == 64 and o.dt == 0.03125
+    assert o.task_walkers == 0
 
 
 def test_create_rejects_bad_host_arguments_without_gpu():

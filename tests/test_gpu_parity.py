@@ -425,3 +425,59 @@ def test_entries_multi_equals_per_count_runs(fp32):
     eo, so = o.estimate(_v_for(v, fp32), idx[:4], 1025)
     e4, _ = g.entries_multi(v, idx[:4], np.full(4, 1025))
     assert _close(e4.cpu().numpy(), eo, RTOL32 if fp32 else RTOL64)
+
+
+# ------------------------------------------------------------ task packing
+def _runs(g, v, idx):
+    out = [g.full(v, m) for m in (1, 37, 300, 1000, 1500)]
+    out += [g.entries(v, idx, 37), g.entries(v, idx, 700)]
+    return [(e.clone(), s.clone()) for e, s in out]
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("cond", [False, True])
+def test_task_packing_is_bitwise_invisible(fp32, cond):
+    """Entries packed into one task (run in several LDS passes when their jumping
+    walkers overflow the list) give bitwise what one entry per task gives: per entry
+    the walkers, their value slots and the summation tree are the same."""
+    for name, t in (("grid2d_16", 2.0), ("special40", 0.9), ("nonsym48", 0.3)):
+        a = MATS[name]
+        v = np.random.default_rng(6).uniform(-0.5, 2.0, a.n)
+        idx = np.concatenate([np.arange(a.n), np.arange(a.n)[::-1], [3, 3, 3]]).astype(np.int64)
+        ref = None
+        for tw in (1, 0, 2048, 65536):
+            g = mc.MCExpmv(a.rowptr, a.col, a.val, t, 8, fp32=fp32, cond=cond, task_walkers=tw)
+            res = _runs(g, v, idx)
+            if ref is None:
+                ref = res
+                continue
+            for k, ((e0, s0), (e1, s1)) in enumerate(zip(ref, res)):
+                assert torch.equal(e0, e1) and torch.equal(s0, s1), (name, tw, k)
+
+
+def test_task_packing_with_proposal_and_relabel():
+    a = MATS["nonsym48"]
+    bias = np.random.default_rng(4).normal(0, 0.6, a.nnz).astype(np.float32)
+    v = np.random.default_rng(5).uniform(0.3, 1.0, a.n)
+    outs = []
+    for tw, rl in ((1, 0), (65536, 0), (65536, 1)):
+        g = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 55, relabel=rl, lds_budget=256 * rl,
+                       task_walkers=tw)
+        g.set_proposal(bias)
+        outs.append([r for m in (50, 900) for r in g.full(v, m)])
+    for other in outs[1:]:
+        assert all(torch.equal(x, y) for x, y in zip(outs[0], other))
+
+
+@pytest.mark.parametrize("mode", [mc.EXACT, mc.LIE])
+def test_task_packing_matches_oracle(mode):
+    """64 entries per task, several passes per task: estimates against the oracle."""
+    a = MATS["grid2d_16"]
+    g = mc.MCExpmv(a.rowptr, a.col, a.val, 1.5, 4, mode=mode, dt=0.1, task_walkers=65536)
+    o = Oracle(a.rowptr, a.col, a.val, 1.5, 4, mode=mode, dt=0.1)
+    v = np.random.default_rng(9).uniform(0.1, 1.0, a.n)
+    for m in (37, 600):
+        est, se = g.full(v, m)
+        eo, so = o.estimate(v, None, m)
+        assert _close(est.cpu().numpy(), eo, RTOL64)
+        assert _close(se.cpu().numpy(), so, 1e-8)
