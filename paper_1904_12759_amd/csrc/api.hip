@@ -936,6 +936,10 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
     for (int i = 0; i < n_inst; ++i) order[(size_t)i] = i;
     auto cls = [&](int i) { return desc[i].mode * 2 + (desc[i].weight_prec == MC_FP32 ? 1 : 0); };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cls(x) < cls(y); });
+    // entries of the whole batch: the instances share one persistent grid, so task
+    // packing is sized by the batch's task count, not by each instance's
+    int64_t k_all = 0;
+    for (int i = 0; i < n_inst; ++i) k_all += desc[i].idx ? desc[i].k : desc[i].n;
     for (int oi = 0; oi < n_inst; ++oi) {
         const int i = order[(size_t)oi];
         const mc_instance_desc &d = desc[i];
@@ -965,7 +969,7 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
         const bool fp32 = d.weight_prec == MC_FP32;
         const int64_t chunk = chunk_walkers(fp32);
         I.chunks = (d.n_walkers + chunk - 1) / chunk;
-        I.group = group_size(d.n_walkers, I.k, 0);
+        I.group = group_size(d.n_walkers, k_all, 0);
         I.task_begin = ntasks;
         I.part_off = part_doubles;
         I.est = d.est;
