@@ -143,28 +143,38 @@ def bench_grid2d_entries(mc, seed):
 
 def bench_locality(mc, w, seed, steps=10):
     """Kernel time of the benchmark workload with the rows in input order, relabelled
-    hot-first (descending exit rate), and relabelled with the hottest rows staged in
-    LDS.  All variants give bitwise identical results."""
+    hot-first (descending exit rate), relabelled with the hottest rows staged in LDS,
+    and relabelled with the wave re-sort by current node; then the same variants on
+    long walks (the same graph at t = 16, 100 walkers per node).  All variants of a
+    workload give bitwise identical results."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
     v = torch.as_tensor(w.v, dtype=torch.float32, device=dev)
     est = torch.empty(w.a.n, dtype=torch.float64, device=dev)
     se = torch.empty(w.a.n, dtype=torch.float64, device=dev)
+    variants = (("input_order", 0, 0, 0), ("relabel", 1, 0, 0), ("relabel_lds16k", 1, 16384, 0),
+                ("relabel_lds64k", 1, 65536, 0), ("relabel_resort1", 1, 0, 1),
+                ("relabel_resort4", 1, 0, 4))
     out = {}
-    ref = None
-    for name, relabel, lds in (("input_order", 0, 0), ("relabel", 1, 0),
-                               ("relabel_lds16k", 1, 16384), ("relabel_lds64k", 1, 65536)):
-        h = mc.MCExpmv(w.a.rowptr, w.a.col, w.a.val, w.t, seed, fp32=True, relabel=relabel,
-                       lds_budget=lds)
-        h.full(v, w.nwalk, est=est, stderr=se)
-        ms = []
-        for _ in range(steps):
-            h.full(v, w.nwalk, est=est, stderr=se)
-            ms.append(h.stats()["ms"])
-        if ref is None:
-            ref = est.clone()
-        out[name] = dict(kernel_ms=float(np.median(ms)), identical=bool(torch.equal(est, ref)))
-        del h
+    for case, t, nwalk in (("t1", w.t, w.nwalk), ("t16_long_walks", 16.0, 100)):
+        ref = None
+        res = {}
+        for name, relabel, lds, resort in variants:
+            h = mc.MCExpmv(w.a.rowptr, w.a.col, w.a.val, t, seed, fp32=True, relabel=relabel,
+                           lds_budget=lds, resort_period=resort)
+            h.full(v, nwalk, est=est, stderr=se)
+            ms = []
+            for _ in range(steps):
+                h.full(v, nwalk, est=est, stderr=se)
+                ms.append(h.stats()["ms"])
+            if ref is None:
+                ref = est.clone()
+            res[name] = dict(kernel_ms=float(np.median(ms)), identical=bool(torch.equal(est, ref)))
+            if name == "input_order":
+                st = h.stats()
+                res["events_per_walker"] = st["events"] / st["walkers"]
+            del h
+        out[case] = res
     return out
 
 

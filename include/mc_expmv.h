@@ -76,7 +76,11 @@ typedef struct {
                                    (paths and results are unchanged). Default 0. */
     uint32_t lds_budget;        /* bytes of LDS per block for hot rows (needs relabel);
                                    0 = off (default) */
-    uint32_t resort_period;     /* reserved, must be 0 */
+    uint32_t resort_period;     /* needs relabel: every this many events a wavefront
+                                   re-sorts its walkers by current (relabelled) node,
+                                   each walker's state moving with it, so that
+                                   neighbouring lanes gather neighbouring rows; results
+                                   are bitwise unchanged.  0 = never (default). */
     uint32_t walkers_per_block; /* threads per block: 64 (default, one wave), 128 or 256 */
     uint32_t instance_id;       /* fourth Philox counter word. Default 0. */
     uint32_t max_events;        /* cap on holding intervals per walker; 0 = 2^24 */

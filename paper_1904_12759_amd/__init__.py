@@ -230,7 +230,8 @@ class MCExpmv:
                  dt: float = 0.03125, fp32: bool = False, instance: int = 0,
                  max_events: int = 0, walkers_per_block: int = 64, relabel: int = 0,
                  lds_budget: int = 0, stream=None, cond: bool = False,
-                 cond_max_rt: float = float("inf"), task_walkers: int = 0):
+                 cond_max_rt: float = float("inf"), task_walkers: int = 0,
+                 resort_period: int = 0):
         import torch
         lib_ = load()
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -245,7 +246,8 @@ class MCExpmv:
                             instance_id=instance, max_events=max_events,
                             walkers_per_block=walkers_per_block, relabel=relabel,
                             lds_budget=lds_budget, stream=stream, cond_first_jump=int(cond),
-                            cond_max_rt=float(cond_max_rt), task_walkers=int(task_walkers))
+                            cond_max_rt=float(cond_max_rt), task_walkers=int(task_walkers),
+                            resort_period=int(resort_period))
         h = ctypes.c_void_p()
         torch.cuda.current_stream().synchronize()
         _check(lib_.mc_expmv_create(ctypes.byref(h), rp.numel() - 1, cl.numel(), _ptr(rp),

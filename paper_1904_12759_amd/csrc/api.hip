@@ -179,7 +179,7 @@ mc_status check_opts(const mc_expmv_opts &o) {
     if (o.mode != MC_EXACT && (!isfinite(o.dt) || !(o.dt > 0.0))) return MC_ERR_INVALID_ARG;
     const uint32_t b = o.walkers_per_block;
     if (b != 64 && b != 128 && b != 256) return MC_ERR_INVALID_ARG;
-    if (o.resort_period != 0) return MC_ERR_INVALID_ARG;
+    if (o.resort_period != 0 && !o.relabel) return MC_ERR_INVALID_ARG;
     if (o.relabel != 0 && o.relabel != 1) return MC_ERR_INVALID_ARG;
     if (o.lds_budget != 0 && (!o.relabel || o.lds_budget > kMaxHotBytes)) return MC_ERR_INVALID_ARG;
     if (o.cond_first_jump != 0 && o.cond_first_jump != 1) return MC_ERR_INVALID_ARG;
@@ -210,6 +210,7 @@ void fill_inst(const mc_expmv_s *h, const void *v, bool prop, InstArgs &P) {
     P.inst = h->opts.instance_id;
     P.max_events = h->opts.max_events ? h->opts.max_events : (1u << 24);
     P.cond_max_rt = h->opts.cond_max_rt;
+    P.resort = rl ? h->opts.resort_period : 0u;
 }
 
 // Run the walk kernel for k entries (idx == null: every node).

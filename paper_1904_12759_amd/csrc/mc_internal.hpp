@@ -79,6 +79,7 @@ struct InstArgs {
     int32_t ngrid;             // N
     uint32_t key0, key1, inst, max_events;
     double cond_max_rt;        // first-jump conditioning for start nodes with t <= this / r
+    uint32_t resort;           // relabelled walks: re-sort a wave's walkers every this many events (0: never)
 };
 
 // Per-walker record (parity checks only).

@@ -28,7 +28,7 @@ namespace {
 // jump totals are reduced per block and written to counters[2*block] without
 // atomics (same-address atomics from every wave serialise across the chip).
 // Dynamic LDS: one GroupLds per wave.
-template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND>
+template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND, bool RESORT>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     using WT = typename WeightT<FP32>::T;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
         TraceOut tr = a.trace;
         tr.base = wbase;
         const GroupOut out{a.est, a.se, a.part, e_first, chunks, c, pbase};
-        run_group<MODE, FP32, PROP, TRACE, LOC, COND>(P, a.idx, a.n, G, (uint32_t)(a.w0 + wbase), cnt, tr,
+        run_group<MODE, FP32, PROP, TRACE, LOC, COND, RESORT>(P, a.idx, a.n, G, (uint32_t)(a.w0 + wbase), cnt, tr,
                                            out, L, my_events, my_jumps, err);
     }
     for (int off = 1; off < WAVE; off <<= 1) err |= __shfl_xor(err, off, WAVE);
@@ -171,12 +171,16 @@ hipError_t launch_t(const WalkArgs &a, int block, hipStream_t s) {
     const size_t lds = (size_t)(block / WAVE) * task_lds +
                        (size_t)a.P.hot * (sizeof(RowRec) + sizeof(WT));
     const dim3 grid((unsigned)walk_grid(a.ntasks, block));
-    if (a.P.perm) {
-        if (a.cond) hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, true>), grid, dim3(block), lds, s, a);
-        else hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, false>), grid, dim3(block), lds, s, a);
+    // the wave re-sort has kernels of its own, so that it costs the others no registers
+    if (a.P.perm && a.P.resort) {
+        if (a.cond) hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, true, true>), grid, dim3(block), lds, s, a);
+        else hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, false, true>), grid, dim3(block), lds, s, a);
+    } else if (a.P.perm) {
+        if (a.cond) hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, true, false>), grid, dim3(block), lds, s, a);
+        else hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, false, false>), grid, dim3(block), lds, s, a);
     } else {
-        if (a.cond) hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, false, true>), grid, dim3(block), lds, s, a);
-        else hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, false, false>), grid, dim3(block), lds, s, a);
+        if (a.cond) hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, false, true, false>), grid, dim3(block), lds, s, a);
+        else hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, false, false, false>), grid, dim3(block), lds, s, a);
     }
     return hipGetLastError();
 }

@@ -199,6 +199,27 @@ __device__ __forceinline__ uint32_t orig_id(const InstArgs &P, uint32_t x) {
     return x;
 }
 
+// Position that the walker in this lane takes when the wave's walkers are sorted
+// by current walk id (lanes without a walker last, ties in lane order): each
+// lane returns the lane whose walker sorts to it.  A bitonic network over the
+// 64 keys (x << 6 | lane), exchanged with lane shuffles; the calling wave must
+// be converged.
+__device__ __forceinline__ uint32_t sorted_source(uint32_t x, bool active, int lane) {
+    unsigned long long key =
+        ((unsigned long long)(active ? x : 0xFFFFFFFFu) << 6) | (unsigned long long)lane;
+    for (int k = 2; k <= WAVE; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const unsigned long long o = __shfl_xor(key, j, WAVE);
+            const bool ascending = (lane & k) == 0;
+            const bool lower = (lane & j) == 0;
+            const unsigned long long lo = key < o ? key : o;
+            const unsigned long long hi = key < o ? o : key;
+            key = lower == ascending ? lo : hi;
+        }
+    }
+    return (uint32_t)(key & (WAVE - 1));
+}
+
 template <bool FP32>
 __device__ __forceinline__ typename WeightT<FP32>::T wexp(typename WeightT<FP32>::T x) {
     if constexpr (FP32)
@@ -357,7 +378,7 @@ struct GroupOut {
 // entry's mean and M2 come from a two-pass reduction over its slots in a fixed
 // order plus its n0 copies of K: the result does not depend on which lane ran
 // which walker, nor on how many entries share the task.
-template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND>
+template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND, bool RESORT = false>
 __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx, int64_t n,
                                           uint32_t G, uint32_t ord0, uint32_t cnt,
                                           const TraceOut &tr, const GroupOut &out,
@@ -525,8 +546,33 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             dx = d_at<FP32, LOC>(P, x);
         }
         uint32_t next = WAVE;
+        uint32_t since_sort = 0;
 
         while (__ballot(active) != 0ull) {
+            if constexpr (LOC && RESORT) {
+                // relabelled tables: every P.resort events the walkers move to the
+                // lanes of their sorted current walk ids, so that neighbouring lanes
+                // gather neighbouring rows; each walker's whole state moves with it
+                // (its list slot included), so no value changes
+                if (++since_sort >= P.resort) {
+                    since_sort = 0;
+                    const int src = (int)sorted_source(x, active, lane);
+                    wl = __shfl(wl, src, WAVE);
+                    active = __shfl((int)active, src, WAVE) != 0;
+                    code = __shfl(code, src, WAVE);
+                    node = __shfl(node, src, WAVE);
+                    x = __shfl(x, src, WAVE);
+                    s = __shfl(s, src, WAVE);
+                    logw = __shfl(logw, src, WAVE);
+                    ev = __shfl(ev, src, WAVE);
+                    ju = __shfl(ju, src, WAVE);
+                    ka = __shfl(ka, src, WAVE);
+                    inv_r = __shfl(inv_r, src, WAVE);
+                    deg = __shfl(deg, src, WAVE);
+                    begin = __shfl(begin, src, WAVE);
+                    dx = __shfl(dx, src, WAVE);
+                }
+            }
             bool fin = false;
             if (active) {
                 if (deg == 0) {
@@ -596,8 +642,8 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                             const uint32_t e = code >> 10;
                             if (L.q[e] > 0.0) f = (WT)(L.K[e] + L.q[e] * (double)f);
                         }
-                        if (!isfinite((double)f)) err |= F_OVERFLOW;
                     }
+                    if (!isfinite((double)f)) err |= F_OVERFLOW;
                     L.fval[wl] = f;
                     evs += ev;
                     jus += ju;
@@ -647,15 +693,20 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 count = 1.0;
             } else {
                 const double K = L.K[g];
-                const double nn0 = (double)L.n0[g];
+                const uint32_t n0 = L.n0[g];
+                const double nn0 = (double)n0;
                 count = (double)cnt;
+                // K enters only through the walkers that stayed: without any, an
+                // infinite K (e^{td} v beyond the FP32 range, taken by no walker)
+                // must not turn 0 * K into NaN; with some, it is an overflow
+                if (n0 && !isfinite(K)) err |= F_OVERFLOW;
                 // lanes stride from the segment start, so the summation tree depends only on
                 // the entry's own walkers
                 const uint32_t J = b1 - b0;
                 double s1 = 0.0;
                 for (uint32_t i = lane; i < J; i += WAVE) s1 += (double)L.fval[b0 + i];
                 s1 = wave_sum_f64(s1);
-                mean = (nn0 * K + s1) / count;
+                mean = n0 ? (nn0 * K + s1) / count : s1 / count;
                 double s2 = 0.0;
                 for (uint32_t i = lane; i < J; i += WAVE) {
                     const double dv = (double)L.fval[b0 + i] - mean;
@@ -663,7 +714,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 }
                 s2 = wave_sum_f64(s2);
                 const double dk = K - mean;
-                m2 = s2 + nn0 * dk * dk;
+                m2 = n0 ? s2 + nn0 * dk * dk : s2;
             }
             if (lane == 0) {
                 if (out.chunks == 1) {

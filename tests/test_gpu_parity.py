@@ -215,6 +215,39 @@ def test_walk_limit_is_reported():
     assert ei.value.code == 8
 
 
+def test_fp32_start_value_overflow_taken_by_no_walker():
+    """A hub with r t = 100 and d = r: its no-jump value e^{td} v overflows FP32, but no
+    walker stays (probability e^{-100}), so the estimate is finite and matches the
+    FP64 oracle; the entry must not become 0 * inf = NaN."""
+    n = 201
+    a = np.zeros((n, n))
+    a[0, 1:] = 1.0
+    a[1:, 0] = 1.0
+    c = wl.from_dense(a)
+    v = np.random.default_rng(1).uniform(0.5, 1.5, n)
+    g, o = _pair(c, 0.5, 3, fp32=True)
+    est, se = g.entries(v, [0, 1, 0], 1000)
+    assert np.all(np.isfinite(est.cpu().numpy())) and np.all(np.isfinite(se.cpu().numpy()))
+    eo, so = o.estimate(_v_for(v, True), [0, 1, 0], 1000)
+    assert _close(est.cpu().numpy(), eo, RTOL32)
+    full, _ = g.full(v, 64)
+    assert np.all(np.isfinite(full.cpu().numpy()))
+
+
+def test_fp32_start_value_overflow_taken_by_walkers_is_reported():
+    """d t = 90 at a node that walkers seldom leave (r t = 0.01): its stayers' value
+    e^{td} v overflows FP32 and the run reports MC_ERR_OVERFLOW."""
+    a = np.array([[900.0, 0.1], [0.1, -1.0]])
+    c = wl.from_dense(a)
+    g = mc.MCExpmv(c.rowptr, c.col, c.val, 0.1, 1, fp32=True)
+    with pytest.raises(mc.MCError) as ei:
+        g.entries(np.ones(2), [0], 100)
+    assert ei.value.code == 9
+    h = mc.MCExpmv(c.rowptr, c.col, c.val, 0.1, 1)          # FP64 weights: in range
+    est, _ = h.entries(np.ones(2), [0], 100)
+    assert np.isfinite(est.item())
+
+
 @pytest.mark.parametrize("kind,code", [("negative", 2), ("nan", 3), ("col", 1), ("rowptr", 1)])
 def test_create_rejects_invalid_matrices(kind, code):
     a = np.array([[-1.0, 0.5, 0.0], [0.5, -1.0, 0.5], [0.0, 0.5, -1.0]])
@@ -481,3 +514,57 @@ def test_task_packing_matches_oracle(mode):
         eo, so = o.estimate(v, None, m)
         assert _close(est.cpu().numpy(), eo, RTOL64)
         assert _close(se.cpu().numpy(), so, 1e-8)
+
+
+# ------------------------------------------------------------ wave re-sort
+@pytest.mark.parametrize("fp32", [False, True])
+def test_wave_resort_does_not_change_results(fp32):
+    """Walkers re-sorted by current (relabelled) node every few events, with and
+    without LDS hot rows: every path and every estimate bitwise as in input order."""
+    w = wl.config_ba_full(n=20_000)
+    a = w.a
+    v = np.random.default_rng(3).uniform(0.5, 1.5, a.n)
+    t = 4.0                                  # long walks: several re-sorts per walker
+    base = mc.MCExpmv(a.rowptr, a.col, a.val, t, 31, fp32=fp32)
+    e0, s0 = base.full(v, 300)
+    idx = np.array([0, 1, 5, 17, a.n - 1, 4000], np.int64)
+    ee0, es0 = base.entries(v, idx, 3000)
+    t0 = base.trace(v, 3, 0, 2000)
+    for period, lds in ((1, 0), (3, 4096), (16, 0)):
+        g = mc.MCExpmv(a.rowptr, a.col, a.val, t, 31, fp32=fp32, relabel=1, lds_budget=lds,
+                       resort_period=period)
+        e1, s1 = g.full(v, 300)
+        assert torch.equal(e0, e1) and torch.equal(s0, s1), (period, lds)
+        ee1, es1 = g.entries(v, idx, 3000)
+        assert torch.equal(ee0, ee1) and torch.equal(es0, es1)
+        t1 = g.trace(v, 3, 0, 2000)
+        for x, y in zip(t0, t1):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("mode,cond,prop", [(mc.LIE, False, False), (mc.EXACT, True, False),
+                                            (mc.EXACT, False, True)])
+def test_wave_resort_other_walks(mode, cond, prop):
+    a = MATS["nonsym48"]
+    v = np.random.default_rng(5).uniform(0.3, 1.0, a.n)
+    bias = np.random.default_rng(4).normal(0, 0.6, a.nnz).astype(np.float32)
+    outs = []
+    for rs in (0, 1, 2):
+        g = mc.MCExpmv(a.rowptr, a.col, a.val, 2.5, 55, mode=mode, dt=0.1, cond=cond,
+                       relabel=1, resort_period=rs)
+        if prop:
+            g.set_proposal(bias)
+        outs.append([r for m in (50, 1500) for r in g.full(v, m)])
+    o = Oracle(a.rowptr, a.col, a.val, 2.5, 55, mode=mode, dt=0.1, cond=cond)
+    if prop:
+        o.set_proposal(bias)
+    eo, so = o.estimate(v, None, 50, proposal=prop)
+    assert _close(outs[0][0].cpu().numpy(), eo, RTOL64)
+    for other in outs[1:]:
+        assert all(torch.equal(x, y) for x, y in zip(outs[0], other))
+
+
+def test_resort_requires_relabel():
+    a = MATS["sym48"]
+    with pytest.raises(mc.MCError):
+        mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 1, resort_period=4)
