@@ -51,20 +51,26 @@ __device__ __forceinline__ int64_t guide_cell(double c, double scale, int64_t G)
 // guide[cell(target)], over about n / G nodes (one or two cache lines).  cdf is
 // the device's parallel prefix sum; should its rounding ever make a node of
 // zero weight the answer, the next node of non-zero weight is taken instead.
+template <bool FP32>
 __device__ __forceinline__ uint32_t draw_start(const FwdArgs &a, uint32_t w, double V,
-                                               double scale) {
+                                               double scale, double &vj) {
     const U4 o = philox(0u, w, kFwdMark, a.P.inst, a.P.key0, a.P.key1);
     const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
     const double target = (double)(m + 1ull) * 0x1p-53 * V;
     int64_t j = a.guide[guide_cell(target, scale, a.gcells)];
     while (a.cdf[j] < target) ++j;          // stops at n - 1 at the latest: cdf[n-1] = V
-    if (a.absv[j] == 0.0) {
+    // v[j] is needed for the sign anyway; |v[j]| = 0 only where the scan's rounding
+    // made the sums non-increasing, and then the nearest node with weight is taken
+    double vv = (double)load_v<FP32>(a.P.v, (uint32_t)j);
+    if (vv == 0.0) {
         int64_t k = j;
         while (k < a.n - 1 && a.absv[k] == 0.0) ++k;
         if (a.absv[k] == 0.0)
             while (k > 0 && a.absv[k] == 0.0) --k;
         j = k;
+        vv = (double)load_v<FP32>(a.P.v, (uint32_t)j);
     }
+    vj = vv;
     return (uint32_t)j;
 }
 
@@ -106,8 +112,9 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs a) {
             int32_t ka = 0;
             WT logw = (WT)0, dx = (WT)0;
             auto start = [&](uint32_t i) {
-                j = draw_start(a, ord0 + i, V, gscale);
-                sgn = (double)load_v<FP32>(P.v, j) > 0.0 ? 1.0 : -1.0;
+                double vj;
+                j = draw_start<FP32>(a, ord0 + i, V, gscale, vj);
+                sgn = vj > 0.0 ? 1.0 : -1.0;
                 x = P.perm ? P.perm[j] : j;
                 const RowRec rr = P.rows[x];
                 inv_r = rr.inv_r;
