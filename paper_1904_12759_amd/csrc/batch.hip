@@ -40,7 +40,7 @@ __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, i
     const int64_t wbase = c * chunk;
     const int64_t rem = I.nwalk - wbase;
     const uint32_t cnt = (uint32_t)(rem < chunk ? rem : chunk);
-    const GroupOut out{I.est, I.se, a.part + I.part_off, e_first, I.chunks, c, e_first * I.chunks + c};
+    const GroupOut out{I.est, I.se, a.part + I.part_off, e_first, I.chunks, e_first * I.chunks + c};
     TraceOut none;
     run_group<MODE, FP32, false, false, false, false>(
         I.P, I.idx, I.n, G, (uint32_t)wbase, cnt, none, out,

@@ -91,13 +91,6 @@ struct TraceOut {
     int64_t base = 0;
 };
 
-// Statistics of one task, identical in every lane of the wave.
-struct TaskResult {
-    double n, mean, m2;        // count, mean and sum of squared deviations
-    unsigned long long events, jumps;
-    uint32_t err;
-};
-
 struct WalkArgs {
     InstArgs P;
     const int64_t *idx;        // null: entry e is node e

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
         const uint32_t cnt = (uint32_t)(rem < (int64_t)a.chunk ? rem : (int64_t)a.chunk);
         TraceOut tr = a.trace;
         tr.base = wbase;
-        const GroupOut out{a.est, a.se, a.part, e_first, chunks, c, pbase};
+        const GroupOut out{a.est, a.se, a.part, e_first, chunks, pbase};
         run_group<MODE, FP32, PROP, TRACE, LOC, COND, RESORT>(P, a.idx, a.n, G, (uint32_t)(a.w0 + wbase), cnt, tr,
                                            out, L, my_events, my_jumps, err);
     }

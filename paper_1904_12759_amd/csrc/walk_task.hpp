@@ -354,10 +354,10 @@ struct alignas(16) GroupLds {
 };
 static_assert(kGroupMax <= 64 && kChunkMax <= 1024, "list codes are 6 + 10 bits");
 
-// Where a task's per-entry results go: entry e_first + g, chunk c of `chunks`.
+// Where a task's per-entry results go: entry e_first + g, one of `chunks` chunks.
 struct GroupOut {
     double *est, *se, *part;
-    int64_t e_first, chunks, c;
+    int64_t e_first, chunks;
     int64_t pbase;             // partial of entry e_first + g at this chunk: pbase + g * chunks
 };
 
@@ -377,7 +377,10 @@ struct GroupOut {
 // finished walker writes its value to the slot of its list position, and each
 // entry's mean and M2 come from a two-pass reduction over its slots in a fixed
 // order plus its n0 copies of K: the result does not depend on which lane ran
-// which walker, nor on how many entries share the task.
+// which walker, nor on how many entries share the task.  When the entries'
+// listed walkers do not all fit the list at once, phases 1 and 2 alternate in
+// sessions (see below); with RESORT (relabelled tables only) the wave re-sorts
+// its walkers by current node every P.resort events.
 template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND, bool RESORT = false>
 __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx, int64_t n,
                                           uint32_t G, uint32_t ord0, uint32_t cnt,
