@@ -339,7 +339,7 @@ void mc_expmv_batch_destroy(mc_batch_t b);
  * mc_expmv_set_proposal.  Variance reduction is the remedy the paper names for
  * the statistical error (Sec. 5, after Eq. (errortotal)); the tilted walk with
  * its importance weights keeps the estimator unbiased whatever the network
- * predicts, so the plain walk stays both the fallback and the judge of bias.
+ * predicts, so the plain walk stays both the fallback and the check on bias.
  *
  *   node features  f_i = [log1p deg_i, r_i, v_i, log1p(mean deg of i's jump
  *                  targets)], each standardised over the nodes (population sd)
