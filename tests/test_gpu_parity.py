@@ -187,6 +187,31 @@ def test_single_walker_and_empty_requests():
     assert est.numel() == 0
 
 
+def test_largest_walker_count():
+    """2^32 - 1 walkers for one entry (the largest count: ordinals are 32-bit), 4.2e6
+    chunk partials merged by a full wave: the sampled walkers at both ends of the
+    ordinal range against the oracle, the estimate against the exact value within 5
+    standard errors, and 2^32 walkers rejected."""
+    a = MATS["cycle31"]
+    g, o = _pair(a, 0.5, 21, fp32=True)
+    v = np.random.default_rng(8).uniform(0.5, 1.5, a.n)
+    m = 2**32 - 1
+    est, se = g.entries(v, [3], m)
+    st = g.stats()
+    assert st["walkers"] == m and st["events"] == st["jumps"] + m
+    exact = refs.expm_multiply_v(a.to_scipy(), 0.5, v)[3]
+    assert abs(est.item() - exact) < 5 * se.item() and se.item() < 1e-4 * exact
+    vv = _v_for(v, True)
+    for w0 in (0, m - 500):
+        xg, eg, jg, fg = g.trace(v, 3, w0, 500)
+        xo, eo, jo, fo, _ = o.trace(vv, 3, w0, 500)
+        assert np.array_equal(xg, xo) and np.array_equal(eg, eo) and np.array_equal(jg, jo)
+        assert _close(fg, fo, RTOL32)
+    with pytest.raises(mc.MCError) as ei:
+        g.entries(v, [3], 2**32)
+    assert ei.value.code == 1
+
+
 def test_diagonal_matrix_exact_on_gpu():
     d = np.array([-1.0, 0.0, 0.3, 2.0])
     a = wl.from_dense(np.diag(d))
