@@ -29,6 +29,7 @@ struct mc_expmv_s {
     Tables plain, prop;
     bool has_prop = false;
     uint32_t *flags = nullptr;           // latched device errors
+    uint32_t *flag_host = nullptr;       // pinned copy of *flags, read by mc_expmv_sync
     unsigned long long *counters = nullptr;
     double *part = nullptr;              // chunk partials
     int64_t part_cap = 0;                // doubles
@@ -321,6 +322,7 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->col);
     (void)hipFree(h->val);
     (void)hipFree(h->flags);
+    if (h->flag_host) (void)hipHostFree(h->flag_host);
     (void)hipFree(h->counters);
     (void)hipFree(h->part);
     (void)hipFree(h->rowof);
@@ -389,6 +391,7 @@ mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t
     CREATE_TRY(hipEventCreate(&h->ev0));
     CREATE_TRY(hipEventCreate(&h->ev1));
     CREATE_TRY(dalloc(&h->flags, 1));
+    CREATE_TRY(hipHostMalloc((void **)&h->flag_host, sizeof(uint32_t), 0));
     CREATE_TRY(dalloc(&h->counters, 2 * (int64_t)kMaxWalkGrid));
     CREATE_TRY(hipMemsetAsync(h->flags, 0, sizeof(uint32_t), h->stream));
     CREATE_TRY(dalloc(&h->rowptr, n + 1));
@@ -601,11 +604,13 @@ mc_status mc_expmv_set_stream(mc_expmv_t h, void *stream) {
 mc_status mc_expmv_sync(mc_expmv_t h) {
     if (!h) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
-    uint32_t f = 0;
+    // the flag word comes back behind the stream's own work and is cleared there,
+    // so the wait below is the only synchronisation
+    HIP_TRY(hipMemcpyAsync(h->flag_host, h->flags, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipMemsetAsync(h->flags, 0, sizeof(uint32_t), h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    HIP_TRY(hipMemcpy(&f, h->flags, sizeof(f), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemset(h->flags, 0, sizeof(uint32_t)));
-    return flags_to_status(f);
+    return flags_to_status(*h->flag_host);
 }
 
 mc_status mc_expmv_stats(mc_expmv_t h, mc_expmv_run_stats *out) {
@@ -724,6 +729,7 @@ struct mc_batch_s {
     unsigned long long *counters = nullptr;
     unsigned long long *queue = nullptr;
     uint32_t *flags = nullptr;
+    uint32_t *flag_host = nullptr;       // pinned copy of *flags, read by mc_expmv_batch_sync
     BatchArgs args{};
     int block = 256, grid = 0;
     uint32_t group = 0;
@@ -750,6 +756,7 @@ void batch_free(mc_batch_s *b) {
     (void)hipFree(b->counters);
     (void)hipFree(b->queue);
     (void)hipFree(b->flags);
+    if (b->flag_host) (void)hipHostFree(b->flag_host);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
     if (b->ev_user) (void)hipEventDestroy(b->ev_user);
@@ -996,6 +1003,7 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
     B_TRY(dalloc(&b->counters, 2 * (int64_t)b->ncu * 64 * (int64_t)b->classes.size()));
     B_TRY(dalloc(&b->queue, 1));
     B_TRY(dalloc(&b->flags, 1));
+    B_TRY(hipHostMalloc((void **)&b->flag_host, sizeof(uint32_t), 0));
     B_TRY(hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BatchInst) * (size_t)n_inst,
                          hipMemcpyHostToDevice, b->stream));
     B_TRY(hipMemcpyAsync(b->d_fin, b->fin_begin.data(), sizeof(int64_t) * (size_t)(n_inst + 1),
@@ -1060,11 +1068,11 @@ mc_status mc_expmv_batch_run(mc_batch_t b) {
 mc_status mc_expmv_batch_sync(mc_batch_t b) {
     if (!b) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(b->dev));
+    HIP_TRY(hipMemcpyAsync(b->flag_host, b->flags, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           b->stream));
+    HIP_TRY(hipMemsetAsync(b->flags, 0, sizeof(uint32_t), b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
-    uint32_t f = 0;
-    HIP_TRY(hipMemcpy(&f, b->flags, sizeof(f), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemset(b->flags, 0, sizeof(uint32_t)));
-    return flags_to_status(f);
+    return flags_to_status(*b->flag_host);
 }
 
 mc_status mc_expmv_batch_stats(mc_batch_t b, mc_expmv_run_stats *out, mc_batch_schedule *sched) {
