@@ -559,8 +559,9 @@ def main():
                          "the reference kernel for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(walkers shard by start node; see the design notes)", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              "(a multi-GPU run would shard walkers by start node, which is not implemented)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
