@@ -148,6 +148,21 @@ def test_no_jump_probability():
     assert stats.binomtest(k, len(ju), np.exp(-2.5 * t)).pvalue > 1e-4
 
 
+def test_walkers_are_independent():
+    """The estimator's error model (Sec. 5, sigma / sqrt(M)) needs independent walkers.
+    With P(no jump) about 1/2 at the start, the first-event outcomes of neighbouring
+    ordinals (2j and 2j+1, 2j+1 and 2j+2) are uncorrelated, for two start nodes and an
+    odd first ordinal."""
+    csr = wl.from_dense(np.array([[0.0, np.log(2.0)], [0.7, 0.0]]))
+    o = Oracle(csr.rowptr, csr.col, csr.val, 1.0, 5)
+    for start, w0 in ((0, 0), (0, 1001), (1, 0)):
+        _, _, ju, _, _ = o.trace(np.ones(2), start, w0, 40_000)
+        j = (ju > 0).astype(float)
+        for a, b in ((j[0::2], j[1::2]), (j[1:-1:2], j[2::2])):
+            r = np.corrcoef(a, b)[0, 1]
+            assert abs(r) < 5.0 / np.sqrt(len(a)), (start, w0, r)
+
+
 # ----------------------------------------------------------- special cases
 def test_diagonal_matrix_is_exact():
     d = np.array([-1.0, 0.0, 0.3, 2.0])
