@@ -406,10 +406,52 @@ def bench_forward_tc(mc, seed, n=1_000_000, m=1_000_000, steps=5):
         st = h.stats()
         tc, tse = tot.cpu().numpy().tolist()
         out[name] = dict(ms_per_tc=float(np.median(ms)), first_call_s=first, tc=tc,
-                         rel_stderr=tse / abs(tc), rel_err_vs_exact=(tc - exact) / exact,
+                         tc_n=tc / a.n, rel_stderr=tse / abs(tc),
+                         rel_err_vs_exact=(tc - exact) / exact,
                          events=st["events"], jumps=st["jumps"],
                          walker_steps_per_s=st["events"] / (float(np.median(ms)) / 1e3))
         del h
+    return out
+
+
+def bench_isim(mc, seed, ms=(100_000, 1_000_000, 10_000_000), per_node=(1_000, 10_000, 100_000)):
+    """Ranking study (Sec. 6, the isim table): small-world networks n = 1000 and 10000
+    (Newman-Watts, p = 0.2), A = adjacency, t = 1, v = 1, so the full vector is every
+    node's total subgraph communicability.  Forward walks (Algorithm 2), STRANG with the
+    paper's dt = 0.03125, M walkers in total, and backward walks (Algorithm 1) with M
+    walkers per node; the Monte Carlo vector ranked against the exact one
+    (expm_multiply) by isim at K = n and K = n/10 (mc_isim on the GPU), with the
+    normalised total communicability TC_n = TC / n."""
+    import torch
+    import scipy.sparse.linalg as sla
+    from paper_1904_12759_amd import workloads as wl
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = {}
+    for n in (1000, 10_000):
+        a = wl.small_world(n, 0.2, 1)
+        exact = sla.expm_multiply(a.to_scipy().tocsr(), np.ones(a.n))
+        ex = torch.as_tensor(exact, device=dev)
+        v = torch.ones(a.n, dtype=torch.float64, device=dev)
+        h = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, seed, mode=mc.STRANG, dt=0.03125)
+        rows = {}
+        for m in ms:
+            est, se, tot = h.forward(v, m)
+            tc = float(tot[0].item())
+            rows[str(m)] = dict(isim_100=mc.isim(est, ex), isim_10=mc.isim(est, ex, n // 10),
+                                tc_n=tc / n, tc_n_exact=float(exact.sum()) / n,
+                                tc_n_rel_stderr=float(tot[1].item()) / abs(tc),
+                                max_rel_err=float(np.max(np.abs(est.cpu().numpy() - exact) / exact)))
+        # the other reading of the sample size: M backward walkers per node (Algorithm 1)
+        back = {}
+        for m in per_node:
+            est, se = h.full(v, m)
+            back[str(m)] = dict(isim_100=mc.isim(est, ex), isim_10=mc.isim(est, ex, n // 10),
+                                max_rel_err=float(np.max(np.abs(est.cpu().numpy() - exact) / exact)),
+                                ms=h.stats()["ms"])
+        out[f"n{n}"] = dict(forward_total_walkers=rows, backward_walkers_per_node=back)
+        del h
+    out["workload"] = ("small world (Newman-Watts, p=0.2), A = adjacency, t = 1, v = 1; forward "
+                       "walks, STRANG dt = 0.03125; isim against expm_multiply")
     return out
 
 
@@ -551,7 +593,7 @@ def main():
                     help="skip every extra measurement (same as --extras none)")
     ap.add_argument("--extras", default="all",
                     help="comma-separated extra measurements after the main step: "
-                         "locality, entries, learned, grid3d, batched, forward, cond, splitting; "
+                         "locality, entries, learned, grid3d, batched, forward, cond, splitting, isim; "
                          "'all' or 'none'")
     ap.add_argument("--seed", type=int, default=12759)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -657,7 +699,8 @@ def main():
             "traffic": measured_traffic(),
         },
     }
-    names = ["locality", "entries", "learned", "grid3d", "batched", "forward", "cond", "splitting"]
+    names = ["locality", "entries", "learned", "grid3d", "batched", "forward", "cond", "splitting",
+             "isim"]
     extras = [] if args.no_extras or args.extras == "none" else \
         names if args.extras == "all" else [x for x in args.extras.split(",") if x]
     unknown = [x for x in extras if x not in names]
@@ -688,6 +731,9 @@ def main():
     if "splitting" in extras:
         log("bench: splitting study (small world n=100, 1000)")
         out["splitting"] = bench_splitting(mc, args.seed)
+    if "isim" in extras:
+        log("bench: ranking study (small world n=1000, 10000)")
+        out["isim"] = bench_isim(mc, args.seed)
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         try:

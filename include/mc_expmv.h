@@ -402,6 +402,28 @@ void mc_learn_default_opts(mc_learn_opts *opts);
 mc_status mc_expmv_learn_proposal(mc_expmv_t h, const void *v, const mc_learn_opts *opts,
                                   mc_learn_report *rep);
 
+/* ---------------------------------------------------------------- rankings */
+
+/*
+ * Intersection similarity of the node rankings of two vectors, the measure
+ * the paper uses (Sec. 6) to compare a Monte Carlo communicability vector with
+ * a reference one:
+ *     isim_K(x, y) = (1/K) sum_{i=1..K} |X_i delta Y_i| / (2 i),
+ * X_i (Y_i) the i nodes with the largest x (y), delta the symmetric
+ * difference; 0 for identical top-K rankings, 1 for disjoint ones.  Ties rank
+ * the lower node index first; -0 counts as +0.
+ *   n        1 .. 2^31 - 1
+ *   x, y     device double[n], finite (MC_ERR_NONFINITE otherwise)
+ *   k        1 .. n (the paper reports K = n and K = n/10)
+ *   out      host double: the value
+ *   stream   hipStream_t or NULL (null stream)
+ * Allocates and frees its scratch on every call.  Synchronous.
+ * Errors: MC_ERR_INVALID_ARG (null pointer, n or k out of range),
+ * MC_ERR_NONFINITE, MC_ERR_NO_MEMORY, MC_ERR_DEVICE.
+ */
+mc_status mc_isim(int64_t n, const double *x, const double *y, int64_t k, double *out,
+                  void *stream);
+
 #ifdef __cplusplus
 }
 #endif

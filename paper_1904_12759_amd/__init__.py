@@ -169,6 +169,8 @@ _SIGS = {
     "mc_learn_default_opts": (None, [ctypes.c_void_p]),
     "mc_expmv_learn_proposal": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_isim": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                               ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -217,6 +219,25 @@ def default_opts(**kw) -> mc_expmv_opts:
             v = ctypes.c_void_p(v)
         setattr(o, k, v)
     return o
+
+
+def isim(x, y, k: int | None = None, stream=None) -> float:
+    """Intersection similarity isim_K of the rankings of x and y (``mc_isim``); x and
+    y are device tensors (or arrays, copied to the device) of one length n, K = k or n."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    xs = torch.as_tensor(x).to(device=dev, dtype=torch.float64).contiguous()
+    ys = torch.as_tensor(y).to(device=dev, dtype=torch.float64).contiguous()
+    if xs.shape != ys.shape or xs.dim() != 1:
+        raise ValueError("x and y must be vectors of one length")
+    n = xs.numel()
+    k = n if k is None else int(k)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    out = ctypes.c_double()
+    _check(load().mc_isim(n, _ptr(xs), _ptr(ys), k, ctypes.byref(out), ctypes.c_void_p(stream)),
+           "mc_isim")
+    return out.value
 
 
 class MCExpmv:

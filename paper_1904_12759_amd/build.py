@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmcexpmv.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "setup.hip", "walk.hip", "batch.hip", "mlp.hip", "forward.hip"]
+SOURCES = ["api.hip", "setup.hip", "walk.hip", "batch.hip", "mlp.hip", "forward.hip", "isim.hip"]
 
 HIPCC_FLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
