@@ -14,6 +14,8 @@ namespace mc {
 namespace {
 
 
+static_assert(sizeof(BatchInst) % 4 == 0, "the instance record is copied as 32-bit words");
+
 // One task of a class's index space: instance, then (entry group, chunk).
 template <int MODE, bool FP32>
 __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, int64_t task,
@@ -26,10 +28,19 @@ __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, i
         if (tb[mid] <= task) lo = mid;
         else hi = mid - 1;
     }
-    // the instance is the same for the whole wave: make that visible to the
-    // compiler so its record is read with scalar loads into scalar registers
+    // the instance is the same for the whole wave.  Its record arrives through
+    // vector loads (the kernel stores to global memory, so the compiler does not
+    // use scalar loads for it); every word is moved to a scalar register at once,
+    // so the instance holds no vector registers during the walk (111 -> 100)
     lo = __builtin_amdgcn_readfirstlane(lo);
-    const BatchInst &I = a.inst[lo];
+    BatchInst I;
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.inst + lo);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&I);
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(BatchInst) / 4); ++i)
+            dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    }
     const int64_t local = task - tb[lo];
     const int64_t grp = local / I.chunks;
     const int64_t c = local - grp * I.chunks;

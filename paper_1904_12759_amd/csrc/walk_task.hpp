@@ -393,6 +393,10 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
     const unsigned long long lanemask_lt = (1ull << lane) - 1ull;
     const double t = P.t;
     uint32_t err = 0;
+    // the task's shape is the same in every lane: scalar registers and scalar branches
+    G = __builtin_amdgcn_readfirstlane(G);
+    ord0 = __builtin_amdgcn_readfirstlane(ord0);
+    cnt = __builtin_amdgcn_readfirstlane(cnt);
 
     // ---- per-entry setup, one lane per entry
     double e0 = 0.0;
@@ -448,7 +452,8 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
     uint32_t g = 0;
     for (;;) {
         for (; g < G;) {
-            const uint32_t node = L.node[g];
+            // LDS values the whole wave shares, read into scalar registers
+            const uint32_t node = __builtin_amdgcn_readfirstlane(L.node[g]);
             const double eg = readlane_f64(e0, (int)g);
             const uint32_t start = nlist;
             if (lane == 0) L.seg[g] = start;
@@ -688,7 +693,8 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         // ---- per-entry statistics: slots in a fixed order, plus n0 copies of K
         for (uint32_t g = g_begin; g < g_end; ++g) {
             const int64_t e = out.e_first + g;
-            const uint32_t b0 = L.seg[g], b1 = L.seg[g + 1];
+            const uint32_t b0 = __builtin_amdgcn_readfirstlane(L.seg[g]);
+            const uint32_t b1 = __builtin_amdgcn_readfirstlane(L.seg[g + 1]);
             double mean, m2, count;
             if (L.node[g] == 0xFFFFFFFFu) {
                 mean = NAN;
@@ -696,7 +702,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 count = 1.0;
             } else {
                 const double K = L.K[g];
-                const uint32_t n0 = L.n0[g];
+                const uint32_t n0 = __builtin_amdgcn_readfirstlane(L.n0[g]);
                 const double nn0 = (double)n0;
                 count = (double)cnt;
                 // K enters only through the walkers that stayed: without any, an
