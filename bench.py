@@ -58,6 +58,23 @@ def measured_traffic(profile=PROFILE, sources=KERNEL_SOURCES):
         return None
 
 
+def measured_valu(profile=PROFILE, sources=KERNEL_SOURCES):
+    """The walk kernel's VALU issue from the same committed summary: busy time
+    (SQ_ACTIVE_INST_VALU x 4 cycles over 1024 SIMDs at 2.4 GHz) against the launch,
+    or None when the kernel sources have changed since."""
+    if measured_traffic(profile, sources) is None:
+        return None
+    import re
+    for ln in open(profile).read().splitlines():
+        m = re.match(r"valu_busy_estimate: .* = ([0-9.e+]+) cycles = ([0-9.]+) ms of a ([0-9.]+) ms launch",
+                     ln)
+        if m:
+            busy, launch = float(m.group(2)), float(m.group(3))
+            return {"busy_ms": busy, "launch_ms": launch, "frac": busy / launch,
+                    "source": "rocprofv3 SQ_ACTIVE_INST_VALU"}
+    return None
+
+
 def cpu_baseline(w, seed, nthreads, min_seconds=10.0):
     """The oracle on the host over the same workload (every node, 1e3 walkers each),
     repeated until at least min_seconds of wall time so the rate is not dominated by
@@ -698,6 +715,9 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(),
         },
+        # the tables are cache resident (traffic above is a few % of the algorithmic
+        # bytes): the kernel is bound by vector-ALU issue, which this reports
+        "valu_issue": measured_valu(),
     }
     names = ["locality", "entries", "learned", "grid3d", "batched", "forward", "cond", "splitting",
              "isim"]
