@@ -48,6 +48,7 @@ struct mc_expmv_s {
     int sym_state = -1;                  // A == A^T: -1 not checked yet, 0 no, 1 yes
     double *fwd_abs = nullptr, *fwd_cdf = nullptr;   // [n] |v| and its cumulative sums
     int32_t *fwd_guide = nullptr;        // guide table over fwd_cdf
+    FwdRow *fwd_rows = nullptr;          // merged state records of the forward walks
     void *fwd_temp = nullptr;            // scan scratch
     size_t fwd_temp_bytes = 0;
     double *fwd_part = nullptr;          // chunk partials of Y
@@ -332,6 +333,7 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->fwd_abs);
     (void)hipFree(h->fwd_cdf);
     (void)hipFree(h->fwd_guide);
+    (void)hipFree(h->fwd_rows);
     (void)hipFree(h->fwd_temp);
     (void)hipFree(h->fwd_part);
     (void)hipFree(h->fwd_acc);
@@ -1490,6 +1492,11 @@ mc_status run_forward(mc_expmv_s *h, const void *v, int64_t w0, int64_t nwalk, d
     FwdArgs a{};
     fill_inst(h, v, false, a.P);
     a.P.hot = 0;
+    if (n > 0 && !h->fwd_rows) {
+        HIP_TRY(dalloc(&h->fwd_rows, n));
+        HIP_TRY(launch_fwd_rows(n, a.P, h->fwd_rows, h->stream));
+    }
+    a.frows = h->fwd_rows;
     a.n = n;
     a.nwalk = nwalk;
     a.w0 = w0;

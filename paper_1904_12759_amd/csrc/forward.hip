@@ -116,11 +116,11 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs a) {
                 j = draw_start<FP32>(a, ord0 + i, V, gscale, vj);
                 sgn = vj > 0.0 ? 1.0 : -1.0;
                 x = P.perm ? P.perm[j] : j;
-                const RowRec rr = P.rows[x];
-                inv_r = rr.inv_r;
-                deg = rr.deg;
-                begin = rr.begin;
-                dx = load_d<FP32>(P, x);
+                const FwdRow fr = a.frows[x];
+                inv_r = fr.inv_r;
+                deg = fr.deg;
+                begin = fr.begin;
+                dx = FP32 ? (WT)fr.d32 : (WT)fr.d64;
                 s = 0.0;
                 logw = (WT)0;
                 ev = 0;
@@ -159,11 +159,11 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs a) {
                             const SlotRec q = P.slots[begin + sl];
                             x = (uint32_t)(o.w < q.thr ? q.self : q.alias);
                             ++ju;
-                            const RowRec rr = P.rows[x];
-                            inv_r = rr.inv_r;
-                            deg = rr.deg;
-                            begin = rr.begin;
-                            dx = load_d<FP32>(P, x);
+                            const FwdRow fr = a.frows[x];
+                            inv_r = fr.inv_r;
+                            deg = fr.deg;
+                            begin = fr.begin;
+                            dx = FP32 ? (WT)fr.d32 : (WT)fr.d64;
                         } else {
                             fin = true;
                         }
@@ -244,6 +244,22 @@ __global__ void k_fwd_guide(int64_t n, int64_t G, const double *__restrict__ cdf
         else lo = mid + 1;
     }
     guide[k] = (int32_t)lo;
+}
+
+// The forward walks' merged state records.
+__global__ void k_fwd_rows(int64_t n, const RowRec *__restrict__ rows, const double *__restrict__ d64,
+                           const float *__restrict__ d32, FwdRow *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const RowRec r = rows[i];
+    FwdRow f;
+    f.inv_r = r.inv_r;
+    f.deg = r.deg;
+    f.begin = r.begin;
+    f.d64 = d64[i];
+    f.d32 = d32[i];
+    f.pad = 0u;
+    out[i] = f;
 }
 
 // acc1 = acc2 = 0 (a kernel, so the sequence can be captured in a graph).
@@ -336,6 +352,13 @@ hipError_t launch_check_symmetric(int64_t nnz, const int64_t *rowptr, const int3
     if (nnz == 0) return hipSuccess;
     hipLaunchKernelGGL(k_check_symmetric, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz,
                        rowptr, rowof, col, val, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_rows(int64_t n, const InstArgs &P, FwdRow *frows, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fwd_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, P.rows,
+                       P.d64, P.d32, frows);
     return hipGetLastError();
 }
 

@@ -119,8 +119,21 @@ struct WalkArgs {
 constexpr uint32_t kFwdChunk = 128;
 // Guide-table cells for n nodes: about eight nodes per cell.
 inline int64_t guide_cells(int64_t n) { return n > 8 ? (n + 7) / 8 : 1; }
+// A visited state's record for the forward walks: the row record and d side by
+// side (one 32-byte gather instead of two), built once per handle from P.rows
+// and P.d64 / P.d32 in the same (walk) order.
+struct alignas(16) FwdRow {
+    double inv_r;
+    uint32_t deg, begin;
+    double d64;
+    float d32;
+    uint32_t pad;
+};
+static_assert(sizeof(FwdRow) == 32, "one 32-byte record per state");
+
 struct FwdArgs {
     InstArgs P;                // plain tables; P.hot must be 0
+    const FwdRow *frows;       // [n] row record + d of every state (walk order)
     int64_t n;
     int64_t nwalk;             // M
     int64_t w0;                // first walker ordinal (trace only)
@@ -214,6 +227,7 @@ constexpr int kMaxWalkGrid = 1 << 16;
 hipError_t launch_check_symmetric(int64_t nnz, const int64_t *rowptr, const int32_t *rowof,
                                   const int32_t *col, const double *val, uint32_t *flag,
                                   hipStream_t s);
+hipError_t launch_fwd_rows(int64_t n, const InstArgs &P, FwdRow *frows, hipStream_t s);
 hipError_t launch_fwd_cdf(int64_t n, const void *v, bool fp32, double *absv, double *cdf,
                           int32_t *guide, void *temp, size_t &temp_bytes, hipStream_t s);
 int forward_grid(int64_t chunks);
