@@ -158,3 +158,31 @@ def test_batched_config_scaled_down():
             eo, _ = o.estimate(w.v, sample, w.nwalk, threads=8)
             got = est[k].cpu().numpy()[sample]
         assert np.all(np.abs(got - eo) <= 1e-12 * np.abs(eo)), k
+
+
+def test_batched_config_full_size_sampled():
+    """The benchmark's 64-instance set at full size (n log-uniform up to 1e6), schedule
+    from the autotuner as the benchmark runs it: sampled oracle parity on instances of
+    every type, among them the largest of each kind."""
+    ws = wl.batched_instances(count=64)
+    insts = [dict(rowptr=w.a.rowptr, col=w.a.col, val=w.a.val, t=w.t, v=w.v, idx=w.idx,
+                  n_walkers=w.nwalk, instance_id=k) for k, w in enumerate(ws)]
+    os.environ.pop("MC_EXPMV_TUNE_CACHE", None)
+    b = mc.MCBatch(insts, 12759)
+    est, se = b.run()
+    sizes = np.array([w.a.n for w in ws])
+    picks = {0, 1, 2, 3}
+    for kind in range(4):
+        ks = [k for k in range(64) if k % 4 == kind]
+        picks.add(max(ks, key=lambda k: sizes[k]))
+    for k in sorted(picks):
+        w = ws[k]
+        o = Oracle(w.a.rowptr, w.a.col, w.a.val, w.t, 12759, instance=k)
+        if w.idx is not None:
+            eo, _ = o.estimate(w.v, w.idx, w.nwalk, threads=8)
+            got = est[k].cpu().numpy()
+        else:
+            sample = np.linspace(0, w.a.n - 1, 40).astype(np.int64)
+            eo, _ = o.estimate(w.v, sample, w.nwalk, threads=8)
+            got = est[k].cpu().numpy()[sample]
+        assert np.all(np.abs(got - eo) <= 1e-12 * np.abs(eo)), (k, int(sizes[k]))
