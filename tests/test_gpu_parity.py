@@ -379,6 +379,26 @@ def test_grid2d_config_full_size_parity():
     assert np.abs(z).max() < 4.5
 
 
+def test_grid2d_entries_at_1e3_production_parity():
+    """The entries/s measurement's production launch: walker counts from a 1e4-walker
+    pilot (1.2 (sigma / (1e-3 x))^2 per entry, up to a few million), all 16 entries in one
+    mc_expmv_entries_multi launch; every entry against the oracle with its own count."""
+    w = wl.config_grid2d_entries()
+    g, o = _pair(w.a, w.t, 12759)
+    est0, se0 = g.entries(w.v, w.idx, 10_000)
+    x = est0.cpu().numpy()
+    sig = se0.cpu().numpy() * np.sqrt(10_000)
+    need = np.ceil(1.2 * (sig / (1e-3 * np.abs(x))) ** 2).astype(np.int64)
+    assert need.max() > 1_000_000
+    est, se = g.entries_multi(w.v, w.idx, need)
+    est, se = est.cpu().numpy(), se.cpu().numpy()
+    for j, (i, m) in enumerate(zip(w.idx, need)):
+        eo, so = o.estimate(w.v, [int(i)], int(m), threads=8)
+        assert _close(est[j:j + 1], eo, RTOL64), (j, int(m))
+        assert np.allclose(se[j], so, rtol=1e-8), (j, int(m))
+    assert np.max(se / np.abs(est)) < 1.2e-3
+
+
 def test_ba_config_full_size_sampled_parity():
     """BA n=1e5, m=3, full vector with 1e3 walkers/node in FP32 weights: the whole
     vector on the GPU, sampled nodes (hubs included) recomputed by the oracle."""
