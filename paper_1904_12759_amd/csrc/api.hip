@@ -47,6 +47,7 @@ struct mc_expmv_s {
     // forward estimator
     int sym_state = -1;                  // A == A^T: -1 not checked yet, 0 no, 1 yes
     double *fwd_abs = nullptr, *fwd_cdf = nullptr;   // [n] |v| and its cumulative sums
+    int8_t *fwd_sign = nullptr;          // [n] sign of v
     int32_t *fwd_guide = nullptr;        // guide table over fwd_cdf
     FwdRow *fwd_rows = nullptr;          // merged state records of the forward walks
     void *fwd_temp = nullptr;            // scan scratch
@@ -331,6 +332,7 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->perm);
     (void)hipFree(h->inv);
     (void)hipFree(h->fwd_abs);
+    (void)hipFree(h->fwd_sign);
     (void)hipFree(h->fwd_cdf);
     (void)hipFree(h->fwd_guide);
     (void)hipFree(h->fwd_rows);
@@ -1466,10 +1468,11 @@ mc_status run_forward(mc_expmv_s *h, const void *v, int64_t w0, int64_t nwalk, d
     const int64_t n = h->n;
     if (n > 0 && !h->fwd_cdf) {
         HIP_TRY(dalloc(&h->fwd_abs, n));
+        HIP_TRY(dalloc(&h->fwd_sign, n));
         HIP_TRY(dalloc(&h->fwd_cdf, n));
         HIP_TRY(dalloc(&h->fwd_guide, guide_cells(n) + 1));
         size_t bytes = 0;
-        HIP_TRY(launch_fwd_cdf(n, v, fp32, h->fwd_abs, h->fwd_cdf, h->fwd_guide, nullptr, bytes,
+        HIP_TRY(launch_fwd_cdf(n, v, fp32, h->fwd_abs, h->fwd_sign, h->fwd_cdf, h->fwd_guide, nullptr, bytes,
                                h->stream));
         HIP_TRY(hipMalloc(&h->fwd_temp, bytes > 0 ? bytes : 1));
         h->fwd_temp_bytes = bytes;
@@ -1486,7 +1489,7 @@ mc_status run_forward(mc_expmv_s *h, const void *v, int64_t w0, int64_t nwalk, d
     HIP_TRY(hipEventRecord(h->ev0, h->stream));
     if (n > 0) {
         size_t bytes = h->fwd_temp_bytes;
-        HIP_TRY(launch_fwd_cdf(n, v, fp32, h->fwd_abs, h->fwd_cdf, h->fwd_guide, h->fwd_temp, bytes,
+        HIP_TRY(launch_fwd_cdf(n, v, fp32, h->fwd_abs, h->fwd_sign, h->fwd_cdf, h->fwd_guide, h->fwd_temp, bytes,
                                h->stream));
     }
     FwdArgs a{};
@@ -1503,6 +1506,7 @@ mc_status run_forward(mc_expmv_s *h, const void *v, int64_t w0, int64_t nwalk, d
     a.chunks = chunks;
     a.cdf = h->fwd_cdf;
     a.absv = h->fwd_abs;
+    a.vsign = h->fwd_sign;
     a.guide = h->fwd_guide;
     a.gcells = guide_cells(n);
     a.acc1 = acc1;

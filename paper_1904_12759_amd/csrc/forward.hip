@@ -51,7 +51,6 @@ __device__ __forceinline__ int64_t guide_cell(double c, double scale, int64_t G)
 // guide[cell(target)], over about n / G nodes (one or two cache lines).  cdf is
 // the device's parallel prefix sum; should its rounding ever make a node of
 // zero weight the answer, the next node of non-zero weight is taken instead.
-template <bool FP32>
 __device__ __forceinline__ uint32_t draw_start(const FwdArgs &a, uint32_t w, double V,
                                                double scale, double &vj) {
     const U4 o = philox(0u, w, kFwdMark, a.P.inst, a.P.key0, a.P.key1);
@@ -59,18 +58,18 @@ __device__ __forceinline__ uint32_t draw_start(const FwdArgs &a, uint32_t w, dou
     const double target = (double)(m + 1ull) * 0x1p-53 * V;
     int64_t j = a.guide[guide_cell(target, scale, a.gcells)];
     while (a.cdf[j] < target) ++j;          // stops at n - 1 at the latest: cdf[n-1] = V
-    // v[j] is needed for the sign anyway; |v[j]| = 0 only where the scan's rounding
-    // made the sums non-increasing, and then the nearest node with weight is taken
-    double vv = (double)load_v<FP32>(a.P.v, (uint32_t)j);
-    if (vv == 0.0) {
+    // the sign of v[j] is needed anyway; v[j] = 0 only where the scan's rounding made
+    // the sums non-increasing, and then the nearest node with weight is taken
+    int8_t sg = a.vsign[j];
+    if (sg == 0) {
         int64_t k = j;
         while (k < a.n - 1 && a.absv[k] == 0.0) ++k;
         if (a.absv[k] == 0.0)
             while (k > 0 && a.absv[k] == 0.0) --k;
         j = k;
-        vv = (double)load_v<FP32>(a.P.v, (uint32_t)j);
+        sg = a.vsign[j];
     }
-    vj = vv;
+    vj = (double)sg;
     return (uint32_t)j;
 }
 
@@ -113,7 +112,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs a) {
             WT logw = (WT)0, dx = (WT)0;
             auto start = [&](uint32_t i) {
                 double vj;
-                j = draw_start<FP32>(a, ord0 + i, V, gscale, vj);
+                j = draw_start(a, ord0 + i, V, gscale, vj);
                 sgn = vj > 0.0 ? 1.0 : -1.0;
                 x = P.perm ? P.perm[j] : j;
                 const FwdRow fr = a.frows[x];
@@ -270,12 +269,14 @@ __global__ void k_fwd_zero(int64_t n, double *acc1, double *acc2) {
     if (acc2) acc2[i] = 0.0;
 }
 
-// |v| in FP64, the input of the cumulative sums.
+// |v| in FP64, the input of the cumulative sums, and the sign of every v_j.
 template <bool FP32>
-__global__ void k_fwd_absv(int64_t n, const void *v, double *out) {
+__global__ void k_fwd_absv(int64_t n, const void *v, double *out, int8_t *sign) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    out[i] = fabs((double)load_v<FP32>(v, (uint32_t)i));
+    const double x = (double)load_v<FP32>(v, (uint32_t)i);
+    out[i] = fabs(x);
+    sign[i] = x > 0.0 ? (int8_t)1 : (x < 0.0 ? (int8_t)-1 : (int8_t)0);
 }
 
 // Per-node mean and standard error from the sums of Y and Y^2, in place.
@@ -362,12 +363,12 @@ hipError_t launch_fwd_rows(int64_t n, const InstArgs &P, FwdRow *frows, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_fwd_cdf(int64_t n, const void *v, bool fp32, double *absv, double *cdf,
+hipError_t launch_fwd_cdf(int64_t n, const void *v, bool fp32, double *absv, int8_t *vsign, double *cdf,
                           int32_t *guide, void *temp, size_t &temp_bytes, hipStream_t s) {
     if (!temp) return hipcub::DeviceScan::InclusiveSum(nullptr, temp_bytes, absv, cdf, (int)n, s);
     const unsigned g = (unsigned)((n + 255) / 256);
-    if (fp32) hipLaunchKernelGGL(k_fwd_absv<true>, dim3(g), dim3(256), 0, s, n, v, absv);
-    else hipLaunchKernelGGL(k_fwd_absv<false>, dim3(g), dim3(256), 0, s, n, v, absv);
+    if (fp32) hipLaunchKernelGGL(k_fwd_absv<true>, dim3(g), dim3(256), 0, s, n, v, absv, vsign);
+    else hipLaunchKernelGGL(k_fwd_absv<false>, dim3(g), dim3(256), 0, s, n, v, absv, vsign);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipcub::DeviceScan::InclusiveSum(temp, temp_bytes, absv, cdf, (int)n, s);

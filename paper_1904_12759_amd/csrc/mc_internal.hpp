@@ -140,6 +140,7 @@ struct FwdArgs {
     int64_t chunks;            // ceil(M / kFwdChunk)
     const double *cdf;         // [n] cumulative sums of |v| in node order
     const double *absv;        // [n] |v|
+    const int8_t *vsign;       // [n] sign of v: 1, -1, or 0 for v = 0 (a small, cache-resident array)
     const int32_t *guide;      // [gcells + 1] guide table over cdf
     int64_t gcells;            // G = guide_cells(n)
     double *acc1, *acc2;       // [n] sums of Y and Y^2 per end node (acc2 may be null)
@@ -228,7 +229,7 @@ hipError_t launch_check_symmetric(int64_t nnz, const int64_t *rowptr, const int3
                                   const int32_t *col, const double *val, uint32_t *flag,
                                   hipStream_t s);
 hipError_t launch_fwd_rows(int64_t n, const InstArgs &P, FwdRow *frows, hipStream_t s);
-hipError_t launch_fwd_cdf(int64_t n, const void *v, bool fp32, double *absv, double *cdf,
+hipError_t launch_fwd_cdf(int64_t n, const void *v, bool fp32, double *absv, int8_t *vsign, double *cdf,
                           int32_t *guide, void *temp, size_t &temp_bytes, hipStream_t s);
 int forward_grid(int64_t chunks);
 hipError_t launch_forward(const FwdArgs &a, int mode, bool fp32, bool trace, double *sum_out,
