@@ -287,7 +287,22 @@ __device__ __forceinline__ void fin_merge(const double *p, int64_t chunks, uint3
     const int64_t q = (chunks + L - 1) / L;
     const int64_t c0 = (int64_t)sub * q;
     const int64_t c1 = c0 + q < chunks ? c0 + q : chunks;
-    for (int64_t c = c0; c < c1; ++c) chan_merge(n, mean, m2, p[3 * c], p[3 * c + 1], p[3 * c + 2]);
+    // partials fetched sixteen at a time, merged one by one in chunk order: the loads
+    // of a batch overlap instead of each waiting for the previous merge
+    constexpr int B = 16;
+    int64_t c = c0;
+    for (; c + B <= c1; c += B) {
+        double bn[B], bm[B], bq[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            bn[k] = p[3 * (c + k)];
+            bm[k] = p[3 * (c + k) + 1];
+            bq[k] = p[3 * (c + k) + 2];
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) chan_merge(n, mean, m2, bn[k], bm[k], bq[k]);
+    }
+    for (; c < c1; ++c) chan_merge(n, mean, m2, p[3 * c], p[3 * c + 1], p[3 * c + 2]);
     for (uint32_t off = 1; off < L; off <<= 1) {
         const double nb = __shfl_down(n, off, (int)L);
         const double mb = __shfl_down(mean, off, (int)L);
