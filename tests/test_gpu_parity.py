@@ -507,7 +507,8 @@ def test_entries_multi_equals_per_count_runs(fp32):
 
 # ------------------------------------------------------------ task packing
 def _runs(g, v, idx):
-    out = [g.full(v, m) for m in (1, 37, 300, 1000, 1500)]
+    # 512 and 1024 fill a whole LDS list (FP64 / FP32): one entry per session
+    out = [g.full(v, m) for m in (1, 37, 300, 512, 1000, 1024, 1500)]
     out += [g.entries(v, idx, 37), g.entries(v, idx, 700)]
     return [(e.clone(), s.clone()) for e, s in out]
 
