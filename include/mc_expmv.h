@@ -221,7 +221,9 @@ mc_status mc_expmv_set_proposal(mc_expmv_t h, const float *edge_bias);
  * (device float[nnz]); MC_ERR_INVALID_ARG when the plain walk is in use.  Synchronous. */
 mc_status mc_expmv_get_proposal(mc_expmv_t h, float *edge_bias);
 
-/* Use `stream` (hipStream_t, NULL = null stream) for the handle's later work. */
+/* Use `stream` (hipStream_t, NULL = null stream) for the handle's later work; that
+ * work is ordered after everything already queued on the previous stream (an event
+ * wait, no host synchronisation). */
 mc_status mc_expmv_set_stream(mc_expmv_t h, void *stream);
 
 /* Wait for the handle's stream; return (and clear) latched device errors. */

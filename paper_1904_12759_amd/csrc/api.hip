@@ -600,7 +600,19 @@ mc_status mc_expmv_get_proposal(mc_expmv_t h, float *edge_bias) {
 
 mc_status mc_expmv_set_stream(mc_expmv_t h, void *stream) {
     if (!h) return MC_ERR_INVALID_ARG;
-    h->stream = (hipStream_t)stream;
+    hipStream_t next = (hipStream_t)stream;
+    if (next != h->stream) {
+        // the handle's scratch (partials, counters, staging) may still be in use by
+        // work queued on the old stream: the new stream waits for it (no host wait)
+        HIP_TRY(hipSetDevice(h->dev));
+        hipEvent_t ev = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        hipError_t e = hipEventRecord(ev, h->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(next, ev, 0);
+        (void)hipEventDestroy(ev);
+        HIP_TRY(e);
+    }
+    h->stream = next;
     h->opts.stream = stream;
     return MC_OK;
 }

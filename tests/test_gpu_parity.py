@@ -312,6 +312,34 @@ def test_stream_ordering_on_a_side_stream():
     assert torch.equal(out, ref)
 
 
+def test_stream_switch_orders_after_queued_work():
+    """Work queued on one stream, then the handle switched to another with no host wait:
+    the second run (same chunk-partial scratch) waits for the first, and both results
+    equal those of synchronous runs."""
+    a = MATS["grid2d_16"]
+    v = np.random.default_rng(9).random(a.n)
+    idx1 = np.arange(0, a.n, 3, dtype=np.int64)
+    idx2 = np.arange(1, a.n, 5, dtype=np.int64)
+    g = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 6)
+    r1, s1 = [x.clone() for x in g.entries(v, idx1, 70_000)]
+    r2, s2 = [x.clone() for x in g.entries(v, idx2, 50_000)]
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    vt = torch.as_tensor(v, device="cuda")
+    torch.cuda.synchronize()
+    g.set_stream(sa.cuda_stream)
+    e1 = torch.empty(len(idx1), dtype=torch.float64, device="cuda")
+    q1 = torch.empty_like(e1)
+    g.entries(vt, idx1, 70_000, est=e1, stderr=q1, sync=False)
+    g.set_stream(sb.cuda_stream)
+    e2 = torch.empty(len(idx2), dtype=torch.float64, device="cuda")
+    q2 = torch.empty_like(e2)
+    g.entries(vt, idx2, 50_000, est=e2, stderr=q2, sync=False)
+    g.sync()
+    sa.synchronize()
+    assert torch.equal(e1, r1) and torch.equal(q1, s1)
+    assert torch.equal(e2, r2) and torch.equal(q2, s2)
+
+
 # ------------------------------------------------------ tilted proposal
 def test_proposal_tables_and_paths_match_oracle():
     a = MATS["nonsym48"]
