@@ -479,12 +479,15 @@ mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx
     HIP_TRY(hipEventSynchronize(h->var_ev));   // the previous call's copy has left the staging
     int64_t *offs = h->var_host, *cnts = h->var_host + k + 1;
     uint64_t walkers = 0;
+    int64_t chunks_max = 0;
     offs[0] = 0;
     for (int64_t e = 0; e < k; ++e) {
         const int64_t m = n_walkers[e];
         if (m < 1 || m > 0xFFFFFFFFll) return MC_ERR_INVALID_ARG;
         cnts[e] = m;
-        offs[e + 1] = offs[e] + (m + chunk - 1) / chunk;
+        const int64_t c = (m + chunk - 1) / chunk;
+        offs[e + 1] = offs[e] + c;
+        if (c > chunks_max) chunks_max = c;
         walkers += (uint64_t)m;
     }
     const int64_t ntasks = offs[k];
@@ -509,8 +512,11 @@ mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx
     a.w0 = 0;
     a.chunk = (uint32_t)chunk;
     a.chunks = 1;
-    a.group = 1;
-    a.ntasks = ntasks;
+    // chunk slots packed per task like entries are (group_size with one chunk's
+    // walkers per slot)
+    a.group = group_size(chunk, ntasks, h->opts.task_walkers);
+    a.var_slots = ntasks;
+    a.ntasks = (ntasks + a.group - 1) / a.group;
     a.est = est;
     a.se = stderr_;
     a.part = h->part;
@@ -519,6 +525,7 @@ mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx
     a.cond = h->opts.cond_first_jump != 0;
     a.var_task = h->var_dev;
     a.var_nwalk = h->var_dev + k + 1;
+    a.var_chunks_max = chunks_max;
     HIP_TRY(hipEventRecord(h->ev0, h->stream));
     HIP_TRY(launch_walk(a, h->opts.mode, fp32, prop, false, (int)h->opts.walkers_per_block,
                         h->stream));
@@ -526,7 +533,7 @@ mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx
     HIP_TRY(hipEventRecord(h->ev1, h->stream));
     h->ran = true;
     h->last_walkers = walkers;
-    h->last_grid = launch_walk_grid(ntasks, (int)h->opts.walkers_per_block);
+    h->last_grid = launch_walk_grid(a.ntasks, (int)h->opts.walkers_per_block);
     h->last_fp32 = fp32;
     h->last_prop = prop;
     h->last_fwd = false;
@@ -1004,10 +1011,15 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
         ntasks += itasks;
         b->classes.back().ninst += 1;
         b->classes.back().ntasks += itasks;
-        b->fin_begin[(size_t)oi] = nfin;
         if (I.chunks > 1) {
+            // a multiple of 64 and of the lane count: a group never spans two blocks
+            const int64_t L = fin_lanes(I.chunks), al = L > 64 ? L : 64;
+            nfin = (nfin + al - 1) / al * al;
+            b->fin_begin[(size_t)oi] = nfin;
             part_doubles += I.k * I.chunks * 3;
-            nfin += (I.k * (int64_t)fin_lanes(I.chunks) + 63) / 64 * 64;
+            nfin += (I.k * L + 63) / 64 * 64;
+        } else {
+            b->fin_begin[(size_t)oi] = nfin;
         }
         b->walkers += (uint64_t)I.k * (uint64_t)I.nwalk;
         b->inst.push_back(I);

@@ -114,30 +114,37 @@ __global__ __launch_bounds__(256) void k_walk_batched(BatchArgs a) {
 __global__ void k_reset_queue(unsigned long long *queue) { *queue = 0ull; }
 
 // Merge chunk partials of every entry that spans several chunks, for all
-// instances: instance i owns the finalize threads fin_begin[i] ..
-// fin_begin[i+1]-1 (a multiple of 64, so a wave never spans two instances),
-// fin_lanes(chunks) of them per entry, exactly as in k_finalize.
-__global__ __launch_bounds__(256) void k_finalize_batched(BatchArgs a) {
+// instances: instance i owns the finalize threads fin_begin[i] .. fin_begin[i]
+// + k * fin_lanes(chunks) - 1 (fin_begin[i] a multiple of 64 and of its lane
+// count, so that a wave never spans two instances and a group never two
+// blocks), fin_lanes(chunks) of them per entry, exactly as in k_finalize.
+__global__ __launch_bounds__(kFinLanesMax) void k_finalize_batched(BatchArgs a) {
+    __shared__ double lds[kFinLanesMax / WAVE][3];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.nfin) return;   // whole waves: nfin is a multiple of 64
-    int lo = 0, hi = a.ninst - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a.fin_begin[mid] <= t) lo = mid;
-        else hi = mid - 1;
+    const BatchInst *I = nullptr;
+    if (t < a.nfin) {   // whole waves: nfin is a multiple of 64
+        int lo = 0, hi = a.ninst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.fin_begin[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        I = &a.inst[lo];
     }
-    const BatchInst &I = a.inst[lo];
-    const uint32_t L = fin_lanes(I.chunks);
-    const int64_t local = t - a.fin_begin[lo];
+    // threads past the instances, or in the padding after one, join the block's
+    // barrier with empty groups of their wave's lane count
+    const int64_t chunks = I && I->chunks > 1 ? I->chunks : 0;
+    const uint32_t L = chunks ? fin_lanes(chunks) : 1;
+    const int64_t local = I ? t - a.fin_begin[I - a.inst] : 0;
     const int64_t e = local / L;
     const uint32_t sub = (uint32_t)(local - e * L);
-    const bool valid = e < I.k;
+    const bool valid = chunks && e < I->k;
     double n, mean, m2;
-    fin_merge(valid ? a.part + I.part_off + e * I.chunks * 3 : nullptr, valid ? I.chunks : 0, L,
-              sub, n, mean, m2);
+    fin_merge(valid ? a.part + I->part_off + e * chunks * 3 : nullptr, valid ? chunks : 0, L, sub, lds,
+              n, mean, m2);
     if (valid && sub == 0) {
-        I.est[e] = mean;
-        if (I.se) I.se[e] = n > 1.0 ? sqrt(m2 / (n - 1.0) / n) : 0.0;
+        I->est[e] = mean;
+        if (I->se) I->se[e] = n > 1.0 ? sqrt(m2 / (n - 1.0) / n) : 0.0;
     }
 }
 
@@ -176,7 +183,7 @@ hipError_t launch_batch(const BatchArgs &base, const BatchClass *classes, int nc
         if (e != hipSuccess) return e;
     }
     if (base.nfin > 0) {
-        const int fb = 256;
+        const int fb = (int)kFinLanesMax;
         hipLaunchKernelGGL(k_finalize_batched, dim3((unsigned)((base.nfin + fb - 1) / fb)), dim3(fb),
                            0, s, base);
         return hipGetLastError();

@@ -109,10 +109,13 @@ struct WalkArgs {
     uint32_t *flags;
     TraceOut trace;
     bool cond;                 // first-jump conditioning
-    // entries with their own walker counts (null otherwise): entry e owns tasks
-    // var_task[e] .. var_task[e+1]-1 (one entry per task) and var_nwalk[e] walkers
+    // entries with their own walker counts (null otherwise): entry e owns the
+    // chunk slots var_task[e] .. var_task[e+1]-1 and var_nwalk[e] walkers; a task
+    // takes `group` consecutive slots of the var_slots
     const int64_t *var_task;
     const int64_t *var_nwalk;
+    int64_t var_slots;
+    int64_t var_chunks_max;    // most chunks of one entry
 };
 
 // Forward (Algorithm 2) walks: one wave per chunk of kFwdChunk walker ordinals.
@@ -181,19 +184,20 @@ struct BatchArgs {
     int64_t nfin;                  // finalize threads (a multiple of 64)
 };
 
-// Walkers per task (an entry with more walkers is split into chunks merged in
-// chunk order), and the most entries one task may pack when they have fewer.
+// Walkers per task (an entry with more walkers is split into chunks merged in a
+// fixed order), and the most entries one task may pack when they have fewer.
 // A task keeps one value per walker that may jump in LDS, so FP64 tasks are
 // half as long as FP32 ones: both then fit five waves per SIMD.
 constexpr uint32_t kChunkMax = 1024;
 constexpr uint32_t kGroupMax = 64;
 constexpr uint32_t chunk_walkers(bool fp32) { return fp32 ? kChunkMax : kChunkMax / 2; }
 // Lanes that merge one entry's chunk partials: one for up to 8 chunks, then
-// doubling up to a whole wave, so that no lane merges more than about eight
-// partials in sequence.
+// doubling up to sixteen waves of one block, so that a lane merges at most
+// about eight partials, fetched together.
+constexpr uint32_t kFinLanesMax = 1024;
 __host__ __device__ constexpr uint32_t fin_lanes(int64_t chunks) {
     uint32_t l = 1;
-    while (l < 64 && (int64_t)l * 8 < chunks) l <<= 1;
+    while (l < kFinLanesMax && (int64_t)l * 8 < chunks) l <<= 1;
     return l;
 }
 // Largest LDS budget for hot rows (bytes per block).

@@ -15,7 +15,7 @@
 // position in the entry's ordinal-ordered list of jumpers; each entry's mean and sum of squared deviations come from a
 // two-pass sum over its slots in a fixed order plus the closed-form
 // contribution of its walkers that never jump, and entries spread over several
-// chunks are merged in chunk order (Chan, Golub, LeVeque).
+// chunks are merged in a fixed order (Chan, Golub, LeVeque).
 #include <math.h>
 
 #include "walk_task.hpp"
@@ -57,21 +57,22 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     for (int64_t task = wave_id; task < a.ntasks; task += nwaves) {
         int64_t e_first, c, chunks, nwalk, pbase;
         uint32_t G;
+        GroupOut out{a.est, a.se, a.part, 0, 0, 0};
         if (a.var_task) {
-            // entries with their own walker counts: one entry per task, entry e owns
-            // tasks var_task[e] .. var_task[e+1]-1 (the last e with var_task[e] <= task)
-            int64_t lo = 0, hi = a.k - 1;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi + 1) >> 1;
-                if (a.var_task[mid] <= task) lo = mid;
-                else hi = mid - 1;
-            }
-            e_first = lo;
-            c = task - a.var_task[lo];
-            chunks = a.var_task[lo + 1] - a.var_task[lo];
-            nwalk = a.var_nwalk[lo];
-            pbase = task;
-            G = 1;
+            // entries with their own walker counts: the task is `group` consecutive
+            // chunk slots, decoded per slot inside run_group
+            const int64_t s0 = task * (int64_t)a.group;
+            const int64_t left = a.var_slots - s0;
+            G = (uint32_t)(left < (int64_t)a.group ? left : (int64_t)a.group);
+            out.var_task = a.var_task;
+            out.var_nwalk = a.var_nwalk;
+            out.s0 = s0;
+            out.k = a.k;
+            c = 0;
+            chunks = 0;
+            nwalk = 0;
+            e_first = 0;
+            pbase = 0;
         } else {
             const int64_t grp = task / a.chunks;
             c = task - grp * a.chunks;
@@ -81,13 +82,15 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
             chunks = a.chunks;
             nwalk = a.nwalk;
             pbase = e_first * chunks + c;
+            out.e_first = e_first;
+            out.chunks = chunks;
+            out.pbase = pbase;
         }
         const int64_t wbase = c * (int64_t)a.chunk;
         const int64_t rem = nwalk - wbase;
         const uint32_t cnt = (uint32_t)(rem < (int64_t)a.chunk ? rem : (int64_t)a.chunk);
         TraceOut tr = a.trace;
         tr.base = wbase;
-        const GroupOut out{a.est, a.se, a.part, e_first, chunks, pbase};
         run_group<MODE, FP32, PROP, TRACE, LOC, COND, RESORT>(P, a.idx, a.n, G, (uint32_t)(a.w0 + wbase), cnt, tr,
                                            out, L, my_events, my_jumps, err);
     }
@@ -112,40 +115,41 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
 
 }  // namespace
 
-// Merge the chunk partials of every entry in chunk order: fin_lanes(chunks)
-// lanes per entry (the grid covers whole waves).
-__global__ __launch_bounds__(256) void k_finalize(int64_t k, int64_t chunks,
-                                                  const double *__restrict__ part,
-                                                  double *__restrict__ est, double *__restrict__ se) {
+// Merge the chunk partials of every entry in a fixed order: fin_lanes(chunks)
+// lanes per entry (the block is a multiple of them; every thread takes part).
+__global__ __launch_bounds__(kFinLanesMax) void k_finalize(int64_t k, int64_t chunks,
+                                                           const double *__restrict__ part,
+                                                           double *__restrict__ est, double *__restrict__ se) {
+    __shared__ double lds[kFinLanesMax / WAVE][3];
     const uint32_t L = fin_lanes(chunks);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t e = t / L;
     const uint32_t sub = (uint32_t)(t - e * L);
     const bool valid = e < k;
     double n, mean, m2;
-    fin_merge(valid ? part + e * chunks * 3 : nullptr, valid ? chunks : 0, L, sub, n, mean, m2);
+    fin_merge(valid ? part + e * chunks * 3 : nullptr, valid ? chunks : 0, L, sub, lds, n, mean, m2);
     if (valid && sub == 0) {
         est[e] = mean;
         if (se) se[e] = n > 1.0 ? sqrt(m2 / (n - 1.0) / n) : 0.0;
     }
 }
 
-// Chunk partials of entries with their own walker counts: one wave per entry,
-// fin_lanes(chunks of the entry) of its lanes merging exactly as k_finalize does
-// (so results equal those of a run with that walker count for every entry).
-__global__ __launch_bounds__(256) void k_finalize_var(int64_t k, const int64_t *__restrict__ var_task,
-                                                      const double *__restrict__ part,
-                                                      double *__restrict__ est, double *__restrict__ se) {
-    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-    const uint32_t lane = threadIdx.x & (WAVE - 1);
-    if (e >= k) return;                      // whole waves
+// Chunk partials of entries with their own walker counts (every entry, one chunk
+// or many, leaves partials): one block per entry, fin_lanes(chunks of the entry)
+// of its threads merging exactly as k_finalize does, and a single partial is
+// copied as it is, so results equal those of a run with that walker count.
+__global__ __launch_bounds__(kFinLanesMax) void k_finalize_var(int64_t k, const int64_t *__restrict__ var_task,
+                                                               const double *__restrict__ part,
+                                                               double *__restrict__ est, double *__restrict__ se) {
+    __shared__ double lds[kFinLanesMax / WAVE][3];
+    const int64_t e = blockIdx.x;
     const int64_t chunks = var_task[e + 1] - var_task[e];
-    if (chunks <= 1) return;                 // written by the walk itself
     const uint32_t L = fin_lanes(chunks);
+    const bool valid = threadIdx.x < L;   // threads past L form empty groups
     double n, mean, m2;
-    fin_merge(lane < L ? part + 3 * var_task[e] : nullptr, lane < L ? chunks : 0, L, lane % L, n,
-              mean, m2);
-    if (lane == 0) {
+    fin_merge(valid ? part + 3 * var_task[e] : nullptr, valid ? chunks : 0, L, threadIdx.x % L, lds,
+              n, mean, m2);
+    if (threadIdx.x == 0) {
         est[e] = mean;
         if (se) se[e] = n > 1.0 ? sqrt(m2 / (n - 1.0) / n) : 0.0;
     }
@@ -222,13 +226,16 @@ hipError_t launch_walk(const WalkArgs &a, int mode, bool fp32, bool prop, bool t
 hipError_t launch_finalize(const WalkArgs &a, hipStream_t s) {
     if (a.var_task) {
         if (a.k == 0) return hipSuccess;
-        hipLaunchKernelGGL(k_finalize_var, dim3((unsigned)((a.k * WAVE + 255) / 256)), dim3(256), 0, s,
-                           a.k, a.var_task, a.part, a.est, a.se);
+        if (a.k > 0x7FFFFFFF) return hipErrorInvalidValue;
+        const uint32_t L = fin_lanes(a.var_chunks_max);
+        hipLaunchKernelGGL(k_finalize_var, dim3((unsigned)a.k), dim3(L > WAVE ? L : WAVE), 0, s, a.k,
+                           a.var_task, a.part, a.est, a.se);
         return hipGetLastError();
     }
     if (a.chunks <= 1 || a.k == 0) return hipSuccess;
-    const int block = 256;
-    const int64_t threads = a.k * (int64_t)fin_lanes(a.chunks);
+    const uint32_t L = fin_lanes(a.chunks);
+    const int block = L > 256 ? (int)L : 256;
+    const int64_t threads = a.k * (int64_t)L;
     const int64_t grid = (threads + block - 1) / block;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)grid), dim3(block), 0, s, a.k, a.chunks, a.part,
                        a.est, a.se);

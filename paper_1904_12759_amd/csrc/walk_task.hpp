@@ -274,40 +274,66 @@ __device__ __forceinline__ uint64_t dpp_u64(uint64_t b) {
 }
 
 // Merge of one entry's chunk partials p[3c .. 3c+2] = (count, mean, M2),
-// c < chunks, by the L lanes sub = 0 .. L-1 of an aligned group: lane sub
-// merges a contiguous range of chunks in order, then lane sub takes in the
-// range of lane sub + off for off = 1, 2, 4, ..., so chunk order is kept at
-// every step.  The result is in sub-lane 0.  Every lane of the wave must call
-// it with the same L (p may be null when chunks is 0).
+// c < chunks, by the L lanes sub = 0 .. L-1 of a group aligned to L in the
+// block, in a fixed order: lane sub takes chunks sub, sub + L, sub + 2L, ...
+// (so that a wave's loads cover consecutive partials), eight at a time as a
+// pairwise tree whose result it merges into its running total; then lane sub
+// takes in the total of lane sub + off for off = 1, 2, 4, ... (across waves
+// through lds, one (count, mean, M2) per wave).  The result is in sub-lane 0.
+// Every thread of the block must call it (it holds a barrier), all lanes of a
+// wave with the same L, all lanes of a group with the same p and chunks (p
+// may be null when chunks is 0).
 __device__ __forceinline__ void fin_merge(const double *p, int64_t chunks, uint32_t L, uint32_t sub,
-                                          double &n, double &mean, double &m2) {
+                                          double (*lds)[3], double &n, double &mean, double &m2) {
     n = 0.0;
     mean = 0.0;
     m2 = 0.0;
-    const int64_t q = (chunks + L - 1) / L;
-    const int64_t c0 = (int64_t)sub * q;
-    const int64_t c1 = c0 + q < chunks ? c0 + q : chunks;
-    // partials fetched sixteen at a time, merged one by one in chunk order: the loads
-    // of a batch overlap instead of each waiting for the previous merge
-    constexpr int B = 16;
-    int64_t c = c0;
-    for (; c + B <= c1; c += B) {
+    // a lane's partials fetched together (past the end: its first chunk read again,
+    // in bounds, and taken as empty, which merges as a no-op), so that the loads
+    // overlap, and merged as a tree of depth three
+    constexpr int B = 8;
+    for (int64_t c = sub; c < chunks; c += (int64_t)B * L) {
         double bn[B], bm[B], bq[B];
 #pragma unroll
         for (int k = 0; k < B; ++k) {
-            bn[k] = p[3 * (c + k)];
-            bm[k] = p[3 * (c + k) + 1];
-            bq[k] = p[3 * (c + k) + 2];
+            const int64_t ck = c + (int64_t)k * L;
+            const bool in = ck < chunks;
+            const int64_t cl = in ? ck : c;
+            bn[k] = in ? p[3 * cl] : 0.0;
+            bm[k] = p[3 * cl + 1];
+            bq[k] = p[3 * cl + 2];
         }
 #pragma unroll
-        for (int k = 0; k < B; ++k) chan_merge(n, mean, m2, bn[k], bm[k], bq[k]);
+        for (int s = 1; s < B; s <<= 1)
+#pragma unroll
+            for (int k = 0; k < B; k += 2 * s) chan_merge(bn[k], bm[k], bq[k], bn[k + s], bm[k + s], bq[k + s]);
+        chan_merge(n, mean, m2, bn[0], bm[0], bq[0]);
     }
-    for (; c < c1; ++c) chan_merge(n, mean, m2, p[3 * c], p[3 * c + 1], p[3 * c + 2]);
-    for (uint32_t off = 1; off < L; off <<= 1) {
-        const double nb = __shfl_down(n, off, (int)L);
-        const double mb = __shfl_down(mean, off, (int)L);
-        const double qb = __shfl_down(m2, off, (int)L);
+    const uint32_t W = L < WAVE ? L : WAVE;
+    for (uint32_t off = 1; off < W; off <<= 1) {
+        const double nb = __shfl_down(n, off, (int)W);
+        const double mb = __shfl_down(mean, off, (int)W);
+        const double qb = __shfl_down(m2, off, (int)W);
         if ((sub & (2 * off - 1)) == 0) chan_merge(n, mean, m2, nb, mb, qb);
+    }
+    const uint32_t wave = threadIdx.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        lds[wave][0] = n;
+        lds[wave][1] = mean;
+        lds[wave][2] = m2;
+    }
+    __syncthreads();
+    if (L > WAVE && sub == 0 && chunks > 0) {
+        // the group's waves wave .. wave + L/64 - 1, merged pairwise in place (an
+        // empty group leaves lds alone: its waves may belong to other groups)
+        const uint32_t nw = L / WAVE;
+        for (uint32_t s = 1; s < nw; s <<= 1)
+            for (uint32_t k = 0; k < nw; k += 2 * s)
+                chan_merge(lds[wave + k][0], lds[wave + k][1], lds[wave + k][2], lds[wave + k + s][0],
+                           lds[wave + k + s][1], lds[wave + k + s][2]);
+        n = lds[wave][0];
+        mean = lds[wave][1];
+        m2 = lds[wave][2];
     }
 }
 
@@ -362,18 +388,25 @@ struct alignas(16) GroupLds {
     double K[kGroupMax];          // value of a walker that never leaves the start node
                                   // (first-jump conditioning: e^{-rt} times that value)
     uint32_t node[kGroupMax];     // start node of each entry (UINT32_MAX: out of range)
-    uint32_t n0[kGroupMax];       // walkers of each entry that never jump
-    uint32_t seg[kGroupMax + 1];  // entry g's jumpers are list[seg[g] .. seg[g+1])
+    uint32_t n0[kGroupMax];       // walkers of entry g that never jump | its walker count << 16
+    uint32_t ord0[kGroupMax];     // first walker ordinal of entry g's chunk
+    uint16_t seg[kGroupMax + 1];  // entry g's jumpers are list[seg[g] .. seg[g+1])
     uint16_t list[C];             // jumpers: (entry << 10) | ordinal, entry-major, ordinal order
     double q[COND ? kGroupMax : 1];  // first-jump conditioning: 1 - e^{-rt} of the start node
 };
 static_assert(kGroupMax <= 64 && kChunkMax <= 1024, "list codes are 6 + 10 bits");
 
 // Where a task's per-entry results go: entry e_first + g, one of `chunks` chunks.
+// With var_task set, the task's "entries" are the chunk slots s0 .. s0+G-1 of
+// entries with their own walker counts (slot s is chunk s - var_task[e] of the
+// entry e with var_task[e] <= s < var_task[e+1], of var_nwalk[e] walkers), and
+// every slot writes its partial to part[s].
 struct GroupOut {
     double *est, *se, *part;
     int64_t e_first, chunks;
     int64_t pbase;             // partial of entry e_first + g at this chunk: pbase + g * chunks
+    const int64_t *var_task = nullptr, *var_nwalk = nullptr;
+    int64_t s0 = 0, k = 0;
 };
 
 // Runs walkers ord0 .. ord0+cnt-1 of G entries on the calling wavefront and
@@ -413,10 +446,29 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
     ord0 = __builtin_amdgcn_readfirstlane(ord0);
     cnt = __builtin_amdgcn_readfirstlane(cnt);
 
-    // ---- per-entry setup, one lane per entry
+    constexpr uint32_t C = GroupLds<WT, COND>::C;
+
+    // ---- per-entry setup, one lane per entry (or per chunk slot)
     double e0 = 0.0;
     if (lane < (int)G) {
-        const int64_t e = out.e_first + lane;
+        int64_t e = out.e_first + lane;
+        uint32_t ordg = ord0, cntg = cnt;
+        if (out.var_task) {
+            const int64_t sl = out.s0 + lane;
+            int64_t lo = 0, hi = out.k - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (out.var_task[mid] <= sl) lo = mid;
+                else hi = mid - 1;
+            }
+            e = lo;
+            const int64_t c = sl - out.var_task[lo];
+            const int64_t rem = out.var_nwalk[lo] - c * (int64_t)C;
+            cntg = (uint32_t)(rem < (int64_t)C ? rem : (int64_t)C);
+            ordg = (uint32_t)(c * (int64_t)C);
+        }
+        L.ord0[lane] = ordg;
+        L.n0[lane] = cntg << 16;
         const int64_t nd = idx ? idx[e] : e;
         uint32_t node = 0xFFFFFFFFu;
         double K = 0.0;
@@ -450,7 +502,6 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         }
         L.node[lane] = node;
         L.K[lane] = K;
-        L.n0[lane] = 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -461,7 +512,6 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
     // the statistics of its entries) and the entry that did not fit is redone in
     // an empty pool, where it always fits (cnt <= C).  An entry's values and its
     // reduction do not depend on which session it falls in.
-    constexpr uint32_t C = GroupLds<WT, COND>::C;
     uint32_t nlist = 0, g_begin = 0;
     unsigned long long evs = 0, jus = 0;
     uint32_t g = 0;
@@ -469,6 +519,8 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         for (; g < G;) {
             // LDS values the whole wave shares, read into scalar registers
             const uint32_t node = __builtin_amdgcn_readfirstlane(L.node[g]);
+            const uint32_t cg = __builtin_amdgcn_readfirstlane(L.n0[g]) >> 16;   // its walkers
+            const uint32_t og = __builtin_amdgcn_readfirstlane(L.ord0[g]);      // first ordinal
             const double eg = readlane_f64(e0, (int)g);
             const uint32_t start = nlist;
             if (lane == 0) L.seg[g] = start;
@@ -479,11 +531,11 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             if (eg >= 1.5) {
                 // no exit rate: every walker holds until t, one holding interval each
                 if (lane == 0) {
-                    L.n0[g] = cnt;
-                    evs += cnt;
+                    L.n0[g] = cg | (cg << 16);
+                    evs += cg;
                 }
                 if constexpr (TRACE) {
-                    for (uint32_t w = lane; w < cnt; w += WAVE) {
+                    for (uint32_t w = lane; w < cg; w += WAVE) {
                         tr.x[tr.base + w] = (int32_t)node;
                         tr.ev[tr.base + w] = 1;
                         tr.ju[tr.base + w] = 0;
@@ -497,25 +549,25 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             uint32_t stay = 0;
             if (eg < 0.125) {
                 // most walkers leave: list them all
-                if (nlist + cnt > C) {
+                if (nlist + cg > C) {
                     fits = false;
                 } else {
-                    for (uint32_t w = lane; w < cnt; w += WAVE) L.list[nlist + w] = (uint16_t)((g << 10) | w);
-                    nlist += cnt;
+                    for (uint32_t w = lane; w < cg; w += WAVE) L.list[nlist + w] = (uint16_t)((g << 10) | w);
+                    nlist += cg;
                 }
             } else {
                 // U >= e0  <=>  m + 1 >= e0 2^53 (U = (m+1) 2^-53 exactly), i.e. m + 1 >= ceil(e0 2^53)
                 const uint64_t m_thr = (uint64_t)ceil(eg * 0x1p53);
-                for (uint32_t b = 0; b < cnt; b += WAVE) {
+                for (uint32_t b = 0; b < cg; b += WAVE) {
                     if (nlist + WAVE > C) {
                         fits = false;
                         break;
                     }
                     const uint32_t w = b + (uint32_t)lane;
-                    const bool valid = w < cnt;
+                    const bool valid = w < cg;
                     bool go = false;
                     if (valid) {
-                        const U4 o = philox(0u, ord0 + w, node, P.inst, P.key0, P.key1);
+                        const U4 o = philox(0u, og + w, node, P.inst, P.key0, P.key1);
                         const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
                         go = m + 1ull >= m_thr;
                     }
@@ -538,7 +590,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 break;
             }
             if (lane == 0) {
-                L.n0[g] = stay;
+                L.n0[g] = stay | (cg << 16);
                 evs += stay;
             }
             ++g;
@@ -553,6 +605,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         bool active = wl < nlist;
         uint32_t code = active ? L.list[wl] : 0u;
         uint32_t node = active ? L.node[code >> 10] : 0u;     // original id: RNG counter
+        uint32_t wb = active ? L.ord0[code >> 10] : 0u;       // first ordinal of its chunk
         uint32_t x = walk_id<LOC>(P, node);                      // walk id
         double s = 0.0;
         WT logw = (WT)0;
@@ -584,6 +637,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     active = __shfl((int)active, src, WAVE) != 0;
                     code = __shfl(code, src, WAVE);
                     node = __shfl(node, src, WAVE);
+                    wb = __shfl(wb, src, WAVE);
                     x = __shfl(x, src, WAVE);
                     s = __shfl(s, src, WAVE);
                     logw = __shfl(logw, src, WAVE);
@@ -605,7 +659,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     err |= F_WALK_LIMIT;
                     fin = true;
                 } else {
-                    const U4 o = philox(ev, ord0 + (code & 1023u), node, P.inst, P.key0, P.key1);
+                    const U4 o = philox(ev, wb + (code & 1023u), node, P.inst, P.key0, P.key1);
                     ++ev;
                     const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
                     double S;
@@ -685,6 +739,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 if (wl < nlist) {
                     code = L.list[wl];
                     node = L.node[code >> 10];
+                    wb = L.ord0[code >> 10];
                     x = walk_id<LOC>(P, node);
                     s = 0.0;
                     logw = (WT)0;
@@ -717,9 +772,10 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 count = 1.0;
             } else {
                 const double K = L.K[g];
-                const uint32_t n0 = __builtin_amdgcn_readfirstlane(L.n0[g]);
+                const uint32_t n0w = __builtin_amdgcn_readfirstlane(L.n0[g]);
+                const uint32_t n0 = n0w & 0xFFFFu;
                 const double nn0 = (double)n0;
-                count = (double)cnt;
+                count = (double)(n0w >> 16);
                 // K enters only through the walkers that stayed: without any, an
                 // infinite K (e^{td} v beyond the FP32 range, taken by no walker)
                 // must not turn 0 * K into NaN; with some, it is an overflow
@@ -741,7 +797,12 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 m2 = n0 ? s2 + nn0 * dk * dk : s2;
             }
             if (lane == 0) {
-                if (out.chunks == 1) {
+                if (out.var_task) {
+                    double *pp = out.part + (out.s0 + (int64_t)g) * 3;
+                    pp[0] = count;
+                    pp[1] = mean;
+                    pp[2] = m2;
+                } else if (out.chunks == 1) {
                     out.est[e] = mean;
                     if (out.se) out.se[e] = count > 1.0 ? sqrt(m2 / (count - 1.0) / count) : 0.0;
                 } else {

@@ -67,6 +67,27 @@ def test_batch_equals_separate_handles():
     assert st["events"] == st["walkers"] + st["jumps"]
 
 
+def test_batch_finalize_groups_of_several_waves():
+    """Instances whose entries span up to 4395 chunks (merged by 256 or 1024 lanes, so
+    across the waves of a block), between instances with one chunk and a few: every
+    instance bitwise equal to a separate handle."""
+    rng = np.random.default_rng(5)
+    a = wl.from_dense(refs.random_metzler(40, 0.2, 1, False))
+    specs = [(False, 1000, 3), (True, 70_000, 5), (False, 2_250_000, 2), (True, 300, 4),
+             (True, 4_500_000, 1), (False, 600_000, 3), (False, 9000, 2)]
+    inst = []
+    for i, (fp32, nw, k) in enumerate(specs):
+        inst.append(dict(rowptr=a.rowptr, col=a.col, val=a.val, t=0.6, v=rng.uniform(0.1, 1.0, a.n),
+                         mode=mc.EXACT, dt=0.05, fp32=fp32, n_walkers=nw, instance_id=300 + i,
+                         idx=rng.choice(a.n, k, replace=True).astype(np.int64)))
+    seed = 4
+    est, se = mc.MCBatch(inst, seed).run()
+    for i, d in enumerate(inst):
+        e1, s1 = _separate(d, a, seed)
+        assert torch.equal(est[i], e1), i
+        assert torch.equal(se[i], s1), i
+
+
 def test_batch_schedule_and_replay_do_not_change_results():
     b = mc.MCBatch([d for d, _ in INSTANCES], 7, walkers_per_block=128, blocks_per_cu=2)
     ref = [e.clone() for e in b.run()[0]]

@@ -521,8 +521,9 @@ def test_entries_multi_equals_per_count_runs(fp32):
     a = MATS["special40"]
     g = mc.MCExpmv(a.rowptr, a.col, a.val, 0.9, 77, fp32=fp32)
     v = np.random.default_rng(3).uniform(-1.0, 2.0, a.n)
-    idx = np.array([0, 5, 7, 11, 39, 3, 5], np.int64)
-    counts = np.array([1, 37, 512, 1025, 5000, 70_000, 2], np.int64)
+    idx = np.array([0, 5, 7, 11, 39, 3, 5, 7], np.int64)
+    # 1.5e6 walkers: 2930 (FP64) or 1465 (FP32) chunk partials, merged across waves
+    counts = np.array([1, 37, 512, 1025, 5000, 70_000, 2, 1_500_000], np.int64)
     est, se = g.entries_multi(v, idx, counts)
     for j, (i, m) in enumerate(zip(idx, counts)):
         e1, s1 = g.entries(v, [int(i)], int(m))
