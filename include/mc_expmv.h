@@ -104,8 +104,9 @@ typedef struct {
                                    need; entries with fewer walkers share a task up to
                                    this many (at most 64 entries).  0 (default):
                                    automatic, from 1024 to 8192 walkers aiming at
-                                   20480 tasks per run.  A tuning knob only: estimates
-                                   do not depend on it, bit for bit. */
+                                   20480 tasks per run, and no fewer than 5120 tasks
+                                   where there are that many entries.  A tuning knob
+                                   only: estimates do not depend on it, bit for bit. */
 } mc_expmv_opts;
 
 typedef struct {

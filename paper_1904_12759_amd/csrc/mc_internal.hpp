@@ -208,10 +208,14 @@ constexpr uint32_t kMaxHotBytes = 65536;
 // packing keeps the lanes of the full-walk phase busy.  task_walkers > 0 asks
 // for about that many walkers per task.  0 aims at kMinTasks tasks (four waves
 // per SIMD slot at five waves per SIMD on 256 CUs, so that the last waves do
-// not run alone) with between kTaskWalkersMin and kTaskWalkersMax walkers each.
+// not run alone) with between kTaskWalkersMin and kTaskWalkersMax walkers each,
+// but leaves at least kFullTasks tasks (five waves on every SIMD) where there
+// are that many entries: a small launch gains more from waves than from full
+// lanes.
 constexpr int64_t kTaskWalkersMin = 1024;
 constexpr int64_t kTaskWalkersMax = 8192;
 constexpr int64_t kMinTasks = 20480;
+constexpr int64_t kFullTasks = 5120;
 inline uint32_t group_size(int64_t nwalk, int64_t k, uint32_t task_walkers) {
     int64_t g;
     if (task_walkers) {
@@ -220,6 +224,7 @@ inline uint32_t group_size(int64_t nwalk, int64_t k, uint32_t task_walkers) {
         g = k / kMinTasks;
         if (g < kTaskWalkersMin / nwalk) g = kTaskWalkersMin / nwalk;
         if (g > kTaskWalkersMax / nwalk) g = kTaskWalkersMax / nwalk;
+        if (g > k / kFullTasks) g = k / kFullTasks;
     }
     if (g > (int64_t)kGroupMax) g = kGroupMax;
     return (uint32_t)(g < 1 ? 1 : g);
