@@ -105,8 +105,10 @@ typedef struct {
                                    this many (at most 64 entries).  0 (default):
                                    automatic, from 1024 to 8192 walkers aiming at
                                    20480 tasks per run, and no fewer than 5120 tasks
-                                   where there are that many entries.  A tuning knob
-                                   only: estimates do not depend on it, bit for bit. */
+                                   where there are that many entries (for
+                                   mc_expmv_entries_multi: chunks of walkers, at most
+                                   2048 walkers a task).  A tuning knob only:
+                                   estimates do not depend on it, bit for bit. */
 } mc_expmv_opts;
 
 typedef struct {

@@ -513,8 +513,10 @@ mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx
     a.chunk = (uint32_t)chunk;
     a.chunks = 1;
     // chunk slots packed per task like entries are (group_size with one chunk's
-    // walkers per slot)
+    // walkers per slot), automatically at most kSlotTaskWalkersMax walkers a task
     a.group = group_size(chunk, ntasks, h->opts.task_walkers);
+    if (!h->opts.task_walkers && a.group > kSlotTaskWalkersMax / chunk)
+        a.group = (uint32_t)(kSlotTaskWalkersMax / chunk);
     a.var_slots = ntasks;
     a.ntasks = (ntasks + a.group - 1) / a.group;
     a.est = est;

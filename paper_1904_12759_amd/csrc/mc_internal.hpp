@@ -216,6 +216,10 @@ constexpr int64_t kTaskWalkersMin = 1024;
 constexpr int64_t kTaskWalkersMax = 8192;
 constexpr int64_t kMinTasks = 20480;
 constexpr int64_t kFullTasks = 5120;
+// Chunk slots of entries with their own walker counts each fill an LDS session
+// already, so packing them only saves per-task work and lengthens the tail: the
+// automatic group stops at this many walkers per task.
+constexpr int64_t kSlotTaskWalkersMax = 2048;
 inline uint32_t group_size(int64_t nwalk, int64_t k, uint32_t task_walkers) {
     int64_t g;
     if (task_walkers) {
