@@ -109,6 +109,15 @@ typedef struct {
                                    mc_expmv_entries_multi: chunks of walkers, at most
                                    2048 walkers a task).  A tuning knob only:
                                    estimates do not depend on it, bit for bit. */
+    int32_t slot_rows;          /* 1: every alias slot also holds the row records and d of
+                                   its two destinations (64-byte slots, 4x the slot
+                                   memory), so that a jump is one gather instead of a
+                                   slot gather followed by the destination's row; pays
+                                   where the tables miss in cache.  -1: separate tables.
+                                   0 (default): 1 when rows, d and slots together exceed
+                                   64 MiB and the 64-byte slots (64 B per stored entry
+                                   of A) fit in 4 GiB.  Estimates do not depend on it,
+                                   bit for bit. */
 } mc_expmv_opts;
 
 typedef struct {
@@ -302,6 +311,7 @@ typedef struct {
     uint32_t max_events;        /* walk-length cap per walker; 0 = 2^24 */
     void *stream;               /* caller's hipStream_t, NULL = null stream: runs are
                                    ordered after prior work on it and before later work */
+    int32_t slot_rows;          /* as mc_expmv_opts.slot_rows, for every instance */
 } mc_batch_opts;
 
 typedef struct {

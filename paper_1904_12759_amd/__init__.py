@@ -53,6 +53,7 @@ class mc_expmv_opts(ctypes.Structure):
         ("cond_first_jump", ctypes.c_int32),
         ("cond_max_rt", ctypes.c_double),
         ("task_walkers", ctypes.c_uint32),
+        ("slot_rows", ctypes.c_int32),
     ]
 
 
@@ -82,7 +83,7 @@ class mc_batch_opts(ctypes.Structure):
         ("struct_size", ctypes.c_uint32), ("walkers_per_block", ctypes.c_uint32),
         ("blocks_per_cu", ctypes.c_uint32), ("group", ctypes.c_uint32),
         ("use_graph", ctypes.c_int32), ("max_events", ctypes.c_uint32),
-        ("stream", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p), ("slot_rows", ctypes.c_int32),
     ]
 
 
@@ -252,7 +253,7 @@ class MCExpmv:
                  max_events: int = 0, walkers_per_block: int = 64, relabel: int = 0,
                  lds_budget: int = 0, stream=None, cond: bool = False,
                  cond_max_rt: float = float("inf"), task_walkers: int = 0,
-                 resort_period: int = 0):
+                 resort_period: int = 0, slot_rows: int = 0):
         import torch
         lib_ = load()
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -268,7 +269,7 @@ class MCExpmv:
                             walkers_per_block=walkers_per_block, relabel=relabel,
                             lds_budget=lds_budget, stream=stream, cond_first_jump=int(cond),
                             cond_max_rt=float(cond_max_rt), task_walkers=int(task_walkers),
-                            resort_period=int(resort_period))
+                            resort_period=int(resort_period), slot_rows=int(slot_rows))
         h = ctypes.c_void_p()
         torch.cuda.current_stream().synchronize()
         _check(lib_.mc_expmv_create(ctypes.byref(h), rp.numel() - 1, cl.numel(), _ptr(rp),
@@ -497,7 +498,7 @@ class MCBatch:
 
     def __init__(self, instances, seed: int, walkers_per_block: int = 0,
                  blocks_per_cu: int = 0, group: int = 0, use_graph: bool = True,
-                 max_events: int = 0, stream=None):
+                 max_events: int = 0, stream=None, slot_rows: int = 0):
         import torch
         lib_ = load()
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -542,6 +543,7 @@ class MCBatch:
         o.walkers_per_block, o.blocks_per_cu, o.group = walkers_per_block, blocks_per_cu, group
         o.use_graph = 1 if use_graph else 0
         o.max_events = max_events
+        o.slot_rows = int(slot_rows)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         o.stream = stream

@@ -28,6 +28,7 @@ struct mc_expmv_s {
     double *val = nullptr;
     Tables plain, prop;
     bool has_prop = false;
+    bool use_fat = false;                // 64-byte slots for every table set
     uint32_t *flags = nullptr;           // latched device errors
     uint32_t *flag_host = nullptr;       // pinned copy of *flags, read by mc_expmv_sync
     unsigned long long *counters = nullptr;
@@ -104,6 +105,7 @@ void free_tables(Tables &tb) {
     (void)hipFree(tb.wrows);
     (void)hipFree(tb.wd64);
     (void)hipFree(tb.wd32);
+    (void)hipFree(tb.fat);
     tb = Tables{};
 }
 
@@ -187,7 +189,19 @@ mc_status check_opts(const mc_expmv_opts &o) {
     if (o.lds_budget != 0 && (!o.relabel || o.lds_budget > kMaxHotBytes)) return MC_ERR_INVALID_ARG;
     if (o.cond_first_jump != 0 && o.cond_first_jump != 1) return MC_ERR_INVALID_ARG;
     if (!(o.cond_max_rt >= 0.0)) return MC_ERR_INVALID_ARG;
+    if (o.slot_rows < -1 || o.slot_rows > 1) return MC_ERR_INVALID_ARG;
     return MC_OK;
+}
+
+// 64-byte slots for a finished table set, when the handle uses them
+mc_status fat_tables(mc_expmv_s *h, Tables &tb) {
+    if (!h->use_fat) return MC_OK;
+    hipError_t e = dalloc(&tb.fat, h->nnz);
+    if (e == hipSuccess)
+        e = launch_fat_slots(h->n, h->nnz, tb, h->perm != nullptr, h->opts.weight_prec == MC_FP32,
+                             h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return from_hip(e);
 }
 
 void fill_inst(const mc_expmv_s *h, const void *v, bool prop, InstArgs &P) {
@@ -198,6 +212,7 @@ void fill_inst(const mc_expmv_s *h, const void *v, bool prop, InstArgs &P) {
     P.d32 = rl ? tb.wd32 : tb.d32;
     P.slots = tb.slots;
     P.corr = prop ? tb.corr : nullptr;
+    P.fat = tb.fat;
     P.v = v;
     P.perm = h->perm;
     P.inv = h->inv;
@@ -296,6 +311,7 @@ void mc_expmv_default_opts(mc_expmv_opts *o) {
     o->cond_first_jump = 0;
     o->cond_max_rt = INFINITY;
     o->task_walkers = 0;
+    o->slot_rows = 0;
 }
 
 const char *mc_expmv_status_string(mc_status s) {
@@ -419,8 +435,16 @@ mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t
         return MC_ERR_INVALID_ARG;
     }
     CREATE_TRY(alloc_tables(h->plain, n, nnz, false));
+    {
+        const int64_t table_bytes = n * (int64_t)(sizeof(RowRec) + sizeof(double)) +
+                                    nnz * (int64_t)sizeof(SlotRec);
+        const int64_t fat_bytes = nnz * (int64_t)sizeof(FatSlot);
+        h->use_fat = o.slot_rows == 1 || (o.slot_rows == 0 && table_bytes > kFatAutoBytes &&
+                                          fat_bytes <= kFatAutoMaxBytes);
+    }
     st = build_tables(h, nullptr, h->plain);
     if (st == MC_OK && o.relabel) st = relabel_tables(h, h->plain, true);
+    if (st == MC_OK) st = fat_tables(h, h->plain);
     if (st != MC_OK) {
         mc_expmv_destroy(h);
         return st;
@@ -586,6 +610,7 @@ mc_status mc_expmv_set_proposal(mc_expmv_t h, const float *edge_bias) {
     HIP_TRY(alloc_tables(h->prop, h->n, h->nnz, true));
     mc_status st = build_tables(h, edge_bias, h->prop);
     if (st == MC_OK && h->perm) st = relabel_tables(h, h->prop, false);
+    if (st == MC_OK) st = fat_tables(h, h->prop);
     if (st != MC_OK) {
         free_tables(h->prop);
         return st;
@@ -909,6 +934,7 @@ void mc_batch_default_opts(mc_batch_opts *o) {
     o->use_graph = 1;
     o->max_events = 0;
     o->stream = nullptr;
+    o->slot_rows = 0;
 }
 
 void mc_expmv_batch_destroy(mc_batch_t b) { batch_free(b); }
@@ -927,6 +953,7 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
     const uint32_t wpb = o.walkers_per_block;
     if (wpb != 0 && wpb != 64 && wpb != 128 && wpb != 256) return MC_ERR_INVALID_ARG;
     if (o.blocks_per_cu > 64) return MC_ERR_INVALID_ARG;
+    if (o.slot_rows < -1 || o.slot_rows > 1) return MC_ERR_INVALID_ARG;
     for (int i = 0; i < n_inst; ++i) {
         const mc_instance_desc &d = desc[i];
         if (!d.v || d.n_walkers < 1 || d.n_walkers > 0xFFFFFFFFll) return MC_ERR_INVALID_ARG;
@@ -986,6 +1013,7 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
         io.instance_id = d.instance_id;
         io.max_events = o.max_events;
         io.stream = b->stream;
+        io.slot_rows = o.slot_rows;
         mc_expmv_t h = nullptr;
         mc_status st = mc_expmv_create(&h, d.n, d.nnz, d.rowptr, d.col, d.val, d.t, seed, &io);
         if (st != MC_OK) {

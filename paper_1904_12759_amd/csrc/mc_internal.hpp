@@ -29,6 +29,25 @@ struct alignas(16) SlotRec {
     uint32_t aslot;
 };
 
+// Alias slot with its two destinations' row records and d values, 64 bytes
+// (one aligned cache-line half): a jump then needs one gather instead of a slot
+// gather followed by the destination's row and d gathers, which halves the
+// chain of dependent loads per event where the tables miss in cache.  ds/da
+// hold the weight precision's d exactly (a float widened to double in FP32
+// mode).  Built from the final (walk-order) tables, so values equal theirs.
+struct alignas(64) FatSlot {
+    SlotRec s;
+    RowRec rs, ra;     // rows of s.self and s.alias
+    double ds, da;     // d of s.self and s.alias
+};
+// Automatic choice (opts.slot_rows == 0): 64-byte slots when the row, d and slot
+// tables together exceed kFatAutoBytes, about the size past which they stop
+// being cache resident, and the 64-byte slots take at most kFatAutoMaxBytes
+// (larger tables, such as those of 3-D grids, come with gathers that stay
+// near each other, where the 4x slot memory buys nothing).
+constexpr int64_t kFatAutoBytes = 64ll << 20;
+constexpr int64_t kFatAutoMaxBytes = 4ll << 30;
+
 // One set of walk tables (plain, or the tilted proposal).
 struct Tables {
     RowRec *rows = nullptr;    // [n]
@@ -42,6 +61,7 @@ struct Tables {
     RowRec *wrows = nullptr;
     double *wd64 = nullptr;
     float *wd32 = nullptr;
+    FatSlot *fat = nullptr;    // [nnz] 64-byte slots of the walk-order tables, or null
 };
 
 // Error flags latched on the device (bit i = status code i).
@@ -67,6 +87,7 @@ struct InstArgs {
     const float *d32;
     const SlotRec *slots;
     const float2 *corr;        // non-null only for the tilted walk
+    const FatSlot *fat;        // non-null: jumps read these instead of slots + rows + d
     const void *v;             // double* (FP64 weights) or float* (FP32 weights)
     const uint32_t *perm;      // relabel: original node -> walk id (null: identity)
     const uint32_t *inv;       // relabel: walk id -> original node (null: identity)
@@ -300,6 +321,10 @@ hipError_t launch_relabel_apply(int64_t n, const int64_t *rowptr, const uint32_t
 hipError_t sort_pairs_u64(void *temp, size_t &temp_bytes, const unsigned long long *kin,
                           unsigned long long *kout, const uint32_t *vin, uint32_t *vout, int64_t n,
                           hipStream_t s);
+
+// 64-byte slots of a finished table set (walk_order: the relabelled copies)
+hipError_t launch_fat_slots(int64_t n, int64_t nnz, const Tables &tb, bool walk_order, bool fp32,
+                            hipStream_t s);
 
 // setup kernels (setup.hip)
 hipError_t launch_check_rowptr(int64_t n, int64_t nnz, const int64_t *rowptr, uint32_t *flags,

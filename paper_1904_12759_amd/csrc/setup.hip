@@ -179,7 +179,39 @@ __global__ void k_relabel_slots(int64_t n, const int64_t *__restrict__ rowptr,
     }
 }
 
+// 64-byte slots from the final tables (rows, d and slots in walk order): slot
+// position j gets slot j and the rows and d of its two destinations.  Positions
+// that hold no slot (the diagonal, zero entries) may hold any bits; they get
+// empty rows unless both destinations are in range, and no walk reads them.
+__global__ void k_fat_slots(int64_t nnz, int64_t n, const SlotRec *__restrict__ slots,
+                            const RowRec *__restrict__ rows, const double *__restrict__ d64,
+                            const float *__restrict__ d32, int fp32, FatSlot *__restrict__ fat) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nnz) return;
+    FatSlot f{};
+    f.s = slots[j];
+    const uint32_t a = (uint32_t)f.s.self, b = (uint32_t)f.s.alias;
+    if (a < (uint64_t)n && b < (uint64_t)n) {
+        f.rs = rows[a];
+        f.ra = rows[b];
+        f.ds = fp32 ? (double)d32[a] : d64[a];
+        f.da = fp32 ? (double)d32[b] : d64[b];
+    }
+    fat[j] = f;
+}
+
 }  // namespace
+
+hipError_t launch_fat_slots(int64_t n, int64_t nnz, const Tables &tb, bool walk_order, bool fp32,
+                            hipStream_t s) {
+    if (nnz == 0) return hipSuccess;
+    const int64_t grid = (nnz + 255) / 256;
+    if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fat_slots, dim3((unsigned)grid), dim3(256), 0, s, nnz, n, tb.slots,
+                       walk_order ? tb.wrows : tb.rows, walk_order ? tb.wd64 : tb.d64,
+                       walk_order ? tb.wd32 : tb.d32, fp32 ? 1 : 0, tb.fat);
+    return hipGetLastError();
+}
 
 hipError_t launch_relabel_keys(int64_t n, const double *r, unsigned long long *keys, uint32_t *vals,
                                hipStream_t s) {

@@ -691,19 +691,32 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                         }
                         s = sn;
                         const uint32_t sl = (uint32_t)(((uint64_t)o.z * (uint64_t)deg) >> 32);
-                        const SlotRec q = P.slots[begin + sl];
-                        const bool keep = o.w < q.thr;
-                        x = (uint32_t)(keep ? q.self : q.alias);
+                        const uint32_t js = begin + sl;
+                        bool keep;
+                        if (P.fat) {
+                            // one gather: the slot with its destinations' rows and d
+                            const FatSlot q = P.fat[js];
+                            keep = o.w < q.s.thr;
+                            x = (uint32_t)(keep ? q.s.self : q.s.alias);
+                            inv_r = keep ? q.rs.inv_r : q.ra.inv_r;
+                            deg = keep ? q.rs.deg : q.ra.deg;
+                            begin = keep ? q.rs.begin : q.ra.begin;
+                            dx = (WT)(keep ? q.ds : q.da);
+                        } else {
+                            const SlotRec q = P.slots[js];
+                            keep = o.w < q.thr;
+                            x = (uint32_t)(keep ? q.self : q.alias);
+                            const RowRec rr = row_at<LOC>(P, x);
+                            inv_r = rr.inv_r;
+                            deg = rr.deg;
+                            begin = rr.begin;
+                            dx = d_at<FP32, LOC>(P, x);
+                        }
                         if constexpr (PROP) {
-                            const float2 cr = P.corr[begin + sl];
+                            const float2 cr = P.corr[js];
                             logw = logw + (WT)(keep ? cr.x : cr.y);
                         }
                         ++ju;
-                        const RowRec rr = row_at<LOC>(P, x);
-                        inv_r = rr.inv_r;
-                        deg = rr.deg;
-                        begin = rr.begin;
-                        dx = d_at<FP32, LOC>(P, x);
                     } else {
                         fin = true;
                     }

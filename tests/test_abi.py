@@ -46,7 +46,10 @@ def test_status_strings_and_default_opts():
     o = pkg.default_opts()
     assert o.struct_size == ctypes.sizeof(pkg.mc_expmv_opts)
     assert o.mode == pkg.EXACT and o.walkers_per_block == 64 and o.dt == 0.03125
-    assert o.task_walkers == 0
+    assert o.task_walkers == 0 and o.slot_rows == 0
+    b = pkg.mc_batch_opts()
+    lib.mc_batch_default_opts(ctypes.byref(b))
+    assert b.struct_size == ctypes.sizeof(pkg.mc_batch_opts) and b.slot_rows == 0
 
 
 def test_create_rejects_bad_host_arguments_without_gpu():

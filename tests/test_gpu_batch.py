@@ -88,6 +88,17 @@ def test_batch_finalize_groups_of_several_waves():
         assert torch.equal(se[i], s1), i
 
 
+def test_batch_with_slot_rows_equals_separate_handles():
+    """Every instance with 64-byte slots (slot_rows=1 for the batch) bitwise equal to a
+    separate handle with the separate tables."""
+    seed = 99
+    est, se = mc.MCBatch([d for d, _ in INSTANCES], seed, slot_rows=1).run()
+    for i, (d, a) in enumerate(INSTANCES):
+        e1, s1 = _separate(d, a, seed)
+        assert torch.equal(est[i], e1), i
+        assert torch.equal(se[i], s1), i
+
+
 def test_batch_schedule_and_replay_do_not_change_results():
     b = mc.MCBatch([d for d, _ in INSTANCES], 7, walkers_per_block=128, blocks_per_cu=2)
     ref = [e.clone() for e in b.run()[0]]

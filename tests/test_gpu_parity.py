@@ -508,6 +508,86 @@ def test_relabel_with_proposal_matches_plain_layout():
     assert torch.equal(e0, e1)
 
 
+# ------------------------------------------------------- 64-byte slots
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("mode", [mc.EXACT, mc.STRANG, mc.LIE])
+def test_slot_rows_are_bitwise_invisible(fp32, mode):
+    """Slots that carry their destinations' rows and d (slot_rows=1) give every path,
+    estimate and standard error bit for bit as the separate tables do, and the paths
+    match the oracle's."""
+    for name in ("special40", "nonsym48", "grid2d_16"):
+        a = MATS[name]
+        v = np.random.default_rng(6).uniform(-0.5, 1.5, a.n)
+        g0 = mc.MCExpmv(a.rowptr, a.col, a.val, 1.1, 17, mode=mode, fp32=fp32, slot_rows=-1)
+        g1 = mc.MCExpmv(a.rowptr, a.col, a.val, 1.1, 17, mode=mode, fp32=fp32, slot_rows=1)
+        e0, s0 = g0.full(v, 700)
+        e1, s1 = g1.full(v, 700)
+        assert torch.equal(e0, e1) and torch.equal(s0, s1), name
+        idx = np.array([0, 3, a.n - 1, 3], np.int64)
+        counts = np.array([5, 3000, 70_000, 1], np.int64)
+        m0 = g0.entries_multi(v, idx, counts)
+        m1 = g1.entries_multi(v, idx, counts)
+        assert torch.equal(m0[0], m1[0]) and torch.equal(m0[1], m1[1]), name
+        t0 = g0.trace(v, 3, 0, 1500)
+        t1 = g1.trace(v, 3, 0, 1500)
+        for x, y in zip(t0, t1):
+            assert np.array_equal(x, y), name
+    o = Oracle(a.rowptr, a.col, a.val, 1.1, 17, mode=mode, dt=0.03125)
+    xo, eo, jo, fo, _ = o.trace(_v_for(v, fp32), 3, 0, 1500)
+    assert np.array_equal(t1[0], xo) and np.array_equal(t1[1], eo) and np.array_equal(t1[2], jo)
+    assert _close(t1[3], fo, RTOL32 if fp32 else RTOL64)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_slot_rows_with_relabel_hot_rows_resort_cond_and_proposal(fp32):
+    """64-byte slots built from relabelled tables (hot rows in LDS, wave re-sort), with
+    first-jump conditioning and with a tilted proposal: bitwise the plain layout."""
+    w = wl.config_ba_full(n=20_000)
+    a = w.a
+    v = np.random.default_rng(3).uniform(0.5, 1.5, a.n)
+    idx = np.array([0, 1, 5, 17, a.n - 1, 4000], np.int64)
+    bias = np.random.default_rng(4).normal(0, 0.4, a.nnz).astype(np.float32)
+    base = mc.MCExpmv(a.rowptr, a.col, a.val, 2.0, 31, fp32=fp32, slot_rows=-1)
+    ref = [base.full(v, 300), base.entries(v, idx, 3000)]
+    cbase = mc.MCExpmv(a.rowptr, a.col, a.val, 2.0, 31, fp32=fp32, cond=True, slot_rows=-1)
+    cref = cbase.full(v, 300)
+    base.set_proposal(bias)
+    pref = base.full(v, 300)
+    for kw in (dict(), dict(relabel=1, lds_budget=32768), dict(relabel=1, resort_period=2)):
+        g = mc.MCExpmv(a.rowptr, a.col, a.val, 2.0, 31, fp32=fp32, slot_rows=1, **kw)
+        for (ea, sa), (eb, sb) in zip(ref, [g.full(v, 300), g.entries(v, idx, 3000)]):
+            assert torch.equal(ea, eb) and torch.equal(sa, sb), kw
+        gc = mc.MCExpmv(a.rowptr, a.col, a.val, 2.0, 31, fp32=fp32, cond=True, slot_rows=1, **kw)
+        ec, sc = gc.full(v, 300)
+        assert torch.equal(cref[0], ec) and torch.equal(cref[1], sc), kw
+        g.set_proposal(bias)
+        ep, sp = g.full(v, 300)
+        assert torch.equal(pref[0], ep) and torch.equal(pref[1], sp), kw
+
+
+def test_slot_rows_automatic_on_large_tables():
+    """ER n = 1e6 (tables of 152 MB, above the 64 MiB threshold, so the default picks
+    64-byte slots): entries and a trace bitwise equal to the separate tables."""
+    a = wl.er_graph(1_000_000, 8.0, 5)
+    lam = wl.lambda_max(a)
+    a = wl.scaled(a, 1.0 / lam)
+    v = np.random.default_rng(2).random(a.n)
+    idx = np.random.default_rng(3).choice(a.n, 64).astype(np.int64)
+    g0 = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 9, slot_rows=-1)
+    g1 = mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 9)
+    e0, s0 = g0.entries(v, idx, 5000)
+    e1, s1 = g1.entries(v, idx, 5000)
+    assert torch.equal(e0, e1) and torch.equal(s0, s1)
+    for x, y in zip(g0.trace(v, int(idx[0]), 0, 3000), g1.trace(v, int(idx[0]), 0, 3000)):
+        assert np.array_equal(x, y)
+
+
+def test_slot_rows_rejects_bad_value():
+    a = MATS["sym48"]
+    with pytest.raises(mc.MCError):
+        mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 1, slot_rows=2)
+
+
 def test_lds_budget_requires_relabel():
     a = MATS["sym48"]
     with pytest.raises(mc.MCError):
