@@ -53,7 +53,8 @@ __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, i
     const uint32_t cnt = (uint32_t)(rem < chunk ? rem : chunk);
     const GroupOut out{I.est, I.se, a.part + I.part_off, e_first, I.chunks, e_first * I.chunks + c};
     TraceOut none;
-    run_group<MODE, FP32, false, false, false, false>(
+    // instances of one class may differ in their slot layout: FAT = 2 tests I.P.fat
+    run_group<MODE, FP32, false, false, false, false, false, 2>(
         I.P, I.idx, I.n, G, (uint32_t)wbase, cnt, none, out,
         *reinterpret_cast<GroupLds<typename WeightT<FP32>::T> *>(lds), my_events, my_jumps, err);
 }

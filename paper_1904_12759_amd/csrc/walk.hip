@@ -28,7 +28,7 @@ namespace {
 // jump totals are reduced per block and written to counters[2*block] without
 // atomics (same-address atomics from every wave serialise across the chip).
 // Dynamic LDS: one GroupLds per wave.
-template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND, bool RESORT>
+template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND, bool RESORT, int FAT>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     using WT = typename WeightT<FP32>::T;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
         const uint32_t cnt = (uint32_t)(rem < (int64_t)a.chunk ? rem : (int64_t)a.chunk);
         TraceOut tr = a.trace;
         tr.base = wbase;
-        run_group<MODE, FP32, PROP, TRACE, LOC, COND, RESORT>(P, a.idx, a.n, G, (uint32_t)(a.w0 + wbase), cnt, tr,
+        run_group<MODE, FP32, PROP, TRACE, LOC, COND, RESORT, FAT>(P, a.idx, a.n, G, (uint32_t)(a.w0 + wbase), cnt, tr,
                                            out, L, my_events, my_jumps, err);
     }
     for (int off = 1; off < WAVE; off <<= 1) err |= __shfl_xor(err, off, WAVE);
@@ -165,6 +165,21 @@ int walk_grid(int64_t ntasks, int block) {
     return (int)grid;
 }
 
+template <int MODE, bool FP32, bool PROP, bool TRACE, int FAT>
+void launch_shape(const WalkArgs &a, dim3 grid, int block, size_t lds, hipStream_t s) {
+    // the wave re-sort has kernels of its own, so that it costs the others no registers
+    if (a.P.perm && a.P.resort) {
+        if (a.cond) hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, true, true, FAT>), grid, dim3(block), lds, s, a);
+        else hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, false, true, FAT>), grid, dim3(block), lds, s, a);
+    } else if (a.P.perm) {
+        if (a.cond) hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, true, false, FAT>), grid, dim3(block), lds, s, a);
+        else hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, false, false, FAT>), grid, dim3(block), lds, s, a);
+    } else {
+        if (a.cond) hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, false, true, false, FAT>), grid, dim3(block), lds, s, a);
+        else hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, false, false, false, FAT>), grid, dim3(block), lds, s, a);
+    }
+}
+
 template <int MODE, bool FP32, bool PROP, bool TRACE>
 hipError_t launch_t(const WalkArgs &a, int block, hipStream_t s) {
     using WT = typename WeightT<FP32>::T;
@@ -175,17 +190,11 @@ hipError_t launch_t(const WalkArgs &a, int block, hipStream_t s) {
     const size_t lds = (size_t)(block / WAVE) * task_lds +
                        (size_t)a.P.hot * (sizeof(RowRec) + sizeof(WT));
     const dim3 grid((unsigned)walk_grid(a.ntasks, block));
-    // the wave re-sort has kernels of its own, so that it costs the others no registers
-    if (a.P.perm && a.P.resort) {
-        if (a.cond) hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, true, true>), grid, dim3(block), lds, s, a);
-        else hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, false, true>), grid, dim3(block), lds, s, a);
-    } else if (a.P.perm) {
-        if (a.cond) hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, true, false>), grid, dim3(block), lds, s, a);
-        else hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, false, false>), grid, dim3(block), lds, s, a);
-    } else {
-        if (a.cond) hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, false, true, false>), grid, dim3(block), lds, s, a);
-        else hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, false, false, false>), grid, dim3(block), lds, s, a);
-    }
+    // 64-byte slots get kernels of their own, so that the others keep their code;
+    // the per-walker trace (parity checks only) tests the pointer instead
+    if constexpr (TRACE) launch_shape<MODE, FP32, PROP, TRACE, 2>(a, grid, block, lds, s);
+    else if (a.P.fat) launch_shape<MODE, FP32, PROP, TRACE, 1>(a, grid, block, lds, s);
+    else launch_shape<MODE, FP32, PROP, TRACE, 0>(a, grid, block, lds, s);
     return hipGetLastError();
 }
 

@@ -187,6 +187,38 @@ __device__ __forceinline__ typename WeightT<FP32>::T d_at(const InstArgs &P, uin
     return load_d<FP32>(P, x);
 }
 
+// A jump from slot js with alias word w: the destination x and its row and d.
+// jump_sep reads the slot, then the destination's row and d; jump_fat reads the
+// 64-byte slot that holds both destinations' rows and d.  Same values either way.
+template <bool FP32, bool LOC>
+__device__ __forceinline__ bool jump_sep(const InstArgs &P, uint32_t js, uint32_t w, uint32_t &x,
+                                         double &inv_r, uint32_t &deg, uint32_t &begin,
+                                         typename WeightT<FP32>::T &dx) {
+    const SlotRec q = P.slots[js];
+    const bool keep = w < q.thr;
+    x = (uint32_t)(keep ? q.self : q.alias);
+    const RowRec rr = row_at<LOC>(P, x);
+    inv_r = rr.inv_r;
+    deg = rr.deg;
+    begin = rr.begin;
+    dx = d_at<FP32, LOC>(P, x);
+    return keep;
+}
+
+template <bool FP32>
+__device__ __forceinline__ bool jump_fat(const InstArgs &P, uint32_t js, uint32_t w, uint32_t &x,
+                                         double &inv_r, uint32_t &deg, uint32_t &begin,
+                                         typename WeightT<FP32>::T &dx) {
+    const FatSlot q = P.fat[js];
+    const bool keep = w < q.s.thr;
+    x = (uint32_t)(keep ? q.s.self : q.s.alias);
+    inv_r = keep ? q.rs.inv_r : q.ra.inv_r;
+    deg = keep ? q.rs.deg : q.ra.deg;
+    begin = keep ? q.rs.begin : q.ra.begin;
+    dx = (typename WeightT<FP32>::T)(keep ? q.ds : q.da);
+    return keep;
+}
+
 // Walk id of an original node, and back (identity without relabelling).
 template <bool LOC>
 __device__ __forceinline__ uint32_t walk_id(const InstArgs &P, uint32_t node) {
@@ -429,7 +461,8 @@ struct GroupOut {
 // listed walkers do not all fit the list at once, phases 1 and 2 alternate in
 // sessions (see below); with RESORT (relabelled tables only) the wave re-sorts
 // its walkers by current node every P.resort events.
-template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND, bool RESORT = false>
+template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND, bool RESORT = false,
+          int FAT = 0>
 __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx, int64_t n,
                                           uint32_t G, uint32_t ord0, uint32_t cnt,
                                           const TraceOut &tr, const GroupOut &out,
@@ -692,26 +725,15 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                         s = sn;
                         const uint32_t sl = (uint32_t)(((uint64_t)o.z * (uint64_t)deg) >> 32);
                         const uint32_t js = begin + sl;
+                        // FAT: 0 separate tables, 1 64-byte slots, 2 whichever P holds
                         bool keep;
-                        if (P.fat) {
-                            // one gather: the slot with its destinations' rows and d
-                            const FatSlot q = P.fat[js];
-                            keep = o.w < q.s.thr;
-                            x = (uint32_t)(keep ? q.s.self : q.s.alias);
-                            inv_r = keep ? q.rs.inv_r : q.ra.inv_r;
-                            deg = keep ? q.rs.deg : q.ra.deg;
-                            begin = keep ? q.rs.begin : q.ra.begin;
-                            dx = (WT)(keep ? q.ds : q.da);
-                        } else {
-                            const SlotRec q = P.slots[js];
-                            keep = o.w < q.thr;
-                            x = (uint32_t)(keep ? q.self : q.alias);
-                            const RowRec rr = row_at<LOC>(P, x);
-                            inv_r = rr.inv_r;
-                            deg = rr.deg;
-                            begin = rr.begin;
-                            dx = d_at<FP32, LOC>(P, x);
-                        }
+                        if constexpr (FAT == 1)
+                            keep = jump_fat<FP32>(P, js, o.w, x, inv_r, deg, begin, dx);
+                        else if constexpr (FAT == 2)
+                            keep = P.fat ? jump_fat<FP32>(P, js, o.w, x, inv_r, deg, begin, dx)
+                                         : jump_sep<FP32, LOC>(P, js, o.w, x, inv_r, deg, begin, dx);
+                        else
+                            keep = jump_sep<FP32, LOC>(P, js, o.w, x, inv_r, deg, begin, dx);
                         if constexpr (PROP) {
                             const float2 cr = P.corr[js];
                             logw = logw + (WT)(keep ? cr.x : cr.y);
