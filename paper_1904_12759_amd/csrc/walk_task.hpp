@@ -461,6 +461,30 @@ struct GroupOut {
 // listed walkers do not all fit the list at once, phases 1 and 2 alternate in
 // sessions (see below); with RESORT (relabelled tables only) the wave re-sorts
 // its walkers by current node every P.resort events.
+// Entries whose listed walkers are summed by one lane rather than the wave.
+constexpr uint32_t kShortSeg = 16;
+
+// An entry's statistics: the estimate and standard error, or its (count, mean,
+// M2) partial when it spans several chunks or has its own walker count.
+__device__ __forceinline__ void put_stats(const GroupOut &out, uint32_t g, double mean, double m2,
+                                          double count) {
+    if (out.var_task) {
+        double *pp = out.part + (out.s0 + (int64_t)g) * 3;
+        pp[0] = count;
+        pp[1] = mean;
+        pp[2] = m2;
+    } else if (out.chunks == 1) {
+        const int64_t e = out.e_first + g;
+        out.est[e] = mean;
+        if (out.se) out.se[e] = count > 1.0 ? sqrt(m2 / (count - 1.0) / count) : 0.0;
+    } else {
+        double *pp = out.part + (out.pbase + (int64_t)g * out.chunks) * 3;
+        pp[0] = count;
+        pp[1] = mean;
+        pp[2] = m2;
+    }
+}
+
 template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND, bool RESORT = false,
           int FAT = 0>
 __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx, int64_t n,
@@ -795,11 +819,47 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // ---- per-entry statistics: slots in a fixed order, plus n0 copies of K
+        // ---- per-entry statistics: slots in a fixed order, plus n0 copies of K.
+        // Entries with at most kShortSeg listed walkers: one lane each (a session
+        // holds at most 64 entries), sums in slot order; the others: the whole
+        // wave, lanes striding the segment, then a fixed tree.  Which one depends
+        // only on the entry's own walkers, so packing changes no result.
+        {
+            const uint32_t g = g_begin + (uint32_t)lane;
+            if (g < g_end) {
+                const uint32_t b0 = L.seg[g], J = L.seg[g + 1] - b0;
+                if (J <= kShortSeg) {
+                    double mean, m2, count;
+                    if (L.node[g] == 0xFFFFFFFFu) {
+                        mean = NAN;
+                        m2 = NAN;
+                        count = 1.0;
+                    } else {
+                        const double K = L.K[g];
+                        const uint32_t n0w = L.n0[g];
+                        const uint32_t n0 = n0w & 0xFFFFu;
+                        const double nn0 = (double)n0;
+                        count = (double)(n0w >> 16);
+                        if (n0 && !isfinite(K)) err |= F_OVERFLOW;
+                        double s1 = 0.0;
+                        for (uint32_t i = 0; i < J; ++i) s1 += (double)L.fval[b0 + i];
+                        mean = n0 ? (nn0 * K + s1) / count : s1 / count;
+                        double s2 = 0.0;
+                        for (uint32_t i = 0; i < J; ++i) {
+                            const double dv = (double)L.fval[b0 + i] - mean;
+                            s2 += dv * dv;
+                        }
+                        const double dk = K - mean;
+                        m2 = n0 ? s2 + nn0 * dk * dk : s2;
+                    }
+                    put_stats(out, g, mean, m2, count);
+                }
+            }
+        }
         for (uint32_t g = g_begin; g < g_end; ++g) {
-            const int64_t e = out.e_first + g;
             const uint32_t b0 = __builtin_amdgcn_readfirstlane(L.seg[g]);
             const uint32_t b1 = __builtin_amdgcn_readfirstlane(L.seg[g + 1]);
+            if (b1 - b0 <= kShortSeg) continue;
             double mean, m2, count;
             if (L.node[g] == 0xFFFFFFFFu) {
                 mean = NAN;
@@ -831,22 +891,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 const double dk = K - mean;
                 m2 = n0 ? s2 + nn0 * dk * dk : s2;
             }
-            if (lane == 0) {
-                if (out.var_task) {
-                    double *pp = out.part + (out.s0 + (int64_t)g) * 3;
-                    pp[0] = count;
-                    pp[1] = mean;
-                    pp[2] = m2;
-                } else if (out.chunks == 1) {
-                    out.est[e] = mean;
-                    if (out.se) out.se[e] = count > 1.0 ? sqrt(m2 / (count - 1.0) / count) : 0.0;
-                } else {
-                    double *pp = out.part + (out.pbase + (int64_t)g * out.chunks) * 3;
-                    pp[0] = count;
-                    pp[1] = mean;
-                    pp[2] = m2;
-                }
-            }
+            if (lane == 0) put_stats(out, g, mean, m2, count);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
