@@ -462,7 +462,7 @@ struct GroupOut {
 // sessions (see below); with RESORT (relabelled tables only) the wave re-sorts
 // its walkers by current node every P.resort events.
 // Entries whose listed walkers are summed by one lane rather than the wave.
-constexpr uint32_t kShortSeg = 16;
+constexpr uint32_t kShortSeg = 32;
 
 // An entry's statistics: the estimate and standard error, or its (count, mean,
 // M2) partial when it spans several chunks or has its own walker count.
