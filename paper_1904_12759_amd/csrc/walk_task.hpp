@@ -384,6 +384,17 @@ __device__ __forceinline__ double dpp_f64(double x) {
     return __longlong_as_double((long long)dpp_u64<CTRL>((uint64_t)__double_as_longlong(x)));
 }
 
+// Sum over each row of 16 lanes: the first four steps of wave_sum_f64, after
+// which every lane of a row holds the row's sum.  Every lane of the wave must be
+// active.
+__device__ __forceinline__ double row_sum_f64(double x) {
+    x = x + dpp_f64<0xB1>(x);
+    x = x + dpp_f64<0x4E>(x);
+    x = x + dpp_f64<0x141>(x);
+    x = x + dpp_f64<0x140>(x);
+    return x;
+}
+
 // Sum over the 64 lanes of a wavefront in a fixed tree: neighbours, pairs,
 // half rows and rows of 16 lanes by DPP (each step adds two equal partial sums
 // in both orders, which commutativity makes bitwise equal), then the four row
@@ -461,8 +472,10 @@ struct GroupOut {
 // listed walkers do not all fit the list at once, phases 1 and 2 alternate in
 // sessions (see below); with RESORT (relabelled tables only) the wave re-sorts
 // its walkers by current node every P.resort events.
-// Entries whose listed walkers are summed by one lane rather than the wave.
+// Entries whose listed walkers are summed by one lane, or by one row of 16
+// lanes, rather than by the whole wave.
 constexpr uint32_t kShortSeg = 32;
+constexpr uint32_t kRowSeg = 256;
 
 // An entry's statistics: the estimate and standard error, or its (count, mean,
 // M2) partial when it spans several chunks or has its own walker count.
@@ -821,45 +834,102 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // ---- per-entry statistics: slots in a fixed order, plus n0 copies of K.
         // Entries with at most kShortSeg listed walkers: one lane each (a session
-        // holds at most 64 entries), sums in slot order; the others: the whole
-        // wave, lanes striding the segment, then a fixed tree.  Which one depends
-        // only on the entry's own walkers, so packing changes no result.
+        // holds at most 64 entries), sums in slot order; up to kRowSeg: one row of
+        // 16 lanes each; the others: the whole wave, lanes striding the segment,
+        // then a fixed tree.  Which one depends only on the entry's own walkers,
+        // so packing changes no result.
+        // lane l looks at entry g_begin + l (a session holds at most 64 entries) and
+        // the wave learns which entries take the row tree and which the wave tree
+        unsigned long long rowm, widem;
         {
             const uint32_t g = g_begin + (uint32_t)lane;
-            if (g < g_end) {
-                const uint32_t b0 = L.seg[g], J = L.seg[g + 1] - b0;
-                if (J <= kShortSeg) {
-                    double mean, m2, count;
-                    if (L.node[g] == 0xFFFFFFFFu) {
-                        mean = NAN;
-                        m2 = NAN;
-                        count = 1.0;
-                    } else {
-                        const double K = L.K[g];
-                        const uint32_t n0w = L.n0[g];
-                        const uint32_t n0 = n0w & 0xFFFFu;
-                        const double nn0 = (double)n0;
-                        count = (double)(n0w >> 16);
-                        if (n0 && !isfinite(K)) err |= F_OVERFLOW;
-                        double s1 = 0.0;
-                        for (uint32_t i = 0; i < J; ++i) s1 += (double)L.fval[b0 + i];
-                        mean = n0 ? (nn0 * K + s1) / count : s1 / count;
-                        double s2 = 0.0;
-                        for (uint32_t i = 0; i < J; ++i) {
-                            const double dv = (double)L.fval[b0 + i] - mean;
-                            s2 += dv * dv;
-                        }
-                        const double dk = K - mean;
-                        m2 = n0 ? s2 + nn0 * dk * dk : s2;
+            const bool in = g < g_end;
+            const uint32_t b0 = in ? L.seg[g] : 0u, J = in ? L.seg[g + 1] - b0 : 0u;
+            rowm = __ballot(in && J > kShortSeg && J <= kRowSeg);
+            widem = __ballot(in && J > kRowSeg);
+            if (in && J <= kShortSeg) {
+                double mean, m2, count;
+                if (L.node[g] == 0xFFFFFFFFu) {
+                    mean = NAN;
+                    m2 = NAN;
+                    count = 1.0;
+                } else {
+                    const double K = L.K[g];
+                    const uint32_t n0w = L.n0[g];
+                    const uint32_t n0 = n0w & 0xFFFFu;
+                    const double nn0 = (double)n0;
+                    count = (double)(n0w >> 16);
+                    if (n0 && !isfinite(K)) err |= F_OVERFLOW;
+                    double s1 = 0.0;
+                    for (uint32_t i = 0; i < J; ++i) s1 += (double)L.fval[b0 + i];
+                    mean = n0 ? (nn0 * K + s1) / count : s1 / count;
+                    double s2 = 0.0;
+                    for (uint32_t i = 0; i < J; ++i) {
+                        const double dv = (double)L.fval[b0 + i] - mean;
+                        s2 += dv * dv;
                     }
-                    put_stats(out, g, mean, m2, count);
+                    const double dk = K - mean;
+                    m2 = n0 ? s2 + nn0 * dk * dk : s2;
                 }
+                put_stats(out, g, mean, m2, count);
             }
         }
-        for (uint32_t g = g_begin; g < g_end; ++g) {
+        // entries of kShortSeg+1 .. kRowSeg listed walkers: four at a time, one per
+        // row of 16 lanes (lanes of a row stride the segment, then the row tree)
+        while (rowm) {
+            // the next (up to) four of them, lowest first
+            const uint32_t sel0 = g_begin + (uint32_t)__builtin_ctzll(rowm);
+            rowm &= rowm - 1ull;
+            uint32_t sel1 = sel0, sel2 = sel0, sel3 = sel0, m = 1;
+            if (rowm) {
+                sel1 = g_begin + (uint32_t)__builtin_ctzll(rowm);
+                rowm &= rowm - 1ull;
+                m = 2;
+            }
+            if (rowm) {
+                sel2 = g_begin + (uint32_t)__builtin_ctzll(rowm);
+                rowm &= rowm - 1ull;
+                m = 3;
+            }
+            if (rowm) {
+                sel3 = g_begin + (uint32_t)__builtin_ctzll(rowm);
+                rowm &= rowm - 1ull;
+                m = 4;
+            }
+            const uint32_t r = (uint32_t)lane >> 4, rl = (uint32_t)lane & 15u;
+            const bool act = r < m;          // rows past m repeat the first entry, unwritten
+            const uint32_t g = r == 1 ? sel1 : r == 2 ? sel2 : r == 3 ? sel3 : sel0;
+            const uint32_t b0 = L.seg[g], J = L.seg[g + 1] - b0;
+            const bool bad = L.node[g] == 0xFFFFFFFFu;
+            const double K = L.K[g];
+            const uint32_t n0w = L.n0[g];
+            const uint32_t n0 = n0w & 0xFFFFu;
+            const double nn0 = (double)n0;
+            double count = (double)(n0w >> 16);
+            if (act && !bad && n0 && !isfinite(K)) err |= F_OVERFLOW;
+            double s1 = 0.0;
+            for (uint32_t i = rl; i < J; i += 16) s1 += (double)L.fval[b0 + i];
+            s1 = row_sum_f64(s1);
+            double mean = n0 ? (nn0 * K + s1) / count : s1 / count;
+            double s2 = 0.0;
+            for (uint32_t i = rl; i < J; i += 16) {
+                const double dv = (double)L.fval[b0 + i] - mean;
+                s2 += dv * dv;
+            }
+            s2 = row_sum_f64(s2);
+            const double dk = K - mean;
+            double m2 = n0 ? s2 + nn0 * dk * dk : s2;
+            if (bad) {
+                mean = NAN;
+                m2 = NAN;
+                count = 1.0;
+            }
+            if (act && rl == 0) put_stats(out, g, mean, m2, count);
+        }
+        for (; widem; widem &= widem - 1ull) {
+            const uint32_t g = g_begin + (uint32_t)__builtin_ctzll(widem);
             const uint32_t b0 = __builtin_amdgcn_readfirstlane(L.seg[g]);
             const uint32_t b1 = __builtin_amdgcn_readfirstlane(L.seg[g + 1]);
-            if (b1 - b0 <= kShortSeg) continue;
             double mean, m2, count;
             if (L.node[g] == 0xFFFFFFFFu) {
                 mean = NAN;
