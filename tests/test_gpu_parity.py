@@ -614,6 +614,30 @@ def test_entries_multi_equals_per_count_runs(fp32):
     assert _close(e4.cpu().numpy(), eo, RTOL32 if fp32 else RTOL64)
 
 
+# ------------------------------------------------------- statistics tiers
+@pytest.mark.parametrize("fp32", [False, True])
+def test_statistics_tiers_match_oracle(fp32):
+    """An entry's listed walkers are summed by one lane (at most 32), one row of 16 lanes
+    (at most 256) or the whole wave.  A two-state chain whose start node jumps before t
+    with probability about 1/2, run with 40 .. 80 and 480 .. 560 walkers, puts entries on
+    both sides of both limits: every estimate and standard error against the oracle."""
+    a = wl.from_dense(np.array([[-0.6931471805599453, 0.6931471805599453], [0.4, -0.4]]))
+    t = 1.0
+    g, o = _pair(a, t, 123, fp32=fp32)
+    v = _v_for(np.array([0.8, 1.7]), fp32)
+    counts = np.array(list(range(40, 81, 3)) + list(range(480, 561, 8)), np.int64)
+    est, se = g.entries_multi(v, np.zeros(len(counts), np.int64), counts)
+    est, se = est.cpu().numpy(), se.cpu().numpy()
+    for j, m in enumerate(counts):
+        eo, so = o.estimate(v, [0], int(m))
+        assert _close(est[j:j + 1], eo, RTOL32 if fp32 else RTOL64), int(m)
+        assert np.allclose(se[j], so, rtol=1e-5 if fp32 else 1e-8), int(m)
+    # the same counts one at a time (a session of one entry): bitwise the same
+    for j in (0, len(counts) - 1):
+        e1, s1 = g.entries(v, [0], int(counts[j]))
+        assert e1.item() == est[j] and s1.item() == se[j]
+
+
 # ------------------------------------------------------------ task packing
 def _runs(g, v, idx):
     # 512 and 1024 fill a whole LDS list (FP64 / FP32): one entry per session
