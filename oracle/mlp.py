@@ -19,12 +19,15 @@ features:
                  b*_e = log h_j - log h_i with h = sqrt(m2), m2 the per-node
                  second moment of W v[X_t] measured by plain runs.
 
-The kernels keep weights in bfloat16, round the hidden activations a1 to
-bfloat16 before the 64x64 product, and round the back-propagated dL/dz2 to
-bfloat16 before the two 64x64 products of the backward pass (dW2 and dL/da1);
-`bf16=True` applies the same roundings here so the comparison isolates
-accumulation order.  Parameter vector layout
-(4801 floats): W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3.
+Where the bfloat16 roundings sit.  The products run with bfloat16 operands
+and FP32 accumulation, so three kinds of value are rounded to bfloat16: the
+weights, the hidden activations a1 (the operand of the 64x64 product), and
+the back-propagated derivative at z2 (the operand of the two 64x64 products
+of the backward pass, dW2 and dL/da1).  The derivative that is rounded is the
+per-edge one of the un-normalised sum  sum_e p_e (b_e - b*_e)^2; the division
+by sum_e p_e is applied to the summed gradient.  `bf=True` applies exactly
+these roundings; `bf=False` is the exact network in FP64.  Parameter vector
+layout (4801 floats): W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3.
 """
 from __future__ import annotations
 
@@ -119,27 +122,30 @@ def forward(p, feats, src, dst, bf=True):
     return b, cache
 
 
-def loss_and_grad(p, feats, src, dst, pw, tgt, bf=True):
-    """Weighted squared error and its gradient w.r.t. the parameter vector."""
+def loss_and_grad(p, feats, src, dst, pw, tgt, bf=True, cache=False):
+    """Weighted squared error and its gradient w.r.t. the parameter vector.
+
+    Back-propagation runs on the un-normalised sum  S = sum_e p_e (b_e - b*_e)^2
+    (per-edge derivatives e_*), and loss and gradient are S and dS/dtheta
+    divided by sum_e p_e.  With cache=True the intermediate values are returned
+    too (a dict), for deriving the kernels' rounding-error bounds."""
     b, (x, z1, a1q, z2, a2, th, (w1, b1, w2, b2, w3, b3)) = forward(p, feats, src, dst, bf)
     pw = np.asarray(pw, np.float64)
     ps = pw.sum()
-    diff = b - np.asarray(tgt, np.float64)
-    loss = float((pw * diff * diff).sum() / ps)
-    g_b = 2.0 * pw * diff / ps
-    g_y = g_b * (1.0 - th * th)
-    g_w3 = a2.T @ g_y
-    g_b3 = g_y.sum()
-    g_a2 = np.outer(g_y, w3)
-    g_z2 = g_a2 * (z2 > 0)
-    g_z2q = bf16(g_z2) if bf else g_z2
-    g_w2 = g_z2q.T @ a1q
-    g_b2 = g_z2.sum(0)
-    g_a1 = g_z2q @ w2
-    g_z1 = g_a1 * (z1 > 0)
-    g_w1 = g_z1.T @ x
-    g_b1 = g_z1.sum(0)
-    return loss, pack(g_w1, g_b1, g_w2, g_b2, g_w3, g_b3)
+    tgt = np.asarray(tgt, np.float64)
+    diff = b - tgt
+    lsum = float((pw * diff * diff).sum())
+    e_y = 2.0 * pw * diff * (1.0 - th * th)              # dS/dy per edge
+    e_z2 = np.outer(e_y, w3) * (z2 > 0)                  # dS/dz2 per edge
+    e_z2q = bf16(e_z2) if bf else e_z2
+    e_z1 = (e_z2q @ w2) * (z1 > 0)                       # dS/dz1 per edge
+    g = pack(e_z1.T @ x, e_z1.sum(0), e_z2q.T @ a1q, e_z2.sum(0), a2.T @ e_y, e_y.sum()) / ps
+    loss = lsum / ps
+    if not cache:
+        return loss, g
+    return loss, g, dict(x=x, z1=z1, a1q=a1q, z2=z2, a2=a2, th=th, b=b, diff=diff, e_y=e_y,
+                         e_z2=e_z2, e_z2q=e_z2q, e_z1=e_z1, lsum=lsum, ps=ps,
+                         w=(w1, b1, w2, b2, w3, b3))
 
 
 def adam(p, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):

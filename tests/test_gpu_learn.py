@@ -10,6 +10,7 @@ torch = pytest.importorskip("torch")
 from oracle import mlp as omlp
 import paper_1904_12759_amd as mc
 from paper_1904_12759_amd import workloads as wl
+import mlp_bounds
 import refs
 
 pytestmark = pytest.mark.gpu
@@ -47,7 +48,22 @@ def _random_params(seed):
     return p
 
 
-def test_forward_matches_oracle(small):
+def _check_within(got, ref, bound, what):
+    """Element-wise |got - ref| <= bound; reports the worst ratio."""
+    err = np.abs(np.asarray(got, np.float64) - ref)
+    ratio = err / bound
+    k = int(np.argmax(ratio))
+    print(f"{what}: max |gpu - oracle| / bound = {ratio[k]:.3g} at {k} "
+          f"(err {err[k]:.3g}, bound {bound[k]:.3g}); median bound / |ref| "
+          f"{np.median(bound / np.maximum(np.abs(ref), 1e-30)):.3g}", flush=True)
+    assert np.all(err <= bound), (what, k, err[k], bound[k], ref[k])
+
+
+@pytest.mark.parametrize("rounded", [True, False])
+def test_forward_matches_oracle(small, rounded):
+    """Every edge's tilt within its own error bound (mlp_bounds): against the
+    oracle with the kernels' bf16 roundings, and against the exact network with
+    the bf16 quantisation budget added."""
     a, v, g = small
     net = mc.MLP(g, seed=3)
     p = _random_params(0)
@@ -55,14 +71,20 @@ def test_forward_matches_oracle(small):
     f = g.features(v)
     b = net.forward(f).cpu().numpy()
     pos, src, dst, _ = omlp.edges(a.rowptr, a.col, a.val)
-    bo, _ = omlp.forward(p.astype(np.float64), f.cpu().numpy().astype(np.float64), src, dst)
-    assert np.abs(b[pos] - bo).max() < 2e-4
+    bo, eb, _ = mlp_bounds.forward_bounds(p.astype(np.float64),
+                                          f.cpu().numpy().astype(np.float64), src, dst, rounded)
+    _check_within(b[pos], bo, eb, f"tilt (rounded={rounded})")
     other = np.setdiff1d(np.arange(a.nnz), pos)
     assert np.all(b[other] == 0.0)
 
 
+@pytest.mark.parametrize("rounded", [True, False])
 @pytest.mark.parametrize("p0,p1", [(0, None), (37, 1003), (500, 501)])
-def test_gradient_matches_oracle(small, p0, p1):
+def test_gradient_matches_oracle(small, p0, p1, rounded):
+    """Each of the 4801 gradient elements and the loss within their own error bounds
+    (mlp_bounds: FP32 accumulation over the visited positions, bf16 roundings that
+    may fall either side of a boundary; with rounded=False also the bf16
+    quantisation of weights, a1 and dS/dz2 against the exact network)."""
     a, v, g = small
     net = mc.MLP(g, seed=3)
     p = _random_params(1)
@@ -78,15 +100,11 @@ def test_gradient_matches_oracle(small, p0, p1):
     grad, loss = net.gradient(f, lh, p0, p1)
     lhn = lh.cpu().numpy().astype(np.float64)
     tgt = lhn[dst[sel]] - lhn[src[sel]]
-    lo, go = omlp.loss_and_grad(p.astype(np.float64), f.cpu().numpy().astype(np.float64),
-                                src[sel], dst[sel], pw[sel], tgt)
-    gg = grad.cpu().numpy()
-    assert abs(loss - lo) <= 1e-4 * max(1.0, abs(lo))
-    # dL/dz2 is rounded to bf16 on both sides, but from an FP32 value on the GPU and
-    # an FP64 one here: a value next to a rounding boundary may land one bf16 ulp
-    # (2^-8 relative) apart, which a single edge's outer product shows undiluted.
-    scale = np.abs(go).max()
-    assert np.abs(gg - go).max() <= 2.0 ** -7 * scale, np.abs(gg - go).max() / scale
+    lo, go, el, eg = mlp_bounds.gradient_bounds(
+        p.astype(np.float64), f.cpu().numpy().astype(np.float64), src[sel], dst[sel], pw[sel],
+        tgt, p1 - p0, rounded)
+    _check_within(np.array([loss]), np.array([lo]), np.array([el]), f"loss (rounded={rounded})")
+    _check_within(grad.cpu().numpy(), go, eg, f"gradient (rounded={rounded})")
 
 
 def test_adam_step_matches_oracle(small):

@@ -126,3 +126,73 @@ def test_training_reduces_loss():
         params, m, v = mlp.adam(params, m, v, g, step, 3e-3)
     l1, _ = mlp.loss_and_grad(params, f, src, dst, p, tgt)
     assert l1 < 0.1 * l0
+
+
+def _two_edge_case():
+    """Two nodes, edges 0 -> 1 and 1 -> 0, weights exactly representable (also in
+    bfloat16), only a few hidden units active, so that every value can be worked
+    out by hand (see test_two_edge_hand_worked)."""
+    feats = np.array([[1.0, 0.0, 0.5, -1.0], [0.0, 2.0, -0.5, 1.0]])
+    src, dst = np.array([0, 1]), np.array([1, 0])
+    w1 = np.zeros((64, 8)); b1 = np.zeros(64)
+    w2 = np.zeros((64, 64)); b2 = np.zeros(64)
+    w3 = np.zeros(64)
+    w1[0, 0], w1[0, 4], b1[0] = 1.0, -1.0, 0.5          # z1_0 = f_i0 - f_j0 + 1/2
+    w1[1, 1], w1[1, 7], b1[1] = 0.5, 0.25, 0.25         # z1_1 = f_i1/2 + f_j3/4 + 1/4
+    w2[0, 0], w2[0, 1], b2[0] = 1.0, -2.0, 0.25         # z2_0 = a1_0 - 2 a1_1 + 1/4
+    w2[1, 0], w2[1, 1], b2[1] = 0.5, 1.0, -0.5          # z2_1 = a1_0/2 + a1_1 - 1/2
+    b2[2] = 0.125                                       # z2_2 = 1/8
+    w3[0], w3[1], w3[2] = 2.0, -1.0, 4.0
+    b3 = -0.5
+    return mlp.pack(w1, b1, w2, b2, w3, b3), feats, src, dst
+
+
+@pytest.mark.parametrize("bf", [False, True])
+def test_two_edge_hand_worked(bf):
+    """Forward values by hand.  Edge 0 (x = [1,0,.5,-1, 0,2,-.5,1]): z1 = (1.5, 0.5, 0...),
+    z2 = (0.75, 0.75, 0.125, 0...), y = 1.5 - 0.75 + 0.5 - 0.5 = 0.75.  Edge 1
+    (x = [0,2,-.5,1, 1,0,.5,-1]): z1 = (-0.5, 1.0, 0...), a1 = (0, 1, 0...),
+    z2 = (-1.75, 0.5, 0.125, 0...), a2 = (0, 0.5, 0.125, 0...), y = -0.5 + 0.5 - 0.5 = -0.5.
+    b = 8 tanh(y / 8).  Every value is a bfloat16, so the rounded network agrees."""
+    p, feats, src, dst = _two_edge_case()
+    b, (x, z1, a1q, z2, a2, th, _) = mlp.forward(p, feats, src, dst, bf=bf)
+    z1e = np.zeros((2, 64)); z1e[0, :2] = [1.5, 0.5]; z1e[1, :2] = [-0.5, 1.0]
+    z2e = np.zeros((2, 64)); z2e[0, :3] = [0.75, 0.75, 0.125]; z2e[1, :3] = [-1.75, 0.5, 0.125]
+    np.testing.assert_array_equal(z1, z1e)
+    np.testing.assert_array_equal(a1q, np.maximum(z1e, 0))
+    np.testing.assert_array_equal(z2, z2e)
+    np.testing.assert_array_equal(a2, np.maximum(z2e, 0))
+    y = np.array([0.75, -0.5])
+    np.testing.assert_allclose(b, 8.0 * np.tanh(y / 8.0), rtol=1e-15, atol=0)
+    assert b[0] > 0 > b[1]
+
+
+def test_two_edge_loss_and_gradient_hand_worked():
+    """Loss and all 4801 gradient elements by hand, with p = (1/4, 3/4) (sum 1) and
+    targets b* = (1/2, -1).  With g_e = 2 p_e (b_e - b*_e)(1 - tanh^2(y_e/8)):
+    dz2 of edge 0 = g_0 (2, -1, 4) (units 0-2 active), of edge 1 = g_1 (0, -1, 4)
+    (unit 0 inactive); dz1 of edge 0 = (1.5 g_0, -5 g_0), of edge 1 = (0, -g_1)
+    (unit 0 inactive there).  Everything else is zero."""
+    p, feats, src, dst = _two_edge_case()
+    pw = np.array([0.25, 0.75])
+    tgt = np.array([0.5, -1.0])
+    loss, g = mlp.loss_and_grad(p, feats, src, dst, pw, tgt, bf=False)
+    th = np.tanh(np.array([0.75, -0.5]) / 8.0)
+    b = 8.0 * th
+    d = b - tgt
+    assert abs(loss - (0.25 * d[0] ** 2 + 0.75 * d[1] ** 2)) < 1e-15
+    g0, g1 = 2.0 * pw * d * (1.0 - th * th)
+    x0 = np.array([1.0, 0.0, 0.5, -1.0, 0.0, 2.0, -0.5, 1.0])
+    x1 = np.array([0.0, 2.0, -0.5, 1.0, 1.0, 0.0, 0.5, -1.0])
+    gw1 = np.zeros((64, 8)); gb1 = np.zeros(64)
+    gw2 = np.zeros((64, 64)); gb2 = np.zeros(64); gw3 = np.zeros(64)
+    gw1[0] = 1.5 * g0 * x0
+    gw1[1] = -5.0 * g0 * x0 - g1 * x1
+    gb1[0], gb1[1] = 1.5 * g0, -5.0 * g0 - g1
+    gw2[0, 0], gw2[0, 1] = 3.0 * g0, g0                 # dz2_0 = 2 g_0 (edge 0 only)
+    gw2[1, 0], gw2[1, 1] = -1.5 * g0, -0.5 * g0 - g1    # dz2_1 = (-g_0, -g_1)
+    gw2[2, 0], gw2[2, 1] = 6.0 * g0, 2.0 * g0 + 4.0 * g1
+    gb2[0], gb2[1], gb2[2] = 2.0 * g0, -g0 - g1, 4.0 * (g0 + g1)
+    gw3[0], gw3[1], gw3[2] = 0.75 * g0, 0.75 * g0 + 0.5 * g1, 0.125 * (g0 + g1)
+    expect = mlp.pack(gw1, gb1, gw2, gb2, gw3, g0 + g1)
+    np.testing.assert_allclose(g, expect, rtol=1e-14, atol=1e-16)
