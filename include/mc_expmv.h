@@ -56,7 +56,9 @@ typedef enum {
     MC_ERR_NO_MEMORY = 6,     /* a device or host allocation failed */
     MC_ERR_DEVICE = 7,        /* a HIP runtime call failed */
     MC_ERR_WALK_LIMIT = 8,    /* a walker reached opts.max_events holding intervals */
-    MC_ERR_OVERFLOW = 9       /* a walker's weight W * v[X_t] is not finite */
+    MC_ERR_OVERFLOW = 9,      /* a walker's weight W * v[X_t] is not finite */
+    MC_ERR_TOO_LARGE = 10     /* mc_expmv_entries_noalloc: the run needs more than its
+                                 fixed scratch */
 } mc_status;
 
 enum { MC_EXACT = 0, MC_STRANG = 1, MC_LIE = 2 };
@@ -166,6 +168,28 @@ mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t
  */
 mc_status mc_expmv_entries(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
                            int64_t n_walkers, double *est, double *stderr_);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): exactly
+ * mc_expmv_entries (same kernels, same arguments, bitwise the same estimates),
+ * but the call allocates nothing.  The (count, mean, M2) partials of entries
+ * that span several walker chunks (chunks of 1024 walkers with MC_FP32
+ * weights, 512 with MC_FP64) live in a static device array of
+ * MC_NOALLOC_SCRATCH_DOUBLES doubles (8 MiB) that each GPU the library runs on
+ * holds until the process ends; its address is looked up per device by
+ * mc_expmv_create.  A run needs 3 * k * ceil(n_walkers / chunk) doubles when
+ * n_walkers exceeds one chunk and none otherwise; larger requests return
+ * MC_ERR_TOO_LARGE before anything is enqueued.  Every partial is written
+ * before it is read, so nothing needs clearing between calls.  All calls of
+ * this function on one GPU share the array: calls that overlap on that GPU
+ * (other streams, other handles, other host threads) race, so callers order
+ * them (one stream, or events).  The handle itself (tables, counters, status
+ * word) is allocated by mc_expmv_create, before.
+ */
+#define MC_NOALLOC_SCRATCH_DOUBLES (1 << 20)
+mc_status mc_expmv_entries_noalloc(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
+                                   int64_t n_walkers, double *est, double *stderr_);
 
 /*
  * As mc_expmv_entries, with its own walker count for every entry (e.g. the

@@ -24,7 +24,7 @@ MC_OK = 0
 STATUS_NAMES = {
     0: "MC_OK", 1: "MC_ERR_INVALID_ARG", 2: "MC_ERR_NOT_METZLER", 3: "MC_ERR_NONFINITE",
     4: "MC_ERR_OUT_OF_RANGE", 5: "MC_ERR_NOT_SYMMETRIC", 6: "MC_ERR_NO_MEMORY",
-    7: "MC_ERR_DEVICE", 8: "MC_ERR_WALK_LIMIT", 9: "MC_ERR_OVERFLOW",
+    7: "MC_ERR_DEVICE", 8: "MC_ERR_WALK_LIMIT", 9: "MC_ERR_OVERFLOW", 10: "MC_ERR_TOO_LARGE",
 }
 
 
@@ -123,6 +123,9 @@ _SIGS = {
     "mc_expmv_entries": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                         ctypes.c_void_p]),
+    "mc_expmv_entries_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                                ctypes.c_void_p]),
     "mc_expmv_full": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_entries_multi": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -325,6 +328,18 @@ class MCExpmv:
         _require_cuda(v, idx, est, stderr)
         _check(load().mc_expmv_entries(self._h, _ptr(v), _ptr(idx), k, int(n_walkers),
                                        _ptr(est), _ptr(stderr)), "mc_expmv_entries")
+        if sync:
+            self.sync()
+        return est, stderr
+
+    def entries_noalloc(self, v, idx, n_walkers: int, est, stderr=None, sync: bool = True):
+        """mc_expmv_entries_noalloc: as entries(), the library allocating nothing (its
+        partials in a fixed static device array).  v, idx, est (and stderr) must be
+        device tensors already."""
+        _require_cuda(v, idx, est, *([stderr] if stderr is not None else []))
+        _check(load().mc_expmv_entries_noalloc(self._h, _ptr(v), _ptr(idx), idx.numel(),
+                                               int(n_walkers), _ptr(est), _ptr(stderr)),
+               "mc_expmv_entries_noalloc")
         if sync:
             self.sync()
         return est, stderr

@@ -6,12 +6,20 @@
 #include <algorithm>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "mc_internal.hpp"
 
 using namespace mc;
+
+// Scratch of mc_expmv_entries_noalloc: the (count, mean, M2) partials of entries
+// that span several walker chunks, in a static device array so that the call
+// allocates nothing.  Every GPU the library runs on holds its own copy, at its
+// own address, until the process ends; host code uses the address obtained from
+// hipGetSymbolAddress for the current device, never the array's name.
+static __device__ __align__(256) double scratch[MC_NOALLOC_SCRATCH_DOUBLES];
 
 struct mc_expmv_s {
     int dev = 0;
@@ -62,10 +70,29 @@ struct mc_expmv_s {
     int64_t *var_host = nullptr;         // pinned staging of the same
     int64_t var_cap = 0;                 // int64 slots in both
     hipEvent_t var_ev = nullptr;         // staging copy done
+    double *scratch = nullptr;           // this device's copy of `scratch` (noalloc entries)
 };
 
 namespace {
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+hipError_t scratch_address(int dev, double **out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
 
 mc_status from_hip(hipError_t e) {
     if (e == hipSuccess) return MC_OK;
@@ -232,9 +259,12 @@ void fill_inst(const mc_expmv_s *h, const void *v, bool prop, InstArgs &P) {
 }
 
 // Run the walk kernel for k entries (idx == null: every node).
+// With ext_part set, chunk partials go there (ext_cap doubles) and nothing is
+// allocated; a run that needs more returns MC_ERR_TOO_LARGE before any launch.
 mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, int64_t nwalk,
                    double *est, double *se, bool trace, int64_t w0, int32_t use_prop,
-                   int32_t *tx, uint32_t *tev, uint32_t *tju, double *tf) {
+                   int32_t *tx, uint32_t *tev, uint32_t *tju, double *tf,
+                   double *ext_part = nullptr, int64_t ext_cap = 0) {
     if (!v || nwalk < 1 || nwalk > 0xFFFFFFFFll) return MC_ERR_INVALID_ARG;
     if (use_prop && !h->has_prop) return MC_ERR_INVALID_ARG;
     if (k < 0) return MC_ERR_INVALID_ARG;
@@ -264,7 +294,10 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
         a.trace.ju = tju;
         a.trace.f = tf;
     }
-    if (chunks > 1) {
+    if (chunks > 1 && ext_part) {
+        if (k > ext_cap / (3 * chunks)) return MC_ERR_TOO_LARGE;
+        a.part = ext_part;
+    } else if (chunks > 1) {
         const int64_t need = k * chunks * 3;
         if (need > h->part_cap) {
             HIP_TRY(hipStreamSynchronize(h->stream));
@@ -326,6 +359,8 @@ const char *mc_expmv_status_string(mc_status s) {
         case MC_ERR_DEVICE: return "HIP runtime error";
         case MC_ERR_WALK_LIMIT: return "walk-length cap reached";
         case MC_ERR_OVERFLOW: return "weight overflow";
+        case MC_ERR_TOO_LARGE:
+            return "request exceeds the fixed scratch of mc_expmv_entries_noalloc";
     }
     return "unknown status";
 }
@@ -408,6 +443,7 @@ mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t
         }                                        \
     } while (0)
     CREATE_TRY(hipGetDevice(&h->dev));
+    CREATE_TRY(scratch_address(h->dev, &h->scratch));
     CREATE_TRY(hipEventCreate(&h->ev0));
     CREATE_TRY(hipEventCreate(&h->ev1));
     CREATE_TRY(dalloc(&h->flags, 1));
@@ -477,6 +513,15 @@ mc_status mc_expmv_entries(mc_expmv_t h, const void *v, const int64_t *idx, int6
     HIP_TRY(hipSetDevice(h->dev));
     return run_walk(h, v, idx, k, n_walkers, est, stderr_, false, 0, h->has_prop ? 1 : 0,
                     nullptr, nullptr, nullptr, nullptr);
+}
+
+mc_status mc_expmv_entries_noalloc(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
+                                   int64_t n_walkers, double *est, double *stderr_) {
+    if (!h || !h->scratch) return MC_ERR_INVALID_ARG;
+    if (k > 0 && (!idx || !est)) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    return run_walk(h, v, idx, k, n_walkers, est, stderr_, false, 0, h->has_prop ? 1 : 0,
+                    nullptr, nullptr, nullptr, nullptr, h->scratch, MC_NOALLOC_SCRATCH_DOUBLES);
 }
 
 mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
