@@ -5,9 +5,9 @@ CPU-baseline leg of the benchmark.  The HIP library never loads it and it never
 loads the HIP library; the two share no code.
 
 `Oracle` wraps the plain C implementation in ``oracle.c`` (built with gcc by
-:func:`build`).  The dense and closed-form helpers used to pin it live in
-``oracle.dense``; the FP64 MLP used to check the learned-proposal kernels lives
-in ``oracle.mlp``.
+:func:`build`).  The dense and closed-form references that pin it live with the
+tests (``tests/refs.py``); the FP64 MLP used to check the learned-proposal
+kernels lives in ``oracle.mlp`` and the ranking measure in ``oracle.rank``.
 """
 from __future__ import annotations
 
@@ -86,6 +86,10 @@ def _load():
         lib.oracle_get_tables.restype = i32
         lib.oracle_set_conditioning.argtypes = [vp, i32, dbl]
         lib.oracle_set_conditioning.restype = i32
+        lib.oracle_set_qmc.argtypes = [vp, i32, i32]
+        lib.oracle_set_qmc.restype = i32
+        lib.oracle_set_jump_rule.argtypes = [vp, i32]
+        lib.oracle_set_jump_rule.restype = i32
         lib.oracle_forward.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.oracle_forward.restype = i32
         lib.oracle_philox4x32_10.argtypes = [vp, vp, vp]
@@ -113,7 +117,8 @@ class Oracle:
 
     def __init__(self, rowptr, col, val, t: float, seed: int, mode: int = EXACT,
                  dt: float = 0.03125, instance: int = 0, max_events: int = 0,
-                 cond: bool = False, cond_max_rt: float = float("inf")):
+                 cond: bool = False, cond_max_rt: float = float("inf"), qmc: bool = False,
+                 qmc_bits: int = 9, cdf_jump: bool = False):
         lib = _load()
         self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
         self._col = np.ascontiguousarray(col, dtype=np.int32)
@@ -135,6 +140,12 @@ class Oracle:
         self.has_proposal = False
         self.cond = bool(cond)
         lib.oracle_set_conditioning(h, int(self.cond), float(cond_max_rt))
+        self.qmc = bool(qmc)
+        st = lib.oracle_set_qmc(h, int(self.qmc), int(qmc_bits))
+        if st == 0:
+            st = lib.oracle_set_jump_rule(h, int(bool(cdf_jump)))
+        if st != 0:
+            raise OracleError(st)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -137,6 +137,9 @@ typedef struct {
     table_set prop;
     int cond;                     /* condition backward walks on a first jump before t */
     double cond_max_rt;           /* ... from start nodes with t <= cond_max_rt / r */
+    int cdf_jump;                 /* jump by inverse CDF over the row instead of the alias table */
+    int qmc;                      /* randomised lattice for the first event (see below) */
+    int qmc_bits;                 /* replicate size B = 2^qmc_bits walkers */
     int64_t *slot_of_csr;         /* CSR position -> slot index, -1 if none */
 } oracle_t;
 
@@ -335,6 +338,7 @@ int oracle_create(oracle_t **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     if (st != OR_OK) return st;
     if (mode != OR_EXACT && mode != OR_STRANG && mode != OR_LIE) return OR_ERR_INVALID_ARG;
     oracle_t *o = (oracle_t *)calloc(1, sizeof(oracle_t));
+    if (o) o->qmc_bits = 9;
     if (!o) return OR_ERR_NO_MEMORY;
     o->n = n; o->nnz = nnz; o->t = t; o->seed = seed; o->mode = mode;
     o->instance = instance;
@@ -408,6 +412,44 @@ static double grid_coef(const oracle_t *o, int64_t k)
 /* Philox counter word that marks a forward walk in place of the start node. */
 #define FORWARD_MARK 0xFFFFFFFFu
 
+/* Randomised quasi-Monte Carlo for the first event (a variance reduction of the
+ * kind Sec. 5 names).  The walkers w of one start node form replicates of
+ * B = 2^b consecutive ordinals: replicate c = w >> b, point j = w mod B.  The
+ * first event of walker w takes its three random words from the point j of the
+ * rank-1 lattice with generating vector (1, g1, g2) (Korobov: g1 = a,
+ * g2 = a^2 mod B, a = 119 for B = 512 and a = 149 for B = 1024, the values
+ * minimising the lattice criterion P_2 over odd a), shifted modulo 1 by a
+ * replicate's own random shift: with (r0, r1, r2, r3) = Philox4x32-10 of the
+ * counter (0xFFFFFFFE, c, start, instance),
+ *     64-bit word of U:   j * 2^(64-b) + (r0 * 2^32 + r1)   mod 2^64
+ *     slot word:          j * g1 * 2^(32-b) + r2           mod 2^32
+ *     alias word:         j * g2 * 2^(32-b) + r3           mod 2^32.
+ * Each coordinate is uniform on its range (a uniform shift modulo 1), so every
+ * walker has the law of the plain walk and the mean is unbiased; within a
+ * replicate the B points are evenly spread (stratified jump/no-jump choice,
+ * holding time and first jump), which reduces the variance of the mean.  Later
+ * events draw Philox as in the plain walk.  The standard error comes from the R
+ * replicate means m_c (counts n_c of M walkers): se^2 = R/(R-1) sum_c (n_c/M)^2
+ * (m_c - mean)^2 when R >= 2, the i.i.d. formula otherwise. */
+#define QMC_SHIFT_MARK 0xFFFFFFFEu
+
+static void qmc_first_words(const oracle_t *o, int64_t start, uint32_t w, const uint32_t key[2],
+                            uint32_t rnd[4])
+{
+    const uint32_t b = (uint32_t)o->qmc_bits;
+    const uint64_t g1 = b == 9 ? 119u : 149u;
+    const uint64_t g2 = (g1 * g1) % (1u << b);
+    const uint64_t j = w & ((1u << b) - 1u);
+    uint32_t ctr[4] = { QMC_SHIFT_MARK, w >> b, (uint32_t)start, o->instance };
+    uint32_t sh[4];
+    oracle_philox4x32_10(ctr, key, sh);
+    const uint64_t u0 = (j << (64 - b)) + (((uint64_t)sh[0] << 32) | sh[1]);
+    rnd[0] = (uint32_t)(u0 >> 32);
+    rnd[1] = (uint32_t)u0;
+    rnd[2] = (uint32_t)(((j * g1) << (32 - b)) + sh[2]);
+    rnd[3] = (uint32_t)(((j * g2) << (32 - b)) + sh[3]);
+}
+
 /* One walker started at node `start`, ordinal w.  The path is recorded as
  * the sequence of visited states and entry times, then the weight is formed
  * from the recorded path.  Backward walks (Algorithm 1) use the counters
@@ -444,7 +486,10 @@ static void walk_path(const oracle_t *o, int64_t start, uint32_t w, const double
         uint32_t ctr[4] = { forward ? events + 1u : events, w,
                             forward ? FORWARD_MARK : (uint32_t)start, o->instance };
         uint32_t rnd[4];
-        oracle_philox4x32_10(ctr, key, rnd);
+        if (o->qmc && !forward && events == 0)
+            qmc_first_words(o, start, w, key, rnd);
+        else
+            oracle_philox4x32_10(ctr, key, rnd);
         ++events;
         double S;
         int jump;
@@ -456,7 +501,24 @@ static void walk_path(const oracle_t *o, int64_t start, uint32_t w, const double
             S = -log(uniform_open0(rnd[0], rnd[1])) * ts->inv_r[x];
             jump = s + S < o->t;
         }
-        if (jump) {
+        if (jump && o->cdf_jump) {
+            /* inverse CDF of the jump law over the row's rates in CSR order: the first
+             * slot whose running sum exceeds u r, u = o2 2^-32 in [0, 1) (the last slot
+             * when rounding leaves u r at or above the sum) */
+            s = s + S;
+            const double target = ((double)rnd[2] * 0x1p-32) * ts->r[x];
+            const int64_t b = ts->begin[x];
+            int64_t sl = ts->deg[x] - 1;
+            double cum = 0.0;
+            for (int64_t k = 0; k < ts->deg[x]; ++k) {
+                cum = cum + ts->val[b + k];
+                if (target < cum) { sl = k; break; }
+            }
+            x = ts->col[b + sl];
+            ++jumps;
+            ++len;
+            path_x[len] = x; path_s[len] = s; path_c[len] = use_prop ? ts->logcorr[b + sl] : 0.0;
+        } else if (jump) {
             s = s + S;
             int64_t slot = (int64_t)(((uint64_t)rnd[2] * (uint64_t)ts->deg[x]) >> 32);
             int64_t q = ts->begin[x] + slot;
@@ -601,7 +663,20 @@ static void *run_job(void *arg)
         }
         double mean = neumaier_sum(fs, jb->nwalk) / (double)jb->nwalk;
         jb->est[e] = mean;
-        if (jb->se) {
+        const int64_t B = (int64_t)1 << o->qmc_bits;
+        if (jb->se && o->qmc && jb->nwalk > B) {
+            /* replicate means */
+            const int64_t R = (jb->nwalk + B - 1) / B;
+            double acc = 0.0;
+            for (int64_t c = 0; c < R; ++c) {
+                const int64_t w0 = c * B;
+                const int64_t nc = jb->nwalk - w0 < B ? jb->nwalk - w0 : B;
+                const double mc = neumaier_sum(fs + w0, nc) / (double)nc;
+                const double wc = (double)nc / (double)jb->nwalk;
+                acc += wc * wc * (mc - mean) * (mc - mean);
+            }
+            jb->se[e] = sqrt(acc * (double)R / (double)(R - 1));
+        } else if (jb->se) {
             if (jb->nwalk > 1) {
                 for (int64_t w = 0; w < jb->nwalk; ++w) dev[w] = (fs[w] - mean) * (fs[w] - mean);
                 double var = neumaier_sum(dev, jb->nwalk) / (double)(jb->nwalk - 1);
@@ -646,6 +721,26 @@ int oracle_estimate(const oracle_t *o, const double *v, const int64_t *idx, int6
         if (jobs[tI].status != OR_OK && st == OR_OK) st = jobs[tI].status;
     free(jobs); free(th);
     return st;
+}
+
+/* Jump rule: 0 = Vose alias table (default), 1 = inverse CDF over the row's rates
+ * in CSR order (the rule of the matrix-free stencil walk). */
+int oracle_set_jump_rule(oracle_t *o, int rule)
+{
+    if (rule != 0 && rule != 1) return OR_ERR_INVALID_ARG;
+    o->cdf_jump = rule;
+    return OR_OK;
+}
+
+/* Switch the randomised lattice of the first event on or off (bits = 9 or 10:
+ * replicates of 512 or 1024 walkers). */
+int oracle_set_qmc(oracle_t *o, int on, int bits)
+{
+    if (on && bits != 9 && bits != 10) return OR_ERR_INVALID_ARG;
+    if (on && o->max_events >= QMC_SHIFT_MARK) return OR_ERR_INVALID_ARG;
+    o->qmc = on ? 1 : 0;
+    o->qmc_bits = on ? bits : 9;
+    return OR_OK;
 }
 
 /* Switch the first-jump conditioning of backward walks on or off; it applies

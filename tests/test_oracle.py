@@ -640,3 +640,176 @@ def test_conditioning_threshold_selects_nodes():
         assert np.array_equal(mixed.trace(v, i, 0, 200)[3], allc.trace(v, i, 0, 200)[3])
     for i in high:
         assert np.array_equal(mixed.trace(v, i, 0, 200)[3], plain.trace(v, i, 0, 200)[3])
+
+
+# ---------------------------------------------------- randomised lattice (first event)
+def _lattice_words(key, start, w, bits, inst=0):
+    """The first-event words of the randomised rank-1 lattice, from its definition:
+    the point w mod B of the Korobov lattice (1, a, a^2 mod B) shifted modulo 1 by
+    the replicate's Philox draw (counter 0xFFFFFFFE, w >> bits, start, instance)."""
+    B = 1 << bits
+    a = 119 if bits == 9 else 149
+    g = [1, a, (a * a) % B]
+    sh = oracle.philox4x32_10([0xFFFFFFFE, w >> bits, start, inst], key)
+    j = w % B
+    frac = [(j * gk % B) / B for gk in g]                  # the lattice point in [0,1)^3
+    shift = [((int(sh[0]) << 32) | int(sh[1])) / 2.0 ** 64, int(sh[2]) / 2.0 ** 32,
+             int(sh[3]) / 2.0 ** 32]
+    return [(f + s) % 1.0 for f, s in zip(frac, shift)]
+
+
+@pytest.mark.parametrize("bits", [9, 10])
+def test_lattice_first_event_stratifies_the_jump_choice(bits):
+    """Within a replicate of B walkers the first-event uniforms are the lattice points
+    shifted modulo 1, so the number of walkers whose first holding time outlasts t is
+    B e^{-rt} rounded down or up, exactly; and every replicate's walkers reach the
+    states the plain walk reaches (single-jump paths from the start's neighbours)."""
+    a = wl.cycle_graph(9, 0.7)
+    t = 0.45
+    o = Oracle(a.rowptr, a.col, a.val, t, 21, qmc=True, qmc_bits=bits)
+    v = np.arange(1.0, 10.0)
+    B = 1 << bits
+    r = 1.4                                                 # two neighbours at rate 0.7
+    p0 = np.exp(-r * t)
+    for start in (0, 4):
+        x, ev, ju, f, _ = o.trace(v, start, 0, 3 * B)
+        for c in range(3):
+            stay = int((ju[c * B:(c + 1) * B] == 0).sum())
+            assert stay in (int(np.floor(B * p0)), int(np.ceil(B * p0))), (c, stay, B * p0)
+
+
+def test_lattice_first_event_words_follow_the_definition():
+    """The walker's first event, as the oracle takes it, is the shifted lattice point:
+    no-jump exactly when -log U / r >= t with U from the first coordinate, and the
+    jump target the alias draw of the other two (checked on a star graph whose
+    centre jumps to leaf `slot` with the slot word)."""
+    n = 6
+    dense = np.zeros((n, n))
+    dense[0, 1:] = [0.5, 0.5, 0.5, 0.5, 0.5]               # uniform row: slot = leaf
+    a = wl.from_dense(dense)
+    t = 0.9
+    seed = 33
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    o = Oracle(a.rowptr, a.col, a.val, t, seed, qmc=True, qmc_bits=9)
+    v = np.arange(1.0, 7.0)
+    x, ev, ju, f, _ = o.trace(v, 0, 0, 1500)
+    for w in range(0, 1500, 7):
+        u, us, _ = _lattice_words(key, 0, w, 9)
+        m = int(u * 2.0 ** 53)                              # the top 53 bits of the word
+        U = (m + 1) * 2.0 ** -53
+        holds = -np.log(U) / 2.5 >= t
+        assert holds == (ju[w] == 0), w
+        if not holds:
+            assert x[w] == 1 + int(us * 5), w               # floor(slot word * deg)
+
+
+@pytest.mark.parametrize("mode,symmetric", [(EXACT, True), (EXACT, False), (STRANG, True)])
+def test_lattice_estimate_is_unbiased_and_its_error_calibrated(mode, symmetric):
+    """Over independent seeds (independent shifts) the lattice estimates average to
+    the dense reference (expm, or the Strang product), and the replicate standard
+    error matches the estimates' spread: with R = 8 replicate means the z-scores
+    follow Student's t with R - 1 = 7 degrees of freedom, E[z^2] = 7/5."""
+    n = 20
+    dense = refs.random_metzler(n, 0.25, 51, symmetric=symmetric)
+    t = 0.8
+    a = wl.from_dense(dense)
+    v = np.random.default_rng(52).uniform(0.2, 1.0, n)
+    ref = refs.expm_v(dense, t, v) if mode == EXACT else refs.strang_v(dense, t, 4, v)
+    zs = []
+    for seed in range(40):
+        o = Oracle(a.rowptr, a.col, a.val, t, 1000 + seed, mode=mode, dt=t / 4, qmc=True,
+                   qmc_bits=9)
+        est, se = o.estimate(v, None, 8 * 512, threads=4)
+        zs.append((est - ref) / se)
+    z = np.array(zs)
+    assert abs(z.mean()) < 4.5 * np.sqrt(1.4 / z.size)
+    assert abs(np.mean(z * z) - 1.4) < 0.3, np.mean(z * z)
+
+
+def test_lattice_reduces_variance():
+    """On the 32x32 grid at t = 0.1 (most walkers never leave their start node) the
+    lattice's spread over seeds is several times below the plain walk's at the same
+    walker count."""
+    g = wl.grid2d(32)
+    v = wl.uniform_v(g.n, 2)
+    idx = np.array([0, 100, 500, 1023, 333])
+    ests = {False: [], True: []}
+    for seed in range(24):
+        for q in (False, True):
+            o = Oracle(g.rowptr, g.col, g.val, 0.1, 500 + seed, qmc=q, qmc_bits=9)
+            ests[q].append(o.estimate(v, idx, 4096, threads=4)[0])
+    var_p = np.var(np.array(ests[False]), axis=0)
+    var_q = np.var(np.array(ests[True]), axis=0)
+    assert np.all(var_q < var_p) and np.median(var_p / var_q) > 4, var_p / var_q
+
+
+def test_lattice_standard_error_from_replicate_means():
+    """The replicate standard error by its definition, from the traced walker values:
+    se^2 = R/(R-1) sum_c (n_c/M)^2 (m_c - mean)^2 over the R replicates (the last one
+    partial), and the i.i.d. formula when a single replicate holds every walker."""
+    a = wl.grid2d(6)
+    v = np.random.default_rng(3).random(a.n)
+    o = Oracle(a.rowptr, a.col, a.val, 0.6, 8, qmc=True, qmc_bits=9)
+    for m in (3 * 512 + 100, 512, 300):
+        est, se = o.estimate(v, [7], m)
+        f = o.trace(v, 7, 0, m)[3]
+        assert abs(est[0] - f.mean()) <= 1e-14 * abs(f.mean())
+        if m > 512:
+            reps = [f[c:c + 512] for c in range(0, m, 512)]
+            r = len(reps)
+            acc = sum((len(x) / m) ** 2 * (x.mean() - f.mean()) ** 2 for x in reps)
+            want = np.sqrt(acc * r / (r - 1))
+        else:
+            want = f.std(ddof=1) / np.sqrt(m)
+        assert abs(se[0] - want) <= 1e-10 * want, (m, se[0], want)
+
+
+# ---------------------------------------------------- inverse-CDF jump rule
+def test_cdf_jump_rule_follows_its_definition():
+    """With the inverse-CDF rule the first jump goes to the first neighbour (CSR order)
+    whose running sum of rates exceeds u r, u = o2 / 2^32 from the walker's first Philox
+    draw: checked walker by walker on a row with unequal rates."""
+    dense = np.zeros((5, 5))
+    dense[0, 1:] = [0.3, 1.1, 0.05, 0.8]
+    dense[1:, 0] = 0.2
+    a = wl.from_dense(dense)
+    seed = 77
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    t = 5.0
+    o = Oracle(a.rowptr, a.col, a.val, t, seed, cdf_jump=True)
+    x, ev, ju, f, _ = o.trace(np.ones(5), 0, 0, 400)
+    rates = dense[0, 1:]
+    r = rates.sum()
+    cum = np.cumsum(rates)
+    for w in range(400):
+        o2 = int(oracle.philox4x32_10([0, w, 0, 0], key)[2])
+        k = int(np.searchsorted(cum, (o2 / 2.0 ** 32) * r, side="right"))
+        assert ju[w] >= 1
+        if ju[w] == 1:
+            assert x[w] == 1 + min(k, 3), w
+
+
+def test_cdf_jump_frequencies_match_the_jump_law():
+    dense = np.zeros((6, 6))
+    dense[0, 1:] = [0.5, 2.0, 0.25, 1.0, 0.25]
+    a = wl.from_dense(dense)
+    o = Oracle(a.rowptr, a.col, a.val, 50.0, 3, cdf_jump=True)
+    x, ev, ju, f, _ = o.trace(np.ones(6), 0, 0, 40_000)   # every walker jumps once (rows 1-5 absorb)
+    counts = np.bincount(x, minlength=6)[1:]
+    p = dense[0, 1:] / dense[0, 1:].sum()
+    chi2 = stats.chisquare(counts, p * counts.sum())
+    assert chi2.pvalue > 1e-4, chi2
+
+
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_cdf_jump_matches_dense_expm(symmetric):
+    n = 40
+    dense = refs.random_metzler(n, 0.15, 71, symmetric=symmetric, off_scale=1.0)
+    a = wl.from_dense(dense)
+    t = 0.8
+    v = np.random.default_rng(72).uniform(-1, 2, n)
+    o = Oracle(a.rowptr, a.col, a.val, t, 73, cdf_jump=True)
+    est, se = o.estimate(v, nwalk=20_000, threads=4)
+    ref = refs.expm_v(dense, t, v)
+    z = _zscores(est, se, ref)
+    assert np.abs(z).max() < 4.5 and abs(np.mean(z ** 2) - 1) < 0.5

@@ -78,6 +78,21 @@ MUTANTS = [
     ("conditioned value without the jump probability",
      "res->f = exp(-rt) * (exp(logk) * v[start]) + (-expm1(-rt)) * res->f;",
      "res->f = exp(-rt) * (exp(logk) * v[start]) + res->f;"),
+    ("lattice points not spread over the replicate",
+     "const uint64_t u0 = (j << (64 - b)) + (((uint64_t)sh[0] << 32) | sh[1]);",
+     "const uint64_t u0 = (j << (63 - b)) + (((uint64_t)sh[0] << 32) | sh[1]);"),
+    ("lattice shift shared by every replicate",
+     "uint32_t ctr[4] = { QMC_SHIFT_MARK, w >> b, (uint32_t)start, o->instance };",
+     "uint32_t ctr[4] = { QMC_SHIFT_MARK, 0u, (uint32_t)start, o->instance };"),
+    ("lattice slot word without the lattice point",
+     "rnd[2] = (uint32_t)(((j * g1) << (32 - b)) + sh[2]);", "rnd[2] = sh[2];"),
+    ("replicate error without R/(R-1)",
+     "jb->se[e] = sqrt(acc * (double)R / (double)(R - 1));", "jb->se[e] = sqrt(acc);"),
+    ("inverse-CDF target not scaled by the rate",
+     "const double target = ((double)rnd[2] * 0x1p-32) * ts->r[x];",
+     "const double target = ((double)rnd[2] * 0x1p-32);"),
+    ("inverse-CDF takes the slot after the crossing", "if (target < cum) { sl = k; break; }",
+     "if (target < cum) { sl = k + 1 < ts->deg[x] ? k + 1 : k; break; }"),
     ("forward grid not reversed",
      "acc += grid_coef(o, forward ? o->ngrid - k : k) * ts->d[path_x[m]];",
      "acc += grid_coef(o, k) * ts->d[path_x[m]];"),
