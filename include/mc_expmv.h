@@ -36,6 +36,11 @@
  *     overflows) are latched in the handle and returned by mc_expmv_sync.
  *   - A handle is not thread safe; use one per host thread.
  *   - No C++ exception crosses this interface.
+ *   - Allocation failures return MC_ERR_NO_MEMORY after freeing what the call
+ *     allocated.  For testing those paths, MC_EXPMV_FAULT=alloc:K in the
+ *     environment makes the K-th device or pinned-host allocation of each call
+ *     fail (the count restarts at every entry point that allocates, nested ones
+ *     included).
  */
 #ifndef MC_EXPMV_H
 #define MC_EXPMV_H
@@ -120,6 +125,26 @@ typedef struct {
                                    64 MiB and the 64-byte slots (64 B per stored entry
                                    of A) fit in 4 GiB.  Estimates do not depend on it,
                                    bit for bit. */
+    int32_t qmc_first;          /* 1: randomised quasi-Monte Carlo for the first event of
+                                   the backward walks (a variance reduction of the kind
+                                   Sec. 5 names): the walker ordinals of an entry form
+                                   replicates of B = 1024 (MC_FP32) or 512 (MC_FP64)
+                                   consecutive walkers, and walker w's first-event words
+                                   are the point w mod B of the Korobov rank-1 lattice
+                                   (1, a, a^2 mod B), a = 149 (B = 1024) or 119 (B = 512),
+                                   shifted modulo 1 by the Philox draw of the counter
+                                   (0xFFFFFFFE, w / B, start node, instance id):
+                                   64-bit U word j 2^(64-b) + (o0 2^32 + o1), slot word
+                                   j g1 2^(32-b) + o2, alias word j g2 2^(32-b) + o3
+                                   (j = w mod B, B = 2^b, wrapping).  Later events are as
+                                   in the plain walk.  Unbiased (every coordinate is a
+                                   uniform shift); stderr_ then comes from the R replicate
+                                   means, R/(R-1) sum_c (n_c/M)^2 (m_c - est)^2, when an
+                                   entry has R >= 2 replicates, else the i.i.d. formula.
+                                   Not with cond_first_jump or relabel, and max_events
+                                   must stay below 0xFFFFFFFE (MC_ERR_INVALID_ARG
+                                   otherwise).
+                                   Default 0. */
 } mc_expmv_opts;
 
 typedef struct {
@@ -154,6 +179,32 @@ const char *mc_expmv_status_string(mc_status s);
 mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t *rowptr,
                           const int32_t *col, const double *val, double t, uint64_t seed,
                           const mc_expmv_opts *opts);
+
+/*
+ * A handle for the matrix-free walk on a 7-point stencil (the variable-coefficient
+ * diffusion operators of the benchmark's 3-D workload): A is given by its face rates
+ * instead of CSR, neighbours come from the node index x = i + nx (j + ny k), and a
+ * jump picks the neighbour by inverse CDF over the six face rates in the column
+ * order of A's row (-z, -y, -x, +x, +y, +z): the first face whose running sum of
+ * rates exceeds u r_x, u = o2 2^-32 from the event's Philox draw (the last face with
+ * a rate when rounding leaves u r_x at or above the sum).  r_x is the sum of the
+ * face rates in that order, d_x = a_xx + r_x (Sec. 2 split, as for CSR input).
+ * The same law as the alias tables of mc_expmv_create, sampled by another rule, so
+ * paths differ from a CSR handle's (they match the oracle's inverse-CDF rule).
+ *   fx, fy, fz  device double[n], n = nx ny nz: the rate between x and its +x / +y /
+ *               +z neighbour (A is symmetric in the stencil's off-diagonals), >= 0,
+ *               0 on the last plane of that axis
+ *   diag        device double[n]: a_xx
+ * Supports entries / entries_multi / full / trace / stats in every weight mode and
+ * precision; not the tilted proposal, the forward estimator, relabelling,
+ * conditioning or the lattice (MC_ERR_INVALID_ARG).  Errors: MC_ERR_INVALID_ARG
+ * (sizes, a positive rate on a last plane, options), MC_ERR_NONFINITE,
+ * MC_ERR_NOT_METZLER (a negative rate).  The arrays are copied; synchronous.
+ */
+mc_status mc_expmv_create_stencil7(mc_expmv_t *out, int64_t nx, int64_t ny, int64_t nz,
+                                   const double *fx, const double *fy, const double *fz,
+                                   const double *diag, double t, uint64_t seed,
+                                   const mc_expmv_opts *opts);
 
 /*
  * Entries idx[0..k-1] of exp(tA) v, n_walkers walkers each (Algorithm 1 and
@@ -462,6 +513,22 @@ mc_status mc_expmv_learn_proposal(mc_expmv_t h, const void *v, const mc_learn_op
  */
 mc_status mc_isim(int64_t n, const double *x, const double *y, int64_t k, double *out,
                   void *stream);
+
+/* ------------------------------------------------------------- diagnostics */
+
+/*
+ * The walk kernels' own FP64 elementary functions on a device array, for
+ * checking their accuracy:  fn = MC_FN_LOG: y = log x (the logarithm of the
+ * holding time S = -log(U) / r, Eq. (paths); x in (0, 1]), MC_FN_EXP: y = e^x
+ * (the FP64 weights W of Theorem 1), MC_FN_ONE_MINUS_EXP_NEG: y = 1 - e^{-x}
+ * for x >= 0 (first-jump conditioning).
+ *   x, y     device double[n]
+ *   stream   hipStream_t or NULL
+ * Errors: MC_ERR_INVALID_ARG (fn, n < 0, null pointer), MC_ERR_DEVICE.
+ * Asynchronous on stream.
+ */
+enum { MC_FN_LOG = 0, MC_FN_EXP = 1, MC_FN_ONE_MINUS_EXP_NEG = 2 };
+mc_status mc_math_eval(int32_t fn, const double *x, double *y, int64_t n, void *stream);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,9 @@ __all__ = ["MCExpmv", "MCBatch", "MLP", "MCError", "EXACT", "STRANG", "LIE", "FP
            "load"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmcexpmv.so")
+# MC_EXPMV_LIB may name another build of the library (the host-code sanitizer build,
+# for CPU checks); by default the in-tree libmcexpmv.so
+LIB_PATH = os.environ.get("MC_EXPMV_LIB") or os.path.join(HERE, "libmcexpmv.so")
 
 EXACT, STRANG, LIE = 0, 1, 2
 FP64, FP32 = 0, 1
@@ -54,6 +56,7 @@ class mc_expmv_opts(ctypes.Structure):
         ("cond_max_rt", ctypes.c_double),
         ("task_walkers", ctypes.c_uint32),
         ("slot_rows", ctypes.c_int32),
+        ("qmc_first", ctypes.c_int32),
     ]
 
 
@@ -120,6 +123,9 @@ _SIGS = {
     "mc_expmv_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p]),
+    "mc_expmv_create_stencil7": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                                ctypes.c_int64] + [ctypes.c_void_p] * 4 +
+                                 [ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p]),
     "mc_expmv_entries": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                         ctypes.c_void_p]),
@@ -173,6 +179,8 @@ _SIGS = {
     "mc_learn_default_opts": (None, [ctypes.c_void_p]),
     "mc_expmv_learn_proposal": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p, ctypes.c_void_p]),
+    "mc_math_eval": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int64, ctypes.c_void_p]),
     "mc_isim": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                ctypes.c_void_p, ctypes.c_void_p]),
 }
@@ -244,6 +252,22 @@ def isim(x, y, k: int | None = None, stream=None) -> float:
     return out.value
 
 
+MATH_FNS = {"log": 0, "exp": 1, "one_minus_exp_neg": 2}
+
+
+def math_eval(fn: str, x):
+    """The walk kernels' own FP64 log / exp / 1 - e^{-x} on a vector (``mc_math_eval``),
+    returned as a device tensor."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    xs = torch.as_tensor(x).to(device=dev, dtype=torch.float64).contiguous()
+    ys = torch.empty_like(xs)
+    stream = torch.cuda.current_stream().cuda_stream
+    _check(load().mc_math_eval(MATH_FNS[fn], _ptr(xs), _ptr(ys), xs.numel(),
+                               ctypes.c_void_p(stream)), "mc_math_eval")
+    return ys
+
+
 class MCExpmv:
     """Handle over ``mc_expmv_create`` for one matrix A, horizon t and seed.
 
@@ -256,7 +280,7 @@ class MCExpmv:
                  max_events: int = 0, walkers_per_block: int = 64, relabel: int = 0,
                  lds_budget: int = 0, stream=None, cond: bool = False,
                  cond_max_rt: float = float("inf"), task_walkers: int = 0,
-                 resort_period: int = 0, slot_rows: int = 0):
+                 resort_period: int = 0, slot_rows: int = 0, qmc: bool = False):
         import torch
         lib_ = load()
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -272,7 +296,8 @@ class MCExpmv:
                             walkers_per_block=walkers_per_block, relabel=relabel,
                             lds_budget=lds_budget, stream=stream, cond_first_jump=int(cond),
                             cond_max_rt=float(cond_max_rt), task_walkers=int(task_walkers),
-                            resort_period=int(resort_period), slot_rows=int(slot_rows))
+                            resort_period=int(resort_period), slot_rows=int(slot_rows),
+                            qmc_first=int(qmc))
         h = ctypes.c_void_p()
         torch.cuda.current_stream().synchronize()
         _check(lib_.mc_expmv_create(ctypes.byref(h), rp.numel() - 1, cl.numel(), _ptr(rp),
@@ -289,6 +314,47 @@ class MCExpmv:
         _check(lib_.mc_expmv_info(h, ctypes.byref(n), ctypes.byref(ns), ctypes.byref(ng),
                                   ctypes.byref(dtv)), "mc_expmv_info")
         self.nslots, self.ngrid, self.dt = ns.value, ng.value, dtv.value
+
+    @classmethod
+    def stencil7(cls, nx, ny, nz, fx, fy, fz, diag, t: float, seed: int, mode: int = EXACT,
+                 dt: float = 0.03125, fp32: bool = False, instance: int = 0,
+                 max_events: int = 0, walkers_per_block: int = 64, stream=None,
+                 task_walkers: int = 0):
+        """Handle over ``mc_expmv_create_stencil7``: the matrix-free walk on a 7-point
+        stencil given by its face rates fx, fy, fz (rate to the +x / +y / +z neighbour,
+        0 on the last plane) and diagonal."""
+        import torch
+        lib_ = load()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        arrs = [torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
+                for a in (fx, fy, fz, diag)]
+        _require_cuda(*arrs)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self = cls.__new__(cls)
+        self.stream = stream
+        opts = default_opts(mode=mode, dt=dt, weight_prec=FP32 if fp32 else FP64,
+                            instance_id=instance, max_events=max_events,
+                            walkers_per_block=walkers_per_block, stream=stream,
+                            task_walkers=int(task_walkers))
+        h = ctypes.c_void_p()
+        torch.cuda.current_stream().synchronize()
+        _check(lib_.mc_expmv_create_stencil7(ctypes.byref(h), int(nx), int(ny), int(nz),
+                                             *[_ptr(a) for a in arrs], float(t),
+                                             int(seed) & (2**64 - 1), ctypes.byref(opts)),
+               "mc_expmv_create_stencil7")
+        self._h = h
+        self.n = int(nx) * int(ny) * int(nz)
+        self.nnz = 0
+        self.t = float(t)
+        self.mode = mode
+        self.fp32 = fp32
+        self.device = dev
+        n, ns, ng, dtv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib_.mc_expmv_info(h, ctypes.byref(n), ctypes.byref(ns), ctypes.byref(ng),
+                                  ctypes.byref(dtv)), "mc_expmv_info")
+        self.nslots, self.ngrid, self.dt = ns.value, ng.value, dtv.value
+        return self
 
     # -- plumbing
     def close(self):

@@ -36,26 +36,38 @@ def _hipcc() -> str:
     return "hipcc"
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-    subprocess.run(cmd, check=True, cwd=BUILD_DIR)
+# Host-code sanitizer build (libmcexpmv_san.so, CPU checks only): AddressSanitizer
+# and UndefinedBehaviorSanitizer on the host side of every source; device code is
+# built as usual.
+SAN_LIB = os.path.join(HERE, "libmcexpmv_san.so")
+SAN_BUILD_DIR = os.path.join(HERE, "_build_san")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
+def _compile(src: str, san: bool = False) -> str:
+    bdir = SAN_BUILD_DIR if san else BUILD_DIR
+    obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
+    cmd = [_hipcc(), *HIPCC_FLAGS, *(SAN_FLAGS if san else []), "-c", os.path.join(CSRC, src),
+           "-o", obj]
+    subprocess.run(cmd, check=True, cwd=bdir)
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    bdir, lib = (SAN_BUILD_DIR, SAN_LIB) if sanitize else (BUILD_DIR, LIB)
+    os.makedirs(bdir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, sanitize), SOURCES))
+    tmp = lib + ".tmp"
     cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
-    subprocess.run(cmd, check=True, cwd=BUILD_DIR)
-    os.replace(tmp, LIB)
+    subprocess.run(cmd, check=True, cwd=bdir)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv[1:])
     sys.exit(0)

@@ -4,12 +4,14 @@
 #include <math.h>
 
 #include <algorithm>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
 #include <new>
 #include <vector>
 
+#include "alloc.hpp"
 #include "mc_internal.hpp"
 
 using namespace mc;
@@ -71,7 +73,44 @@ struct mc_expmv_s {
     int64_t var_cap = 0;                 // int64 slots in both
     hipEvent_t var_ev = nullptr;         // staging copy done
     double *scratch = nullptr;           // this device's copy of `scratch` (noalloc entries)
+    // matrix-free 7-point stencil (mc_expmv_create_stencil7): face rates and a_xx
+    bool stencil = false;
+    double *sfx = nullptr, *sfy = nullptr, *sfz = nullptr, *sdiag = nullptr;
+    uint32_t snx = 0, snxy = 0;
 };
+
+namespace mc {
+
+namespace {
+thread_local int g_fault_at = 0;     // MC_EXPMV_FAULT=alloc:K -> K (0: off)
+thread_local int g_fault_count = 0;  // allocations made since the scope began
+
+bool fault_fires() { return g_fault_at > 0 && ++g_fault_count == g_fault_at; }
+}  // namespace
+
+void fault_scope_begin() {
+    g_fault_at = 0;
+    g_fault_count = 0;
+    const char *f = getenv("MC_EXPMV_FAULT");
+    if (f && strncmp(f, "alloc:", 6) == 0) {
+        const long k = strtol(f + 6, nullptr, 10);
+        if (k > 0 && k < 1000000) g_fault_at = (int)k;
+    }
+}
+
+hipError_t dev_malloc(void **p, size_t bytes) {
+    *p = nullptr;
+    if (fault_fires()) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+}
+
+hipError_t host_malloc(void **p, size_t bytes) {
+    *p = nullptr;
+    if (fault_fires()) return hipErrorOutOfMemory;
+    return hipHostMalloc(p, bytes, 0);
+}
+
+}  // namespace mc
 
 namespace {
 
@@ -119,7 +158,7 @@ template <class T>
 hipError_t dalloc(T **p, int64_t count) {
     *p = nullptr;
     if (count <= 0) count = 1;
-    return hipMalloc((void **)p, sizeof(T) * (size_t)count);
+    return dev_malloc((void **)p, sizeof(T) * (size_t)count);
 }
 
 void free_tables(Tables &tb) {
@@ -167,7 +206,7 @@ mc_status relabel_tables(mc_expmv_s *h, Tables &tb, bool build) {
         if (e == hipSuccess) e = dalloc(&vin, n);
         if (e == hipSuccess) e = launch_relabel_keys(n, tb.r, kin, vin, h->stream);
         if (e == hipSuccess) e = sort_pairs_u64(nullptr, tmp_bytes, kin, kout, vin, h->inv, n, h->stream);
-        if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
+        if (e == hipSuccess) e = dev_malloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
         if (e == hipSuccess) e = sort_pairs_u64(tmp, tmp_bytes, kin, kout, vin, h->inv, n, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         (void)hipFree(kin);
@@ -217,6 +256,10 @@ mc_status check_opts(const mc_expmv_opts &o) {
     if (o.cond_first_jump != 0 && o.cond_first_jump != 1) return MC_ERR_INVALID_ARG;
     if (!(o.cond_max_rt >= 0.0)) return MC_ERR_INVALID_ARG;
     if (o.slot_rows < -1 || o.slot_rows > 1) return MC_ERR_INVALID_ARG;
+    if (o.qmc_first != 0 && o.qmc_first != 1) return MC_ERR_INVALID_ARG;
+    // the lattice's shift counters (kQmcShiftMark, ...) must never be an event index
+    if (o.qmc_first && (o.cond_first_jump || o.relabel || o.max_events >= kQmcShiftMark))
+        return MC_ERR_INVALID_ARG;
     return MC_OK;
 }
 
@@ -256,6 +299,13 @@ void fill_inst(const mc_expmv_s *h, const void *v, bool prop, InstArgs &P) {
     P.max_events = h->opts.max_events ? h->opts.max_events : (1u << 24);
     P.cond_max_rt = h->opts.cond_max_rt;
     P.resort = rl ? h->opts.resort_period : 0u;
+    P.qmc = h->opts.qmc_first ? 1u : 0u;
+    P.fx = h->stencil ? h->sfx : nullptr;
+    P.fy = h->sfy;
+    P.fz = h->sfz;
+    P.diag = h->sdiag;
+    P.nx = h->snx;
+    P.nxy = h->snxy;
 }
 
 // Run the walk kernel for k entries (idx == null: every node).
@@ -283,6 +333,7 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
     a.chunks = chunks;
     a.group = trace ? 1u : group_size(nwalk, k, h->opts.task_walkers);
     a.cond = h->opts.cond_first_jump != 0;
+    a.qmc = h->opts.qmc_first != 0;
     a.ntasks = (k + a.group - 1) / a.group * chunks;
     a.est = est;
     a.se = se;
@@ -391,6 +442,10 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->fwd_part);
     (void)hipFree(h->fwd_acc);
     (void)hipFree(h->var_dev);
+    (void)hipFree(h->sfx);
+    (void)hipFree(h->sfy);
+    (void)hipFree(h->sfz);
+    (void)hipFree(h->sdiag);
     if (h->var_host) (void)hipHostFree(h->var_host);
     if (h->var_ev) (void)hipEventDestroy(h->var_ev);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -401,6 +456,7 @@ void mc_expmv_destroy(mc_expmv_t h) {
 mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t *rowptr,
                           const int32_t *col, const double *val, double t, uint64_t seed,
                           const mc_expmv_opts *opts) {
+    fault_scope_begin();
     if (!out) return MC_ERR_INVALID_ARG;
     *out = nullptr;
     mc_expmv_opts o;
@@ -447,7 +503,7 @@ mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t
     CREATE_TRY(hipEventCreate(&h->ev0));
     CREATE_TRY(hipEventCreate(&h->ev1));
     CREATE_TRY(dalloc(&h->flags, 1));
-    CREATE_TRY(hipHostMalloc((void **)&h->flag_host, sizeof(uint32_t), 0));
+    CREATE_TRY(host_malloc((void **)&h->flag_host, sizeof(uint32_t)));
     CREATE_TRY(dalloc(&h->counters, 2 * (int64_t)kMaxWalkGrid));
     CREATE_TRY(hipMemsetAsync(h->flags, 0, sizeof(uint32_t), h->stream));
     CREATE_TRY(dalloc(&h->rowptr, n + 1));
@@ -506,8 +562,97 @@ mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t
     return MC_OK;
 }
 
+mc_status mc_expmv_create_stencil7(mc_expmv_t *out, int64_t nx, int64_t ny, int64_t nz,
+                                   const double *fx, const double *fy, const double *fz,
+                                   const double *diag, double t, uint64_t seed,
+                                   const mc_expmv_opts *opts) {
+    fault_scope_begin();
+    if (!out) return MC_ERR_INVALID_ARG;
+    *out = nullptr;
+    mc_expmv_opts o;
+    mc_expmv_default_opts(&o);
+    if (opts) {
+        if (opts->struct_size != sizeof(mc_expmv_opts)) return MC_ERR_INVALID_ARG;
+        o = *opts;
+    }
+    mc_status st = check_opts(o);
+    if (st != MC_OK) return st;
+    if (o.relabel || o.cond_first_jump || o.qmc_first || o.slot_rows == 1) return MC_ERR_INVALID_ARG;
+    if (nx < 1 || ny < 1 || nz < 1 || nx * ny >= ((int64_t)1 << 31) ||
+        nx * ny * nz >= ((int64_t)1 << 31))
+        return MC_ERR_INVALID_ARG;
+    if (!fx || !fy || !fz || !diag) return MC_ERR_INVALID_ARG;
+    if (!isfinite(t) || !(t >= 0.0)) return MC_ERR_INVALID_ARG;
+    const int64_t n = nx * ny * nz;
+    mc_expmv_s *h = new (std::nothrow) mc_expmv_s();
+    if (!h) return MC_ERR_NO_MEMORY;
+    h->n = n;
+    h->nnz = 0;
+    h->t = t;
+    h->seed = seed;
+    h->opts = o;
+    h->stream = (hipStream_t)o.stream;
+    h->stencil = true;
+    h->snx = (uint32_t)nx;
+    h->snxy = (uint32_t)(nx * ny);
+    if (o.mode != MC_EXACT) {
+        const double steps = ceil(t / o.dt);
+        if (!(steps <= 2147483647.0)) {
+            delete h;
+            return MC_ERR_INVALID_ARG;
+        }
+        h->ngrid = steps < 1.0 ? 1 : (int64_t)steps;
+    }
+    h->dt = t / (double)h->ngrid;
+    h->inv_dt = (double)h->ngrid / t;
+#define CREATE_TRY(expr)                         \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) {                  \
+            mc_status s_ = from_hip(e_);         \
+            mc_expmv_destroy(h);                 \
+            return s_;                           \
+        }                                        \
+    } while (0)
+    CREATE_TRY(hipGetDevice(&h->dev));
+    CREATE_TRY(scratch_address(h->dev, &h->scratch));
+    CREATE_TRY(hipEventCreate(&h->ev0));
+    CREATE_TRY(hipEventCreate(&h->ev1));
+    CREATE_TRY(dalloc(&h->flags, 1));
+    CREATE_TRY(host_malloc((void **)&h->flag_host, sizeof(uint32_t)));
+    CREATE_TRY(dalloc(&h->counters, 2 * (int64_t)kMaxWalkGrid));
+    CREATE_TRY(dalloc(&h->sfx, n));
+    CREATE_TRY(dalloc(&h->sfy, n));
+    CREATE_TRY(dalloc(&h->sfz, n));
+    CREATE_TRY(dalloc(&h->sdiag, n));
+    const size_t bytes = sizeof(double) * (size_t)n;
+    CREATE_TRY(hipMemcpyAsync(h->sfx, fx, bytes, hipMemcpyDefault, h->stream));
+    CREATE_TRY(hipMemcpyAsync(h->sfy, fy, bytes, hipMemcpyDefault, h->stream));
+    CREATE_TRY(hipMemcpyAsync(h->sfz, fz, bytes, hipMemcpyDefault, h->stream));
+    CREATE_TRY(hipMemcpyAsync(h->sdiag, diag, bytes, hipMemcpyDefault, h->stream));
+    // counters[0] doubles as the slot count of the check (cleared by a fill kernel later)
+    CREATE_TRY(hipMemsetAsync(h->flags, 0, sizeof(uint32_t), h->stream));
+    CREATE_TRY(hipMemsetAsync(h->counters, 0, sizeof(unsigned long long), h->stream));
+    CREATE_TRY(launch_check_stencil(n, nx, ny, h->sfx, h->sfy, h->sfz, h->sdiag, h->flags,
+                                    h->counters, h->stream));
+    uint32_t f = 0;
+    unsigned long long slots = 0;
+    CREATE_TRY(hipMemcpyAsync(&f, h->flags, sizeof(f), hipMemcpyDeviceToHost, h->stream));
+    CREATE_TRY(hipMemcpyAsync(&slots, h->counters, sizeof(slots), hipMemcpyDeviceToHost, h->stream));
+    CREATE_TRY(hipStreamSynchronize(h->stream));
+#undef CREATE_TRY
+    if (f) {
+        mc_expmv_destroy(h);
+        return flags_to_status(f);
+    }
+    h->nslots = (int64_t)slots;
+    *out = h;
+    return MC_OK;
+}
+
 mc_status mc_expmv_entries(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
                            int64_t n_walkers, double *est, double *stderr_) {
+    fault_scope_begin();
     if (!h) return MC_ERR_INVALID_ARG;
     if (k > 0 && (!idx || !est)) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
@@ -517,6 +662,7 @@ mc_status mc_expmv_entries(mc_expmv_t h, const void *v, const int64_t *idx, int6
 
 mc_status mc_expmv_entries_noalloc(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
                                    int64_t n_walkers, double *est, double *stderr_) {
+    fault_scope_begin();
     if (!h || !h->scratch) return MC_ERR_INVALID_ARG;
     if (k > 0 && (!idx || !est)) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
@@ -524,8 +670,16 @@ mc_status mc_expmv_entries_noalloc(mc_expmv_t h, const void *v, const int64_t *i
                     nullptr, nullptr, nullptr, nullptr, h->scratch, MC_NOALLOC_SCRATCH_DOUBLES);
 }
 
+mc_status mc_math_eval(int32_t fn, const double *x, double *y, int64_t n, void *stream) {
+    if (fn < MC_FN_LOG || fn > MC_FN_ONE_MINUS_EXP_NEG || n < 0) return MC_ERR_INVALID_ARG;
+    if (n > 0 && (!x || !y)) return MC_ERR_INVALID_ARG;
+    HIP_TRY(launch_math_eval(fn, x, y, n, (hipStream_t)stream));
+    return MC_OK;
+}
+
 mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
                                  const int64_t *n_walkers, double *est, double *stderr_) {
+    fault_scope_begin();
     if (!h || !v || k < 0) return MC_ERR_INVALID_ARG;
     if (k > 0 && (!idx || !est || !n_walkers)) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
@@ -541,7 +695,7 @@ mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx
         h->var_host = nullptr;
         h->var_cap = 0;
         HIP_TRY(dalloc(&h->var_dev, need));
-        HIP_TRY(hipHostMalloc((void **)&h->var_host, sizeof(int64_t) * (size_t)need, 0));
+        HIP_TRY(host_malloc((void **)&h->var_host, sizeof(int64_t) * (size_t)need));
         h->var_cap = need;
     }
     if (!h->var_ev) HIP_TRY(hipEventCreateWithFlags(&h->var_ev, hipEventDisableTiming));
@@ -594,6 +748,7 @@ mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx
     a.counters = h->counters;
     a.flags = h->flags;
     a.cond = h->opts.cond_first_jump != 0;
+    a.qmc = h->opts.qmc_first != 0;
     a.var_task = h->var_dev;
     a.var_nwalk = h->var_dev + k + 1;
     a.var_chunks_max = chunks_max;
@@ -613,6 +768,7 @@ mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx
 
 mc_status mc_expmv_full(mc_expmv_t h, const void *v, int64_t n_per_node, double *est,
                         double *stderr_) {
+    fault_scope_begin();
     if (!h) return MC_ERR_INVALID_ARG;
     if (h->n > 0 && !est) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
@@ -623,6 +779,7 @@ mc_status mc_expmv_full(mc_expmv_t h, const void *v, int64_t n_per_node, double 
 mc_status mc_expmv_trace(mc_expmv_t h, const void *v, int64_t start, int64_t w0, int64_t count,
                          int32_t use_proposal, int32_t *x_end, uint32_t *events,
                          uint32_t *jumps, double *f) {
+    fault_scope_begin();
     if (!h || !x_end || !events || !jumps || !f) return MC_ERR_INVALID_ARG;
     if (count < 1 || count > (1 << 20) || w0 < 0 || w0 + count > 0xFFFFFFFFll)
         return MC_ERR_INVALID_ARG;
@@ -645,7 +802,8 @@ mc_status mc_expmv_trace(mc_expmv_t h, const void *v, int64_t start, int64_t w0,
 }
 
 mc_status mc_expmv_set_proposal(mc_expmv_t h, const float *edge_bias) {
-    if (!h) return MC_ERR_INVALID_ARG;
+    fault_scope_begin();
+    if (!h || h->stencil) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
     HIP_TRY(hipStreamSynchronize(h->stream));
     free_tables(h->prop);
@@ -669,7 +827,7 @@ mc_status mc_expmv_set_proposal(mc_expmv_t h, const float *edge_bias) {
 }
 
 mc_status mc_expmv_get_proposal(mc_expmv_t h, float *edge_bias) {
-    if (!h || !edge_bias || !h->has_prop) return MC_ERR_INVALID_ARG;
+    if (!h || h->stencil || !edge_bias || !h->has_prop) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
     HIP_TRY(hipMemcpyAsync(edge_bias, h->bias, sizeof(float) * (size_t)h->nnz,
                            hipMemcpyDeviceToDevice, h->stream));
@@ -737,6 +895,8 @@ mc_status mc_expmv_stats(mc_expmv_t h, mc_expmv_run_stats *out) {
     const double row = 16.0 + dbytes;
     const double slot = 12.0 + (h->last_prop ? 8.0 : 0.0);
     out->alg_bytes = row * (double)(c[0]) + slot * (double)c[1] + dbytes * (double)h->last_walkers;
+    if (h->stencil)   // six face rates and a_xx per visited state, the faces again per jump
+        out->alg_bytes = 56.0 * (double)c[0] + 48.0 * (double)c[1] + dbytes * (double)h->last_walkers;
     if (h->last_fwd) {
         // forward walks: per walker also the binary search over the cumulative
         // sums (8 B per step) and two FP64 read-modify-writes at the end node
@@ -749,7 +909,7 @@ mc_status mc_expmv_stats(mc_expmv_t h, mc_expmv_run_stats *out) {
 mc_status mc_expmv_get_tables(mc_expmv_t h, int32_t use_proposal, double *r, double *d,
                               double *inv_r, int64_t *deg, int64_t *begin, int32_t *col,
                               uint32_t *thr, int32_t *alias) {
-    if (!h) return MC_ERR_INVALID_ARG;
+    if (!h || h->stencil) return MC_ERR_INVALID_ARG;
     if (use_proposal && !h->has_prop) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -986,6 +1146,7 @@ void mc_expmv_batch_destroy(mc_batch_t b) { batch_free(b); }
 
 mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instance_desc *desc,
                                 uint64_t seed, const mc_batch_opts *opts) {
+    fault_scope_begin();
     if (!out) return MC_ERR_INVALID_ARG;
     *out = nullptr;
     if (n_inst < 1 || n_inst > kMaxBatch || !desc) return MC_ERR_INVALID_ARG;
@@ -1106,7 +1267,7 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
     B_TRY(dalloc(&b->counters, 2 * (int64_t)b->ncu * 64 * (int64_t)b->classes.size()));
     B_TRY(dalloc(&b->queue, 1));
     B_TRY(dalloc(&b->flags, 1));
-    B_TRY(hipHostMalloc((void **)&b->flag_host, sizeof(uint32_t), 0));
+    B_TRY(host_malloc((void **)&b->flag_host, sizeof(uint32_t)));
     B_TRY(hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BatchInst) * (size_t)n_inst,
                          hipMemcpyHostToDevice, b->stream));
     B_TRY(hipMemcpyAsync(b->d_fin, b->fin_begin.data(), sizeof(int64_t) * (size_t)(n_inst + 1),
@@ -1248,6 +1409,7 @@ struct mc_mlp_s {
     float *w = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *loss = nullptr;
     uint16_t *wbf = nullptr;
     float *gpart = nullptr;
+    double *gsum = nullptr;              // [kMlpParams + 2] FP64 column sums of gpart
     int gpart_blocks = 0;
     int step = 0;
 };
@@ -1297,10 +1459,12 @@ void mc_mlp_destroy(mc_mlp_t m) {
     (void)hipFree(m->loss);
     (void)hipFree(m->wbf);
     (void)hipFree(m->gpart);
+    (void)hipFree(m->gsum);
     delete m;
 }
 
 mc_status mc_mlp_create(mc_mlp_t *out, uint64_t seed, void *stream) {
+    fault_scope_begin();
     if (!out) return MC_ERR_INVALID_ARG;
     *out = nullptr;
     mc_mlp_s *m = new (std::nothrow) mc_mlp_s();
@@ -1320,6 +1484,7 @@ mc_status mc_mlp_create(mc_mlp_t *out, uint64_t seed, void *stream) {
     M_TRY(dalloc(&m->m, kMlpParams));
     M_TRY(dalloc(&m->v, kMlpParams));
     M_TRY(dalloc(&m->grad, kMlpParams));
+    M_TRY(dalloc(&m->gsum, kMlpParams + 2));
     M_TRY(dalloc(&m->loss, 1));
     M_TRY(dalloc(&m->wbf, kMlpParams));
     M_TRY(launch_mlp_init(m->w, m->m, m->v, m->wbf, seed, m->stream));
@@ -1351,7 +1516,8 @@ mc_status mc_mlp_set_params(mc_mlp_t m, const float *host) {
 }
 
 mc_status mc_mlp_features(mc_expmv_t h, const void *v, float *feats) {
-    if (!h || !v || (h->n > 0 && !feats)) return MC_ERR_INVALID_ARG;
+    fault_scope_begin();
+    if (!h || h->stencil || !v || (h->n > 0 && !feats)) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
     double *raw = nullptr, *stats = nullptr;
     HIP_TRY(dalloc(&raw, 4 * h->n));
@@ -1367,14 +1533,15 @@ mc_status mc_mlp_features(mc_expmv_t h, const void *v, float *feats) {
 
 mc_status mc_mlp_log_h(mc_expmv_t h, const double *est, const double *se, int64_t n_walkers,
                        float *lh) {
-    if (!h || !est || !se || !lh || n_walkers < 2) return MC_ERR_INVALID_ARG;
+    if (!h || h->stencil || !est || !se || !lh || n_walkers < 2) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
     HIP_TRY(launch_log_h(h->n, est, se, (double)n_walkers, lh, h->stream));
     return MC_OK;
 }
 
 mc_status mc_mlp_forward(mc_mlp_t m, mc_expmv_t h, const float *feats, float *bias) {
-    if (!m || !h || !feats || (h->nnz > 0 && !bias)) return MC_ERR_INVALID_ARG;
+    fault_scope_begin();
+    if (!m || !h || h->stencil || !feats || (h->nnz > 0 && !bias)) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
     HIP_TRY(hipStreamSynchronize(m->stream));
     HIP_TRY(ensure_rowof(h));
@@ -1385,17 +1552,19 @@ mc_status mc_mlp_forward(mc_mlp_t m, mc_expmv_t h, const float *feats, float *bi
 
 mc_status mc_mlp_gradient(mc_mlp_t m, mc_expmv_t h, const float *feats, const float *lh,
                           int64_t p0, int64_t p1, float *grad, float *loss) {
-    if (!m || !h || !feats || !lh || !grad) return MC_ERR_INVALID_ARG;
+    fault_scope_begin();
+    if (!m || !h || h->stencil || !feats || !lh || !grad) return MC_ERR_INVALID_ARG;
     if (p0 < 0 || p1 > h->nnz || p1 <= p0) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(h->dev));
     HIP_TRY(hipStreamSynchronize(m->stream));
     HIP_TRY(ensure_rowof(h));
     const int64_t tile0 = p0 / 16;
     const int64_t ntile = (p1 - tile0 * 16 + 15) / 16;
-    const int blocks = mlp_blocks(ntile, 1024);
+    const int blocks = mlp_blocks(ntile, kMlpTrainBlocks);
     HIP_TRY(ensure_gpart(m, blocks));
     HIP_TRY(launch_net_gradient(m->wbf, feats, h->rowof, h->col, h->val, h->plain.r, lh, p0, p1,
-                                tile0, ntile, 1, (int64_t)1 << 62, blocks, m->gpart, grad, loss,
+                                tile0, ntile, 1, (int64_t)1 << 62, blocks, m->gpart, m->gsum, grad,
+                                loss,
                                 h->stream));
     return MC_OK;
 }
@@ -1410,7 +1579,8 @@ mc_status mc_mlp_adam_step(mc_mlp_t m, const float *grad, float lr) {
 
 mc_status mc_mlp_train(mc_mlp_t m, mc_expmv_t h, const float *feats, const float *lh,
                        int32_t steps, int64_t batch, float lr, float *loss_host) {
-    if (!m || !h || !feats || !lh || steps < 1 || batch < 16 || !(lr > 0.0f))
+    fault_scope_begin();
+    if (!m || !h || h->stencil || !feats || !lh || steps < 1 || batch < 16 || !(lr > 0.0f))
         return MC_ERR_INVALID_ARG;
     if (h->nnz == 0) return MC_OK;
     HIP_TRY(hipSetDevice(h->dev));
@@ -1424,7 +1594,7 @@ mc_status mc_mlp_train(mc_mlp_t m, mc_expmv_t h, const float *feats, const float
     int64_t stride = (int64_t)(0.6180339887498949 * (double)tmod) | 1;
     while (stride > 1 && gcd64(stride, tmod) != 1) stride += 2;
     if (stride < 1 || stride >= tmod) stride = 1;
-    const int blocks = mlp_blocks(ntile, 1024);
+    const int blocks = mlp_blocks(ntile, kMlpTrainBlocks);
     HIP_TRY(ensure_gpart(m, blocks));
     float *dloss = nullptr;
     HIP_TRY(dalloc(&dloss, steps));
@@ -1433,7 +1603,7 @@ mc_status mc_mlp_train(mc_mlp_t m, mc_expmv_t h, const float *feats, const float
         const int64_t tile0 = ((int64_t)s * ntile % tmod) * stride % tmod;
         hipError_t e = launch_net_gradient(m->wbf, feats, h->rowof, h->col, h->val, h->plain.r,
                                            lh, 0, h->nnz, tile0, ntile, stride, tmod, blocks,
-                                           m->gpart, m->grad, dloss + s, h->stream);
+                                           m->gpart, m->gsum, m->grad, dloss + s, h->stream);
         if (e == hipSuccess) {
             m->step += 1;
             e = launch_adam(m->grad, m->w, m->m, m->v, m->wbf, lr, m->step, h->stream);
@@ -1461,7 +1631,8 @@ void mc_learn_default_opts(mc_learn_opts *o) {
 
 mc_status mc_expmv_learn_proposal(mc_expmv_t h, const void *v, const mc_learn_opts *opts,
                                   mc_learn_report *rep) {
-    if (!h || !v) return MC_ERR_INVALID_ARG;
+    fault_scope_begin();
+    if (!h || h->stencil || !v) return MC_ERR_INVALID_ARG;
     mc_learn_opts o;
     mc_learn_default_opts(&o);
     if (opts) {
@@ -1573,7 +1744,7 @@ mc_status run_forward(mc_expmv_s *h, const void *v, int64_t w0, int64_t nwalk, d
         size_t bytes = 0;
         HIP_TRY(launch_fwd_cdf(n, v, fp32, h->fwd_abs, h->fwd_sign, h->fwd_cdf, h->fwd_guide, nullptr, bytes,
                                h->stream));
-        HIP_TRY(hipMalloc(&h->fwd_temp, bytes > 0 ? bytes : 1));
+        HIP_TRY(dev_malloc(&h->fwd_temp, bytes > 0 ? bytes : 1));
         h->fwd_temp_bytes = bytes;
     }
     const int64_t chunks = (nwalk + kFwdChunk - 1) / kFwdChunk;
@@ -1635,7 +1806,8 @@ extern "C" {
 
 mc_status mc_expmv_forward(mc_expmv_t h, const void *v, int64_t n_walkers, double *est,
                            double *stderr_, double *sum_out) {
-    if (!h) return MC_ERR_INVALID_ARG;
+    fault_scope_begin();
+    if (!h || h->stencil) return MC_ERR_INVALID_ARG;
     return run_forward(h, v, 0, n_walkers, est, stderr_, sum_out, false, nullptr, nullptr,
                        nullptr, nullptr, nullptr);
 }
@@ -1643,7 +1815,8 @@ mc_status mc_expmv_forward(mc_expmv_t h, const void *v, int64_t n_walkers, doubl
 mc_status mc_expmv_forward_trace(mc_expmv_t h, const void *v, int64_t w0, int64_t count,
                                  int32_t *start, int32_t *end, uint32_t *events, uint32_t *jumps,
                                  double *y) {
-    if (!h || !start || !end || !events || !jumps || !y) return MC_ERR_INVALID_ARG;
+    fault_scope_begin();
+    if (!h || h->stencil || !start || !end || !events || !jumps || !y) return MC_ERR_INVALID_ARG;
     if (!h->fwd_acc && h->n > 0) HIP_TRY(dalloc(&h->fwd_acc, h->n));
     return run_forward(h, v, w0, count, h->fwd_acc, nullptr, nullptr, true, start, end, events,
                        jumps, y);

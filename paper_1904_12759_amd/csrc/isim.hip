@@ -16,6 +16,7 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include "alloc.hpp"
 #include "mc_internal.hpp"
 
 namespace mc {
@@ -86,6 +87,7 @@ mc_status status_of(hipError_t e) {
 extern "C" mc_status mc_isim(int64_t n, const double *x, const double *y, int64_t k, double *out,
                              void *stream) {
     using namespace mc;
+    fault_scope_begin();
     if (!x || !y || !out || n < 1 || n > 0x7FFFFFFFll || k < 1 || k > n) return MC_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     double *keys = nullptr, *keys_sorted = nullptr, *res = nullptr;
@@ -97,17 +99,17 @@ extern "C" mc_status mc_isim(int64_t n, const double *x, const double *y, int64_
     hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, sort_bytes, keys, keys_sorted,
                                                                 vals, order, nn, 0, 64, s);
     if (e == hipSuccess) e = hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, cnt, cum, kk, s);
-    if (e == hipSuccess) e = hipMalloc((void **)&keys, sizeof(double) * 2 * (size_t)n);
-    if (e == hipSuccess) e = hipMalloc((void **)&keys_sorted, sizeof(double) * 2 * (size_t)n);
-    if (e == hipSuccess) e = hipMalloc((void **)&vals, sizeof(int32_t) * 2 * (size_t)n);
-    if (e == hipSuccess) e = hipMalloc((void **)&order, sizeof(int32_t) * 2 * (size_t)n);
-    if (e == hipSuccess) e = hipMalloc((void **)&rank, sizeof(int32_t) * 2 * (size_t)n);
-    if (e == hipSuccess) e = hipMalloc((void **)&cnt, sizeof(int32_t) * (size_t)k);
-    if (e == hipSuccess) e = hipMalloc((void **)&cum, sizeof(int32_t) * (size_t)k);
-    if (e == hipSuccess) e = hipMalloc((void **)&res, sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&flag, sizeof(uint32_t));
+    if (e == hipSuccess) e = dev_malloc((void **)&keys, sizeof(double) * 2 * (size_t)n);
+    if (e == hipSuccess) e = dev_malloc((void **)&keys_sorted, sizeof(double) * 2 * (size_t)n);
+    if (e == hipSuccess) e = dev_malloc((void **)&vals, sizeof(int32_t) * 2 * (size_t)n);
+    if (e == hipSuccess) e = dev_malloc((void **)&order, sizeof(int32_t) * 2 * (size_t)n);
+    if (e == hipSuccess) e = dev_malloc((void **)&rank, sizeof(int32_t) * 2 * (size_t)n);
+    if (e == hipSuccess) e = dev_malloc((void **)&cnt, sizeof(int32_t) * (size_t)k);
+    if (e == hipSuccess) e = dev_malloc((void **)&cum, sizeof(int32_t) * (size_t)k);
+    if (e == hipSuccess) e = dev_malloc((void **)&res, sizeof(double));
+    if (e == hipSuccess) e = dev_malloc((void **)&flag, sizeof(uint32_t));
     const size_t temp_bytes = sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
-    if (e == hipSuccess) e = hipMalloc(&temp, temp_bytes ? temp_bytes : 1);
+    if (e == hipSuccess) e = dev_malloc(&temp, temp_bytes ? temp_bytes : 1);
     const unsigned g = (unsigned)((n + 255) / 256);
     if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(uint32_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)k, s);

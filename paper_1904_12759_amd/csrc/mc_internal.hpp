@@ -101,7 +101,20 @@ struct InstArgs {
     uint32_t key0, key1, inst, max_events;
     double cond_max_rt;        // first-jump conditioning for start nodes with t <= this / r
     uint32_t resort;           // relabelled walks: re-sort a wave's walkers every this many events (0: never)
+    uint32_t qmc;              // 1: first event from the randomised rank-1 lattice (backward walks)
+    // matrix-free 7-point stencil (fx null: the tables above): node x = i + nx (j + ny k),
+    // fx[x] / fy[x] / fz[x] the rate between x and its +x / +y / +z neighbour (0 on the
+    // last plane of that axis), diag[x] = a_xx
+    const double *fx, *fy, *fz, *diag;
+    uint32_t nx, nxy;
 };
+
+// Randomised rank-1 lattice of the first event: replicates of B = 2^b walker
+// ordinals (b = 10 with FP32 weights, 9 with FP64: one replicate per chunk),
+// Korobov generator a (119 for B = 512, 149 for B = 1024), shift drawn from
+// the Philox counter (kQmcShiftMark, replicate, start node, instance).
+constexpr uint32_t kQmcShiftMark = 0xFFFFFFFEu;
+__host__ __device__ constexpr uint32_t qmc_bits(bool fp32) { return fp32 ? 10u : 9u; }
 
 // Per-walker record (parity checks only).
 struct TraceOut {
@@ -130,6 +143,7 @@ struct WalkArgs {
     uint32_t *flags;
     TraceOut trace;
     bool cond;                 // first-jump conditioning
+    bool qmc;                  // standard errors from the replicate (chunk) means
     // entries with their own walker counts (null otherwise): entry e owns the
     // chunk slots var_task[e] .. var_task[e+1]-1 and var_nwalk[e] walkers; a task
     // takes `group` consecutive slots of the var_slots
@@ -223,6 +237,7 @@ __host__ __device__ constexpr uint32_t fin_lanes(int64_t chunks) {
 }
 // Largest LDS budget for hot rows (bytes per block).
 constexpr uint32_t kMaxHotBytes = 65536;
+constexpr uint32_t kLdsPerCu = 160 * 1024;   // LDS bytes of one gfx950 compute unit
 
 // Entries packed into one task when each of k entries has nwalk walkers.  A task
 // runs its entries in LDS sessions of up to chunk_walkers() listed walkers, so
@@ -274,6 +289,7 @@ int launch_walk_grid(int64_t ntasks, int block);
 hipError_t launch_walk(const WalkArgs &a, int mode, bool fp32, bool prop, bool trace,
                        int block, hipStream_t s);
 hipError_t launch_finalize(const WalkArgs &a, hipStream_t s);
+hipError_t launch_math_eval(int fn, const double *x, double *y, int64_t n, hipStream_t s);
 
 // batched launch (batch.hip): queue reset, persistent walk, finalize
 // Instances of one weight mode and precision, contiguous in the batch.
@@ -293,6 +309,9 @@ hipError_t launch_batch(const BatchArgs &a, const BatchClass *classes, int nclas
 constexpr int kMlpParams = 64 * 8 + 64 + 64 * 64 + 64 + 64 + 1;
 int mlp_grad_stride();
 int mlp_blocks(int64_t ntile, int max_blocks);
+// Blocks (of four waves) of a training step: each wave then accumulates several
+// 16-edge tiles, and the per-wave partials to reduce stay few.
+constexpr int kMlpTrainBlocks = 256;
 hipError_t launch_rowof(int64_t n, const int64_t *rowptr, int32_t *rowof, hipStream_t s);
 hipError_t launch_features(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
                            const RowRec *rows, const double *r, const void *v, int v_fp32,
@@ -306,7 +325,8 @@ hipError_t launch_net_gradient(const uint16_t *wbf, const float *feats, const in
                                const int32_t *col, const double *val, const double *r,
                                const float *lh, int64_t p0, int64_t p1, int64_t tile0,
                                int64_t ntile, int64_t stride, int64_t tmod, int blocks,
-                               float *gpart, float *grad, float *loss, hipStream_t s);
+                               float *gpart, double *gsum, float *grad, float *loss,
+                               hipStream_t s);
 hipError_t launch_adam(const float *grad, float *w, float *m, float *v, uint16_t *wbf, float lr,
                        int step, hipStream_t s);
 hipError_t launch_mlp_init(float *w, float *m, float *v, uint16_t *wbf, uint64_t seed,
@@ -327,6 +347,9 @@ hipError_t launch_fat_slots(int64_t n, int64_t nnz, const Tables &tb, bool walk_
                             hipStream_t s);
 
 // setup kernels (setup.hip)
+hipError_t launch_check_stencil(int64_t n, int64_t nx, int64_t ny, const double *fx, const double *fy,
+                                const double *fz, const double *diag, uint32_t *flags,
+                                unsigned long long *nslots, hipStream_t s);
 hipError_t launch_check_rowptr(int64_t n, int64_t nnz, const int64_t *rowptr, uint32_t *flags,
                                hipStream_t s);
 hipError_t launch_setup_rows(int64_t n, const int64_t *rowptr, const int32_t *col,

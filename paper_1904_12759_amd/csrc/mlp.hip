@@ -158,6 +158,7 @@ __global__ __launch_bounds__(256) void k_net(NetArgs a) {
     __shared__ uint16_t s_dz2[WAVES][H][16];   // dL/dz2 (bf16), [feature][edge]
     __shared__ float s_dz1[WAVES][H][16];      // dL/dz1, [feature][edge]
     __shared__ float s_x[WAVES][NIN][16];      // inputs, [feature][edge]
+    __shared__ float s_g[TRAIN ? GSTRIDE : 1]; // the block's gradient partial
 
     for (int k = threadIdx.x; k < H * NIN; k += blockDim.x) s_w1[k] = bf2f(a.wbf[OFF_W1 + k]);
     for (int k = threadIdx.x; k < H; k += blockDim.x) {
@@ -321,13 +322,6 @@ __global__ __launch_bounds__(256) void k_net(NetArgs a) {
     }
 
     if constexpr (TRAIN) {
-        float *g = a.gpart + wave_id * GSTRIDE;
-        for (int c = 0; c < NIN; ++c) g[OFF_W1 + lane * NIN + c] = gw1[c];
-        g[OFF_B1 + lane] = gb1;
-        for (int mt = 0; mt < 4; ++mt)
-            for (int nk = 0; nk < 4; ++nk)
-                for (int i = 0; i < 4; ++i)
-                    g[OFF_W2 + (16 * mt + 4 * q + i) * H + 16 * nk + e] = gw2[mt][nk][i];
         // per-feature sums over the 16 edges of each quarter
         for (int k = 0; k < 16; ++k) {
             float s3 = gw3[k], s2 = gb2[k];
@@ -335,36 +329,74 @@ __global__ __launch_bounds__(256) void k_net(NetArgs a) {
                 s3 += __shfl_xor(s3, off, 64);
                 s2 += __shfl_xor(s2, off, 64);
             }
-            if (e == 0) {
-                const int f = 16 * (k >> 2) + 4 * q + (k & 3);
-                g[OFF_W3 + f] = s3;
-                g[OFF_B2 + f] = s2;
-            }
+            gw3[k] = s3;
+            gb2[k] = s2;
         }
         for (int off = 1; off < 64; off <<= 1) {
             gb3 += __shfl_xor(gb3, off, 64);
             lsum += __shfl_xor(lsum, off, 64);
             psum += __shfl_xor(psum, off, 64);
         }
-        if (lane == 0) {
-            g[OFF_B3] = gb3;
-            g[kMlpParams] = lsum;
-            g[kMlpParams + 1] = psum;
+        // the block's partial: the waves' partials added into LDS in wave order
+        for (int step = 0; step < WAVES; ++step) {
+            if (wv == step) {
+                const bool first = step == 0;
+                auto put = [&](int j, float x) { s_g[j] = first ? x : s_g[j] + x; };
+                for (int c = 0; c < NIN; ++c) put(OFF_W1 + lane * NIN + c, gw1[c]);
+                put(OFF_B1 + lane, gb1);
+                for (int mt = 0; mt < 4; ++mt)
+                    for (int nk = 0; nk < 4; ++nk)
+                        for (int i = 0; i < 4; ++i)
+                            put(OFF_W2 + (16 * mt + 4 * q + i) * H + 16 * nk + e, gw2[mt][nk][i]);
+                if (e == 0)
+                    for (int k = 0; k < 16; ++k) {
+                        const int f = 16 * (k >> 2) + 4 * q + (k & 3);
+                        put(OFF_W3 + f, gw3[k]);
+                        put(OFF_B2 + f, gb2[k]);
+                    }
+                if (lane == 0) {
+                    put(OFF_B3, gb3);
+                    put(kMlpParams, lsum);
+                    put(kMlpParams + 1, psum);
+                }
+            }
+            __syncthreads();
         }
+        float *g = a.gpart + (int64_t)blockIdx.x * GSTRIDE;
+        for (int j = threadIdx.x; j < GSTRIDE; j += blockDim.x) g[j] = s_g[j];
     }
 }
 
-// Sum the per-wave partials in wave order (FP64), normalise by sum p.
-__global__ void k_grad_reduce(int64_t nwaves, const float *__restrict__ gpart,
-                              float *__restrict__ grad, float *__restrict__ loss) {
+// Sum the per-block partials (FP64) in a fixed order: thread (column j, split s)
+// of a block adds the partials of blocks s, s + RS, s + 2 RS, ... of its column,
+// then the RS split sums of a column meet in a fixed tree in LDS.  16 columns
+// (parameters, then sum p (b - t)^2 and sum p) per block.
+constexpr int RS = 16;
+__global__ __launch_bounds__(256) void k_grad_reduce(int64_t nparts, const float *__restrict__ gpart,
+                                                     double *__restrict__ gsum) {
+    __shared__ double sh[RS][16];
+    const int pl = threadIdx.x & 15, sp = threadIdx.x >> 4;
+    const int j = blockIdx.x * 16 + pl;
+    double acc = 0.0;
+    if (j < GSTRIDE)
+        for (int64_t w = sp; w < nparts; w += RS) acc += (double)gpart[w * GSTRIDE + j];
+    sh[sp][pl] = acc;
+    __syncthreads();
+    for (int h = RS / 2; h > 0; h >>= 1) {
+        if (sp < h) sh[sp][pl] += sh[sp + h][pl];
+        __syncthreads();
+    }
+    if (sp == 0 && j < GSTRIDE) gsum[j] = sh[0][pl];
+}
+
+// Gradient and loss: the sums divided by sum p, rounded to FP32.
+__global__ void k_grad_scale(const double *__restrict__ gsum, float *__restrict__ grad,
+                             float *__restrict__ loss) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= kMlpParams + 1) return;
-    double ps = 0.0;
-    for (int64_t w = 0; w < nwaves; ++w) ps += (double)gpart[w * GSTRIDE + kMlpParams + 1];
+    const double ps = gsum[kMlpParams + 1];
     const int col = j < kMlpParams ? j : kMlpParams;
-    double s = 0.0;
-    for (int64_t w = 0; w < nwaves; ++w) s += (double)gpart[w * GSTRIDE + col];
-    const double v = ps > 0.0 ? s / ps : 0.0;
+    const double v = ps > 0.0 ? gsum[col] / ps : 0.0;
     if (j < kMlpParams) grad[j] = (float)v;
     else if (loss) *loss = (float)v;
 }
@@ -464,13 +496,18 @@ hipError_t launch_net_gradient(const uint16_t *wbf, const float *feats, const in
                                const int32_t *col, const double *val, const double *r,
                                const float *lh, int64_t p0, int64_t p1, int64_t tile0,
                                int64_t ntile, int64_t stride, int64_t tmod, int blocks,
-                               float *gpart, float *grad, float *loss, hipStream_t s) {
+                               float *gpart, double *gsum, float *grad, float *loss,
+                               hipStream_t s) {
     NetArgs a{wbf, feats, rowof, col, val, r, lh, p0, p1, tile0, ntile, stride, tmod, nullptr, gpart};
     hipLaunchKernelGGL(k_net<true>, dim3((unsigned)blocks), dim3(64 * WAVES), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, s,
-                       (int64_t)blocks * WAVES, gpart, grad, loss);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((GSTRIDE + 15) / 16), dim3(256), 0, s, (int64_t)blocks,
+                       gpart, gsum);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grad_scale, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, s, gsum, grad,
+                       loss);
     return hipGetLastError();
 }
 

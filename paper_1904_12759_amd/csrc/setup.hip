@@ -239,6 +239,42 @@ hipError_t launch_relabel_apply(int64_t n, const int64_t *rowptr, const uint32_t
     return hipGetLastError();
 }
 
+// Face rates of a matrix-free 7-point stencil: finite and non-negative, zero on the
+// last plane of their axis (no neighbour there); a_xx finite.  Counts the jump
+// slots (positive face rates, each seen from both sides) into *nslots.
+__global__ void k_check_stencil(int64_t n, int64_t nx, int64_t ny, const double *__restrict__ fx,
+                                const double *__restrict__ fy, const double *__restrict__ fz,
+                                const double *__restrict__ diag, uint32_t *flags,
+                                unsigned long long *nslots) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+    const int64_t nz = n / (nx * ny);
+    const double f[3] = {fx[i], fy[i], fz[i]};
+    const bool last[3] = {x == nx - 1, y == ny - 1, z == nz - 1};
+    uint32_t bad = 0;
+    unsigned long long cnt = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (!isfinite(f[a])) bad |= F_NONFINITE;
+        else if (f[a] < 0.0) bad |= F_NOT_METZLER;
+        else if (f[a] > 0.0 && last[a]) bad |= F_INVALID_ARG;
+        if (f[a] > 0.0) cnt += 2;
+    }
+    if (!isfinite(diag[i])) bad |= F_NONFINITE;
+    if (bad) atomicOr(flags, bad);
+    if (cnt) atomicAdd(nslots, cnt);
+}
+
+hipError_t launch_check_stencil(int64_t n, int64_t nx, int64_t ny, const double *fx, const double *fy,
+                                const double *fz, const double *diag, uint32_t *flags,
+                                unsigned long long *nslots, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int64_t grid = (n + 255) / 256;
+    hipLaunchKernelGGL(k_check_stencil, dim3((unsigned)grid), dim3(256), 0, s, n, nx, ny, fx, fy, fz,
+                       diag, flags, nslots);
+    return hipGetLastError();
+}
+
 hipError_t launch_check_rowptr(int64_t n, int64_t nnz, const int64_t *rowptr, uint32_t *flags,
                                hipStream_t s) {
     const int64_t threads = n + 1;

@@ -28,7 +28,8 @@ namespace {
 // jump totals are reduced per block and written to counters[2*block] without
 // atomics (same-address atomics from every wave serialise across the chip).
 // Dynamic LDS: one GroupLds per wave.
-template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND, bool RESORT, int FAT>
+template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND, bool RESORT, int FAT,
+          bool QMC = false, bool STENCIL = false>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     using WT = typename WeightT<FP32>::T;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
         const uint32_t cnt = (uint32_t)(rem < (int64_t)a.chunk ? rem : (int64_t)a.chunk);
         TraceOut tr = a.trace;
         tr.base = wbase;
-        run_group<MODE, FP32, PROP, TRACE, LOC, COND, RESORT, FAT>(P, a.idx, a.n, G, (uint32_t)(a.w0 + wbase), cnt, tr,
+        run_group<MODE, FP32, PROP, TRACE, LOC, COND, RESORT, FAT, QMC, STENCIL>(P, a.idx, a.n, G, (uint32_t)(a.w0 + wbase), cnt, tr,
                                            out, L, my_events, my_jumps, err);
     }
     for (int off = 1; off < WAVE; off <<= 1) err |= __shfl_xor(err, off, WAVE);
@@ -155,6 +156,55 @@ __global__ __launch_bounds__(kFinLanesMax) void k_finalize_var(int64_t k, const 
     }
 }
 
+// Standard errors of lattice (randomised quasi-Monte Carlo) estimates from the R
+// replicate means of an entry, one replicate per chunk partial (count n_c, mean
+// m_c): se^2 = R/(R-1) sum_c (n_c/N)^2 (m_c - est)^2, N = sum_c n_c, after the
+// finalize kernel has written est.  One wavefront per entry: lane l takes chunks
+// l, l + 64, ... in order, then the wave's fixed tree.  Entries with a single
+// replicate keep the i.i.d. standard error.  part + 3 * first[e] holds entry e's
+// R = first[e+1] - first[e] partials (first null: R = chunks for every entry).
+__global__ __launch_bounds__(256) void k_qmc_stderr(int64_t k, int64_t chunks,
+                                                    const int64_t *__restrict__ first,
+                                                    const double *__restrict__ part,
+                                                    const double *__restrict__ est,
+                                                    double *__restrict__ se) {
+    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (e >= k) return;                       // whole waves leave together
+    const int64_t c0 = first ? first[e] : e * chunks;
+    const int64_t R = first ? first[e + 1] - first[e] : chunks;
+    if (R < 2) return;
+    const double *p = part + 3 * c0;
+    double nsum = 0.0;
+    for (int64_t c = lane; c < R; c += WAVE) nsum += p[3 * c];
+    nsum = wave_sum_f64(nsum);
+    const double mean = est[e];
+    double acc = 0.0;
+    for (int64_t c = lane; c < R; c += WAVE) {
+        const double wc = p[3 * c] / nsum;
+        const double dm = p[3 * c + 1] - mean;
+        acc += wc * wc * dm * dm;
+    }
+    acc = wave_sum_f64(acc);
+    if (lane == 0) se[e] = sqrt(acc * (double)R / (double)(R - 1));
+}
+
+__global__ void k_math_eval(int fn, const double *__restrict__ x, double *__restrict__ y,
+                            int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double a = x[i];
+    y[i] = fn == 0 ? log_unit(a) : fn == 1 ? exp_f64(a) : one_minus_exp_neg(a);
+}
+
+hipError_t launch_math_eval(int fn, const double *x, double *y, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int64_t grid = (n + 255) / 256;
+    if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_math_eval, dim3((unsigned)grid), dim3(256), 0, s, fn, x, y, n);
+    return hipGetLastError();
+}
+
 namespace {
 
 int walk_grid(int64_t ntasks, int block) {
@@ -167,6 +217,19 @@ int walk_grid(int64_t ntasks, int block) {
 
 template <int MODE, bool FP32, bool PROP, bool TRACE, int FAT>
 void launch_shape(const WalkArgs &a, dim3 grid, int block, size_t lds, hipStream_t s) {
+    // the randomised-lattice first event has kernels of its own (plain layout, no
+    // conditioning: checked at create), so that the others keep their code
+    if (a.P.qmc) {
+        hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, false, false, false, FAT, true>), grid, dim3(block), lds, s, a);
+        return;
+    }
+    // the matrix-free stencil walk (plain proposal, input order: checked at create)
+    if constexpr (!PROP && FAT != 1) {
+        if (a.P.fx) {
+            hipLaunchKernelGGL((k_walk<MODE, FP32, false, TRACE, false, false, false, 0, false, true>), grid, dim3(block), lds, s, a);
+            return;
+        }
+    }
     // the wave re-sort has kernels of its own, so that it costs the others no registers
     if (a.P.perm && a.P.resort) {
         if (a.cond) hipLaunchKernelGGL((k_walk<MODE, FP32, PROP, TRACE, true, true, true, FAT>), grid, dim3(block), lds, s, a);
@@ -189,7 +252,19 @@ hipError_t launch_t(const WalkArgs &a, int block, hipStream_t s) {
     const size_t task_lds = a.cond ? sizeof(GroupLds<WT, true>) : sizeof(GroupLds<WT, false>);
     const size_t lds = (size_t)(block / WAVE) * task_lds +
                        (size_t)a.P.hot * (sizeof(RowRec) + sizeof(WT));
-    const dim3 grid((unsigned)walk_grid(a.ntasks, block));
+    dim3 grid((unsigned)walk_grid(a.ntasks, block));
+    if (a.P.hot) {
+        // hot rows are staged once per block: launch only the blocks that stay
+        // resident (LDS per CU), each looping over many tasks
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cus > 0) {
+            const int64_t per_cu = (int64_t)kLdsPerCu / (int64_t)(lds + 1024);
+            const int64_t resident = (int64_t)cus * (per_cu > 1 ? per_cu : 1);
+            if ((int64_t)grid.x > resident) grid.x = (unsigned)resident;
+        }
+    }
     // 64-byte slots get kernels of their own, so that the others keep their code;
     // the per-walker trace (parity checks only) tests the pointer instead
     if constexpr (TRACE) launch_shape<MODE, FP32, PROP, TRACE, 2>(a, grid, block, lds, s);
@@ -239,6 +314,9 @@ hipError_t launch_finalize(const WalkArgs &a, hipStream_t s) {
         const uint32_t L = fin_lanes(a.var_chunks_max);
         hipLaunchKernelGGL(k_finalize_var, dim3((unsigned)a.k), dim3(L > WAVE ? L : WAVE), 0, s, a.k,
                            a.var_task, a.part, a.est, a.se);
+        if (a.qmc && a.se)
+            hipLaunchKernelGGL(k_qmc_stderr, dim3((unsigned)((a.k + 3) / 4)), dim3(256), 0, s,
+                               a.k, (int64_t)0, a.var_task, a.part, a.est, a.se);
         return hipGetLastError();
     }
     if (a.chunks <= 1 || a.k == 0) return hipSuccess;
@@ -248,6 +326,12 @@ hipError_t launch_finalize(const WalkArgs &a, hipStream_t s) {
     const int64_t grid = (threads + block - 1) / block;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)grid), dim3(block), 0, s, a.k, a.chunks, a.part,
                        a.est, a.se);
+    if (a.qmc && a.se) {
+        const int64_t g2 = (a.k + 3) / 4;
+        if (g2 > 0x7FFFFFFF) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_qmc_stderr, dim3((unsigned)g2), dim3(256), 0, s, a.k, a.chunks,
+                           (const int64_t *)nullptr, a.part, a.est, a.se);
+    }
     return hipGetLastError();
 }
 

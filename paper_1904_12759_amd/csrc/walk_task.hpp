@@ -29,7 +29,8 @@ __device__ __forceinline__ double sconst(double c) {
 // Natural logarithm of u in (0, 1].  With u = m 2^e, m in [1/sqrt2, sqrt2),
 // log u = e ln2 + 2 atanh(f), f = (m-1)/(m+1), |f| < 0.1716, and atanh(f)/f is
 // the Taylor series sum_k f^{2k}/(2k+1), kept to f^24 (truncation < 1e-19).
-// Within about 2 ulp of the correctly rounded logarithm.
+// Within 3 ulp of the correctly rounded logarithm (the largest errors, about
+// 2.5 ulp, where e ln2 and 2 atanh(f) partly cancel, u just below 1/sqrt2).
 __device__ __forceinline__ double log_unit(double u) {
     int e;
     double m = frexp(u, &e);
@@ -126,6 +127,22 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     return U4{c0, c1, c2, c3};
 }
 
+// First-event words of walker w from the randomised rank-1 lattice: with
+// o = Philox of the replicate's shift counter, B = 2^b and j = w mod B,
+//   64-bit word of U:  j 2^(64-b) + (o.x 2^32 + o.y)   mod 2^64
+//   slot word:         j g1 2^(32-b) + o.z             mod 2^32
+//   alias word:        j g2 2^(32-b) + o.w             mod 2^32
+// with (1, g1, g2) = (1, a, a^2 mod B): every coordinate is a uniform shift of
+// the lattice point modulo 1.
+__device__ __forceinline__ U4 lattice_words(U4 o, uint32_t w, uint32_t b) {
+    const uint32_t g1 = b == 9u ? 119u : 149u;
+    const uint32_t g2 = (g1 * g1) & ((1u << b) - 1u);
+    const uint32_t j = w & ((1u << b) - 1u);
+    const uint64_t u0 = ((uint64_t)j << (64u - b)) + (((uint64_t)o.x << 32) | o.y);
+    return U4{(uint32_t)(u0 >> 32), (uint32_t)u0, ((j * g1) << (32u - b)) + o.z,
+              ((j * g2) << (32u - b)) + o.w};
+}
+
 template <bool FP32>
 struct WeightT {
     using T = double;
@@ -217,6 +234,64 @@ __device__ __forceinline__ bool jump_fat(const InstArgs &P, uint32_t js, uint32_
     begin = keep ? q.rs.begin : q.ra.begin;
     dx = (typename WeightT<FP32>::T)(keep ? q.ds : q.da);
     return keep;
+}
+
+// Matrix-free 7-point stencil: the six face rates of node x in the column order of
+// its matrix row (-z, -y, -x, +x, +y, +z; 0 where the grid ends: fx of the last
+// x-plane is 0, so fx[x - 1] is 0 on the first, and likewise for y; z needs the
+// bound), and the neighbour behind face k.
+__device__ __forceinline__ void stencil_faces(const InstArgs &P, uint32_t x, double f[6]) {
+    f[0] = x >= P.nxy ? P.fz[x - P.nxy] : 0.0;
+    f[1] = x >= P.nx ? P.fy[x - P.nx] : 0.0;
+    f[2] = x >= 1u ? P.fx[x - 1u] : 0.0;
+    f[3] = P.fx[x];
+    f[4] = P.fy[x];
+    f[5] = P.fz[x];
+}
+
+__device__ __forceinline__ uint32_t stencil_neighbour(const InstArgs &P, uint32_t x, int k) {
+    return k == 0 ? x - P.nxy : k == 1 ? x - P.nx : k == 2 ? x - 1u : k == 3 ? x + 1u
+           : k == 4 ? x + P.nx : x + P.nxy;
+}
+
+// The state record of node x from the face rates: r summed in column order (as the
+// row split sums a matrix row), 1/r, the number of exits and d = a_xx + r.
+template <bool FP32>
+__device__ __forceinline__ void stencil_row(const InstArgs &P, uint32_t x, double &inv_r,
+                                            uint32_t &deg, typename WeightT<FP32>::T &dx) {
+    double f[6];
+    stencil_faces(P, x, f);
+    double r = 0.0;
+    uint32_t k = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        r = r + f[i];
+        k += f[i] > 0.0 ? 1u : 0u;
+    }
+    deg = k;
+    inv_r = k ? 1.0 / r : 0.0;
+    dx = (typename WeightT<FP32>::T)(P.diag[x] + r);
+}
+
+// The jump from x: the first face (column order) whose running sum of rates exceeds
+// u r, u = o2 2^-32 in [0, 1), or the last face with a rate when rounding leaves
+// u r at or above the sum (the inverse-CDF rule; zero faces never cross).
+__device__ __forceinline__ uint32_t stencil_jump(const InstArgs &P, uint32_t x, uint32_t o2) {
+    double f[6];
+    stencil_faces(P, x, f);
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) r = r + f[i];
+    const double target = ((double)o2 * 0x1p-32) * r;
+    double cum = 0.0;
+    int sl = -1, last = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        cum = cum + f[i];
+        if (f[i] > 0.0) last = i;
+        if (sl < 0 && target < cum) sl = i;
+    }
+    return stencil_neighbour(P, x, sl < 0 ? last : sl);
 }
 
 // Walk id of an original node, and back (identity without relabelling).
@@ -499,7 +574,7 @@ __device__ __forceinline__ void put_stats(const GroupOut &out, uint32_t g, doubl
 }
 
 template <int MODE, bool FP32, bool PROP, bool TRACE, bool LOC, bool COND, bool RESORT = false,
-          int FAT = 0>
+          int FAT = 0, bool QMC = false, bool STENCIL = false>
 __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx, int64_t n,
                                           uint32_t G, uint32_t ord0, uint32_t cnt,
                                           const TraceOut &tr, const GroupOut &out,
@@ -545,8 +620,15 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         if (nd >= 0 && nd < n) {
             node = (uint32_t)nd;
             const uint32_t x0 = walk_id<LOC>(P, node);
-            const RowRec r0 = row_at<LOC>(P, x0);
-            const WT d0 = d_at<FP32, LOC>(P, x0);
+            RowRec r0;
+            WT d0;
+            if constexpr (STENCIL) {
+                stencil_row<FP32>(P, x0, r0.inv_r, r0.deg, d0);
+                r0.begin = 0u;
+            } else {
+                r0 = row_at<LOC>(P, x0);
+                d0 = d_at<FP32, LOC>(P, x0);
+            }
             const WT v0 = load_v<FP32>(P.v, node);
             K = (double)(wexp<FP32>(final_term<MODE, FP32>(d0, 0.0, 0, P)) * v0);
             // first-jump conditioning (start nodes with exits and r t <= cond_max_rt):
@@ -628,6 +710,14 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             } else {
                 // U >= e0  <=>  m + 1 >= e0 2^53 (U = (m+1) 2^-53 exactly), i.e. m + 1 >= ceil(e0 2^53)
                 const uint64_t m_thr = (uint64_t)ceil(eg * 0x1p53);
+                // lattice first events: a chunk starting on a replicate boundary is one
+                // replicate (every run but a per-walker trace from an unaligned
+                // ordinal), whose shift the whole entry shares
+                const uint32_t qb = qmc_bits(FP32);
+                const bool one_rep = QMC && (og & ((1u << qb) - 1u)) == 0u;
+                const U4 shift = one_rep ? philox(kQmcShiftMark, og >> qb, node, P.inst, P.key0,
+                                                  P.key1)
+                                         : U4{0u, 0u, 0u, 0u};
                 for (uint32_t b = 0; b < cg; b += WAVE) {
                     if (nlist + WAVE > C) {
                         fits = false;
@@ -637,7 +727,16 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     const bool valid = w < cg;
                     bool go = false;
                     if (valid) {
-                        const U4 o = philox(0u, og + w, node, P.inst, P.key0, P.key1);
+                        const uint32_t wo = og + w;
+                        U4 o;
+                        if constexpr (QMC) {
+                            o = lattice_words(one_rep ? shift
+                                                      : philox(kQmcShiftMark, wo >> qb, node, P.inst,
+                                                               P.key0, P.key1),
+                                              wo, qb);
+                        } else {
+                            o = philox(0u, wo, node, P.inst, P.key0, P.key1);
+                        }
                         const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
                         go = m + 1ull >= m_thr;
                     }
@@ -685,11 +784,15 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         uint32_t deg = 0, begin = 0;
         WT dx = (WT)0;
         if (active) {
-            const RowRec rr = row_at<LOC>(P, x);
-            inv_r = rr.inv_r;
-            deg = rr.deg;
-            begin = rr.begin;
-            dx = d_at<FP32, LOC>(P, x);
+            if constexpr (STENCIL) {
+                stencil_row<FP32>(P, x, inv_r, deg, dx);
+            } else {
+                const RowRec rr = row_at<LOC>(P, x);
+                inv_r = rr.inv_r;
+                deg = rr.deg;
+                begin = rr.begin;
+                dx = d_at<FP32, LOC>(P, x);
+            }
         }
         uint32_t next = WAVE;
         uint32_t since_sort = 0;
@@ -729,7 +832,16 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     err |= F_WALK_LIMIT;
                     fin = true;
                 } else {
-                    const U4 o = philox(ev, wb + (code & 1023u), node, P.inst, P.key0, P.key1);
+                    const uint32_t wo = wb + (code & 1023u);
+                    U4 o;
+                    if constexpr (QMC) {
+                        const bool lat = ev == 0;
+                        o = philox(lat ? kQmcShiftMark : ev, lat ? wo >> qmc_bits(FP32) : wo, node,
+                                   P.inst, P.key0, P.key1);
+                        if (lat) o = lattice_words(o, wo, qmc_bits(FP32));
+                    } else {
+                        o = philox(ev, wo, node, P.inst, P.key0, P.key1);
+                    }
                     ++ev;
                     const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
                     double S;
@@ -763,8 +875,11 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                         const uint32_t sl = (uint32_t)(((uint64_t)o.z * (uint64_t)deg) >> 32);
                         const uint32_t js = begin + sl;
                         // FAT: 0 separate tables, 1 64-byte slots, 2 whichever P holds
-                        bool keep;
-                        if constexpr (FAT == 1)
+                        bool keep = true;
+                        if constexpr (STENCIL) {
+                            x = stencil_jump(P, x, o.z);
+                            stencil_row<FP32>(P, x, inv_r, deg, dx);
+                        } else if constexpr (FAT == 1)
                             keep = jump_fat<FP32>(P, js, o.w, x, inv_r, deg, begin, dx);
                         else if constexpr (FAT == 2)
                             keep = P.fat ? jump_fat<FP32>(P, js, o.w, x, inv_r, deg, begin, dx)
@@ -818,11 +933,15 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     ev = 0;
                     ju = 0;
                     ka = 0;
-                    const RowRec rr = row_at<LOC>(P, x);
-                    inv_r = rr.inv_r;
-                    deg = rr.deg;
-                    begin = rr.begin;
-                    dx = d_at<FP32, LOC>(P, x);
+                    if constexpr (STENCIL) {
+                        stencil_row<FP32>(P, x, inv_r, deg, dx);
+                    } else {
+                        const RowRec rr = row_at<LOC>(P, x);
+                        inv_r = rr.inv_r;
+                        deg = rr.deg;
+                        begin = rr.begin;
+                        dx = d_at<FP32, LOC>(P, x);
+                    }
                 } else {
                     active = false;
                 }

@@ -279,3 +279,31 @@ def batched_instances(count: int = 64, seed: int = 4, nmin: float = 1e3, nmax: f
         else:
             out.append(Workload(f"inst{k}", a, t, v, None, walk_full, False))
     return out
+
+
+def stencil7_faces(a: CSR, nx: int, ny: int, nz: int):
+    """The face-rate form of a 7-point matrix on an nx x ny x nz grid (node
+    i + nx (j + ny k)): fx[x] = a(x, x+1) (0 on the last x-plane), fy[x] = a(x, x+nx),
+    fz[x] = a(x, x+nx ny), diag[x] = a(x, x): the entries themselves, copied."""
+    n = nx * ny * nz
+    assert a.n == n
+    rows = np.repeat(np.arange(n), np.diff(a.rowptr))
+    col = np.asarray(a.col, np.int64)
+    val = np.asarray(a.val, np.float64)
+    fx = np.zeros(n)
+    fy = np.zeros(n)
+    fz = np.zeros(n)
+    diag = np.zeros(n)
+    d = col - rows
+    xs = rows % nx
+    ys = (rows // nx) % ny
+    m = d == 1
+    m &= xs[:] < nx - 1
+    fx[rows[m]] = val[m]
+    m = (d == nx) & (ys < ny - 1)
+    fy[rows[m]] = val[m]
+    m = d == nx * ny
+    fz[rows[m]] = val[m]
+    m = d == 0
+    np.add.at(diag, rows[m], val[m])
+    return fx, fy, fz, diag

@@ -495,6 +495,40 @@ def test_relabel_and_hot_rows_do_not_change_results(fp32):
             assert np.array_equal(tg[key], tb[key]), key
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("lds,block", [(4096, 64), (32768, 64), (32768, 256), (65536, 256)])
+def test_hot_rows_in_lds_match_oracle(fp32, lds, block):
+    """The kernel that reads the hottest rows from LDS (staged once per block; with
+    256-thread blocks the grid holds only blocks that stay resident, each looping
+    over many tasks), against the oracle directly: per-walker final state, events
+    and jumps identical, per-walker values and the full vector within tolerance,
+    on a graph whose hubs sit in the staged rows and whose walks are long enough
+    to come back to them."""
+    w = wl.config_ba_full(n=20_000)
+    a = w.a
+    v = np.random.default_rng(5).uniform(0.5, 1.5, a.n)
+    t = 3.0
+    g = mc.MCExpmv(a.rowptr, a.col, a.val, t, 77, fp32=fp32, relabel=1, lds_budget=lds,
+                   walkers_per_block=block)
+    o = Oracle(a.rowptr, a.col, a.val, t, 77)
+    vo = _v_for(v, fp32)
+    tol = RTOL32 if fp32 else RTOL64
+    deg = np.diff(a.rowptr)
+    hubs = np.argsort(-deg)[:3]
+    for start in list(hubs) + [a.n - 1]:
+        xg, evg, jug, fg = g.trace(v, int(start), 0, 3000)
+        xo, evo, juo, fo, _ = o.trace(vo, int(start), 0, 3000)
+        assert np.array_equal(xg, xo) and np.array_equal(evg, evo) and np.array_equal(jug, juo)
+        assert _close(fg, fo, tol)
+    est, se = g.full(v, 40)
+    eo, so = o.estimate(vo, None, 40, threads=8)
+    assert _close(est.cpu().numpy(), eo, tol)
+    idx = np.concatenate([hubs, [0, 17, a.n - 1]]).astype(np.int64)
+    ee, _ = g.entries(v, idx, 5000)
+    eeo, _ = o.estimate(vo, idx, 5000, threads=8)
+    assert _close(ee.cpu().numpy(), eeo, tol)
+
+
 def test_relabel_with_proposal_matches_plain_layout():
     a = MATS["nonsym48"]
     bias = np.random.default_rng(4).normal(0, 0.6, a.nnz).astype(np.float32)
@@ -619,13 +653,25 @@ def test_entries_multi_equals_per_count_runs(fp32):
 def test_statistics_tiers_match_oracle(fp32):
     """An entry's listed walkers are summed by one lane (at most 32), one row of 16 lanes
     (at most 256) or the whole wave.  A two-state chain whose start node jumps before t
-    with probability about 1/2, run with 40 .. 80 and 480 .. 560 walkers, puts entries on
-    both sides of both limits: every estimate and standard error against the oracle."""
-    a = wl.from_dense(np.array([[-0.6931471805599453, 0.6931471805599453], [0.4, -0.4]]))
+    with probability 0.55, run with 40 .. 80 and 440 .. 530 walkers, puts chunks (of 512
+    walkers with FP64 weights, 1024 with FP32) on both sides of both limits, as counted
+    from the oracle's walkers: every estimate and standard error against the oracle."""
+    r = -np.log(0.45)
+    a = wl.from_dense(np.array([[-r, r], [0.4, -0.4]]))
     t = 1.0
     g, o = _pair(a, t, 123, fp32=fp32)
     v = _v_for(np.array([0.8, 1.7]), fp32)
-    counts = np.array(list(range(40, 81, 3)) + list(range(480, 561, 8)), np.int64)
+    counts = np.array(list(range(40, 81, 3)) + list(range(440, 531, 6)), np.int64)
+    # listed walkers per chunk, from the oracle's walkers: a walker is listed when its
+    # first draw lets it leave (jumps > 0; the band [e0, e^{-rt}) of width 2^-16 e^{-rt}
+    # where a listed walker would still stay holds none of these walkers)
+    chunk = 1024 if fp32 else 512
+    ju = o.trace(v, 0, 0, int(counts.max()))[2]
+    js = [int((ju[c:min(c + chunk, m)] > 0).sum()) for m in counts for c in range(0, m, chunk)]
+    js = np.array(js)
+    assert ((js > 16) & (js <= 32)).any() and ((js > 32) & (js <= 256)).any() and (js > 256).any()
+    assert ((js >= 29) & (js <= 32)).any() and ((js >= 33) & (js <= 36)).any(), js
+    assert ((js >= 250) & (js <= 256)).any() and ((js >= 257) & (js <= 262)).any(), js
     est, se = g.entries_multi(v, np.zeros(len(counts), np.int64), counts)
     est, se = est.cpu().numpy(), se.cpu().numpy()
     for j, m in enumerate(counts):
@@ -747,3 +793,38 @@ def test_resort_requires_relabel():
     a = MATS["sym48"]
     with pytest.raises(mc.MCError):
         mc.MCExpmv(a.rowptr, a.col, a.val, 1.0, 1, resort_period=4)
+
+
+@pytest.mark.parametrize("fn", ["log", "exp", "one_minus_exp_neg"])
+def test_walk_math_within_two_ulp(fn):
+    """The walk's own FP64 logarithm (holding times), exponential (FP64 weights) and
+    1 - e^{-x} (conditioning) against long-double references, within 3 ulp for the
+    logarithm (which loses up to about half an ulp more where e ln2 and the atanh
+    series partly cancel) and 2 ulp for the others, on
+    seeded arguments across their ranges: every table interval of the logarithm
+    (and the 2^-53 grid of U), the exponential's whole range and its limits."""
+    rng = np.random.default_rng(11)
+    if fn == "log":
+        m = rng.integers(0, 2 ** 53, 200_000, dtype=np.uint64)
+        u = ((m + np.uint64(1)).astype(np.float64)) * 2.0 ** -53       # the walk's U
+        near1 = 1.0 - rng.integers(1, 2 ** 20, 20_000) * 2.0 ** -53
+        grid = np.concatenate([1.0 + np.arange(128) / 128.0, 0.75 + np.arange(64) / 256.0])
+        edges = np.concatenate([grid, np.nextafter(grid, 0), np.nextafter(grid, 2)]) / 2.0
+        x = np.concatenate([u, near1, edges, [1.0, 2.0 ** -53, 0.5, 0.75, 2.0 ** -1022]])
+        x = x[(x > 0) & (x <= 1)]
+        ref = np.log(x.astype(np.longdouble))
+    elif fn == "exp":
+        x = np.concatenate([rng.uniform(-700, 700, 100_000), rng.uniform(-1, 1, 50_000),
+                            rng.normal(0, 1e-3, 20_000), [0.0, -0.0, 1.0, -1.0, 709.0, -708.0]])
+        ref = np.exp(x.astype(np.longdouble))
+    else:
+        x = np.concatenate([rng.uniform(0, 40, 100_000), 10.0 ** rng.uniform(-12, 0, 50_000),
+                            [0.0, 0.34657359027997264, np.nextafter(0.34657359027997264, 0)]])
+        ref = -np.expm1(-x.astype(np.longdouble))
+    y = mc.math_eval(fn, x).cpu().numpy()
+    ulp = np.spacing(np.abs(ref).astype(np.float64))
+    ulp = np.where(ref == 0, np.finfo(np.float64).tiny, ulp)
+    err = np.abs(y.astype(np.longdouble) - ref) / ulp
+    k = int(np.argmax(err))
+    print(f"{fn}: max error {float(err[k]):.3f} ulp at x = {x[k]!r}", flush=True)
+    assert float(err.max()) <= (3.0 if fn == "log" else 2.0)

@@ -1,0 +1,125 @@
+"""GPU parity of the matrix-free 7-point stencil walk (mc_expmv_create_stencil7:
+neighbours from the node index, face rates instead of tables, jumps by inverse CDF
+over the six faces) against the oracle run on the same matrix in CSR form with its
+inverse-CDF jump rule: per-walker final states, events and jumps bit-identical,
+values and estimates within 1e-12 (FP64) / 1e-5 (FP32); invalid face arrays are
+rejected; the walk is unbiased against expm."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import Oracle
+import paper_1904_12759_amd as mc
+from paper_1904_12759_amd import workloads as wl
+import refs
+
+pytestmark = pytest.mark.gpu
+
+
+def _v_for(v, fp32):
+    return np.asarray(v, np.float32).astype(np.float64) if fp32 else np.asarray(v, np.float64)
+
+
+def _close(a, b, rtol):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.all(np.abs(a - b) <= rtol * np.maximum(np.abs(b), 1e-300))
+
+
+def _box(nx, ny, nz, seed=1):
+    """A variable-coefficient 7-point operator on an nx x ny x nz box, from the
+    benchmark's 3-D recipe (cubic grid) or, for a non-cubic box, the same recipe by
+    hand: harmonic-mean faces of log-uniform cell coefficients, Dirichlet."""
+    rng = np.random.default_rng(seed)
+    kap = np.exp(rng.uniform(np.log(0.1), np.log(10.0), size=(nz, ny, nx)))
+    n = nx * ny * nz
+    fx = np.zeros((nz, ny, nx)); fy = np.zeros((nz, ny, nx)); fz = np.zeros((nz, ny, nx))
+    fx[:, :, :-1] = 2 * kap[:, :, :-1] * kap[:, :, 1:] / (kap[:, :, :-1] + kap[:, :, 1:])
+    fy[:, :-1, :] = 2 * kap[:, :-1, :] * kap[:, 1:, :] / (kap[:, :-1, :] + kap[:, 1:, :])
+    fz[:-1, :, :] = 2 * kap[:-1] * kap[1:] / (kap[:-1] + kap[1:])
+    fx, fy, fz = fx.ravel(), fy.ravel(), fz.ravel()
+    # diagonal: minus the six faces, a boundary face taking the cell's kappa
+    diag = -(fx + fy + fz)
+    diag -= np.concatenate([[0.0], fx[:-1]])
+    diag -= np.concatenate([np.zeros(nx), fy[:-nx]])
+    diag -= np.concatenate([np.zeros(nx * ny), fz[:-nx * ny]])
+    k = kap.ravel()
+    xs, ys, zs = np.arange(n) % nx, (np.arange(n) // nx) % ny, np.arange(n) // (nx * ny)
+    for c, m in ((xs, nx), (ys, ny), (zs, nz)):
+        diag -= k * ((c == 0).astype(float) + (c == m - 1).astype(float))
+    dense = np.diag(diag)
+    for f, off in ((fx, 1), (fy, nx), (fz, nx * ny)):
+        i = np.nonzero(f > 0)[0]
+        dense[i, i + off] = f[i]
+        dense[i + off, i] = f[i]
+    return fx, fy, fz, diag, dense
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("mode", [mc.EXACT, mc.STRANG])
+def test_stencil_walk_matches_oracle(fp32, mode):
+    nx, ny, nz = 7, 5, 4
+    fx, fy, fz, diag, dense = _box(nx, ny, nz)
+    a = wl.from_dense(dense)
+    t = 0.3
+    v = np.random.default_rng(2).uniform(0.2, 1.0, a.n)
+    g = mc.MCExpmv.stencil7(nx, ny, nz, fx, fy, fz, diag, t, 41, mode=mode, dt=t / 3, fp32=fp32)
+    o = Oracle(a.rowptr, a.col, a.val, t, 41, mode=mode, dt=t / 3, cdf_jump=True)
+    vo = _v_for(v, fp32)
+    tol = 1e-5 if fp32 else 1e-12
+    for start in (0, nx - 1, nx * ny * nz - 1, 17, 2 * nx * ny + 3):
+        xg, evg, jug, fg = g.trace(v, start, 0, 2000)
+        xo, evo, juo, fo, _ = o.trace(vo, start, 0, 2000)
+        assert np.array_equal(xg, xo) and np.array_equal(evg, evo) and np.array_equal(jug, juo), start
+        assert _close(fg, fo, tol)
+    est, se = g.full(v, 3000)
+    eo, so = o.estimate(vo, None, 3000, threads=8)
+    assert _close(est.cpu().numpy(), eo, tol)
+    idx = np.array([0, 5, 33, 139, 5], np.int64)
+    ee, _ = g.entries(v, idx, 7000)
+    eeo, _ = o.estimate(vo, idx, 7000, threads=8)
+    assert _close(ee.cpu().numpy(), eeo, tol)
+
+
+def test_stencil_walk_unbiased_and_grid3d_faces_equal_its_csr():
+    fx, fy, fz, diag, dense = _box(6, 6, 5, seed=3)
+    t = 0.4
+    v = np.random.default_rng(4).uniform(0.2, 1.0, len(diag))
+    g = mc.MCExpmv.stencil7(6, 6, 5, fx, fy, fz, diag, t, 9)
+    est, se = g.full(v, 20_000)
+    ref = refs.expm_v(dense, t, v)
+    z = (est.cpu().numpy() - ref) / se.cpu().numpy()
+    assert np.abs(z).max() < 4.5 and abs(np.mean(z * z) - 1) < 0.5
+    # the benchmark's grid3d CSR in face form: the oracle on the CSR with the
+    # inverse-CDF rule and the stencil walk agree walker for walker
+    m = 12
+    a = wl.grid3d(m, 1)
+    fx, fy, fz, diag = wl.stencil7_faces(a, m, m, m)
+    v = wl.bump_v(m, 2)
+    g = mc.MCExpmv.stencil7(m, m, m, fx, fy, fz, diag, 0.05, 12759, fp32=True)
+    o = Oracle(a.rowptr, a.col, a.val, 0.05, 12759, cdf_jump=True)
+    for start in (0, 700, m ** 3 - 1):
+        xg, evg, jug, _ = g.trace(v, start, 0, 3000)
+        xo, evo, juo, _, _ = o.trace(_v_for(v, True), start, 0, 3000)
+        assert np.array_equal(xg, xo) and np.array_equal(evg, evo) and np.array_equal(jug, juo)
+
+
+def test_stencil_rejects_invalid_faces():
+    fx, fy, fz, diag, _ = _box(4, 3, 2)
+    bad = fx.copy()
+    bad[3] = 0.5                         # a rate on the last x-plane
+    with pytest.raises(mc.MCError):
+        mc.MCExpmv.stencil7(4, 3, 2, bad, fy, fz, diag, 0.3, 1)
+    bad = fy.copy()
+    bad[0] = -1.0
+    with pytest.raises(mc.MCError) as err:
+        mc.MCExpmv.stencil7(4, 3, 2, fx, bad, fz, diag, 0.3, 1)
+    assert err.value.code == 2           # MC_ERR_NOT_METZLER
+    bad = diag.copy()
+    bad[5] = np.nan
+    with pytest.raises(mc.MCError) as err:
+        mc.MCExpmv.stencil7(4, 3, 2, fx, fy, fz, bad, 0.3, 1)
+    assert err.value.code == 3           # MC_ERR_NONFINITE
+    g = mc.MCExpmv.stencil7(4, 3, 2, fx, fy, fz, diag, 0.3, 1)
+    with pytest.raises(mc.MCError):
+        g.set_proposal(None)           # no tables: no proposal
