@@ -181,10 +181,11 @@ mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t
                           const mc_expmv_opts *opts);
 
 /*
- * A handle for the matrix-free walk on a 7-point stencil (the variable-coefficient
- * diffusion operators of the benchmark's 3-D workload): A is given by its face rates
- * instead of CSR, neighbours come from the node index x = i + nx (j + ny k), and a
- * jump picks the neighbour by inverse CDF over the six face rates in the column
+ * A handle for the walk on a 7-point stencil without jump tables (the variable-
+ * coefficient diffusion operators of the benchmark's 3-D workload): A is given by
+ * its face rates instead of CSR, neighbours come from the node index
+ * x = i + nx (j + ny k), and a jump picks the neighbour by inverse CDF over the six
+ * face rates in the column
  * order of A's row (-z, -y, -x, +x, +y, +z): the first face whose running sum of
  * rates exceeds u r_x, u = o2 2^-32 from the event's Philox draw (the last face with
  * a rate when rounding leaves u r_x at or above the sum).  r_x is the sum of the
@@ -198,8 +199,12 @@ mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t
  * Supports entries / entries_multi / full / trace / stats in every weight mode and
  * precision; not the tilted proposal, the forward estimator, relabelling,
  * conditioning or the lattice (MC_ERR_INVALID_ARG).  Errors: MC_ERR_INVALID_ARG
- * (sizes, a positive rate on a last plane, options), MC_ERR_NONFINITE,
- * MC_ERR_NOT_METZLER (a negative rate).  The arrays are copied; synchronous.
+ * (sizes, a positive rate on a last plane, a node whose 1/r_x overflows, options),
+ * MC_ERR_NONFINITE, MC_ERR_NOT_METZLER (a negative rate).  The arrays are copied;
+ * synchronous.  Device memory per node: the three face rates (24 B), the state
+ * record (1/r_x and the exit count, 16 B) and d_x in both precisions (12 B), 52 B
+ * (0.87 GB for 256^3); the CSR form holds the same records plus a 16 B alias slot
+ * per exit (2.3 GB for 256^3).
  */
 mc_status mc_expmv_create_stencil7(mc_expmv_t *out, int64_t nx, int64_t ny, int64_t nz,
                                    const double *fx, const double *fy, const double *fz,

@@ -303,7 +303,6 @@ void fill_inst(const mc_expmv_s *h, const void *v, bool prop, InstArgs &P) {
     P.fx = h->stencil ? h->sfx : nullptr;
     P.fy = h->sfy;
     P.fz = h->sfz;
-    P.diag = h->sdiag;
     P.nx = h->snx;
     P.nxy = h->snxy;
 }
@@ -625,6 +624,9 @@ mc_status mc_expmv_create_stencil7(mc_expmv_t *out, int64_t nx, int64_t ny, int6
     CREATE_TRY(dalloc(&h->sfy, n));
     CREATE_TRY(dalloc(&h->sfz, n));
     CREATE_TRY(dalloc(&h->sdiag, n));
+    CREATE_TRY(dalloc(&h->plain.rows, n));
+    CREATE_TRY(dalloc(&h->plain.d64, n));
+    CREATE_TRY(dalloc(&h->plain.d32, n));
     const size_t bytes = sizeof(double) * (size_t)n;
     CREATE_TRY(hipMemcpyAsync(h->sfx, fx, bytes, hipMemcpyDefault, h->stream));
     CREATE_TRY(hipMemcpyAsync(h->sfy, fy, bytes, hipMemcpyDefault, h->stream));
@@ -633,8 +635,8 @@ mc_status mc_expmv_create_stencil7(mc_expmv_t *out, int64_t nx, int64_t ny, int6
     // counters[0] doubles as the slot count of the check (cleared by a fill kernel later)
     CREATE_TRY(hipMemsetAsync(h->flags, 0, sizeof(uint32_t), h->stream));
     CREATE_TRY(hipMemsetAsync(h->counters, 0, sizeof(unsigned long long), h->stream));
-    CREATE_TRY(launch_check_stencil(n, nx, ny, h->sfx, h->sfy, h->sfz, h->sdiag, h->flags,
-                                    h->counters, h->stream));
+    CREATE_TRY(launch_stencil_rows(n, nx, ny, h->sfx, h->sfy, h->sfz, h->sdiag, h->plain.rows,
+                                   h->plain.d64, h->plain.d32, h->flags, h->counters, h->stream));
     uint32_t f = 0;
     unsigned long long slots = 0;
     CREATE_TRY(hipMemcpyAsync(&f, h->flags, sizeof(f), hipMemcpyDeviceToHost, h->stream));
@@ -645,6 +647,9 @@ mc_status mc_expmv_create_stencil7(mc_expmv_t *out, int64_t nx, int64_t ny, int6
         mc_expmv_destroy(h);
         return flags_to_status(f);
     }
+    // the walk reads the state records and the faces; a_xx lives on in d
+    (void)hipFree(h->sdiag);
+    h->sdiag = nullptr;
     h->nslots = (int64_t)slots;
     *out = h;
     return MC_OK;
@@ -895,8 +900,8 @@ mc_status mc_expmv_stats(mc_expmv_t h, mc_expmv_run_stats *out) {
     const double row = 16.0 + dbytes;
     const double slot = 12.0 + (h->last_prop ? 8.0 : 0.0);
     out->alg_bytes = row * (double)(c[0]) + slot * (double)c[1] + dbytes * (double)h->last_walkers;
-    if (h->stencil)   // six face rates and a_xx per visited state, the faces again per jump
-        out->alg_bytes = 56.0 * (double)c[0] + 48.0 * (double)c[1] + dbytes * (double)h->last_walkers;
+    if (h->stencil)   // the same state records; six FP64 face rates instead of a slot per jump
+        out->alg_bytes = row * (double)(c[0]) + 48.0 * (double)c[1] + dbytes * (double)h->last_walkers;
     if (h->last_fwd) {
         // forward walks: per walker also the binary search over the cumulative
         // sums (8 B per step) and two FP64 read-modify-writes at the end node

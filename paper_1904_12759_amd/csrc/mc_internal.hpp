@@ -102,10 +102,10 @@ struct InstArgs {
     double cond_max_rt;        // first-jump conditioning for start nodes with t <= this / r
     uint32_t resort;           // relabelled walks: re-sort a wave's walkers every this many events (0: never)
     uint32_t qmc;              // 1: first event from the randomised rank-1 lattice (backward walks)
-    // matrix-free 7-point stencil (fx null: the tables above): node x = i + nx (j + ny k),
-    // fx[x] / fy[x] / fz[x] the rate between x and its +x / +y / +z neighbour (0 on the
-    // last plane of that axis), diag[x] = a_xx
-    const double *fx, *fy, *fz, *diag;
+    // 7-point stencil without slots (fx null: the alias slots above): node
+    // x = i + nx (j + ny k), fx[x] / fy[x] / fz[x] the rate between x and its +x / +y / +z
+    // neighbour (0 on the last plane of that axis); rows and d64 / d32 hold the states
+    const double *fx, *fy, *fz;
     uint32_t nx, nxy;
 };
 
@@ -347,9 +347,10 @@ hipError_t launch_fat_slots(int64_t n, int64_t nnz, const Tables &tb, bool walk_
                             hipStream_t s);
 
 // setup kernels (setup.hip)
-hipError_t launch_check_stencil(int64_t n, int64_t nx, int64_t ny, const double *fx, const double *fy,
-                                const double *fz, const double *diag, uint32_t *flags,
-                                unsigned long long *nslots, hipStream_t s);
+hipError_t launch_stencil_rows(int64_t n, int64_t nx, int64_t ny, const double *fx, const double *fy,
+                               const double *fz, const double *diag, RowRec *rows, double *d64,
+                               float *d32, uint32_t *flags, unsigned long long *nslots,
+                               hipStream_t s);
 hipError_t launch_check_rowptr(int64_t n, int64_t nnz, const int64_t *rowptr, uint32_t *flags,
                                hipStream_t s);
 hipError_t launch_setup_rows(int64_t n, const int64_t *rowptr, const int32_t *col,

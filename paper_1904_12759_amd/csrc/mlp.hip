@@ -7,16 +7,22 @@
 // (Sec. 5); tilting jump rates with an importance-weight correction is this
 // library's way of doing it.  The network is small (4801 parameters) but its
 // 64 x 64 layer is a dense contraction over many edges, so that layer runs on
-// the matrix cores: v_mfma_f32_16x16x16_bf16 with bfloat16 operands and FP32
-// accumulation.
+// the matrix cores with bfloat16 operands and FP32 accumulation: the forward
+// product and the backward dL/da1 = W2^T dL/dz2 on gfx950's
+// v_mfma_f32_16x16x32_bf16 (two per 16 x 16 output tile), the weight gradient
+// dW2 = dz2 a1^T, a contraction over a tile's 16 edges, on
+// v_mfma_f32_16x16x16_bf16.
 //
 // Register layout.  A wave handles tiles of 16 edges.  Lane l works on edge
-// e = l % 16 and on the hidden features 16*k + 4*(l/16) + i (k, i < 4).  With
-// the 16x16x16 MFMA's operand layouts (A[m][kk]: lane m + 16*(kk/4); B[kk][n]:
-// lane n + 16*(kk/4); D[m][n]: lane n + 16*(m/4)) this makes layer 1's output
-// the B operand of layer 2, layer 2's output (D) land in the same per-lane
-// layout, and the backward product dL/da1 = W2^T dL/dz2 likewise; only the
-// weight gradient dW2 = dz2 a1^T, a contraction over edges, goes through LDS.
+// e = l % 16 and owns the hidden features 16*k + 4*(l/16) + i (k, i < 4): the
+// rows of the MFMA result D[m][n] (lane n + 16*(m/4), element m%4) that fall to
+// it.  A 16x16x32 operand gives lane m + 16*(kk/8) (A) or n + 16*(kk/8) (B) the
+// eight elements kk%8 of its contraction index; a contraction does not depend on
+// which feature stands at which kk as long as A and B agree, so element j of
+// K-block kb is taken to be the lane's own feature of tile 2*kb + j/4 (index
+// j%4).  Then layer 1's output is layer 2's B operand and layer 2's output (D)
+// is the backward product's B operand without moving between lanes; only dW2
+// goes through LDS.
 #include "walk_task.hpp"
 
 namespace mc {
@@ -35,7 +41,19 @@ constexpr int GSTRIDE = kMlpParams + 2;   // gradient partial row: params, sum p
 constexpr int WAVES = 4;                  // waves per block
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Hidden feature at element j of K-block kb of a lane in quarter q (see above).
+__device__ __forceinline__ int kfeat(int kb, int q, int j) {
+    return 16 * (2 * kb + (j >> 2)) + 4 * q + (j & 3);
+}
+
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                  __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
 
 // float -> bfloat16, round to nearest even
 __device__ __forceinline__ uint16_t f2bf(float x) {
@@ -152,7 +170,7 @@ struct NetArgs {
 // Forward (TRAIN = false: write b for every position; TRAIN = true: also
 // back-propagate the weighted squared error and accumulate per-wave gradients).
 template <bool TRAIN>
-__global__ __launch_bounds__(256) void k_net(NetArgs a) {
+__global__ __launch_bounds__(256, TRAIN ? 1 : 2) void k_net(NetArgs a) {
     __shared__ float s_w1[H * NIN], s_b1[H], s_b2[H], s_w3[H], s_b3;
     __shared__ uint16_t s_a1[WAVES][H][16];    // a1 (bf16), [feature][edge]
     __shared__ uint16_t s_dz2[WAVES][H][16];   // dL/dz2 (bf16), [feature][edge]
@@ -173,19 +191,19 @@ __global__ __launch_bounds__(256) void k_net(NetArgs a) {
     const int wv = threadIdx.x >> 6;
     const int e = lane & 15;
     const int q = lane >> 4;
-    // layer-2 weights as A operands: W2[16 mt + e][16 ks + 4 q + i]
-    v4s w2f[4][4];
+    // layer-2 weights as A operands: w2f[mt][kb][j] = W2[16 mt + e][kfeat(kb, q, j)]
+    v8s w2f[4][2];
     for (int mt = 0; mt < 4; ++mt)
-        for (int ks = 0; ks < 4; ++ks)
-            for (int i = 0; i < 4; ++i)
-                w2f[mt][ks][i] = (short)a.wbf[OFF_W2 + (16 * mt + e) * H + 16 * ks + 4 * q + i];
-    // and transposed for the backward product: W2^T[16 mt + e][16 ks + 4 q + i]
-    v4s w2t[4][4];
+        for (int kb = 0; kb < 2; ++kb)
+            for (int j = 0; j < 8; ++j)
+                w2f[mt][kb][j] = (short)a.wbf[OFF_W2 + (16 * mt + e) * H + kfeat(kb, q, j)];
+    // and transposed for the backward product: W2^T[16 mt + e][kfeat(kb, q, j)]
+    v8s w2t[4][2];
     if constexpr (TRAIN) {
         for (int mt = 0; mt < 4; ++mt)
-            for (int ks = 0; ks < 4; ++ks)
-                for (int i = 0; i < 4; ++i)
-                    w2t[mt][ks][i] = (short)a.wbf[OFF_W2 + (16 * ks + 4 * q + i) * H + 16 * mt + e];
+            for (int kb = 0; kb < 2; ++kb)
+                for (int j = 0; j < 8; ++j)
+                    w2t[mt][kb][j] = (short)a.wbf[OFF_W2 + kfeat(kb, q, j) * H + 16 * mt + e];
     }
 
     v4f gw2[4][4];
@@ -217,8 +235,7 @@ __global__ __launch_bounds__(256) void k_net(NetArgs a) {
         }
         // layer 1 (VALU): features f = 16 ks + 4 q + i
         uint32_t m1 = 0;
-        v4s a1b[4];
-        float a1v[16];
+        v8s a1b[2];                  // a1b[kb][j]: feature kfeat(kb, q, j)
         for (int ks = 0; ks < 4; ++ks)
             for (int i = 0; i < 4; ++i) {
                 const int f = 16 * ks + 4 * q + i;
@@ -227,16 +244,14 @@ __global__ __launch_bounds__(256) void k_net(NetArgs a) {
                 const float av = z > 0.0f ? z : 0.0f;
                 if (z > 0.0f) m1 |= 1u << (4 * ks + i);
                 const uint16_t hb = f2bf(av);
-                a1b[ks][i] = (short)hb;
-                a1v[4 * ks + i] = bf2f(hb);
+                a1b[ks >> 1][4 * (ks & 1) + i] = (short)hb;
             }
         // layer 2 (MFMA): z2[16 mt + 4 q + i] for edge e
         float a2[16];
         uint32_t m2 = 0;
         for (int mt = 0; mt < 4; ++mt) {
             v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            for (int ks = 0; ks < 4; ++ks)
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2f[mt][ks], a1b[ks], acc, 0, 0, 0);
+            for (int kb = 0; kb < 2; ++kb) acc = mfma32(w2f[mt][kb], a1b[kb], acc);
             for (int i = 0; i < 4; ++i) {
                 const int f = 16 * mt + 4 * q + i;
                 const float z = acc[i] + s_b2[f];
@@ -269,7 +284,7 @@ __global__ __launch_bounds__(256) void k_net(NetArgs a) {
                 }
             }
             if (q == 0) gb3 += gy;
-            v4s dz2b[4];
+            v8s dz2b[2];             // dz2b[kb][j]: feature kfeat(kb, q, j)
             for (int mt = 0; mt < 4; ++mt)
                 for (int i = 0; i < 4; ++i) {
                     const int k = 4 * mt + i;
@@ -278,16 +293,14 @@ __global__ __launch_bounds__(256) void k_net(NetArgs a) {
                     const float dz = (m2 >> k) & 1u ? gy * s_w3[f] : 0.0f;
                     gb2[k] += dz;
                     const uint16_t db = f2bf(dz);
-                    dz2b[mt][i] = (short)db;
+                    dz2b[mt >> 1][4 * (mt & 1) + i] = (short)db;
                     s_dz2[wv][f][e] = db;
-                    s_a1[wv][f][e] = (uint16_t)a1b[mt][i];
+                    s_a1[wv][f][e] = (uint16_t)a1b[mt >> 1][4 * (mt & 1) + i];
                 }
             // dL/da1 = W2^T dL/dz2 (MFMA), masked by layer 1's ReLU
             for (int mt = 0; mt < 4; ++mt) {
                 v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-                for (int ks = 0; ks < 4; ++ks)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2t[mt][ks], dz2b[ks], acc, 0, 0,
-                                                                   0);
+                for (int kb = 0; kb < 2; ++kb) acc = mfma32(w2t[mt][kb], dz2b[kb], acc);
                 for (int i = 0; i < 4; ++i) {
                     const int k = 4 * mt + i;
                     s_dz1[wv][16 * mt + 4 * q + i][e] = (m1 >> k) & 1u ? acc[i] : 0.0f;

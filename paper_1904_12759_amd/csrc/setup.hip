@@ -239,39 +239,64 @@ hipError_t launch_relabel_apply(int64_t n, const int64_t *rowptr, const uint32_t
     return hipGetLastError();
 }
 
-// Face rates of a matrix-free 7-point stencil: finite and non-negative, zero on the
-// last plane of their axis (no neighbour there); a_xx finite.  Counts the jump
-// slots (positive face rates, each seen from both sides) into *nslots.
-__global__ void k_check_stencil(int64_t n, int64_t nx, int64_t ny, const double *__restrict__ fx,
-                                const double *__restrict__ fy, const double *__restrict__ fz,
-                                const double *__restrict__ diag, uint32_t *flags,
-                                unsigned long long *nslots) {
+// One thread per node of the 7-point stencil: its three face rates checked
+// (finite, >= 0, and 0 on the last plane of their axis, where no neighbour
+// exists) and a_xx finite; two slots counted per positive face (an exit in each
+// direction); and its state record as the row split makes it for the same
+// matrix in CSR form: r summed over the six faces in column order (-z, -y, -x,
+// +x, +y, +z), 1/r when the node has an exit, its number of exits, and
+// d = a_xx + r.  The faces toward lower indices are the neighbours' own, which
+// their threads check.
+__global__ void k_stencil_rows(int64_t n, int64_t nx, int64_t ny, const double *__restrict__ fx,
+                               const double *__restrict__ fy, const double *__restrict__ fz,
+                               const double *__restrict__ diag, RowRec *__restrict__ rows,
+                               double *__restrict__ d64, float *__restrict__ d32, uint32_t *flags,
+                               unsigned long long *nslots) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
-    const int64_t nz = n / (nx * ny);
-    const double f[3] = {fx[i], fy[i], fz[i]};
+    const int64_t nxy = nx * ny;
+    const int64_t x = i % nx, y = (i / nx) % ny, z = i / nxy;
+    const int64_t nz = n / nxy;
+    const double up[3] = {fx[i], fy[i], fz[i]};
     const bool last[3] = {x == nx - 1, y == ny - 1, z == nz - 1};
     uint32_t bad = 0;
     unsigned long long cnt = 0;
     for (int a = 0; a < 3; ++a) {
-        if (!isfinite(f[a])) bad |= F_NONFINITE;
-        else if (f[a] < 0.0) bad |= F_NOT_METZLER;
-        else if (f[a] > 0.0 && last[a]) bad |= F_INVALID_ARG;
-        if (f[a] > 0.0) cnt += 2;
+        if (!isfinite(up[a])) bad |= F_NONFINITE;
+        else if (up[a] < 0.0) bad |= F_NOT_METZLER;
+        else if (up[a] > 0.0 && last[a]) bad |= F_INVALID_ARG;
+        if (up[a] > 0.0) cnt += 2;
     }
-    if (!isfinite(diag[i])) bad |= F_NONFINITE;
+    const double f[6] = {i >= nxy ? fz[i - nxy] : 0.0, i >= nx ? fy[i - nx] : 0.0,
+                         i >= 1 ? fx[i - 1] : 0.0, up[0], up[1], up[2]};
+    double r = 0.0;
+    uint32_t deg = 0;
+    for (int k = 0; k < 6; ++k) {
+        r = r + f[k];
+        deg += f[k] > 0.0 ? 1u : 0u;
+    }
+    double inv_r = 0.0;
+    if (deg > 0) {
+        inv_r = 1.0 / r;
+        if (!isfinite(inv_r)) bad |= F_INVALID_ARG;
+    }
+    const double d = diag[i] + r;
+    if (!isfinite(d)) bad |= F_NONFINITE;
     if (bad) atomicOr(flags, bad);
     if (cnt) atomicAdd(nslots, cnt);
+    rows[i] = RowRec{inv_r, deg, 0u};
+    d64[i] = d;
+    d32[i] = (float)d;
 }
 
-hipError_t launch_check_stencil(int64_t n, int64_t nx, int64_t ny, const double *fx, const double *fy,
-                                const double *fz, const double *diag, uint32_t *flags,
-                                unsigned long long *nslots, hipStream_t s) {
+hipError_t launch_stencil_rows(int64_t n, int64_t nx, int64_t ny, const double *fx, const double *fy,
+                               const double *fz, const double *diag, RowRec *rows, double *d64,
+                               float *d32, uint32_t *flags, unsigned long long *nslots,
+                               hipStream_t s) {
     if (n == 0) return hipSuccess;
     const int64_t grid = (n + 255) / 256;
-    hipLaunchKernelGGL(k_check_stencil, dim3((unsigned)grid), dim3(256), 0, s, n, nx, ny, fx, fy, fz,
-                       diag, flags, nslots);
+    hipLaunchKernelGGL(k_stencil_rows, dim3((unsigned)grid), dim3(256), 0, s, n, nx, ny, fx, fy, fz,
+                       diag, rows, d64, d32, flags, nslots);
     return hipGetLastError();
 }
 

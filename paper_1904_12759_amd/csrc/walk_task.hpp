@@ -254,25 +254,6 @@ __device__ __forceinline__ uint32_t stencil_neighbour(const InstArgs &P, uint32_
            : k == 4 ? x + P.nx : x + P.nxy;
 }
 
-// The state record of node x from the face rates: r summed in column order (as the
-// row split sums a matrix row), 1/r, the number of exits and d = a_xx + r.
-template <bool FP32>
-__device__ __forceinline__ void stencil_row(const InstArgs &P, uint32_t x, double &inv_r,
-                                            uint32_t &deg, typename WeightT<FP32>::T &dx) {
-    double f[6];
-    stencil_faces(P, x, f);
-    double r = 0.0;
-    uint32_t k = 0;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        r = r + f[i];
-        k += f[i] > 0.0 ? 1u : 0u;
-    }
-    deg = k;
-    inv_r = k ? 1.0 / r : 0.0;
-    dx = (typename WeightT<FP32>::T)(P.diag[x] + r);
-}
-
 // The jump from x: the first face (column order) whose running sum of rates exceeds
 // u r, u = o2 2^-32 in [0, 1), or the last face with a rate when rounding leaves
 // u r at or above the sum (the inverse-CDF rule; zero faces never cross).
@@ -622,13 +603,8 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             const uint32_t x0 = walk_id<LOC>(P, node);
             RowRec r0;
             WT d0;
-            if constexpr (STENCIL) {
-                stencil_row<FP32>(P, x0, r0.inv_r, r0.deg, d0);
-                r0.begin = 0u;
-            } else {
-                r0 = row_at<LOC>(P, x0);
-                d0 = d_at<FP32, LOC>(P, x0);
-            }
+            r0 = row_at<LOC>(P, x0);
+            d0 = d_at<FP32, LOC>(P, x0);
             const WT v0 = load_v<FP32>(P.v, node);
             K = (double)(wexp<FP32>(final_term<MODE, FP32>(d0, 0.0, 0, P)) * v0);
             // first-jump conditioning (start nodes with exits and r t <= cond_max_rt):
@@ -784,15 +760,11 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         uint32_t deg = 0, begin = 0;
         WT dx = (WT)0;
         if (active) {
-            if constexpr (STENCIL) {
-                stencil_row<FP32>(P, x, inv_r, deg, dx);
-            } else {
-                const RowRec rr = row_at<LOC>(P, x);
-                inv_r = rr.inv_r;
-                deg = rr.deg;
-                begin = rr.begin;
-                dx = d_at<FP32, LOC>(P, x);
-            }
+            const RowRec rr = row_at<LOC>(P, x);
+            inv_r = rr.inv_r;
+            deg = rr.deg;
+            begin = rr.begin;
+            dx = d_at<FP32, LOC>(P, x);
         }
         uint32_t next = WAVE;
         uint32_t since_sort = 0;
@@ -878,7 +850,10 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                         bool keep = true;
                         if constexpr (STENCIL) {
                             x = stencil_jump(P, x, o.z);
-                            stencil_row<FP32>(P, x, inv_r, deg, dx);
+                            const RowRec rr = row_at<false>(P, x);
+                            inv_r = rr.inv_r;
+                            deg = rr.deg;
+                            dx = d_at<FP32, false>(P, x);
                         } else if constexpr (FAT == 1)
                             keep = jump_fat<FP32>(P, js, o.w, x, inv_r, deg, begin, dx);
                         else if constexpr (FAT == 2)
@@ -933,15 +908,11 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     ev = 0;
                     ju = 0;
                     ka = 0;
-                    if constexpr (STENCIL) {
-                        stencil_row<FP32>(P, x, inv_r, deg, dx);
-                    } else {
-                        const RowRec rr = row_at<LOC>(P, x);
-                        inv_r = rr.inv_r;
-                        deg = rr.deg;
-                        begin = rr.begin;
-                        dx = d_at<FP32, LOC>(P, x);
-                    }
+                    const RowRec rr = row_at<LOC>(P, x);
+                    inv_r = rr.inv_r;
+                    deg = rr.deg;
+                    begin = rr.begin;
+                    dx = d_at<FP32, LOC>(P, x);
                 } else {
                     active = false;
                 }

@@ -107,3 +107,33 @@ def test_batch_create_and_isim_fail_cleanly(fault):
         assert err.value.code == NO_MEMORY
     fault(None)
     assert mc.isim(x, y) == want
+
+
+def test_stencil_create_fails_cleanly_at_every_allocation(fault):
+    m = 24
+    a = wl.grid3d(m, 1)
+    fx, fy, fz, diag = wl.stencil7_faces(a, m, m, m)
+    v = wl.bump_v(m, 2)
+    idx = np.array([0, 5000, a.n - 1])
+    ref = mc.MCExpmv.stencil7(m, m, m, fx, fy, fz, diag, 0.05, 4)
+    e0, s0 = ref.entries(v, idx, 3000)
+    del ref
+    f0 = _free()
+    seen = 0
+    for k in range(1, 100):
+        fault(k)
+        try:
+            h = mc.MCExpmv.stencil7(m, m, m, fx, fy, fz, diag, 0.05, 4)
+        except mc.MCError as err:
+            assert err.code == NO_MEMORY, (k, err)
+            seen += 1
+            fault(None)
+            assert _free() >= f0, (k, f0 - _free())
+            continue
+        fault(None)
+        break
+    else:
+        pytest.fail("create_stencil7 never succeeded")
+    assert seen >= 8
+    e1, s1 = h.entries(v, idx, 3000)
+    assert torch.equal(e0, e1) and torch.equal(s0, s1)

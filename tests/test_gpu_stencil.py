@@ -120,6 +120,17 @@ def test_stencil_rejects_invalid_faces():
     with pytest.raises(mc.MCError) as err:
         mc.MCExpmv.stencil7(4, 3, 2, fx, fy, fz, bad, 0.3, 1)
     assert err.value.code == 3           # MC_ERR_NONFINITE
+    tiny = np.zeros_like(fx)             # one exit of rate 1e-310: 1/r overflows
+    tiny[0] = 1e-310
+    with pytest.raises(mc.MCError) as err:
+        mc.MCExpmv.stencil7(4, 3, 2, tiny, 0 * fy, 0 * fz, diag, 0.3, 1)
+    assert err.value.code == 1           # MC_ERR_INVALID_ARG, as for the same CSR matrix
+    dense = np.diag(diag)
+    dense[0, 1] = dense[1, 0] = 1e-310
+    a = wl.from_dense(dense)
+    with pytest.raises(mc.MCError) as err:
+        mc.MCExpmv(a.rowptr, a.col, a.val, 0.3, 1)
+    assert err.value.code == 1
     g = mc.MCExpmv.stencil7(4, 3, 2, fx, fy, fz, diag, 0.3, 1)
     with pytest.raises(mc.MCError):
         g.set_proposal(None)           # no tables: no proposal
