@@ -130,13 +130,15 @@ typedef struct {
                                    Sec. 5 names): the walker ordinals of an entry form
                                    replicates of B = 1024 (MC_FP32) or 512 (MC_FP64)
                                    consecutive walkers, and walker w's first-event words
-                                   are the point w mod B of the Korobov rank-1 lattice
+                                   are the point j of the Korobov rank-1 lattice
                                    (1, a, a^2 mod B), a = 149 (B = 1024) or 119 (B = 512),
                                    shifted modulo 1 by the Philox draw of the counter
                                    (0xFFFFFFFE, w / B, start node, instance id):
                                    64-bit U word j 2^(64-b) + (o0 2^32 + o1), slot word
                                    j g1 2^(32-b) + o2, alias word j g2 2^(32-b) + o3
-                                   (j = w mod B, B = 2^b, wrapping).  Later events are as
+                                   (B = 2^b, wrapping; j = the b bits of w mod B
+                                   reversed, so the first 2^k walkers of a replicate are
+                                   the 2^k-point sub-lattice).  Later events are as
                                    in the plain walk.  Unbiased (every coordinate is a
                                    uniform shift); stderr_ then comes from the R replicate
                                    means, R/(R-1) sum_c (n_c/M)^2 (m_c - est)^2, when an
@@ -203,8 +205,8 @@ mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t
  * MC_ERR_NONFINITE, MC_ERR_NOT_METZLER (a negative rate).  The arrays are copied;
  * synchronous.  Device memory per node: the three face rates (24 B), the state
  * record (1/r_x and the exit count, 16 B) and d_x in both precisions (12 B), 52 B
- * (0.87 GB for 256^3); the CSR form holds the same records plus a 16 B alias slot
- * per exit (2.3 GB for 256^3).
+ * (0.87 GB for 256^3); the CSR form holds the same records, r_x (8 B) and a 16 B
+ * alias slot per stored entry (2.5 GB for 256^3).
  */
 mc_status mc_expmv_create_stencil7(mc_expmv_t *out, int64_t nx, int64_t ny, int64_t nz,
                                    const double *fx, const double *fy, const double *fz,

@@ -414,8 +414,11 @@ static double grid_coef(const oracle_t *o, int64_t k)
 
 /* Randomised quasi-Monte Carlo for the first event (a variance reduction of the
  * kind Sec. 5 names).  The walkers w of one start node form replicates of
- * B = 2^b consecutive ordinals: replicate c = w >> b, point j = w mod B.  The
- * first event of walker w takes its three random words from the point j of the
+ * B = 2^b consecutive ordinals: replicate c = w >> b, and within it the walker
+ * w mod B takes point j = the b bits of w mod B reversed (radical-inverse order,
+ * so that the first 2^k walkers of a replicate are the 2^k-point sub-lattice and
+ * a replicate cut short stays stratified).  The first event of walker w takes its
+ * three random words from the point j of the
  * rank-1 lattice with generating vector (1, g1, g2) (Korobov: g1 = a,
  * g2 = a^2 mod B, a = 119 for B = 512 and a = 149 for B = 1024, the values
  * minimising the lattice criterion P_2 over odd a), shifted modulo 1 by a
@@ -433,13 +436,22 @@ static double grid_coef(const oracle_t *o, int64_t k)
  * (m_c - mean)^2 when R >= 2, the i.i.d. formula otherwise. */
 #define QMC_SHIFT_MARK 0xFFFFFFFEu
 
+/* The b low bits of j in reverse order. */
+static uint64_t radical_index(uint32_t j, uint32_t b)
+{
+    uint64_t r = 0;
+    for (uint32_t i = 0; i < b; ++i)
+        r |= (uint64_t)((j >> i) & 1u) << (b - 1 - i);
+    return r;
+}
+
 static void qmc_first_words(const oracle_t *o, int64_t start, uint32_t w, const uint32_t key[2],
                             uint32_t rnd[4])
 {
     const uint32_t b = (uint32_t)o->qmc_bits;
     const uint64_t g1 = b == 9 ? 119u : 149u;
     const uint64_t g2 = (g1 * g1) % (1u << b);
-    const uint64_t j = w & ((1u << b) - 1u);
+    const uint64_t j = radical_index(w & ((1u << b) - 1u), b);
     uint32_t ctr[4] = { QMC_SHIFT_MARK, w >> b, (uint32_t)start, o->instance };
     uint32_t sh[4];
     oracle_philox4x32_10(ctr, key, sh);

@@ -128,7 +128,9 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 }
 
 // First-event words of walker w from the randomised rank-1 lattice: with
-// o = Philox of the replicate's shift counter, B = 2^b and j = w mod B,
+// o = Philox of the replicate's shift counter, B = 2^b and j = the b bits of
+// w mod B reversed (radical-inverse order: the first 2^k walkers of a replicate
+// are the 2^k-point sub-lattice),
 //   64-bit word of U:  j 2^(64-b) + (o.x 2^32 + o.y)   mod 2^64
 //   slot word:         j g1 2^(32-b) + o.z             mod 2^32
 //   alias word:        j g2 2^(32-b) + o.w             mod 2^32
@@ -137,7 +139,7 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 __device__ __forceinline__ U4 lattice_words(U4 o, uint32_t w, uint32_t b) {
     const uint32_t g1 = b == 9u ? 119u : 149u;
     const uint32_t g2 = (g1 * g1) & ((1u << b) - 1u);
-    const uint32_t j = w & ((1u << b) - 1u);
+    const uint32_t j = __builtin_bitreverse32(w) >> (32u - b);
     const uint64_t u0 = ((uint64_t)j << (64u - b)) + (((uint64_t)o.x << 32) | o.y);
     return U4{(uint32_t)(u0 >> 32), (uint32_t)u0, ((j * g1) << (32u - b)) + o.z,
               ((j * g2) << (32u - b)) + o.w};
@@ -797,13 +799,11 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             }
             bool fin = false;
             if (active) {
-                if (deg == 0) {
-                    ++ev;                    // no exit rate: holds until t
-                    fin = true;
-                } else if (ev >= P.max_events) {
-                    err |= F_WALK_LIMIT;
-                    fin = true;
-                } else {
+                // the rare walkers (no exit rate: holds until t; at the walk-length
+                // cap) draw like the others and are settled after the draw, which
+                // keeps the event block out of a nested branch
+                const bool live = deg != 0 && ev < P.max_events;
+                {
                     const uint32_t wo = wb + (code & 1023u);
                     U4 o;
                     if constexpr (QMC) {
@@ -814,7 +814,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     } else {
                         o = philox(ev, wo, node, P.inst, P.key0, P.key1);
                     }
-                    ++ev;
+                    ev += (live || deg == 0) ? 1u : 0u;
                     const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
                     double S;
                     bool forced = false;
@@ -834,7 +834,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                         S = -log_unit(U) * inv_r;
                     }
                     const double sn = s + S;
-                    if (forced || sn < t) {
+                    if (live && (forced || sn < t)) {
                         if constexpr (MODE == MC_EXACT) {
                             logw = logw + dx * (WT)S;
                         } else {
@@ -868,6 +868,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                         ++ju;
                     } else {
                         fin = true;
+                        if (!live && deg != 0) err |= F_WALK_LIMIT;
                     }
                 }
                 if (fin) {

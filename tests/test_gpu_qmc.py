@@ -42,7 +42,7 @@ def test_lattice_paths_and_estimates_match_oracle(fp32, mode):
         assert np.array_equal(xg, xo) and np.array_equal(evg, evo) and np.array_equal(jug, juo)
         assert _close(fg, fo, tol)
     idx = np.array([0, 5, 57, 200, 399, 57], np.int64)
-    for m in (700, 4096, 5 * 1024 + 37):                  # one and several replicates, ragged
+    for m in (256, 700, 4096, 5 * 1024 + 37):             # part of one, one and several replicates, ragged
         est, se = g.entries(v, idx, m)
         eo, so = o.estimate(vo, idx, m, threads=4)
         assert _close(est.cpu().numpy(), eo, tol), m

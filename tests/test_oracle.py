@@ -645,13 +645,14 @@ def test_conditioning_threshold_selects_nodes():
 # ---------------------------------------------------- randomised lattice (first event)
 def _lattice_words(key, start, w, bits, inst=0):
     """The first-event words of the randomised rank-1 lattice, from its definition:
-    the point w mod B of the Korobov lattice (1, a, a^2 mod B) shifted modulo 1 by
-    the replicate's Philox draw (counter 0xFFFFFFFE, w >> bits, start, instance)."""
+    the point j of the Korobov lattice (1, a, a^2 mod B), j = w mod B written in
+    `bits` binary digits and read backwards, shifted modulo 1 by the replicate's
+    Philox draw (counter 0xFFFFFFFE, w >> bits, start, instance)."""
     B = 1 << bits
     a = 119 if bits == 9 else 149
     g = [1, a, (a * a) % B]
     sh = oracle.philox4x32_10([0xFFFFFFFE, w >> bits, start, inst], key)
-    j = w % B
+    j = int(format(w % B, f"0{bits}b")[::-1], 2)
     frac = [(j * gk % B) / B for gk in g]                  # the lattice point in [0,1)^3
     shift = [((int(sh[0]) << 32) | int(sh[1])) / 2.0 ** 64, int(sh[2]) / 2.0 ** 32,
              int(sh[3]) / 2.0 ** 32]
@@ -676,6 +677,22 @@ def test_lattice_first_event_stratifies_the_jump_choice(bits):
         for c in range(3):
             stay = int((ju[c * B:(c + 1) * B] == 0).sum())
             assert stay in (int(np.floor(B * p0)), int(np.ceil(B * p0))), (c, stay, B * p0)
+
+
+@pytest.mark.parametrize("count", [256, 128, 64])
+def test_lattice_prefix_of_a_replicate_is_stratified(count):
+    """The first 2^k walkers of a replicate take the 2^k-point sub-lattice (radical-
+    inverse order), so a run with fewer walkers per node than a replicate holds is
+    still stratified: of `count` walkers, floor or ceil of count e^{-rt} stay."""
+    a = wl.cycle_graph(9, 0.7)
+    t = 0.45
+    o = Oracle(a.rowptr, a.col, a.val, t, 23, qmc=True, qmc_bits=9)
+    v = np.arange(1.0, 10.0)
+    p0 = np.exp(-1.4 * t)
+    for start in (0, 3, 8):
+        x, ev, ju, f, _ = o.trace(v, start, 0, count)
+        stay = int((ju == 0).sum())
+        assert stay in (int(np.floor(count * p0)), int(np.ceil(count * p0))), (start, stay)
 
 
 def test_lattice_first_event_words_follow_the_definition():

@@ -81,6 +81,9 @@ MUTANTS = [
     ("lattice points not spread over the replicate",
      "const uint64_t u0 = (j << (64 - b)) + (((uint64_t)sh[0] << 32) | sh[1]);",
      "const uint64_t u0 = (j << (63 - b)) + (((uint64_t)sh[0] << 32) | sh[1]);"),
+    ("lattice points in ordinal order, not radical-inverse",
+     "const uint64_t j = radical_index(w & ((1u << b) - 1u), b);",
+     "const uint64_t j = w & ((1u << b) - 1u);"),
     ("lattice shift shared by every replicate",
      "uint32_t ctr[4] = { QMC_SHIFT_MARK, w >> b, (uint32_t)start, o->instance };",
      "uint32_t ctr[4] = { QMC_SHIFT_MARK, 0u, (uint32_t)start, o->instance };"),
