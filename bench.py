@@ -171,7 +171,7 @@ def cpu_baseline(w, seed, nthreads, gpu_events, min_seconds=10.0):
 
 
 def entries_at_1e3(mc, h, v, idx, pilot: int, target: float = 1e-3, cap: int = 1 << 31,
-                   max_passes: int = 4, margin: float = 1.2, exact=None):
+                   max_passes: int = 4, margin: float = 1.2, exact=None, min_walkers: int = 2):
     """Entries/s at a relative standard error target (the error model of Sec. 5).  A
     pilot of `pilot` walkers per entry estimates sigma_i / x_i; every entry is then run
     with N_i = ceil(margin (sigma_i / (target x_i))^2) walkers (the margin covers the
@@ -180,7 +180,9 @@ def entries_at_1e3(mc, h, v, idx, pilot: int, target: float = 1e-3, cap: int = 1
     exceeds the target (a pilot underestimates heavy tails) are re-run with N scaled
     by (error / target)^2 * 1.25, up to max_passes.  entries_per_s counts every
     production pass; entries_per_s_with_pilot adds the pilot.  With `exact` (the
-    deterministic values of the entries) the achieved errors are reported too."""
+    deterministic values of the entries) the achieved errors are reported too.
+    min_walkers floors each entry's production count (the lattice's standard error
+    needs several replicates to be an estimate at all)."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
     idx = np.asarray(idx, np.int64)
@@ -192,7 +194,7 @@ def entries_at_1e3(mc, h, v, idx, pilot: int, target: float = 1e-3, cap: int = 1
     pilot_s = time.perf_counter() - t0
     x = est.cpu().numpy()
     sig = se.cpu().numpy() * np.sqrt(pilot)
-    need = np.clip(np.ceil(margin * (sig / (target * np.abs(x))) ** 2), 2, cap)
+    need = np.clip(np.ceil(margin * (sig / (target * np.abs(x))) ** 2), min_walkers, cap)
     todo = np.arange(len(idx))
     final_rel = np.zeros(len(idx))
     final_n = np.zeros(len(idx))
@@ -201,6 +203,7 @@ def entries_at_1e3(mc, h, v, idx, pilot: int, target: float = 1e-3, cap: int = 1
     seconds = 0.0
     walkers = 0
     passes = 0
+    rerun = []
     while len(todo) and passes < max_passes:
         passes += 1
         counts = np.minimum(need[todo], cap).astype(np.int64)
@@ -222,10 +225,13 @@ def entries_at_1e3(mc, h, v, idx, pilot: int, target: float = 1e-3, cap: int = 1
         bad = rel > target
         need[todo[bad]] = np.minimum(np.ceil(counts[bad] * (rel[bad] / target) ** 2 * 1.25), cap)
         todo = todo[bad]
+        if passes == 1:
+            rerun = [int(i) for i in todo]
     out = dict(entries=len(idx), seconds=seconds, entries_per_s=len(idx) / seconds,
                pilot_walkers_per_entry=pilot, pilot_s=pilot_s,
                entries_per_s_with_pilot=len(idx) / (seconds + pilot_s),
-               walkers=int(walkers), passes=passes, max_rel_stderr=float(final_rel.max()),
+               walkers=int(walkers), passes=passes, rerun_after_first_pass=rerun,
+               max_rel_stderr=float(final_rel.max()),
                entries_above_target=int((final_rel > target).sum()),
                final_walkers_max=int(final_n.max()))
     if exact is not None:
@@ -739,12 +745,19 @@ def bench_qmc(mc, seed, seeds=8):
     out = {}
     g2 = wl.config_grid2d_entries()
     x = sla.expm_multiply((g2.t * g2.a.to_scipy()).tocsr(), np.asarray(g2.v, np.float64))
-    # the lattice's pilot: 32 replicates of 512, so that its replicate standard
-    # error, which sizes the production run, is not itself too noisy
-    for name, q, pilot in (("plain", False, 10_000), ("lattice", True, 32 * 512)):
+    # the lattice's pilot: 32 replicates of 512, whose replicate standard error (31
+    # degrees of freedom, about 13 % relative error) sizes the production run, so its
+    # margin covers 2.5 such errors, (1 + 2.5 / sqrt(62))^2 = 1.73, for one pass; and
+    # every production entry gets at least 16 replicates, since with one replicate
+    # the reported error falls back to the i.i.d. formula, which overstates it
+    for name, q, pilot, margin, floor in (("plain", False, 10_000, 1.2, 2),
+                                          ("lattice", True, 32 * 512, 1.73, 16 * 512)):
         h = mc.MCExpmv(g2.a.rowptr, g2.a.col, g2.a.val, g2.t, seed, qmc=q)
-        entries_at_1e3(mc, h, g2.v, g2.idx, pilot)                    # warm-up
-        r = entries_at_1e3(mc, h, g2.v, g2.idx, pilot, exact=x[g2.idx])
+        entries_at_1e3(mc, h, g2.v, g2.idx, pilot, margin=margin, min_walkers=floor)
+        r = entries_at_1e3(mc, h, g2.v, g2.idx, pilot, margin=margin, min_walkers=floor,
+                           exact=x[g2.idx])
+        r["margin"] = margin
+        r["min_walkers"] = floor
         out[f"grid2d_entries_at_1e3_{name}"] = r
     w = wl.config_ba_full()
     dev = torch.device("cuda", torch.cuda.current_device())

@@ -86,3 +86,21 @@ def test_lattice_unbiased_against_dense_expm():
     # 16 replicate means per estimate: Student's t with 15 degrees of freedom
     assert abs(z.mean()) < 4.5 * np.sqrt(15 / 13 / z.size)
     assert abs(np.mean(z * z) - 15 / 13) < 0.25
+
+
+def test_lattice_full_size_sampled_parity():
+    """The headline workload (grid3d 256^3, full vector, 256 walkers per node: a quarter
+    of a 1024-walker replicate, FP32) with the lattice first event, in the launch
+    configuration the benchmark times: sampled nodes against the oracle's lattice walk
+    (estimates within 1e-5; one partial replicate, so the i.i.d. standard error)."""
+    w = wl.config_grid3d_full(256)
+    g = mc.MCExpmv(w.a.rowptr, w.a.col, w.a.val, w.t, 12759, fp32=True, qmc=True)
+    est, se = g.full(w.v, w.nwalk)
+    est, se = est.cpu().numpy(), se.cpu().numpy()
+    assert np.isfinite(est).all()
+    rng = np.random.default_rng(2)
+    sample = np.unique(np.concatenate([[0, w.a.n - 1], rng.choice(w.a.n, 300, replace=False)]))
+    o = Oracle(w.a.rowptr, w.a.col, w.a.val, w.t, 12759, qmc=True, qmc_bits=10)
+    eo, so = o.estimate(_v_for(w.v, True), sample, w.nwalk, threads=8)
+    assert _close(est[sample], eo, 1e-5)
+    assert _close(se[sample], so, 1e-5)

@@ -134,3 +134,26 @@ def test_stencil_rejects_invalid_faces():
     g = mc.MCExpmv.stencil7(4, 3, 2, fx, fy, fz, diag, 0.3, 1)
     with pytest.raises(mc.MCError):
         g.set_proposal(None)           # no tables: no proposal
+
+
+def test_stencil_full_size_sampled_parity():
+    """The headline workload (grid3d 256^3, t = 0.05, full vector, 256 walkers per node,
+    FP32) as a stencil handle, in the launch configuration the benchmark times: sampled
+    nodes (corners, centre, 300 random) against the oracle on the CSR form with its
+    inverse-CDF rule, within 1e-5."""
+    m = 256
+    w = wl.config_grid3d_full(m)
+    fx, fy, fz, diag = wl.stencil7_faces(w.a, m, m, m)
+    g = mc.MCExpmv.stencil7(m, m, m, fx, fy, fz, diag, w.t, 12759, fp32=True)
+    est, se = g.full(w.v, w.nwalk)
+    st = g.stats()
+    assert st["walkers"] == w.a.n * w.nwalk and st["events"] == st["walkers"] + st["jumps"]
+    est = est.cpu().numpy()
+    assert np.isfinite(est).all()
+    rng = np.random.default_rng(1)
+    corner = [0, m - 1, m * m - 1, w.a.n - 1]
+    centre = [(m // 2) + m * ((m // 2) + m * (m // 2))]
+    sample = np.unique(np.concatenate([corner, centre, rng.choice(w.a.n, 300, replace=False)]))
+    o = Oracle(w.a.rowptr, w.a.col, w.a.val, w.t, 12759, cdf_jump=True)
+    eo, _ = o.estimate(_v_for(w.v, True), sample, w.nwalk, threads=8)
+    assert _close(est[sample], eo, 1e-5)
