@@ -613,11 +613,16 @@ def bench_forward_tc(mc, seed, n=1_000_000, m=1_000_000, steps=5):
             ms.append(h.stats()["ms"])
         st = h.stats()
         tc, tse = tot.cpu().numpy().tolist()
-        out[name] = dict(ms_per_tc=float(np.median(ms)), first_call_s=first, tc=tc,
+        kms = float(np.median(ms))
+        out[name] = dict(ms_per_tc=kms, first_call_s=first, tc=tc,
                          tc_n=tc / a.n, rel_stderr=tse / abs(tc),
                          rel_err_vs_exact=(tc - exact) / exact,
                          events=st["events"], jumps=st["jumps"],
-                         walker_steps_per_s=st["events"] / (float(np.median(ms)) / 1e3))
+                         walker_steps_per_s=st["events"] / (kms / 1e3),
+                         # the call is bound by random gathers, not arithmetic: the ALU
+                         # fraction beside the gather bytes (no reuse) per second
+                         roofline=alu_roofline(st["events"], kms, None),
+                         gather_gbs_no_reuse=st["alg_bytes"] / (kms / 1e3) / 1e9)
         del h
     return out
 
@@ -894,7 +899,8 @@ def bench_stencil(mc, seed, steps=5):
         st = h.stats()
         kms = float(np.median(ms))
         res[name] = dict(kernel_ms=kms, walker_steps_per_s=st["events"] / (kms / 1e3),
-                         events=st["events"], jumps=st["jumps"])
+                         events=st["events"], jumps=st["jumps"],
+                         roofline=alu_roofline(st["events"], kms, None))
         res[name + "_est"] = (est, se)
         del h
     (e1, s1), (e2, s2) = res.pop("table_est"), res.pop("stencil_est")

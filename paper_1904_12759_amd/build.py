@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmcexpmv.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "setup.hip", "walk.hip", "batch.hip", "mlp.hip", "forward.hip", "isim.hip"]
+SOURCES = ["api.hip", "setup.hip", "walk.hip", "batch.hip", "mlp.hip", "forward.hip", "isim.hip",
+           "sort.hip"]
 
 HIPCC_FLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -20,7 +20,6 @@
 // sum_i x_i is bitwise reproducible.
 #include <math.h>
 
-#include <hipcub/hipcub.hpp>
 
 #include "walk_task.hpp"
 
@@ -269,14 +268,95 @@ __global__ void k_fwd_zero(int64_t n, double *acc1, double *acc2) {
     if (acc2) acc2[i] = 0.0;
 }
 
-// |v| in FP64, the input of the cumulative sums, and the sign of every v_j.
+// Inclusive sums of |v| in FP64, written here rather than taken from a library so
+// that their order is fixed and visible.  Tiles of kScanTile values, kScanItems
+// consecutive ones per thread: a thread's values are summed left to right, the
+// thread sums of a tile are scanned left to right by one lane (so the last prefix of
+// a thread equals the next thread's starting sum bit for bit, and the tile's last
+// prefix its total), and the tile totals are scanned left to right by one lane.  A
+// prefix is offset(tile) + (start of its thread + running sum within the thread):
+// non-decreasing in i (every step adds a non-negative value to one summand, and
+// rounding is monotone) and deterministic; its rounding differs from a plain
+// left-to-right sum in the last bits.  The first pass also writes |v| and the sign
+// of each entry.
+constexpr int kScanItems = 16;
+constexpr int kScanThreads = 256;
+constexpr int64_t kScanTile = (int64_t)kScanItems * kScanThreads;
+
+int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
 template <bool FP32>
-__global__ void k_fwd_absv(int64_t n, const void *v, double *out, int8_t *sign) {
+__global__ __launch_bounds__(kScanThreads) void k_fwd_scan_tiles(int64_t n, const void *v,
+                                                                 double *__restrict__ absv,
+                                                                 int8_t *__restrict__ sign,
+                                                                 double *__restrict__ local,
+                                                                 double *__restrict__ tsum) {
+    __shared__ double sh[kScanThreads + 1];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanItems;
+    double run = 0.0;
+    double loc[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        double a = 0.0;
+        if (i < n) {
+            const double x = (double)load_v<FP32>(v, (uint32_t)i);
+            a = fabs(x);
+            absv[i] = a;
+            sign[i] = x > 0.0 ? (int8_t)1 : (x < 0.0 ? (int8_t)-1 : (int8_t)0);
+        }
+        run = run + a;
+        loc[k] = run;
+    }
+    sh[t] = run;
+    __syncthreads();
+    if (t == 0) {
+        double e = 0.0;
+        for (int u = 0; u < kScanThreads; ++u) {
+            const double su = sh[u];
+            sh[u] = e;
+            e = e + su;
+        }
+        sh[kScanThreads] = e;
+    }
+    __syncthreads();
+    const double start = sh[t];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        if (i < n) local[i] = start + loc[k];
+    }
+    if (t == 0) tsum[blockIdx.x] = sh[kScanThreads];
+}
+
+// Tile offsets: off[b] = sum of the totals of tiles 0 .. b-1, left to right (the
+// totals pass through LDS 1024 at a time; one lane adds).
+__global__ __launch_bounds__(256) void k_fwd_scan_offsets(int64_t tiles, const double *__restrict__ tsum,
+                                                         double *__restrict__ off) {
+    __shared__ double sh[1024];
+    double e = 0.0;
+    for (int64_t b0 = 0; b0 < tiles; b0 += 1024) {
+        const int64_t m = tiles - b0 < 1024 ? tiles - b0 : 1024;
+        for (int64_t u = threadIdx.x; u < m; u += blockDim.x) sh[u] = tsum[b0 + u];
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int64_t u = 0; u < m; ++u) {
+                const double su = sh[u];
+                sh[u] = e;
+                e = e + su;
+            }
+        __syncthreads();
+        for (int64_t u = threadIdx.x; u < m; u += blockDim.x) off[b0 + u] = sh[u];
+        __syncthreads();
+    }
+}
+
+// cdf[i] = off[tile of i] + local[i], in place.
+__global__ void k_fwd_scan_add(int64_t n, const double *__restrict__ off, double *__restrict__ cdf) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double x = (double)load_v<FP32>(v, (uint32_t)i);
-    out[i] = fabs(x);
-    sign[i] = x > 0.0 ? (int8_t)1 : (x < 0.0 ? (int8_t)-1 : (int8_t)0);
+    cdf[i] = off[i / kScanTile] + cdf[i];
 }
 
 // Per-node mean and standard error from the sums of Y and Y^2, in place.
@@ -365,13 +445,27 @@ hipError_t launch_fwd_rows(int64_t n, const InstArgs &P, FwdRow *frows, hipStrea
 
 hipError_t launch_fwd_cdf(int64_t n, const void *v, bool fp32, double *absv, int8_t *vsign, double *cdf,
                           int32_t *guide, void *temp, size_t &temp_bytes, hipStream_t s) {
-    if (!temp) return hipcub::DeviceScan::InclusiveSum(nullptr, temp_bytes, absv, cdf, (int)n, s);
-    const unsigned g = (unsigned)((n + 255) / 256);
-    if (fp32) hipLaunchKernelGGL(k_fwd_absv<true>, dim3(g), dim3(256), 0, s, n, v, absv, vsign);
-    else hipLaunchKernelGGL(k_fwd_absv<false>, dim3(g), dim3(256), 0, s, n, v, absv, vsign);
+    const int64_t tiles = scan_tiles(n);
+    if (!temp) {
+        temp_bytes = sizeof(double) * 2 * (size_t)tiles;
+        return hipSuccess;
+    }
+    if (n <= 0) return hipSuccess;
+    if (tiles > 0x7FFFFFFF || temp_bytes < sizeof(double) * 2 * (size_t)tiles) return hipErrorInvalidValue;
+    double *tsum = static_cast<double *>(temp), *off = tsum + tiles;
+    if (fp32)
+        hipLaunchKernelGGL(k_fwd_scan_tiles<true>, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, n, v,
+                           absv, vsign, cdf, tsum);
+    else
+        hipLaunchKernelGGL(k_fwd_scan_tiles<false>, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, n, v,
+                           absv, vsign, cdf, tsum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hipcub::DeviceScan::InclusiveSum(temp, temp_bytes, absv, cdf, (int)n, s);
+    hipLaunchKernelGGL(k_fwd_scan_offsets, dim3(1), dim3(256), 0, s, tiles, tsum, off);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fwd_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, off, cdf);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t G = guide_cells(n);
     hipLaunchKernelGGL(k_fwd_guide, dim3((unsigned)((G + 256) / 256)), dim3(256), 0, s, n, G, cdf,

@@ -4,7 +4,6 @@
 // one gather instead of the row scan discussed in Sec. 4.
 #include <math.h>
 
-#include <hipcub/hipcub.hpp>
 
 #include "mc_internal.hpp"
 
@@ -219,13 +218,6 @@ hipError_t launch_relabel_keys(int64_t n, const double *r, unsigned long long *k
     hipLaunchKernelGGL(k_relabel_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, r, keys,
                        vals);
     return hipGetLastError();
-}
-
-hipError_t sort_pairs_u64(void *temp, size_t &temp_bytes, const unsigned long long *kin,
-                          unsigned long long *kout, const uint32_t *vin, uint32_t *vout, int64_t n,
-                          hipStream_t s) {
-    return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, kin, kout, vin, vout, (int)n, 0, 64,
-                                              s);
 }
 
 hipError_t launch_relabel_apply(int64_t n, const int64_t *rowptr, const uint32_t *inv,
