@@ -338,8 +338,6 @@ hipError_t launch_relabel_keys(int64_t n, const double *r, unsigned long long *k
                                hipStream_t s);
 hipError_t launch_relabel_apply(int64_t n, const int64_t *rowptr, const uint32_t *inv,
                                 uint32_t *perm, Tables &tb, bool build_perm, hipStream_t s);
-// stable ascending sort of (key, value) pairs (sort.hip); temp == null: the bytes
-// of scratch it needs go to temp_bytes
 hipError_t sort_pairs_u64(void *temp, size_t &temp_bytes, const unsigned long long *kin,
                           unsigned long long *kout, const uint32_t *vin, uint32_t *vout, int64_t n,
                           hipStream_t s);

@@ -132,6 +132,9 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+// Sorts n pairs (kin, vin) into (kout, vout) on stream s.  With temp == null only
+// the scratch size (alternate key and value buffers and the digit counts) is written
+// to temp_bytes; otherwise temp must hold that many bytes.  kin / vin are not changed.
 hipError_t sort_pairs_u64(void *temp, size_t &temp_bytes, const unsigned long long *kin,
                           unsigned long long *kout, const uint32_t *vin, uint32_t *vout, int64_t n,
                           hipStream_t s) {
