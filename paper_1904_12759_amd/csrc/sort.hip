@@ -3,7 +3,7 @@
 // library needs an order (relabelling rows hot-first, the rankings of the isim
 // measure); written here so that the library carries no sort of someone else's.
 //
-// A pass over tiles of kTile pairs (256 threads x 16 items, item k of thread t at
+// A pass over tiles of kSortTile pairs (256 threads x 16 items, item k of thread t at
 // tile position 256 k + t, so loads are coalesced and positions run in (k, t)
 // order):
 //   1. every tile counts its digits (LDS atomics; counts do not depend on order),
