@@ -249,7 +249,7 @@ constexpr uint32_t kLdsPerCu = 160 * 1024;   // LDS bytes of one gfx950 compute 
 // are that many entries: a small launch gains more from waves than from full
 // lanes.
 constexpr int64_t kTaskWalkersMin = 1024;
-constexpr int64_t kTaskWalkersMax = 8192;
+constexpr int64_t kTaskWalkersMax = 16384;
 constexpr int64_t kMinTasks = 20480;
 constexpr int64_t kFullTasks = 5120;
 // Chunk slots of entries with their own walker counts each fill an LDS session
