@@ -247,6 +247,43 @@ def entries_at_1e3(mc, h, v, idx, pilot: int, target: float = 1e-3, cap: int = 1
     return out
 
 
+def entries_at_1e3_device(mc, h, v, idx, pilot: int, target: float = 1e-3, margin: float = 1.2,
+                          max_walkers: int = 1 << 26, exact=None):
+    """The same two-pass rule with both passes on the device in one call
+    (mc_expmv_entries_to_target: the production walker counts are computed on the GPU
+    from the pilot, so the host does not wait between the passes).  One pass: no
+    re-run of entries that miss the target.  entries_per_s includes the pilot."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    v = h._v(v)
+    ti = torch.as_tensor(np.asarray(idx, np.int64), device=dev)
+    k = ti.numel()
+    est = torch.empty(k, dtype=torch.float64, device=dev)
+    se = torch.empty(k, dtype=torch.float64, device=dev)
+    nw = torch.empty(k, dtype=torch.int64, device=dev)
+    h.entries_to_target(v, ti, pilot, target, margin, 2, max_walkers, est, se, nw)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.entries_to_target(v, ti, pilot, target, margin, 2, max_walkers, est, se, nw)
+    seconds = time.perf_counter() - t0
+    en, sn, nn = est.cpu().numpy(), se.cpu().numpy(), nw.cpu().numpy()
+    rel = sn / np.abs(en)
+    out = dict(entries=k, seconds=seconds, entries_per_s_with_pilot=k / seconds,
+               pilot_walkers_per_entry=pilot, margin=margin, walkers=int(nn.sum()),
+               max_rel_stderr=float(rel.max()), entries_above_target=int((rel > target).sum()),
+               final_walkers_max=int(nn.max()))
+    if exact is not None:
+        ex = np.asarray(exact, np.float64)
+        err = np.abs(en - ex) / np.abs(ex)
+        z = (en - ex) / np.maximum(sn, 1e-300)
+        out.update(achieved_max_rel_err=float(err.max()),
+                   achieved_median_rel_err=float(np.median(err)),
+                   achieved_frac_within_1e3=float(np.mean(err <= target)),
+                   achieved_frac_within_3e3=float(np.mean(err <= 3 * target)),
+                   max_abs_z=float(np.abs(z).max()), rms_z=float(np.sqrt(np.mean(z * z))))
+    return out
+
+
 def bench_grid2d_entries(mc, seed):
     """2-D Dirichlet Laplacian 32x32, t = 0.1, 16 entries, FP64: entries/s at 1e-3,
     and the achieved errors against exp(tA) v from expm_multiply."""
@@ -258,6 +295,7 @@ def bench_grid2d_entries(mc, seed):
     entries_at_1e3(mc, h, w.v, w.idx, 10_000)                       # warm-up
     r = entries_at_1e3(mc, h, w.v, w.idx, 10_000, exact=x[w.idx])
     r["workload"] = "grid2d 32x32 Dirichlet, t=0.1, 16 entries, FP64, two-pass (pilot 1e4)"
+    r["device_sized"] = entries_at_1e3_device(mc, h, w.v, w.idx, 10_000, exact=x[w.idx])
     return r
 
 
@@ -528,6 +566,8 @@ def bench_learned(mc, seed, n=1_000_000, m=4, plain_cap=1 << 28):
     steps_p = float(n_plain.sum() * ev_plain)
     steps_l = float(n_learn.sum() * ev_learn)
     prod = entries_at_1e3(mc, h, v, idx, 10_000, exact=x[idx])
+    prod["device_sized"] = entries_at_1e3_device(mc, h, v, idx, 10_000, max_walkers=1 << 24,
+                                                 exact=x[idx])
     learn_feas = entries_at_1e3(mc, h, v, feas, 10_000, exact=x[feas])
     tail_learn = _tail_diagnostics(h, v, diag_nodes, 100_000, True)
     out = dict(workload=f"BA n={n} m={m} seed 1, A=(0.5/lambda_max)*adjacency "

@@ -260,6 +260,32 @@ mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx
                                  const int64_t *n_walkers, double *est, double *stderr_);
 
 /*
+ * Entries to a relative standard error target, both passes on the device (the
+ * error model of Sec. 5: the statistical error of M walkers is sigma / sqrt(M)).
+ * A pilot of pilot_walkers walkers per entry (ordinals 0 .. pilot-1) gives x_e and
+ * sigma_e = se_e sqrt(pilot); entry e then gets
+ * N_e = ceil(margin (sigma_e / (target |x_e|))^2) walkers, clamped to
+ * [min_walkers, max_walkers] (min_walkers when the pilot saw no spread, max_walkers
+ * when x_e = 0 or a value is not finite), walked with the ordinals pilot ..
+ * pilot + N_e - 1 (independent of the pilot) in one launch whose task count the
+ * device reads, so the host does not wait between the passes.  est, stderr_ are
+ * the production run's (entry e's values are those of a run of N_e walkers from
+ * ordinal pilot); walkers_out (device int64_t[k], may be NULL) receives N_e.
+ *   pilot_walkers  2 .. 2^31 (with opts.qmc_first a multiple of the replicate,
+ *                  512 (FP64) or 1024 (FP32), so the production run's replicates
+ *                  are whole);  target > 0 finite;  margin >= 1 finite;
+ *   2 <= min_walkers <= max_walkers, pilot_walkers + max_walkers <= 2^32
+ * Asynchronous on the handle's stream like mc_expmv_entries_multi; device memory
+ * for the chunk partials is sized for max_walkers (24 B per chunk of 512 (FP64)
+ * or 1024 (FP32) walkers per entry).  Errors: MC_ERR_INVALID_ARG,
+ * MC_ERR_NO_MEMORY, and the walk's latched errors at the next mc_expmv_sync.
+ */
+mc_status mc_expmv_entries_to_target(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
+                                     int64_t pilot_walkers, double target, double margin,
+                                     int64_t min_walkers, int64_t max_walkers, double *est,
+                                     double *stderr_, int64_t *walkers_out);
+
+/*
  * Every entry of exp(tA) v with n_per_node walkers started at each node
  * (Algorithm 1 applied at every node; equal to mc_expmv_entries with
  * idx = 0..n-1).  est, stderr_: device double[n] (stderr_ may be NULL).

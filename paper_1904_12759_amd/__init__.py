@@ -137,6 +137,10 @@ _SIGS = {
     "mc_expmv_entries_multi": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p]),
+    "mc_expmv_entries_to_target": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                                  ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_forward_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -431,6 +435,30 @@ class MCExpmv:
         if sync:
             self.sync()
         return est, stderr
+
+    def entries_to_target(self, v, idx, pilot_walkers: int, target: float = 1e-3,
+                          margin: float = 1.2, min_walkers: int = 2, max_walkers: int = 1 << 26,
+                          est=None, stderr=None, walkers=None, sync: bool = True):
+        """Entries to a relative standard error target, pilot and production on the
+        device (mc_expmv_entries_to_target): returns (est, stderr, walkers per entry)."""
+        import torch
+        v = self._v(v)
+        idx = torch.as_tensor(idx).to(device=self.device, dtype=torch.int64).contiguous()
+        k = idx.numel()
+        if est is None:
+            est = torch.empty(k, dtype=torch.float64, device=self.device)
+        if stderr is None:
+            stderr = torch.empty(k, dtype=torch.float64, device=self.device)
+        if walkers is None:
+            walkers = torch.empty(k, dtype=torch.int64, device=self.device)
+        _require_cuda(v, idx, est, stderr, walkers)
+        _check(load().mc_expmv_entries_to_target(self._h, _ptr(v), _ptr(idx), k, int(pilot_walkers),
+                                                 float(target), float(margin), int(min_walkers),
+                                                 int(max_walkers), _ptr(est), _ptr(stderr),
+                                                 _ptr(walkers)), "mc_expmv_entries_to_target")
+        if sync:
+            self.sync()
+        return est, stderr, walkers
 
     def full(self, v, n_per_node: int, est=None, stderr=None, sync: bool = True):
         import torch

@@ -48,6 +48,7 @@ struct mc_expmv_s {
     // last run
     bool ran = false;
     uint64_t last_walkers = 0;
+    const int64_t *last_walkers_dev = nullptr;   // walker total written on the device
     int last_grid = 0;
     int32_t *rowof = nullptr;            // row of each CSR position (learned proposal)
     uint32_t *perm = nullptr;            // relabel: original node -> walk id
@@ -72,6 +73,8 @@ struct mc_expmv_s {
     int64_t *var_host = nullptr;         // pinned staging of the same
     int64_t var_cap = 0;                 // int64 slots in both
     hipEvent_t var_ev = nullptr;         // staging copy done
+    double *tgt_se = nullptr;            // pilot standard errors of entries_to_target
+    int64_t tgt_se_cap = 0;
     double *scratch = nullptr;           // this device's copy of `scratch` (noalloc entries)
     // matrix-free 7-point stencil (mc_expmv_create_stencil7): face rates and a_xx
     bool stencil = false;
@@ -366,6 +369,7 @@ mc_status run_walk(mc_expmv_s *h, const void *v, const int64_t *idx, int64_t k, 
     HIP_TRY(hipEventRecord(h->ev1, h->stream));
     h->ran = true;
     h->last_walkers = (uint64_t)k * (uint64_t)nwalk;
+    h->last_walkers_dev = nullptr;
     h->last_grid = a.ntasks > 0 ? launch_walk_grid(a.ntasks, (int)h->opts.walkers_per_block) : 0;
     h->last_fp32 = fp32;
     h->last_prop = prop;
@@ -447,6 +451,7 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->sdiag);
     if (h->var_host) (void)hipHostFree(h->var_host);
     if (h->var_ev) (void)hipEventDestroy(h->var_ev);
+    (void)hipFree(h->tgt_se);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
@@ -764,6 +769,116 @@ mc_status mc_expmv_entries_multi(mc_expmv_t h, const void *v, const int64_t *idx
     HIP_TRY(hipEventRecord(h->ev1, h->stream));
     h->ran = true;
     h->last_walkers = walkers;
+    h->last_walkers_dev = nullptr;
+    h->last_grid = launch_walk_grid(a.ntasks, (int)h->opts.walkers_per_block);
+    h->last_fp32 = fp32;
+    h->last_prop = prop;
+    h->last_fwd = false;
+    return MC_OK;
+}
+
+mc_status mc_expmv_entries_to_target(mc_expmv_t h, const void *v, const int64_t *idx, int64_t k,
+                                     int64_t pilot_walkers, double target, double margin,
+                                     int64_t min_walkers, int64_t max_walkers, double *est,
+                                     double *stderr_, int64_t *walkers_out) {
+    fault_scope_begin();
+    if (!h || !v || k < 0) return MC_ERR_INVALID_ARG;
+    if (k > 0 && (!idx || !est)) return MC_ERR_INVALID_ARG;
+    if (pilot_walkers < 2 || pilot_walkers > ((int64_t)1 << 31)) return MC_ERR_INVALID_ARG;
+    if (!isfinite(target) || !(target > 0.0) || !isfinite(margin) || !(margin >= 1.0))
+        return MC_ERR_INVALID_ARG;
+    if (min_walkers < 2 || max_walkers < min_walkers || pilot_walkers + max_walkers > 0x100000000ll)
+        return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    if (k == 0) return MC_OK;
+    if (k > 0x7FFFFFFF) return MC_ERR_INVALID_ARG;
+    const bool fp32 = h->opts.weight_prec == MC_FP32;
+    const int64_t chunk = chunk_walkers(fp32);
+    // lattice replicates are chunks of ordinals: the production run starts on one
+    if (h->opts.qmc_first && pilot_walkers % chunk != 0) return MC_ERR_INVALID_ARG;
+    const int64_t per_entry = (max_walkers + chunk - 1) / chunk;
+    if (per_entry > ((int64_t)1 << 40) / k) return MC_ERR_INVALID_ARG;
+    const int64_t ub = k * per_entry;            // most chunk slots the sizing can ask for
+    // pilot: ordinals 0 .. pilot-1, its estimates in est / stderr_ (a stderr buffer
+    // of the handle's when the caller passes none: the sizing needs it)
+    double *pse = stderr_;
+    if (!pse) {
+        if (k > h->tgt_se_cap) {
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            (void)hipFree(h->tgt_se);
+            h->tgt_se = nullptr;
+            h->tgt_se_cap = 0;
+            HIP_TRY(dalloc(&h->tgt_se, k));
+            h->tgt_se_cap = k;
+        }
+        pse = h->tgt_se;
+    }
+    mc_status st = run_walk(h, v, idx, k, pilot_walkers, est, pse, false, 0, h->has_prop ? 1 : 0,
+                            nullptr, nullptr, nullptr, nullptr);
+    if (st != MC_OK) return st;
+    const int64_t need = 2 * k + 3;
+    if (need > h->var_cap) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        (void)hipFree(h->var_dev);
+        if (h->var_host) (void)hipHostFree(h->var_host);
+        h->var_dev = nullptr;
+        h->var_host = nullptr;
+        h->var_cap = 0;
+        HIP_TRY(dalloc(&h->var_dev, need));
+        HIP_TRY(host_malloc((void **)&h->var_host, sizeof(int64_t) * (size_t)need));
+        h->var_cap = need;
+    }
+    if (ub * 3 > h->part_cap) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        (void)hipFree(h->part);
+        h->part = nullptr;
+        h->part_cap = 0;
+        HIP_TRY(dalloc(&h->part, ub * 3));
+        h->part_cap = ub * 3;
+    }
+    // the previous entries_multi's staging copy into var_dev is ordered before this
+    // stream's work, so the sizing kernel may overwrite var_dev
+    int64_t *var_task = h->var_dev, *var_nwalk = h->var_dev + k + 1, *out2 = h->var_dev + 2 * k + 1;
+    HIP_TRY(launch_size_to_target(k, pilot_walkers, target, margin, min_walkers, max_walkers, chunk,
+                                  est, pse, var_task, var_nwalk, out2, h->stream));
+    const bool prop = h->has_prop;
+    WalkArgs a{};
+    fill_inst(h, v, prop, a.P);
+    a.idx = idx;
+    a.k = k;
+    a.n = h->n;
+    a.nwalk = 0;
+    a.w0 = pilot_walkers;
+    a.chunk = (uint32_t)chunk;
+    a.chunks = 1;
+    a.group = 1;
+    // the grid covers at most the waves that stay resident several times over; the
+    // kernel walks the device's slot count with a grid stride
+    const int64_t grid_tasks = ub < kTargetGridTasks ? ub : kTargetGridTasks;
+    a.var_slots = grid_tasks;
+    a.ntasks = grid_tasks;
+    a.slots_dev = out2;
+    a.est = est;
+    a.se = stderr_;
+    a.part = h->part;
+    a.counters = h->counters;
+    a.flags = h->flags;
+    a.cond = h->opts.cond_first_jump != 0;
+    a.qmc = h->opts.qmc_first != 0;
+    a.var_task = var_task;
+    a.var_nwalk = var_nwalk;
+    a.var_chunks_max = per_entry;
+    HIP_TRY(hipEventRecord(h->ev0, h->stream));
+    HIP_TRY(launch_walk(a, h->opts.mode, fp32, prop, false, (int)h->opts.walkers_per_block,
+                        h->stream));
+    HIP_TRY(launch_finalize(a, h->stream));
+    HIP_TRY(hipEventRecord(h->ev1, h->stream));
+    if (walkers_out)
+        HIP_TRY(hipMemcpyAsync(walkers_out, var_nwalk, sizeof(int64_t) * (size_t)k,
+                               hipMemcpyDeviceToDevice, h->stream));
+    h->ran = true;
+    h->last_walkers = 0;
+    h->last_walkers_dev = out2 + 1;
     h->last_grid = launch_walk_grid(a.ntasks, (int)h->opts.walkers_per_block);
     h->last_fp32 = fp32;
     h->last_prop = prop;
@@ -888,6 +1003,12 @@ mc_status mc_expmv_stats(mc_expmv_t h, mc_expmv_run_stats *out) {
             c[0] += pc[2 * (size_t)b];
             c[1] += pc[2 * (size_t)b + 1];
         }
+    }
+    if (h->last_walkers_dev) {
+        int64_t w = 0;
+        HIP_TRY(hipMemcpy(&w, h->last_walkers_dev, sizeof(w), hipMemcpyDeviceToHost));
+        h->last_walkers = (uint64_t)w;
+        h->last_walkers_dev = nullptr;
     }
     out->walkers = h->last_walkers;
     out->events = c[0];
@@ -1798,6 +1919,7 @@ mc_status run_forward(mc_expmv_s *h, const void *v, int64_t w0, int64_t nwalk, d
     HIP_TRY(hipEventRecord(h->ev1, h->stream));
     h->ran = true;
     h->last_walkers = (uint64_t)nwalk;
+    h->last_walkers_dev = nullptr;
     h->last_grid = forward_grid(chunks);
     h->last_fp32 = fp32;
     h->last_prop = false;

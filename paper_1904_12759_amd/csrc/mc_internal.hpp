@@ -131,7 +131,7 @@ struct WalkArgs {
     int64_t k;                 // entries
     int64_t n;
     int64_t nwalk;             // walkers per entry
-    int64_t w0;                // first walker ordinal (trace only)
+    int64_t w0;                // first walker ordinal (trace, and entries sized on the device)
     uint32_t chunk;            // walkers per task
     int64_t chunks;            // chunks per entry
     uint32_t group;            // entries per task (1 when chunks > 1)
@@ -151,6 +151,9 @@ struct WalkArgs {
     const int64_t *var_nwalk;
     int64_t var_slots;
     int64_t var_chunks_max;    // most chunks of one entry
+    // walker counts written on the device (null otherwise): *slots_dev chunk slots,
+    // one per task; ntasks and var_slots are then only an upper bound for the grid
+    const int64_t *slots_dev;
 };
 
 // Forward (Algorithm 2) walks: one wave per chunk of kFwdChunk walker ordinals.
@@ -174,7 +177,7 @@ struct FwdArgs {
     const FwdRow *frows;       // [n] row record + d of every state (walk order)
     int64_t n;
     int64_t nwalk;             // M
-    int64_t w0;                // first walker ordinal (trace only)
+    int64_t w0;                // first walker ordinal (trace, and entries sized on the device)
     int64_t chunks;            // ceil(M / kFwdChunk)
     const double *cdf;         // [n] cumulative sums of |v| in node order
     const double *absv;        // [n] |v|
@@ -270,6 +273,10 @@ inline uint32_t group_size(int64_t nwalk, int64_t k, uint32_t task_walkers) {
     return (uint32_t)(g < 1 ? 1 : g);
 }
 
+// Tasks the grid of a run sized on the device covers at most (five waves on each
+// of 1024 SIMDs, twice): the kernel then strides over the device's slot count.
+constexpr int64_t kTargetGridTasks = 10240;
+
 // Largest walk grid (blocks); the per-block counter buffer has this many pairs.
 constexpr int kMaxWalkGrid = 1 << 16;
 
@@ -289,6 +296,13 @@ int launch_walk_grid(int64_t ntasks, int block);
 hipError_t launch_walk(const WalkArgs &a, int mode, bool fp32, bool prop, bool trace,
                        int block, hipStream_t s);
 hipError_t launch_finalize(const WalkArgs &a, hipStream_t s);
+// Walker counts of a run to a relative standard error target from a pilot run's
+// estimates (walk.hip): var_task[0 .. k], var_nwalk[0 .. k), and at out2 the total
+// chunk slots and the total walkers.
+hipError_t launch_size_to_target(int64_t k, int64_t pilot, double target, double margin,
+                                 int64_t min_walkers, int64_t max_walkers, int64_t chunk,
+                                 const double *est, const double *se, int64_t *var_task,
+                                 int64_t *var_nwalk, int64_t *out2, hipStream_t s);
 hipError_t launch_math_eval(int fn, const double *x, double *y, int64_t n, hipStream_t s);
 
 // batched launch (batch.hip): queue reset, persistent walk, finalize

@@ -55,7 +55,9 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     unsigned long long my_events = 0, my_jumps = 0;
     uint32_t err = 0;
-    for (int64_t task = wave_id; task < a.ntasks; task += nwaves) {
+    const int64_t ntasks = a.slots_dev ? *a.slots_dev : a.ntasks;
+    const int64_t var_slots = a.slots_dev ? ntasks : a.var_slots;
+    for (int64_t task = wave_id; task < ntasks; task += nwaves) {
         int64_t e_first, c, chunks, nwalk, pbase;
         uint32_t G;
         GroupOut out{a.est, a.se, a.part, 0, 0, 0};
@@ -63,7 +65,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
             // entries with their own walker counts: the task is `group` consecutive
             // chunk slots, decoded per slot inside run_group
             const int64_t s0 = task * (int64_t)a.group;
-            const int64_t left = a.var_slots - s0;
+            const int64_t left = var_slots - s0;
             G = (uint32_t)(left < (int64_t)a.group ? left : (int64_t)a.group);
             out.var_task = a.var_task;
             out.var_nwalk = a.var_nwalk;
@@ -289,6 +291,82 @@ hipError_t launch_m(const WalkArgs &a, bool fp32, bool prop, bool trace, int blo
 }
 
 }  // namespace
+
+namespace {
+
+// Walker counts to a relative standard error target (the two-pass rule of the
+// error model of Sec. 5, eps ~ sigma / sqrt(M)): entry e gets
+// N_e = ceil(margin (sigma_e / (target |x_e|))^2) walkers, sigma_e = se_e sqrt(pilot)
+// from the pilot's estimate x_e and standard error se_e, clamped to
+// [min_walkers, max_walkers] (min_walkers when the pilot saw no spread, max_walkers
+// when |x_e| = 0 or a value is not finite), then the chunk slots of every entry and
+// their prefix sums.  One block: thread j takes a contiguous run of entries, one lane
+// scans the run totals (integers, exact).
+__global__ __launch_bounds__(1024) void k_size_to_target(int64_t k, int64_t pilot, double target,
+                                                         double margin, int64_t min_w, int64_t max_w,
+                                                         int64_t chunk, const double *__restrict__ est,
+                                                         const double *__restrict__ se,
+                                                         int64_t *__restrict__ var_task,
+                                                         int64_t *__restrict__ var_nwalk,
+                                                         int64_t *__restrict__ out2) {
+    __shared__ long long run_s[1024], run_w[1024];
+    const int j = threadIdx.x;
+    const int64_t per = (k + 1023) / 1024;
+    const int64_t lo = (int64_t)j * per;
+    const int64_t hi = lo + per < k ? lo + per : k;
+    const double sp = sqrt((double)pilot);
+    long long cs = 0, ws = 0;
+    for (int64_t e = lo; e < hi; ++e) {
+        const double x = fabs(est[e]);
+        const double sig = (se ? se[e] : 0.0) * sp;
+        double nd;
+        if (!isfinite(x) || !isfinite(sig)) nd = (double)max_w;
+        else if (sig == 0.0) nd = (double)min_w;
+        else if (x == 0.0) nd = (double)max_w;
+        else {
+            const double r = sig / (target * x);
+            nd = ceil(margin * r * r);
+        }
+        if (!(nd >= (double)min_w)) nd = (double)min_w;
+        if (nd > (double)max_w) nd = (double)max_w;
+        const int64_t m = (int64_t)nd;
+        var_nwalk[e] = m;
+        cs += (m + chunk - 1) / chunk;
+        ws += m;
+    }
+    run_s[j] = cs;
+    run_w[j] = ws;
+    __syncthreads();
+    if (j == 0) {
+        long long e_s = 0, e_w = 0;
+        for (int u = 0; u < 1024; ++u) {
+            const long long a = run_s[u];
+            run_s[u] = e_s;
+            e_s += a;
+            e_w += run_w[u];
+        }
+        var_task[k] = e_s;
+        out2[0] = e_s;
+        out2[1] = e_w;
+    }
+    __syncthreads();
+    long long o = run_s[j];
+    for (int64_t e = lo; e < hi; ++e) {
+        var_task[e] = o;
+        o += (var_nwalk[e] + chunk - 1) / chunk;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_size_to_target(int64_t k, int64_t pilot, double target, double margin,
+                                 int64_t min_walkers, int64_t max_walkers, int64_t chunk,
+                                 const double *est, const double *se, int64_t *var_task,
+                                 int64_t *var_nwalk, int64_t *out2, hipStream_t s) {
+    hipLaunchKernelGGL(k_size_to_target, dim3(1), dim3(1024), 0, s, k, pilot, target, margin,
+                       min_walkers, max_walkers, chunk, est, se, var_task, var_nwalk, out2);
+    return hipGetLastError();
+}
 
 int launch_walk_grid(int64_t ntasks, int block) { return walk_grid(ntasks, block); }
 

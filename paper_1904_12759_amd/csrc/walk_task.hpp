@@ -593,7 +593,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             const int64_t c = sl - out.var_task[lo];
             const int64_t rem = out.var_nwalk[lo] - c * (int64_t)C;
             cntg = (uint32_t)(rem < (int64_t)C ? rem : (int64_t)C);
-            ordg = (uint32_t)(c * (int64_t)C);
+            ordg = ord0 + (uint32_t)(c * (int64_t)C);
         }
         L.ord0[lane] = ordg;
         L.n0[lane] = cntg << 16;

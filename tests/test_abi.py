@@ -82,3 +82,6 @@ def test_null_handle_calls_are_rejected():
     assert lib.mc_expmv_full(None, None, 1, None, None) == 1
     assert lib.mc_expmv_sync(None) == 1
     lib.mc_expmv_destroy(None)
+    assert lib.mc_expmv_entries_multi(None, None, None, 1, None, None, None) == 1
+    assert lib.mc_expmv_entries_to_target(None, None, None, 1, 100, 1e-3, 1.2, 2, 1000,
+                                          None, None, None) == 1
