@@ -53,3 +53,20 @@ def test_isim_errors():
     with pytest.raises(mc.MCError) as ei:
         mc.isim(x, y)
     assert ei.value.code == 3
+
+
+def test_isim_extreme_values_and_constant_vectors():
+    """Keys across the whole double range (largest and smallest magnitudes of both
+    signs, subnormals, signed zeros) in a vector longer than two sort tiles and not a
+    multiple of one, and constant vectors (every node tied)."""
+    rng = np.random.default_rng(11)
+    n = 9001
+    vals = np.array([-1.7e308, -1.0, -5e-324, -0.0, 0.0, 5e-324, 1e-300, 1.0, 1.7e308])
+    x = rng.choice(vals, n)
+    y = rng.choice(vals, n)
+    for k in (1, 17, n // 3, n):
+        assert mc.isim(x, y, k) == pytest.approx(rank.isim(x, y, k), rel=1e-12, abs=1e-15), k
+    z = np.full(n, 3.5)
+    assert mc.isim(z, z) == 0.0
+    assert mc.isim(z, -np.arange(n, dtype=np.float64), n // 2) == \
+        pytest.approx(rank.isim(z, -np.arange(n, dtype=np.float64), n // 2), rel=1e-12)
