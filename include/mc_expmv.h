@@ -412,7 +412,7 @@ typedef struct {
 typedef struct {
     uint32_t struct_size;       /* sizeof(mc_batch_opts) */
     uint32_t walkers_per_block; /* 64, 128 or 256; 0 = autotune */
-    uint32_t blocks_per_cu;     /* persistent grid = CUs * this (1..64); 0 = autotune */
+    uint32_t blocks_per_cu;     /* persistent grid = CUs * this (1..128); 0 = autotune */
     uint32_t group;             /* tasks taken per grab from a global counter; 0 = static
                                    stride over the task list */
     int32_t use_graph;          /* 1 (default): capture the launch in a HIP graph */

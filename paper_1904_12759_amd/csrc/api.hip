@@ -118,6 +118,8 @@ hipError_t host_malloc(void **p, size_t bytes) {
 namespace {
 
 constexpr int kMaxDevices = 64;
+// Largest batch grid per compute unit (the per-block counters are sized for it).
+constexpr int kBatchBlocksPerCuMax = 128;
 std::mutex g_scratch_mu;
 double *g_scratch_dev[kMaxDevices] = {};
 
@@ -1219,8 +1221,10 @@ void tune_cache_store(const mc_batch_s *b, const Sched &s) {
 // the fastest.
 mc_status autotune(mc_batch_s *b, float *best_ms_out) {
     static const Sched cands[] = {
-        {256, 4, 0},  {256, 8, 0},   {128, 8, 0},   {128, 16, 0}, {64, 16, 0},  {64, 32, 0},
-        {256, 8, 16}, {256, 8, 128}, {128, 16, 16}, {64, 32, 16}, {64, 32, 64}, {256, 16, 64},
+        {256, 4, 0},  {256, 8, 0},   {256, 16, 0},  {256, 32, 0}, {256, 64, 0}, {256, 128, 0},
+        {128, 8, 0},
+        {128, 16, 0}, {128, 32, 0},  {64, 16, 0},   {64, 32, 0},  {256, 8, 16}, {256, 8, 128},
+        {128, 16, 16}, {64, 32, 16}, {64, 32, 64},  {256, 16, 64},
     };
     float best = 1e30f;
     Sched bs = cands[0];
@@ -1284,7 +1288,7 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
     }
     const uint32_t wpb = o.walkers_per_block;
     if (wpb != 0 && wpb != 64 && wpb != 128 && wpb != 256) return MC_ERR_INVALID_ARG;
-    if (o.blocks_per_cu > 64) return MC_ERR_INVALID_ARG;
+    if (o.blocks_per_cu > kBatchBlocksPerCuMax) return MC_ERR_INVALID_ARG;
     if (o.slot_rows < -1 || o.slot_rows > 1) return MC_ERR_INVALID_ARG;
     for (int i = 0; i < n_inst; ++i) {
         const mc_instance_desc &d = desc[i];
@@ -1390,7 +1394,7 @@ mc_status mc_expmv_batch_create(mc_batch_t *out, int32_t n_inst, const mc_instan
     B_TRY(dalloc(&b->d_inst, n_inst));
     B_TRY(dalloc(&b->d_fin, n_inst + 1));
     B_TRY(dalloc(&b->part, part_doubles));
-    B_TRY(dalloc(&b->counters, 2 * (int64_t)b->ncu * 64 * (int64_t)b->classes.size()));
+    B_TRY(dalloc(&b->counters, 2 * (int64_t)b->ncu * kBatchBlocksPerCuMax * (int64_t)b->classes.size()));
     B_TRY(dalloc(&b->queue, 1));
     B_TRY(dalloc(&b->flags, 1));
     B_TRY(host_malloc((void **)&b->flag_host, sizeof(uint32_t)));
@@ -1516,7 +1520,7 @@ mc_status mc_expmv_batch_set_schedule(mc_batch_t b, const mc_batch_schedule *sch
     if (!b || !sched) return MC_ERR_INVALID_ARG;
     const uint32_t wpb = sched->walkers_per_block;
     if (wpb != 64 && wpb != 128 && wpb != 256) return MC_ERR_INVALID_ARG;
-    if (sched->blocks_per_cu < 1 || sched->blocks_per_cu > 64) return MC_ERR_INVALID_ARG;
+    if (sched->blocks_per_cu < 1 || sched->blocks_per_cu > kBatchBlocksPerCuMax) return MC_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(b->dev));
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->block = (int)wpb;
