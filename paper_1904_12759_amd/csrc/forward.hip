@@ -291,14 +291,17 @@ __global__ __launch_bounds__(kScanThreads) void k_fwd_scan_tiles(int64_t n, cons
                                                                  int8_t *__restrict__ sign,
                                                                  double *__restrict__ local,
                                                                  double *__restrict__ tsum) {
+    // the tile passes through LDS so that global loads and stores stay coalesced
+    // (position p = 256 k + t for lane t) while each thread scans its own 16
+    // consecutive values (row p / 16, padded to 17 against bank conflicts)
+    __shared__ double tile[kScanThreads * (kScanItems + 1)];
     __shared__ double sh[kScanThreads + 1];
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanItems;
-    double run = 0.0;
-    double loc[kScanItems];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = base + k;
+        const int p = k * kScanThreads + t;
+        const int64_t i = base + p;
         double a = 0.0;
         if (i < n) {
             const double x = (double)load_v<FP32>(v, (uint32_t)i);
@@ -306,8 +309,14 @@ __global__ __launch_bounds__(kScanThreads) void k_fwd_scan_tiles(int64_t n, cons
             absv[i] = a;
             sign[i] = x > 0.0 ? (int8_t)1 : (x < 0.0 ? (int8_t)-1 : (int8_t)0);
         }
-        run = run + a;
-        loc[k] = run;
+        tile[(p / kScanItems) * (kScanItems + 1) + p % kScanItems] = a;
+    }
+    __syncthreads();
+    double run = 0.0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        run = run + tile[t * (kScanItems + 1) + j];
+        tile[t * (kScanItems + 1) + j] = run;
     }
     sh[t] = run;
     __syncthreads();
@@ -321,11 +330,12 @@ __global__ __launch_bounds__(kScanThreads) void k_fwd_scan_tiles(int64_t n, cons
         sh[kScanThreads] = e;
     }
     __syncthreads();
-    const double start = sh[t];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = base + k;
-        if (i < n) local[i] = start + loc[k];
+        const int p = k * kScanThreads + t;
+        const int64_t i = base + p;
+        const int owner = p / kScanItems;
+        if (i < n) local[i] = sh[owner] + tile[owner * (kScanItems + 1) + p % kScanItems];
     }
     if (t == 0) tsum[blockIdx.x] = sh[kScanThreads];
 }
