@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "alloc.hpp"
+#include "mlp.hpp"
 #include "mc_internal.hpp"
 
 using namespace mc;
@@ -1651,7 +1652,7 @@ mc_status mc_mlp_features(mc_expmv_t h, const void *v, float *feats) {
     HIP_TRY(hipSetDevice(h->dev));
     double *raw = nullptr, *stats = nullptr;
     HIP_TRY(dalloc(&raw, 4 * h->n));
-    hipError_t e = dalloc(&stats, 8);
+    hipError_t e = dalloc(&stats, kFeatStatsDoubles);
     if (e == hipSuccess)
         e = launch_features(h->n, h->rowptr, h->col, h->val, h->plain.rows, h->plain.r, v,
                             h->opts.weight_prec == MC_FP32, raw, stats, feats, h->stream);

@@ -24,6 +24,7 @@
 // is the backward product's B operand without moving between lanes; only dW2
 // goes through LDS.
 #include "walk_task.hpp"
+#include "mlp.hpp"
 
 namespace mc {
 namespace {
@@ -64,25 +65,39 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ---------------------------------------------------------------- features
+// The row of every CSR position, 16 lanes per row (a hub's row is long).
 __global__ void k_rowof(int64_t n, const int64_t *__restrict__ rowptr, int32_t *__restrict__ rowof) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     if (i >= n) return;
-    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) rowof[p] = (int32_t)i;
+    for (int64_t p = rowptr[i] + (threadIdx.x & 15); p < rowptr[i + 1]; p += 16) rowof[p] = (int32_t)i;
 }
 
 // raw features [log1p deg, r, v, log1p(mean target degree)] in FP64
-__global__ void k_feat_raw(int64_t n, const int64_t *__restrict__ rowptr,
-                           const int32_t *__restrict__ col, const double *__restrict__ val,
-                           const RowRec *__restrict__ rows, const double *__restrict__ r,
-                           const void *v, int v_fp32, double *__restrict__ raw) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t deg = rows[i].deg;
-    double nsum = 0.0;
-    for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-        const int32_t j = col[p];
-        if (j != i && val[p] > 0.0) nsum += (double)rows[j].deg;
+// One row of 16 lanes per node: lanes stride the row's entries, then the row's
+// fixed DPP tree, so a hub's many neighbours are summed by 16 lanes instead of one
+// thread (whose serial loop set the time of the whole launch on power-law graphs).
+__global__ __launch_bounds__(256) void k_feat_raw(int64_t n, const int64_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col,
+                                                  const double *__restrict__ val,
+                                                  const RowRec *__restrict__ rows,
+                                                  const double *__restrict__ r, const void *v,
+                                                  int v_fp32, double *__restrict__ raw) {
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int rl = threadIdx.x & 15;
+    const bool in = i < n;                   // whole rows share `in`; all lanes stay for the tree
+    // neighbour degrees are integers: their sum is exact in any order
+    uint64_t dsum = 0;
+    if (in) {
+        const int64_t p1 = rowptr[i + 1];
+#pragma unroll 4
+        for (int64_t p = rowptr[i] + rl; p < p1; p += 16) {
+            const int32_t j = col[p];
+            if (j != i && val[p] > 0.0) dsum += rows[j].deg;
+        }
     }
+    const double nsum = row_sum_f64((double)dsum);
+    if (!in || rl != 0) return;
+    const uint32_t deg = rows[i].deg;
     const double vi = v_fp32 ? (double)static_cast<const float *>(v)[i]
                              : static_cast<const double *>(v)[i];
     raw[4 * i + 0] = log1p((double)deg);
@@ -91,43 +106,58 @@ __global__ void k_feat_raw(int64_t n, const int64_t *__restrict__ rowptr,
     raw[4 * i + 3] = log1p(deg ? nsum / (double)deg : 0.0);
 }
 
-// Column means and population standard deviations (two passes, one block,
-// fixed-order tree reductions).
-__global__ __launch_bounds__(1024) void k_feat_stats(int64_t n, const double *__restrict__ raw,
-                                                     double *__restrict__ stats) {
-    __shared__ double sh[1024][4];
-    __shared__ double mean[4];
+// Column means and population standard deviations, two passes, each over many
+// blocks: thread t of block b adds rows b*256 + t, + grid*256, ... in order, the
+// block's fixed tree gives its partial, and one block adds the partials in block
+// order (deterministic; one block alone read the 32 MB of a 1e6-node graph twice at
+// a single CU's bandwidth).
+__global__ __launch_bounds__(256) void k_feat_colsum(int64_t n, const double *__restrict__ raw,
+                                                     const double *__restrict__ stats,
+                                                     double *__restrict__ part) {
+    __shared__ double sh[256][4];
     const int tid = threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = tid; i < n; i += 1024)
-        for (int c = 0; c < 4; ++c) acc[c] += raw[4 * i + c];
-    for (int c = 0; c < 4; ++c) sh[tid][c] = acc[c];
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (tid < w)
-            for (int c = 0; c < 4; ++c) sh[tid][c] += sh[tid + w][c];
-        __syncthreads();
-    }
-    if (tid < 4) mean[tid] = sh[0][tid] / (double)n;
-    __syncthreads();
-    for (int c = 0; c < 4; ++c) acc[c] = 0.0;
-    for (int64_t i = tid; i < n; i += 1024)
+    for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256)
         for (int c = 0; c < 4; ++c) {
-            const double d = raw[4 * i + c] - mean[c];
-            acc[c] += d * d;
+            const double x = raw[4 * i + c];
+            if (stats) {
+                const double d = x - stats[c];
+                acc[c] += d * d;
+            } else {
+                acc[c] += x;
+            }
         }
-    __syncthreads();
     for (int c = 0; c < 4; ++c) sh[tid][c] = acc[c];
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
+    for (int w = 128; w > 0; w >>= 1) {
         if (tid < w)
             for (int c = 0; c < 4; ++c) sh[tid][c] += sh[tid + w][c];
         __syncthreads();
     }
-    if (tid < 4) {
-        const double sd = sqrt(sh[0][tid] / (double)n);
-        stats[tid] = mean[tid];
-        stats[4 + tid] = sd > 0.0 ? sd : 1.0;
+    if (tid < 4) part[4 * blockIdx.x + tid] = sh[0][tid];
+}
+
+// sd == false: stats[c] = mean; true: stats[4 + c] = population sd (1 if 0).  One
+// block of kStatBlocks threads: thread b takes block b's partials, then a fixed tree.
+__global__ __launch_bounds__(kStatBlocks) void k_feat_colfin(int64_t n, const double *__restrict__ part,
+                                                            double *__restrict__ stats, int sd) {
+    __shared__ double sh[kStatBlocks][4];
+    const int b = threadIdx.x;
+    for (int c = 0; c < 4; ++c) sh[b][c] = part[4 * b + c];
+    __syncthreads();
+    for (int w = kStatBlocks / 2; w > 0; w >>= 1) {
+        if (b < w)
+            for (int c = 0; c < 4; ++c) sh[b][c] += sh[b + w][c];
+        __syncthreads();
+    }
+    if (b < 4) {
+        const double s = sh[0][b];
+        if (!sd) {
+            stats[b] = s / (double)n;
+        } else {
+            const double v = sqrt(s / (double)n);
+            stats[4 + b] = v > 0.0 ? v : 1.0;
+        }
     }
 }
 
@@ -461,7 +491,9 @@ int mlp_grad_stride() { return GSTRIDE; }
 
 hipError_t launch_rowof(int64_t n, const int64_t *rowptr, int32_t *rowof, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rowof, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, rowptr, rowof);
+    const int64_t g = (16 * n + 255) / 256;
+    if (g > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rowof, dim3((unsigned)g), dim3(256), 0, s, n, rowptr, rowof);
     return hipGetLastError();
 }
 
@@ -469,10 +501,17 @@ hipError_t launch_features(int64_t n, const int64_t *rowptr, const int32_t *col,
                            const RowRec *rows, const double *r, const void *v, int v_fp32,
                            double *raw, double *stats, float *feats, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    const unsigned g = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_feat_raw, dim3(g), dim3(256), 0, s, n, rowptr, col, val, rows, r, v, v_fp32,
-                       raw);
-    hipLaunchKernelGGL(k_feat_stats, dim3(1), dim3(1024), 0, s, n, raw, stats);
+    const int64_t g = (16 * n + 255) / 256;
+    if (g > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_feat_raw, dim3((unsigned)g), dim3(256), 0, s, n, rowptr, col, val, rows, r, v,
+                       v_fp32, raw);
+    // partials after the 8 statistics words
+    double *part = stats + 8;
+    hipLaunchKernelGGL(k_feat_colsum, dim3(kStatBlocks), dim3(256), 0, s, n, raw,
+                       (const double *)nullptr, part);
+    hipLaunchKernelGGL(k_feat_colfin, dim3(1), dim3(kStatBlocks), 0, s, n, part, stats, 0);
+    hipLaunchKernelGGL(k_feat_colsum, dim3(kStatBlocks), dim3(256), 0, s, n, raw, stats, part);
+    hipLaunchKernelGGL(k_feat_colfin, dim3(1), dim3(kStatBlocks), 0, s, n, part, stats, 1);
     hipLaunchKernelGGL(k_feat_norm, dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, s, n, raw,
                        stats, feats);
     return hipGetLastError();
