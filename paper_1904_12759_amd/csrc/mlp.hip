@@ -236,6 +236,14 @@ __global__ __launch_bounds__(256, TRAIN ? 1 : 2) void k_net(NetArgs a) {
                     w2t[mt][kb][j] = (short)a.wbf[OFF_W2 + kfeat(kb, q, j) * H + 16 * mt + e];
     }
 
+    // layer-1 weights as 16x16x4 A operands: lane (e, q) holds W1[16 ks + e][q] and
+    // W1[16 ks + e][4 + q]
+    float w1a[4], w1b[4];
+    for (int ks = 0; ks < 4; ++ks) {
+        w1a[ks] = s_w1[(16 * ks + e) * NIN + q];
+        w1b[ks] = s_w1[(16 * ks + e) * NIN + 4 + q];
+    }
+
     v4f gw2[4][4];
     float gw3[16], gb2[16], gw1[NIN], gb1 = 0.0f, gb3 = 0.0f, lsum = 0.0f, psum = 0.0f;
     if constexpr (TRAIN) {
@@ -258,24 +266,25 @@ __global__ __launch_bounds__(256, TRAIN ? 1 : 2) void k_net(NetArgs a) {
             dst = a.col[pos];
             valid = dst != src && a.val[pos] > 0.0;
         }
-        float x[NIN];
-        for (int c = 0; c < 4; ++c) {
-            x[c] = valid ? a.feats[4 * (int64_t)src + c] : 0.0f;
-            x[4 + c] = valid ? a.feats[4 * (int64_t)dst + c] : 0.0f;
-        }
-        // layer 1 (VALU): features f = 16 ks + 4 q + i
+        // the edge's inputs: lane q holds x[q] (source feature q) and x[4 + q]
+        // (destination feature q), the B operands of layer 1's two K-steps
+        const float xs = valid ? a.feats[4 * (int64_t)src + q] : 0.0f;
+        const float xd = valid ? a.feats[4 * (int64_t)dst + q] : 0.0f;
+        // layer 1 (MFMA, FP32 16x16x4, the bias as accumulator): z1[16 ks + 4 q + i]
         uint32_t m1 = 0;
         v8s a1b[2];                  // a1b[kb][j]: feature kfeat(kb, q, j)
-        for (int ks = 0; ks < 4; ++ks)
+        for (int ks = 0; ks < 4; ++ks) {
+            v4f z = {s_b1[16 * ks + 4 * q], s_b1[16 * ks + 4 * q + 1], s_b1[16 * ks + 4 * q + 2],
+                     s_b1[16 * ks + 4 * q + 3]};
+            z = __builtin_amdgcn_mfma_f32_16x16x4f32(w1a[ks], xs, z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_16x16x4f32(w1b[ks], xd, z, 0, 0, 0);
             for (int i = 0; i < 4; ++i) {
-                const int f = 16 * ks + 4 * q + i;
-                float z = s_b1[f];
-                for (int c = 0; c < NIN; ++c) z += s_w1[f * NIN + c] * x[c];
-                const float av = z > 0.0f ? z : 0.0f;
-                if (z > 0.0f) m1 |= 1u << (4 * ks + i);
+                const float av = z[i] > 0.0f ? z[i] : 0.0f;
+                if (z[i] > 0.0f) m1 |= 1u << (4 * ks + i);
                 const uint16_t hb = f2bf(av);
                 a1b[ks >> 1][4 * (ks & 1) + i] = (short)hb;
             }
+        }
         // layer 2 (MFMA): z2[16 mt + 4 q + i] for edge e
         float a2[16];
         uint32_t m2 = 0;
@@ -336,8 +345,8 @@ __global__ __launch_bounds__(256, TRAIN ? 1 : 2) void k_net(NetArgs a) {
                     s_dz1[wv][16 * mt + 4 * q + i][e] = (m1 >> k) & 1u ? acc[i] : 0.0f;
                 }
             }
-            if (q == 0)
-                for (int c = 0; c < NIN; ++c) s_x[wv][c][e] = x[c];
+            s_x[wv][q][e] = xs;
+            s_x[wv][4 + q][e] = xd;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
