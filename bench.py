@@ -949,9 +949,10 @@ def bench_stencil(mc, seed, steps=5):
     z = ((e1 - e2)[pos] / torch.sqrt(d2[pos])).cpu().numpy()
     res["workload"] = "grid3d 256^3 (the headline workload), full vector, 256 walkers/node, FP32"
     res["speedup"] = res["table"]["kernel_ms"] / res["stencil"]["kernel_ms"]
-    # device bytes of the operator: faces 24 B, row record 16 B and d in both precisions
-    # 12 B per node; the tables add r (8 B per node) and a 16 B slot per CSR position
-    res["operator_bytes_stencil"] = (24 + 16 + 12) * w.a.n
+    # device bytes of the operator: a 32 B state record and d in both precisions (12 B)
+    # per node; the tables hold a 16 B row record, d, r (8 B) per node and a 16 B slot
+    # per CSR position
+    res["operator_bytes_stencil"] = (32 + 12) * w.a.n
     res["operator_bytes_table"] = (16 + 12 + 8) * w.a.n + 16 * w.a.nnz
     res["rms_z_table_vs_stencil"] = float(np.sqrt(np.mean(z * z)))
     res["frac_abs_z_above_4"] = float(np.mean(np.abs(z) > 4))

@@ -203,10 +203,14 @@ mc_status mc_expmv_create(mc_expmv_t *out, int64_t n, int64_t nnz, const int64_t
  * conditioning or the lattice (MC_ERR_INVALID_ARG).  Errors: MC_ERR_INVALID_ARG
  * (sizes, a positive rate on a last plane, a node whose 1/r_x overflows, options),
  * MC_ERR_NONFINITE, MC_ERR_NOT_METZLER (a negative rate).  The arrays are copied;
- * synchronous.  Device memory per node: the three face rates (24 B), the state
- * record (1/r_x and the exit count, 16 B) and d_x in both precisions (12 B), 52 B
- * (0.87 GB for 256^3); the CSR form holds the same records, r_x (8 B) and a 16 B
- * alias slot per stored entry (2.5 GB for 256^3).
+ * synchronous.  At create each node's 32-byte state record is built from its faces:
+ * 1/r_x, which faces carry a rate, and the rule's thresholds on o2 (for each face
+ * with a rate but the last, the largest o2 whose u r_x stays below the running sum
+ * up to it), so the walk picks the face by integer comparisons with the same result
+ * as the rule.  Device memory per node: that record and d_x in both precisions,
+ * 44 B (0.74 GB for 256^3; the faces and a_xx, 32 B per node more, only during
+ * create); the CSR form holds 16 B row records, d_x, r_x and a 16 B alias slot per
+ * stored entry (2.5 GB for 256^3).
  */
 mc_status mc_expmv_create_stencil7(mc_expmv_t *out, int64_t nx, int64_t ny, int64_t nz,
                                    const double *fx, const double *fy, const double *fz,
@@ -373,6 +377,20 @@ mc_status mc_expmv_trace(mc_expmv_t h, const void *v, int64_t start, int64_t w0,
 mc_status mc_expmv_get_tables(mc_expmv_t h, int32_t use_proposal, double *r, double *d,
                               double *inv_r, int64_t *deg, int64_t *begin, int32_t *col,
                               uint32_t *thr, int32_t *alias);
+
+/*
+ * Copy a stencil handle's state records (mc_expmv_create_stencil7) to host memory:
+ *   d, inv_r  host double[n]: d_x and 1/r_x (0 for a node without exits)
+ *   faces     host uint32[n]: the number k of faces with a rate (bits 0..2) and those
+ *             faces in column order, 3 bits each from bit 3 (codes 0..5 for -z, -y,
+ *             -x, +x, +y, +z)
+ *   thr       host uint32[5 n]: per node, for the j-th face with a rate (j < k) the
+ *             largest o2 in [0, 2^32) with (o2 2^-32) r_x below the running sum of
+ *             the faces up to it, both products rounded in FP64; 2^32 - 1 from j = k on
+ * Any pointer may be NULL.  MC_ERR_INVALID_ARG for a CSR handle.  Synchronous.
+ */
+mc_status mc_expmv_get_stencil(mc_expmv_t h, double *d, double *inv_r, uint32_t *faces,
+                               uint32_t *thr);
 
 /* Sizes of a handle: n, number of jump slots, splitting steps N and dt = t/N. */
 mc_status mc_expmv_info(mc_expmv_t h, int64_t *n, int64_t *nslots, int64_t *ngrid, double *dt);

@@ -154,6 +154,7 @@ _SIGS = {
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p]),
     "mc_expmv_get_tables": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 8),
+    "mc_expmv_get_stencil": (ctypes.c_int, [ctypes.c_void_p] * 5),
     "mc_expmv_info": (ctypes.c_int, [ctypes.c_void_p] * 5),
     "mc_expmv_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mc_expmv_destroy": (None, [ctypes.c_void_p]),
@@ -594,6 +595,18 @@ class MCExpmv:
             "r", "d", "inv_r", "deg", "begin", "col", "thr", "alias")]), "mc_expmv_get_tables")
         for k in ("col", "thr", "alias"):
             out[k] = out[k][:ns]
+        return out
+
+    def stencil_records(self) -> dict:
+        """A stencil handle's state records (host copies): d, inv_r, the face word
+        and the five jump thresholds per node (shape (n, 5))."""
+        import numpy as np
+        n = self.n
+        out = dict(d=np.zeros(n), inv_r=np.zeros(n), faces=np.zeros(n, np.uint32),
+                   thr=np.zeros((n, 5), np.uint32))
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(load().mc_expmv_get_stencil(self._h, *[p(out[k]) for k in (
+            "d", "inv_r", "faces", "thr")]), "mc_expmv_get_stencil")
         return out
 
 

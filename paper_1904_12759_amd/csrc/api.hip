@@ -77,9 +77,9 @@ struct mc_expmv_s {
     double *tgt_se = nullptr;            // pilot standard errors of entries_to_target
     int64_t tgt_se_cap = 0;
     double *scratch = nullptr;           // this device's copy of `scratch` (noalloc entries)
-    // matrix-free 7-point stencil (mc_expmv_create_stencil7): face rates and a_xx
+    // matrix-free 7-point stencil (mc_expmv_create_stencil7): state records (d in plain)
     bool stencil = false;
-    double *sfx = nullptr, *sfy = nullptr, *sfz = nullptr, *sdiag = nullptr;
+    StencilRec *srec = nullptr;
     uint32_t snx = 0, snxy = 0;
 };
 
@@ -306,9 +306,7 @@ void fill_inst(const mc_expmv_s *h, const void *v, bool prop, InstArgs &P) {
     P.cond_max_rt = h->opts.cond_max_rt;
     P.resort = rl ? h->opts.resort_period : 0u;
     P.qmc = h->opts.qmc_first ? 1u : 0u;
-    P.fx = h->stencil ? h->sfx : nullptr;
-    P.fy = h->sfy;
-    P.fz = h->sfz;
+    P.srec = h->stencil ? h->srec : nullptr;
     P.nx = h->snx;
     P.nxy = h->snxy;
 }
@@ -448,10 +446,7 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->fwd_part);
     (void)hipFree(h->fwd_acc);
     (void)hipFree(h->var_dev);
-    (void)hipFree(h->sfx);
-    (void)hipFree(h->sfy);
-    (void)hipFree(h->sfz);
-    (void)hipFree(h->sdiag);
+    (void)hipFree(h->srec);
     if (h->var_host) (void)hipHostFree(h->var_host);
     if (h->var_ev) (void)hipEventDestroy(h->var_ev);
     (void)hipFree(h->tgt_se);
@@ -628,36 +623,38 @@ mc_status mc_expmv_create_stencil7(mc_expmv_t *out, int64_t nx, int64_t ny, int6
     CREATE_TRY(dalloc(&h->flags, 1));
     CREATE_TRY(host_malloc((void **)&h->flag_host, sizeof(uint32_t)));
     CREATE_TRY(dalloc(&h->counters, 2 * (int64_t)kMaxWalkGrid));
-    CREATE_TRY(dalloc(&h->sfx, n));
-    CREATE_TRY(dalloc(&h->sfy, n));
-    CREATE_TRY(dalloc(&h->sfz, n));
-    CREATE_TRY(dalloc(&h->sdiag, n));
-    CREATE_TRY(dalloc(&h->plain.rows, n));
+    CREATE_TRY(dalloc(&h->srec, n));
     CREATE_TRY(dalloc(&h->plain.d64, n));
     CREATE_TRY(dalloc(&h->plain.d32, n));
+    // the faces and a_xx are needed only to build the state records and d
+    double *faces = nullptr;
+    CREATE_TRY(dalloc(&faces, 4 * n));
     const size_t bytes = sizeof(double) * (size_t)n;
-    CREATE_TRY(hipMemcpyAsync(h->sfx, fx, bytes, hipMemcpyDefault, h->stream));
-    CREATE_TRY(hipMemcpyAsync(h->sfy, fy, bytes, hipMemcpyDefault, h->stream));
-    CREATE_TRY(hipMemcpyAsync(h->sfz, fz, bytes, hipMemcpyDefault, h->stream));
-    CREATE_TRY(hipMemcpyAsync(h->sdiag, diag, bytes, hipMemcpyDefault, h->stream));
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(faces, fx, bytes, hipMemcpyDefault, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(faces + n, fy, bytes, hipMemcpyDefault, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(faces + 2 * n, fz, bytes, hipMemcpyDefault, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(faces + 3 * n, diag, bytes, hipMemcpyDefault, h->stream);
     // counters[0] doubles as the slot count of the check (cleared by a fill kernel later)
-    CREATE_TRY(hipMemsetAsync(h->flags, 0, sizeof(uint32_t), h->stream));
-    CREATE_TRY(hipMemsetAsync(h->counters, 0, sizeof(unsigned long long), h->stream));
-    CREATE_TRY(launch_stencil_rows(n, nx, ny, h->sfx, h->sfy, h->sfz, h->sdiag, h->plain.rows,
-                                   h->plain.d64, h->plain.d32, h->flags, h->counters, h->stream));
+    if (e == hipSuccess) e = hipMemsetAsync(h->flags, 0, sizeof(uint32_t), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->counters, 0, sizeof(unsigned long long), h->stream);
+    if (e == hipSuccess)
+        e = launch_stencil_rows(n, nx, ny, faces, faces + n, faces + 2 * n, faces + 3 * n, h->srec,
+                                h->plain.d64, h->plain.d32, h->flags, h->counters, h->stream);
     uint32_t f = 0;
     unsigned long long slots = 0;
-    CREATE_TRY(hipMemcpyAsync(&f, h->flags, sizeof(f), hipMemcpyDeviceToHost, h->stream));
-    CREATE_TRY(hipMemcpyAsync(&slots, h->counters, sizeof(slots), hipMemcpyDeviceToHost, h->stream));
-    CREATE_TRY(hipStreamSynchronize(h->stream));
+    if (e == hipSuccess) e = hipMemcpyAsync(&f, h->flags, sizeof(f), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&slots, h->counters, sizeof(slots), hipMemcpyDeviceToHost, h->stream);
+    const hipError_t es = hipStreamSynchronize(h->stream);   // also before freeing on failure
+    if (e == hipSuccess) e = es;
+    (void)hipFree(faces);
+    CREATE_TRY(e);
 #undef CREATE_TRY
     if (f) {
         mc_expmv_destroy(h);
         return flags_to_status(f);
     }
-    // the walk reads the state records and the faces; a_xx lives on in d
-    (void)hipFree(h->sdiag);
-    h->sdiag = nullptr;
     h->nslots = (int64_t)slots;
     *out = h;
     return MC_OK;
@@ -1024,13 +1021,35 @@ mc_status mc_expmv_stats(mc_expmv_t h, mc_expmv_run_stats *out) {
     const double row = 16.0 + dbytes;
     const double slot = 12.0 + (h->last_prop ? 8.0 : 0.0);
     out->alg_bytes = row * (double)(c[0]) + slot * (double)c[1] + dbytes * (double)h->last_walkers;
-    if (h->stencil)   // the same state records; six FP64 face rates instead of a slot per jump
-        out->alg_bytes = row * (double)(c[0]) + 48.0 * (double)c[1] + dbytes * (double)h->last_walkers;
+    if (h->stencil)   // a 32-byte state record and d per visited state, nothing per jump
+        out->alg_bytes = (32.0 + dbytes) * (double)(c[0]) + dbytes * (double)h->last_walkers;
     if (h->last_fwd) {
         // forward walks: per walker also the binary search over the cumulative
         // sums (8 B per step) and two FP64 read-modify-writes at the end node
         const double steps = h->n > 1 ? ceil(log2((double)h->n)) : 0.0;
         out->alg_bytes += (8.0 * steps + 32.0) * (double)h->last_walkers;
+    }
+    return MC_OK;
+}
+
+mc_status mc_expmv_get_stencil(mc_expmv_t h, double *d, double *inv_r, uint32_t *faces,
+                               uint32_t *thr) {
+    if (!h || !h->stencil) return MC_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(h->dev));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const size_t n = (size_t)h->n;
+    std::vector<StencilRec> rec(n);
+    std::vector<double> dd(n);
+    if (n > 0) {
+        HIP_TRY(hipMemcpy(rec.data(), h->srec, sizeof(StencilRec) * n, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(dd.data(), h->plain.d64, sizeof(double) * n, hipMemcpyDeviceToHost));
+    }
+    for (size_t i = 0; i < n; ++i) {
+        if (d) d[i] = dd[i];
+        if (inv_r) inv_r[i] = rec[i].inv_r;
+        if (faces) faces[i] = rec[i].meta;
+        if (thr)
+            for (int j = 0; j < 5; ++j) thr[5 * i + (size_t)j] = rec[i].e[j];
     }
     return MC_OK;
 }

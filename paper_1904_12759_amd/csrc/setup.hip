@@ -231,17 +231,32 @@ hipError_t launch_relabel_apply(int64_t n, const int64_t *rowptr, const uint32_t
     return hipGetLastError();
 }
 
+// Largest o in [0, 2^32) with (o 2^-32) r < c, for c > 0 (o = 0 always
+// qualifies): the product rounds monotonically in o, so the o that keep u r below
+// c form a prefix and bisection finds its end.  Both multiplications are the ones
+// the inverse-CDF rule makes (the first is exact).
+__device__ uint32_t cdf_threshold(double c, double r) {
+    uint64_t lo = 0, hi = 1ull << 32;    // (lo 2^-32) r < c; hi == 2^32 or fails
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (((double)mid * 0x1p-32) * r < c) lo = mid;
+        else hi = mid;
+    }
+    return (uint32_t)lo;
+}
+
 // One thread per node of the 7-point stencil: its three face rates checked
 // (finite, >= 0, and 0 on the last plane of their axis, where no neighbour
 // exists) and a_xx finite; two slots counted per positive face (an exit in each
-// direction); and its state record as the row split makes it for the same
-// matrix in CSR form: r summed over the six faces in column order (-z, -y, -x,
-// +x, +y, +z), 1/r when the node has an exit, its number of exits, and
+// direction); and its state record: r summed over the six faces in column order
+// (-z, -y, -x, +x, +y, +z) as the row split sums the same matrix in CSR form, 1/r
+// when the node has an exit, the faces with a rate, the jump thresholds of the
+// inverse-CDF rule over the running sums (all but the last such face), and
 // d = a_xx + r.  The faces toward lower indices are the neighbours' own, which
 // their threads check.
 __global__ void k_stencil_rows(int64_t n, int64_t nx, int64_t ny, const double *__restrict__ fx,
                                const double *__restrict__ fy, const double *__restrict__ fz,
-                               const double *__restrict__ diag, RowRec *__restrict__ rows,
+                               const double *__restrict__ diag, StencilRec *__restrict__ srec,
                                double *__restrict__ d64, float *__restrict__ d32, uint32_t *flags,
                                unsigned long long *nslots) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -267,28 +282,41 @@ __global__ void k_stencil_rows(int64_t n, int64_t nx, int64_t ny, const double *
         r = r + f[k];
         deg += f[k] > 0.0 ? 1u : 0u;
     }
-    double inv_r = 0.0;
-    if (deg > 0) {
-        inv_r = 1.0 / r;
-        if (!isfinite(inv_r)) bad |= F_INVALID_ARG;
+    StencilRec rec;
+    rec.inv_r = 0.0;
+    rec.meta = deg;
+    for (int j = 0; j < 5; ++j) rec.e[j] = 0xFFFFFFFFu;
+    if (deg > 0 && !bad) {
+        rec.inv_r = 1.0 / r;
+        if (!isfinite(rec.inv_r)) bad |= F_INVALID_ARG;
+        double cum = 0.0;
+        uint32_t j = 0;
+        for (int k = 0; k < 6; ++k) {
+            cum = cum + f[k];
+            if (f[k] > 0.0) {
+                rec.meta |= (uint32_t)k << (3 + 3 * j);
+                if (j + 1 < deg) rec.e[j] = cdf_threshold(cum, r);
+                ++j;
+            }
+        }
     }
     const double d = diag[i] + r;
     if (!isfinite(d)) bad |= F_NONFINITE;
     if (bad) atomicOr(flags, bad);
     if (cnt) atomicAdd(nslots, cnt);
-    rows[i] = RowRec{inv_r, deg, 0u};
+    srec[i] = rec;
     d64[i] = d;
     d32[i] = (float)d;
 }
 
 hipError_t launch_stencil_rows(int64_t n, int64_t nx, int64_t ny, const double *fx, const double *fy,
-                               const double *fz, const double *diag, RowRec *rows, double *d64,
+                               const double *fz, const double *diag, StencilRec *srec, double *d64,
                                float *d32, uint32_t *flags, unsigned long long *nslots,
                                hipStream_t s) {
     if (n == 0) return hipSuccess;
     const int64_t grid = (n + 255) / 256;
     hipLaunchKernelGGL(k_stencil_rows, dim3((unsigned)grid), dim3(256), 0, s, n, nx, ny, fx, fy, fz,
-                       diag, rows, d64, d32, flags, nslots);
+                       diag, srec, d64, d32, flags, nslots);
     return hipGetLastError();
 }
 

@@ -238,43 +238,41 @@ __device__ __forceinline__ bool jump_fat(const InstArgs &P, uint32_t js, uint32_
     return keep;
 }
 
-// Matrix-free 7-point stencil: the six face rates of node x in the column order of
-// its matrix row (-z, -y, -x, +x, +y, +z; 0 where the grid ends: fx of the last
-// x-plane is 0, so fx[x - 1] is 0 on the first, and likewise for y; z needs the
-// bound), and the neighbour behind face k.
-__device__ __forceinline__ void stencil_faces(const InstArgs &P, uint32_t x, double f[6]) {
-    f[0] = x >= P.nxy ? P.fz[x - P.nxy] : 0.0;
-    f[1] = x >= P.nx ? P.fy[x - P.nx] : 0.0;
-    f[2] = x >= 1u ? P.fx[x - 1u] : 0.0;
-    f[3] = P.fx[x];
-    f[4] = P.fy[x];
-    f[5] = P.fz[x];
+// Matrix-free 7-point stencil.  The first half of x's state record read as a row
+// record (deg = the face word, non-zero iff x has an exit; begin = the first
+// threshold).
+__device__ __forceinline__ RowRec stencil_head(const InstArgs &P, uint32_t x) {
+    const uint4 h = reinterpret_cast<const uint4 *>(P.srec)[2 * (size_t)x];
+    RowRec r;
+    r.inv_r = __hiloint2double((int)h.y, (int)h.x);
+    r.deg = h.z;
+    r.begin = h.w;
+    return r;
 }
 
-__device__ __forceinline__ uint32_t stencil_neighbour(const InstArgs &P, uint32_t x, int k) {
-    return k == 0 ? x - P.nxy : k == 1 ? x - P.nx : k == 2 ? x - 1u : k == 3 ? x + 1u
-           : k == 4 ? x + P.nx : x + P.nxy;
-}
-
-// The jump from x: the first face (column order) whose running sum of rates exceeds
+// The jump from x by the inverse-CDF rule over its six faces in column order
+// (-z, -y, -x, +x, +y, +z): the first face whose running sum of rates exceeds
 // u r, u = o2 2^-32 in [0, 1), or the last face with a rate when rounding leaves
-// u r at or above the sum (the inverse-CDF rule; zero faces never cross).
-__device__ __forceinline__ uint32_t stencil_jump(const InstArgs &P, uint32_t x, uint32_t o2) {
-    double f[6];
-    stencil_faces(P, x, f);
-    double r = 0.0;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) r = r + f[i];
-    const double target = ((double)o2 * 0x1p-32) * r;
-    double cum = 0.0;
-    int sl = -1, last = 0;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        cum = cum + f[i];
-        if (f[i] > 0.0) last = i;
-        if (sl < 0 && target < cum) sl = i;
-    }
-    return stencil_neighbour(P, x, sl < 0 ? last : sl);
+// u r at or above the sum.  The record's thresholds turn that into a count of
+// integer comparisons; meta and e0 are the head's face word and first threshold,
+// the other four come from the record's second half.  The neighbour comes from
+// the index.
+__device__ __forceinline__ uint32_t stencil_jump(const InstArgs &P, uint32_t x, uint32_t meta,
+                                                 uint32_t e0, uint32_t o2) {
+    const uint4 e = reinterpret_cast<const uint4 *>(P.srec)[2 * (size_t)x + 1];
+    const uint32_t m = (o2 > e0 ? 1u : 0u) + (o2 > e.x ? 1u : 0u) + (o2 > e.y ? 1u : 0u) +
+                       (o2 > e.z ? 1u : 0u) + (o2 > e.w ? 1u : 0u);
+    const uint32_t face = (meta >> (3u + 3u * m)) & 7u;
+    const uint32_t axis = face < 3u ? 2u - face : face - 3u;     // 0: x, 1: y, 2: z
+    const uint32_t step = axis == 0u ? 1u : axis == 1u ? P.nx : P.nxy;
+    return face < 3u ? x - step : x + step;
+}
+
+// A walker's state record: the stencil's head, else the row table's.
+template <bool LOC, bool STENCIL>
+__device__ __forceinline__ RowRec state_at(const InstArgs &P, uint32_t x) {
+    if constexpr (STENCIL) return stencil_head(P, x);
+    else return row_at<LOC>(P, x);
 }
 
 // Walk id of an original node, and back (identity without relabelling).
@@ -605,7 +603,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             const uint32_t x0 = walk_id<LOC>(P, node);
             RowRec r0;
             WT d0;
-            r0 = row_at<LOC>(P, x0);
+            r0 = state_at<LOC, STENCIL>(P, x0);
             d0 = d_at<FP32, LOC>(P, x0);
             const WT v0 = load_v<FP32>(P.v, node);
             K = (double)(wexp<FP32>(final_term<MODE, FP32>(d0, 0.0, 0, P)) * v0);
@@ -762,7 +760,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         uint32_t deg = 0, begin = 0;
         WT dx = (WT)0;
         if (active) {
-            const RowRec rr = row_at<LOC>(P, x);
+            const RowRec rr = state_at<LOC, STENCIL>(P, x);
             inv_r = rr.inv_r;
             deg = rr.deg;
             begin = rr.begin;
@@ -849,10 +847,11 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                         // FAT: 0 separate tables, 1 64-byte slots, 2 whichever P holds
                         bool keep = true;
                         if constexpr (STENCIL) {
-                            x = stencil_jump(P, x, o.z);
-                            const RowRec rr = row_at<false>(P, x);
+                            x = stencil_jump(P, x, deg, begin, o.z);
+                            const RowRec rr = stencil_head(P, x);
                             inv_r = rr.inv_r;
                             deg = rr.deg;
+                            begin = rr.begin;
                             dx = d_at<FP32, false>(P, x);
                         } else if constexpr (FAT == 1)
                             keep = jump_fat<FP32>(P, js, o.w, x, inv_r, deg, begin, dx);
@@ -909,7 +908,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     ev = 0;
                     ju = 0;
                     ka = 0;
-                    const RowRec rr = row_at<LOC>(P, x);
+                    const RowRec rr = state_at<LOC, STENCIL>(P, x);
                     inv_r = rr.inv_r;
                     deg = rr.deg;
                     begin = rr.begin;

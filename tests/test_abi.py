@@ -85,3 +85,4 @@ def test_null_handle_calls_are_rejected():
     assert lib.mc_expmv_entries_multi(None, None, None, 1, None, None, None) == 1
     assert lib.mc_expmv_entries_to_target(None, None, None, 1, 100, 1e-3, 1.2, 2, 1000,
                                           None, None, None) == 1
+    assert lib.mc_expmv_get_stencil(None, None, None, None, None) == 1

@@ -134,6 +134,7 @@ def test_stencil_create_fails_cleanly_at_every_allocation(fault):
         break
     else:
         pytest.fail("create_stencil7 never succeeded")
-    assert seen >= 8
+    # flags, host flag, counters, state records, d64, d32, the face staging
+    assert seen >= 7
     e1, s1 = h.entries(v, idx, 3000)
     assert torch.equal(e0, e1) and torch.equal(s0, s1)

@@ -157,3 +157,87 @@ def test_stencil_full_size_sampled_parity():
     o = Oracle(w.a.rowptr, w.a.col, w.a.val, w.t, 12759, cdf_jump=True)
     eo, _ = o.estimate(_v_for(w.v, True), sample, w.nwalk, threads=8)
     assert _close(est[sample], eo, 1e-5)
+
+
+def _odd_box(nx=6, ny=5, nz=4, seed=7):
+    """A 7-point operator with the cases the jump thresholds must get right:
+    interior faces of rate 0 (skipped by the rule), faces too small to change the
+    running sum they join (never chosen: the threshold before them is 2^32 - 1),
+    rates spread over twelve decades, and a node cut off on all six sides (no exit)."""
+    rng = np.random.default_rng(seed)
+    n = nx * ny * nz
+    xs, ys, zs = np.arange(n) % nx, (np.arange(n) // nx) % ny, np.arange(n) // (nx * ny)
+    fx = np.exp(rng.uniform(np.log(1e-6), np.log(1e6), n)) * (xs < nx - 1)
+    fy = np.exp(rng.uniform(np.log(1e-6), np.log(1e6), n)) * (ys < ny - 1)
+    fz = np.exp(rng.uniform(np.log(1e-6), np.log(1e6), n)) * (zs < nz - 1)
+    for f in (fx, fy, fz):
+        f[rng.random(n) < 0.2] = 0.0
+    absorbed = rng.choice(n, n // 6, replace=False)
+    fz[absorbed] = np.where(zs[absorbed] < nz - 1, 1e-22, 0.0)    # below half an ulp of the rest
+    iso = 1 + nx + nx * ny + 2                                       # an interior node, cut off
+    fx[iso] = fy[iso] = fz[iso] = 0.0
+    fx[iso - 1] = fy[iso - nx] = fz[iso - nx * ny] = 0.0
+    diag = -(fx + fy + fz) - rng.uniform(0.0, 1.0, n)
+    dense = np.diag(diag)
+    for f, off in ((fx, 1), (fy, nx), (fz, nx * ny)):
+        i = np.nonzero(f > 0)[0]
+        dense[i, i + off] = f[i]
+        dense[i + off, i] = f[i]
+    return fx, fy, fz, diag, dense, iso
+
+
+def test_stencil_records_follow_the_inverse_cdf_rule():
+    """Every node's state record against the rule's definition in FP64 (numpy's
+    IEEE products): 1/r, the faces with a rate in column order, and each threshold
+    the largest o2 whose (o2 2^-32) r stays below the running sum (checked at o2
+    and o2 + 1); then per-walker paths identical to the oracle's inverse-CDF walk
+    on the same matrix in CSR form, from the cut-off node and from neighbours of
+    zero and absorbed faces."""
+    nx, ny, nz = 6, 5, 4
+    fx, fy, fz, diag, dense, iso = _odd_box(nx, ny, nz)
+    n = nx * ny * nz
+    t = 2e-6                              # r t up to about 10 on the fastest nodes
+    g = mc.MCExpmv.stencil7(nx, ny, nz, fx, fy, fz, diag, t, 5)
+    rec = g.stencil_records()
+    top = np.uint32(0xFFFFFFFF)
+    seen_top = 0
+    for i in range(n):
+        f = [fz[i - nx * ny] if i >= nx * ny else 0.0, fy[i - nx] if i >= nx else 0.0,
+             fx[i - 1] if i >= 1 else 0.0, fx[i], fy[i], fz[i]]
+        r = np.float64(0.0)
+        for q in f:
+            r = r + np.float64(q)
+        pos = [k for k in range(6) if f[k] > 0.0]
+        k = len(pos)
+        word = k | sum(p << (3 + 3 * j) for j, p in enumerate(pos))
+        assert rec["faces"][i] == word, i
+        assert rec["inv_r"][i] == (np.float64(1.0) / r if k else 0.0), i
+        assert rec["d"][i] == np.float64(diag[i]) + r, i
+        cum = np.float64(0.0)
+        j = 0
+        for q in range(6):
+            cum = cum + np.float64(f[q])
+            if f[q] > 0.0:
+                if j + 1 < k:
+                    e = rec["thr"][i, j]
+                    assert (np.float64(e) * 2.0 ** -32) * r < cum, (i, j)
+                    if e != top:
+                        assert not (np.float64(int(e) + 1) * 2.0 ** -32) * r < cum, (i, j)
+                    else:
+                        seen_top += 1
+                j += 1
+        assert (rec["thr"][i, max(k - 1, 0):] == top).all(), i
+    assert rec["faces"][iso] == 0 and rec["inv_r"][iso] == 0.0
+    assert seen_top > 0                   # absorbed faces were exercised
+    a = wl.from_dense(dense)
+    o = Oracle(a.rowptr, a.col, a.val, t, 5, cdf_jump=True)
+    v = np.random.default_rng(8).uniform(0.2, 1.0, n)
+    starts = [iso, iso + 1, 0, n - 1, 37, 61, 90]
+    for start in starts:
+        xg, evg, jug, fg = g.trace(v, start, 0, 4000)
+        xo, evo, juo, fo, _ = o.trace(v, start, 0, 4000)
+        assert np.array_equal(xg, xo) and np.array_equal(evg, evo) and np.array_equal(jug, juo), start
+        assert _close(fg, fo, 1e-12)
+    est, _ = g.full(v, 2000)
+    eo, _ = o.estimate(v, None, 2000, threads=8)
+    assert _close(est.cpu().numpy(), eo, 1e-12)
