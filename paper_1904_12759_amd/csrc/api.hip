@@ -77,9 +77,10 @@ struct mc_expmv_s {
     double *tgt_se = nullptr;            // pilot standard errors of entries_to_target
     int64_t tgt_se_cap = 0;
     double *scratch = nullptr;           // this device's copy of `scratch` (noalloc entries)
-    // matrix-free 7-point stencil (mc_expmv_create_stencil7): state records (d in plain)
+    // matrix-free 7-point stencil (mc_expmv_create_stencil7): the other half of the
+    // state (rows and d in plain)
     bool stencil = false;
-    StencilRec *srec = nullptr;
+    uint4 *stail = nullptr;
     uint32_t snx = 0, snxy = 0;
 };
 
@@ -306,7 +307,7 @@ void fill_inst(const mc_expmv_s *h, const void *v, bool prop, InstArgs &P) {
     P.cond_max_rt = h->opts.cond_max_rt;
     P.resort = rl ? h->opts.resort_period : 0u;
     P.qmc = h->opts.qmc_first ? 1u : 0u;
-    P.srec = h->stencil ? h->srec : nullptr;
+    P.stail = h->stencil ? h->stail : nullptr;
     P.nx = h->snx;
     P.nxy = h->snxy;
 }
@@ -446,7 +447,7 @@ void mc_expmv_destroy(mc_expmv_t h) {
     (void)hipFree(h->fwd_part);
     (void)hipFree(h->fwd_acc);
     (void)hipFree(h->var_dev);
-    (void)hipFree(h->srec);
+    (void)hipFree(h->stail);
     if (h->var_host) (void)hipHostFree(h->var_host);
     if (h->var_ev) (void)hipEventDestroy(h->var_ev);
     (void)hipFree(h->tgt_se);
@@ -623,7 +624,8 @@ mc_status mc_expmv_create_stencil7(mc_expmv_t *out, int64_t nx, int64_t ny, int6
     CREATE_TRY(dalloc(&h->flags, 1));
     CREATE_TRY(host_malloc((void **)&h->flag_host, sizeof(uint32_t)));
     CREATE_TRY(dalloc(&h->counters, 2 * (int64_t)kMaxWalkGrid));
-    CREATE_TRY(dalloc(&h->srec, n));
+    CREATE_TRY(dalloc(&h->plain.rows, n));
+    CREATE_TRY(dalloc(&h->stail, n));
     CREATE_TRY(dalloc(&h->plain.d64, n));
     CREATE_TRY(dalloc(&h->plain.d32, n));
     // the faces and a_xx are needed only to build the state records and d
@@ -639,8 +641,9 @@ mc_status mc_expmv_create_stencil7(mc_expmv_t *out, int64_t nx, int64_t ny, int6
     if (e == hipSuccess) e = hipMemsetAsync(h->flags, 0, sizeof(uint32_t), h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->counters, 0, sizeof(unsigned long long), h->stream);
     if (e == hipSuccess)
-        e = launch_stencil_rows(n, nx, ny, faces, faces + n, faces + 2 * n, faces + 3 * n, h->srec,
-                                h->plain.d64, h->plain.d32, h->flags, h->counters, h->stream);
+        e = launch_stencil_rows(n, nx, ny, faces, faces + n, faces + 2 * n, faces + 3 * n,
+                                h->plain.rows, h->stail, h->plain.d64, h->plain.d32, h->flags,
+                                h->counters, h->stream);
     uint32_t f = 0;
     unsigned long long slots = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&f, h->flags, sizeof(f), hipMemcpyDeviceToHost, h->stream);
@@ -1021,8 +1024,8 @@ mc_status mc_expmv_stats(mc_expmv_t h, mc_expmv_run_stats *out) {
     const double row = 16.0 + dbytes;
     const double slot = 12.0 + (h->last_prop ? 8.0 : 0.0);
     out->alg_bytes = row * (double)(c[0]) + slot * (double)c[1] + dbytes * (double)h->last_walkers;
-    if (h->stencil)   // a 32-byte state record and d per visited state, nothing per jump
-        out->alg_bytes = (32.0 + dbytes) * (double)(c[0]) + dbytes * (double)h->last_walkers;
+    if (h->stencil)   // a row record and d per visited state, 16 B of thresholds per jump
+        out->alg_bytes = row * (double)(c[0]) + 16.0 * (double)c[1] + dbytes * (double)h->last_walkers;
     if (h->last_fwd) {
         // forward walks: per walker also the binary search over the cumulative
         // sums (8 B per step) and two FP64 read-modify-writes at the end node
@@ -1038,18 +1041,26 @@ mc_status mc_expmv_get_stencil(mc_expmv_t h, double *d, double *inv_r, uint32_t 
     HIP_TRY(hipSetDevice(h->dev));
     HIP_TRY(hipStreamSynchronize(h->stream));
     const size_t n = (size_t)h->n;
-    std::vector<StencilRec> rec(n);
+    std::vector<RowRec> head(n);
+    std::vector<uint4> tail(n);
     std::vector<double> dd(n);
     if (n > 0) {
-        HIP_TRY(hipMemcpy(rec.data(), h->srec, sizeof(StencilRec) * n, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(head.data(), h->plain.rows, sizeof(RowRec) * n, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(tail.data(), h->stail, sizeof(uint4) * n, hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(dd.data(), h->plain.d64, sizeof(double) * n, hipMemcpyDeviceToHost));
     }
     for (size_t i = 0; i < n; ++i) {
         if (d) d[i] = dd[i];
-        if (inv_r) inv_r[i] = rec[i].inv_r;
-        if (faces) faces[i] = rec[i].meta;
-        if (thr)
-            for (int j = 0; j < 5; ++j) thr[5 * i + (size_t)j] = rec[i].e[j];
+        if (inv_r) inv_r[i] = head[i].inv_r;
+        if (faces) faces[i] = head[i].deg;
+        if (thr) {
+            uint32_t *q = thr + 5 * i;
+            q[0] = head[i].begin;
+            q[1] = tail[i].x;
+            q[2] = tail[i].y;
+            q[3] = tail[i].z;
+            q[4] = tail[i].w;
+        }
     }
     return MC_OK;
 }

@@ -40,20 +40,17 @@ struct alignas(64) FatSlot {
     RowRec rs, ra;     // rows of s.self and s.alias
     double ds, da;     // d of s.self and s.alias
 };
-// State record of the matrix-free 7-point stencil, 32 bytes per node (one half
-// cache line): 1/r, which faces carry a rate, and the jump thresholds.  Faces of
-// x in column order are -z, -y, -x, +x, +y, +z (codes 0..5); with p_1 < ... < p_k
-// the faces of positive rate, the inverse-CDF jump with u = o2 2^-32 goes to
-// p_{1+m}, m = #{j < k : o2 > e[j-1]}: e[j-1] is the largest o2 whose u r stays
-// below the running sum of the faces up to p_j (found exactly at setup, so the
-// walk compares integers), and e[j-1] = 2^32 - 1 for j >= k (never counted).
-// The first 16 bytes read as a RowRec: deg = meta (non-zero iff k > 0), begin = e[0].
-struct alignas(32) StencilRec {
-    double inv_r;      // 1 / r_x (0 when k == 0)
-    uint32_t meta;     // k (bits 0..2) | p_j (3 bits at bit 3j, j = 1..k)
-    uint32_t e[5];
-};
-static_assert(sizeof(StencilRec) == 32, "two 16-byte halves");
+// State of a node of the matrix-free 7-point stencil: 1/r, which faces carry a
+// rate, and the jump thresholds, 32 bytes in two arrays -- a RowRec in `rows`
+// (deg = the face word, non-zero iff the node has an exit; begin = the first
+// threshold) read with the state as for the table walk, and the other four
+// thresholds (a uint4 in the tail array) read at a jump.  Faces of x in column
+// order are -z, -y, -x, +x, +y, +z (codes 0..5); with p_1 < ... < p_k the faces of
+// positive rate, the inverse-CDF jump with u = o2 2^-32 goes to p_{1+m},
+// m = #{j < k : o2 > e_j}: e_j is the largest o2 whose u r stays below the running
+// sum of the faces up to p_j (found exactly at setup, so the walk compares
+// integers), and e_j = 2^32 - 1 for j >= k (never counted).  The face word is
+// k (bits 0..2) | p_j (3 bits at bit 3j, j = 1..k).
 
 // Automatic choice (opts.slot_rows == 0): 64-byte slots when the row, d and slot
 // tables together exceed kFatAutoBytes, about the size past which they stop
@@ -117,9 +114,9 @@ struct InstArgs {
     double cond_max_rt;        // first-jump conditioning for start nodes with t <= this / r
     uint32_t resort;           // relabelled walks: re-sort a wave's walkers every this many events (0: never)
     uint32_t qmc;              // 1: first event from the randomised rank-1 lattice (backward walks)
-    // 7-point stencil without slots (srec null: the alias slots above): node
-    // x = i + nx (j + ny k) has state record srec[x] and d64 / d32 [x]; rows unused
-    const StencilRec *srec;
+    // 7-point stencil without slots (stail null: the alias slots above): node
+    // x = i + nx (j + ny k) has its state in rows[x], stail[x] and d64 / d32 [x]
+    const uint4 *stail;
     uint32_t nx, nxy;
 };
 
@@ -376,8 +373,8 @@ hipError_t launch_fat_slots(int64_t n, int64_t nnz, const Tables &tb, bool walk_
 
 // setup kernels (setup.hip)
 hipError_t launch_stencil_rows(int64_t n, int64_t nx, int64_t ny, const double *fx, const double *fy,
-                               const double *fz, const double *diag, StencilRec *srec, double *d64,
-                               float *d32, uint32_t *flags, unsigned long long *nslots,
+                               const double *fz, const double *diag, RowRec *rows, uint4 *stail,
+                               double *d64, float *d32, uint32_t *flags, unsigned long long *nslots,
                                hipStream_t s);
 hipError_t launch_check_rowptr(int64_t n, int64_t nnz, const int64_t *rowptr, uint32_t *flags,
                                hipStream_t s);

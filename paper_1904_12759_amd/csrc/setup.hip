@@ -256,8 +256,9 @@ __device__ uint32_t cdf_threshold(double c, double r) {
 // their threads check.
 __global__ void k_stencil_rows(int64_t n, int64_t nx, int64_t ny, const double *__restrict__ fx,
                                const double *__restrict__ fy, const double *__restrict__ fz,
-                               const double *__restrict__ diag, StencilRec *__restrict__ srec,
-                               double *__restrict__ d64, float *__restrict__ d32, uint32_t *flags,
+                               const double *__restrict__ diag, RowRec *__restrict__ rows,
+                               uint4 *__restrict__ stail, double *__restrict__ d64,
+                               float *__restrict__ d32, uint32_t *flags,
                                unsigned long long *nslots) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -282,20 +283,19 @@ __global__ void k_stencil_rows(int64_t n, int64_t nx, int64_t ny, const double *
         r = r + f[k];
         deg += f[k] > 0.0 ? 1u : 0u;
     }
-    StencilRec rec;
-    rec.inv_r = 0.0;
-    rec.meta = deg;
-    for (int j = 0; j < 5; ++j) rec.e[j] = 0xFFFFFFFFu;
+    double inv_r = 0.0;
+    uint32_t meta = deg;
+    uint32_t e[5] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
     if (deg > 0 && !bad) {
-        rec.inv_r = 1.0 / r;
-        if (!isfinite(rec.inv_r)) bad |= F_INVALID_ARG;
+        inv_r = 1.0 / r;
+        if (!isfinite(inv_r)) bad |= F_INVALID_ARG;
         double cum = 0.0;
         uint32_t j = 0;
         for (int k = 0; k < 6; ++k) {
             cum = cum + f[k];
             if (f[k] > 0.0) {
-                rec.meta |= (uint32_t)k << (3 + 3 * j);
-                if (j + 1 < deg) rec.e[j] = cdf_threshold(cum, r);
+                meta |= (uint32_t)k << (3 + 3 * j);
+                if (j + 1 < deg) e[j] = cdf_threshold(cum, r);
                 ++j;
             }
         }
@@ -304,19 +304,20 @@ __global__ void k_stencil_rows(int64_t n, int64_t nx, int64_t ny, const double *
     if (!isfinite(d)) bad |= F_NONFINITE;
     if (bad) atomicOr(flags, bad);
     if (cnt) atomicAdd(nslots, cnt);
-    srec[i] = rec;
+    rows[i] = RowRec{inv_r, meta, e[0]};
+    stail[i] = make_uint4(e[1], e[2], e[3], e[4]);
     d64[i] = d;
     d32[i] = (float)d;
 }
 
 hipError_t launch_stencil_rows(int64_t n, int64_t nx, int64_t ny, const double *fx, const double *fy,
-                               const double *fz, const double *diag, StencilRec *srec, double *d64,
-                               float *d32, uint32_t *flags, unsigned long long *nslots,
+                               const double *fz, const double *diag, RowRec *rows, uint4 *stail,
+                               double *d64, float *d32, uint32_t *flags, unsigned long long *nslots,
                                hipStream_t s) {
     if (n == 0) return hipSuccess;
     const int64_t grid = (n + 255) / 256;
     hipLaunchKernelGGL(k_stencil_rows, dim3((unsigned)grid), dim3(256), 0, s, n, nx, ny, fx, fy, fz,
-                       diag, srec, d64, d32, flags, nslots);
+                       diag, rows, stail, d64, d32, flags, nslots);
     return hipGetLastError();
 }
 

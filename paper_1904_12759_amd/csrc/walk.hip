@@ -227,7 +227,7 @@ void launch_shape(const WalkArgs &a, dim3 grid, int block, size_t lds, hipStream
     }
     // the matrix-free stencil walk (plain proposal, input order: checked at create)
     if constexpr (!PROP && FAT != 1) {
-        if (a.P.srec) {
+        if (a.P.stail) {
             hipLaunchKernelGGL((k_walk<MODE, FP32, false, TRACE, false, false, false, 0, false, true>), grid, dim3(block), lds, s, a);
             return;
         }

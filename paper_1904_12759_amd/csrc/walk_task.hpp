@@ -238,41 +238,22 @@ __device__ __forceinline__ bool jump_fat(const InstArgs &P, uint32_t js, uint32_
     return keep;
 }
 
-// Matrix-free 7-point stencil.  The first half of x's state record read as a row
-// record (deg = the face word, non-zero iff x has an exit; begin = the first
-// threshold).
-__device__ __forceinline__ RowRec stencil_head(const InstArgs &P, uint32_t x) {
-    const uint4 h = reinterpret_cast<const uint4 *>(P.srec)[2 * (size_t)x];
-    RowRec r;
-    r.inv_r = __hiloint2double((int)h.y, (int)h.x);
-    r.deg = h.z;
-    r.begin = h.w;
-    return r;
-}
-
-// The jump from x by the inverse-CDF rule over its six faces in column order
-// (-z, -y, -x, +x, +y, +z): the first face whose running sum of rates exceeds
-// u r, u = o2 2^-32 in [0, 1), or the last face with a rate when rounding leaves
-// u r at or above the sum.  The record's thresholds turn that into a count of
-// integer comparisons; meta and e0 are the head's face word and first threshold,
-// the other four come from the record's second half.  The neighbour comes from
-// the index.
+// Matrix-free 7-point stencil: the jump from x by the inverse-CDF rule over its
+// six faces in column order (-z, -y, -x, +x, +y, +z): the first face whose running
+// sum of rates exceeds u r, u = o2 2^-32 in [0, 1), or the last face with a rate
+// when rounding leaves u r at or above the sum.  The state's thresholds turn that
+// into a count of integer comparisons; meta and e0 (the face word and the first
+// threshold) came with the row record, the other four are read here.  The
+// neighbour comes from the index.
 __device__ __forceinline__ uint32_t stencil_jump(const InstArgs &P, uint32_t x, uint32_t meta,
                                                  uint32_t e0, uint32_t o2) {
-    const uint4 e = reinterpret_cast<const uint4 *>(P.srec)[2 * (size_t)x + 1];
+    const uint4 e = P.stail[x];
     const uint32_t m = (o2 > e0 ? 1u : 0u) + (o2 > e.x ? 1u : 0u) + (o2 > e.y ? 1u : 0u) +
                        (o2 > e.z ? 1u : 0u) + (o2 > e.w ? 1u : 0u);
     const uint32_t face = (meta >> (3u + 3u * m)) & 7u;
     const uint32_t axis = face < 3u ? 2u - face : face - 3u;     // 0: x, 1: y, 2: z
     const uint32_t step = axis == 0u ? 1u : axis == 1u ? P.nx : P.nxy;
     return face < 3u ? x - step : x + step;
-}
-
-// A walker's state record: the stencil's head, else the row table's.
-template <bool LOC, bool STENCIL>
-__device__ __forceinline__ RowRec state_at(const InstArgs &P, uint32_t x) {
-    if constexpr (STENCIL) return stencil_head(P, x);
-    else return row_at<LOC>(P, x);
 }
 
 // Walk id of an original node, and back (identity without relabelling).
@@ -603,7 +584,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             const uint32_t x0 = walk_id<LOC>(P, node);
             RowRec r0;
             WT d0;
-            r0 = state_at<LOC, STENCIL>(P, x0);
+            r0 = row_at<LOC>(P, x0);
             d0 = d_at<FP32, LOC>(P, x0);
             const WT v0 = load_v<FP32>(P.v, node);
             K = (double)(wexp<FP32>(final_term<MODE, FP32>(d0, 0.0, 0, P)) * v0);
@@ -760,7 +741,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         uint32_t deg = 0, begin = 0;
         WT dx = (WT)0;
         if (active) {
-            const RowRec rr = state_at<LOC, STENCIL>(P, x);
+            const RowRec rr = row_at<LOC>(P, x);
             inv_r = rr.inv_r;
             deg = rr.deg;
             begin = rr.begin;
@@ -848,7 +829,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                         bool keep = true;
                         if constexpr (STENCIL) {
                             x = stencil_jump(P, x, deg, begin, o.z);
-                            const RowRec rr = stencil_head(P, x);
+                            const RowRec rr = row_at<false>(P, x);
                             inv_r = rr.inv_r;
                             deg = rr.deg;
                             begin = rr.begin;
@@ -908,7 +889,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     ev = 0;
                     ju = 0;
                     ka = 0;
-                    const RowRec rr = state_at<LOC, STENCIL>(P, x);
+                    const RowRec rr = row_at<LOC>(P, x);
                     inv_r = rr.inv_r;
                     deg = rr.deg;
                     begin = rr.begin;
