@@ -38,7 +38,15 @@ __device__ __forceinline__ double log_unit(double u) {
         m = m + m;
         e -= 1;
     }
-    const double f = (m - 1.0) / (m + 1.0);
+    // f = (m - 1) / (m + 1), m + 1 in [1.7, 2.5): the hardware reciprocal, two
+    // Newton steps and a residual correction (within an ulp of the quotient; no
+    // operand scaling or special cases are needed in this range)
+    const double a = m - 1.0, b = m + 1.0;
+    double y = __builtin_amdgcn_rcp(b);
+    y = fma(fma(-b, y, 1.0), y, y);
+    y = fma(fma(-b, y, 1.0), y, y);
+    const double q0 = a * y;
+    const double f = fma(fma(-b, q0, a), y, q0);
     const double f2 = f * f;
     double p = sconst(1.0 / 25.0);
     p = fma(p, f2, sconst(1.0 / 23.0));
@@ -750,7 +758,8 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
         uint32_t next = WAVE;
         uint32_t since_sort = 0;
 
-        while (__ballot(active) != 0ull) {
+        // (tested at the bottom: lane 0 is active iff the list is not empty)
+        if (nlist > 0) do {
             if constexpr (LOC && RESORT) {
                 // relabelled tables: every P.resort events the walkers move to the
                 // lanes of their sorted current walk ids, so that neighbouring lanes
@@ -899,7 +908,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 }
             }
             next += (uint32_t)__popcll(fmask);
-        }
+        } while (__ballot(active) != 0ull);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
