@@ -259,9 +259,12 @@ __device__ __forceinline__ uint32_t stencil_jump(const InstArgs &P, uint32_t x, 
     const uint32_t m = (o2 > e0 ? 1u : 0u) + (o2 > e.x ? 1u : 0u) + (o2 > e.y ? 1u : 0u) +
                        (o2 > e.z ? 1u : 0u) + (o2 > e.w ? 1u : 0u);
     const uint32_t face = (meta >> (3u + 3u * m)) & 7u;
-    const uint32_t axis = face < 3u ? 2u - face : face - 3u;     // 0: x, 1: y, 2: z
-    const uint32_t step = axis == 0u ? 1u : axis == 1u ? P.nx : P.nxy;
-    return face < 3u ? x - step : x + step;
+    // |x offset| 1, nx or nx ny for the x, y or z axis, selected without branches
+    const bool lower = face < 3u;
+    const uint32_t axis = lower ? 2u - face : face - 3u;          // 0: x, 1: y, 2: z
+    const uint32_t step = 1u + ((P.nx - 1u) & (0u - (uint32_t)(axis != 0u))) +
+                          ((P.nxy - P.nx) & (0u - (uint32_t)(axis == 2u)));
+    return x + (lower ? 0u - step : step);
 }
 
 // Walk id of an original node, and back (identity without relabelling).
@@ -872,7 +875,6 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                             if (L.q[e] > 0.0) f = (WT)(L.K[e] + L.q[e] * (double)f);
                         }
                     }
-                    if (!isfinite((double)f)) err |= F_OVERFLOW;
                     L.fval[wl] = f;
                     evs += ev;
                     jus += ju;
@@ -942,6 +944,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     if (n0 && !isfinite(K)) err |= F_OVERFLOW;
                     double s1 = 0.0;
                     for (uint32_t i = 0; i < J; ++i) s1 += (double)L.fval[b0 + i];
+                    if (!isfinite(s1)) err |= F_OVERFLOW;      // a walker's value is not finite
                     mean = n0 ? (nn0 * K + s1) / count : s1 / count;
                     double s2 = 0.0;
                     for (uint32_t i = 0; i < J; ++i) {
@@ -990,6 +993,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             double s1 = 0.0;
             for (uint32_t i = rl; i < J; i += 16) s1 += (double)L.fval[b0 + i];
             s1 = row_sum_f64(s1);
+            if (act && !isfinite(s1)) err |= F_OVERFLOW;
             double mean = n0 ? (nn0 * K + s1) / count : s1 / count;
             double s2 = 0.0;
             for (uint32_t i = rl; i < J; i += 16) {
@@ -1031,6 +1035,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 double s1 = 0.0;
                 for (uint32_t i = lane; i < J; i += WAVE) s1 += (double)L.fval[b0 + i];
                 s1 = wave_sum_f64(s1);
+                if (!isfinite(s1)) err |= F_OVERFLOW;
                 mean = n0 ? (nn0 * K + s1) / count : s1 / count;
                 double s2 = 0.0;
                 for (uint32_t i = lane; i < J; i += WAVE) {

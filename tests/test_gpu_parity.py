@@ -273,6 +273,27 @@ def test_fp32_start_value_overflow_taken_by_walkers_is_reported():
     assert np.isfinite(est.item())
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_walker_value_overflow_is_reported_in_every_statistics_tier(fp32):
+    """Walkers that jump from node 0 (d = 0) into node 1 (d = 201, or 2001 with FP64
+    weights) and hold there pick up e^{d (t - s)} beyond the weight type's range: a
+    listed walker's value is infinite, which each per-entry reduction (one lane for
+    up to 32 listed walkers, a row of 16 lanes up to 256, the wave beyond) reports
+    as MC_ERR_OVERFLOW; the start value K = v[0] stays finite."""
+    big = 200.0 if fp32 else 2000.0
+    a = np.array([[-1.0, 1.0], [1.0, big]])
+    c = wl.from_dense(a)
+    for nwalk in (40, 300, 3000):            # about 25, 190 and 1900 listed walkers
+        g = mc.MCExpmv(c.rowptr, c.col, c.val, 1.0, 7, fp32=fp32)
+        with pytest.raises(mc.MCError) as ei:
+            g.entries(np.ones(2), [0], nwalk)
+        assert ei.value.code == 9, nwalk
+    # a hold short enough to stay in range: no error
+    g = mc.MCExpmv(c.rowptr, c.col, c.val, 0.01, 7, fp32=fp32)
+    est, _ = g.entries(np.ones(2), [0], 3000)
+    assert np.isfinite(est.item())
+
+
 @pytest.mark.parametrize("kind,code", [("negative", 2), ("nan", 3), ("col", 1), ("rowptr", 1)])
 def test_create_rejects_invalid_matrices(kind, code):
     a = np.array([[-1.0, 0.5, 0.0], [0.5, -1.0, 0.5], [0.0, 0.5, -1.0]])
