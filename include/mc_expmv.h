@@ -572,13 +572,14 @@ mc_status mc_isim(int64_t n, const double *x, const double *y, int64_t k, double
  * checking their accuracy:  fn = MC_FN_LOG: y = log x (the logarithm of the
  * holding time S = -log(U) / r, Eq. (paths); x in (0, 1]), MC_FN_EXP: y = e^x
  * (the FP64 weights W of Theorem 1), MC_FN_ONE_MINUS_EXP_NEG: y = 1 - e^{-x}
- * for x >= 0 (first-jump conditioning).
+ * for x >= 0 (first-jump conditioning), MC_FN_EXP_F32: y = e^x in FP32 for x
+ * rounded to FP32 (the FP32 weights; 0 below -104, +inf beyond the range).
  *   x, y     device double[n]
  *   stream   hipStream_t or NULL
  * Errors: MC_ERR_INVALID_ARG (fn, n < 0, null pointer), MC_ERR_DEVICE.
  * Asynchronous on stream.
  */
-enum { MC_FN_LOG = 0, MC_FN_EXP = 1, MC_FN_ONE_MINUS_EXP_NEG = 2 };
+enum { MC_FN_LOG = 0, MC_FN_EXP = 1, MC_FN_ONE_MINUS_EXP_NEG = 2, MC_FN_EXP_F32 = 3 };
 mc_status mc_math_eval(int32_t fn, const double *x, double *y, int64_t n, void *stream);
 
 #ifdef __cplusplus

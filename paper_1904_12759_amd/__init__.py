@@ -257,11 +257,11 @@ def isim(x, y, k: int | None = None, stream=None) -> float:
     return out.value
 
 
-MATH_FNS = {"log": 0, "exp": 1, "one_minus_exp_neg": 2}
+MATH_FNS = {"log": 0, "exp": 1, "one_minus_exp_neg": 2, "exp_f32": 3}
 
 
 def math_eval(fn: str, x):
-    """The walk kernels' own FP64 log / exp / 1 - e^{-x} on a vector (``mc_math_eval``),
+    """The walk kernels' own FP64 log / exp / 1 - e^{-x} and FP32 exp on a vector (``mc_math_eval``),
     returned as a device tensor."""
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())

@@ -684,7 +684,7 @@ mc_status mc_expmv_entries_noalloc(mc_expmv_t h, const void *v, const int64_t *i
 }
 
 mc_status mc_math_eval(int32_t fn, const double *x, double *y, int64_t n, void *stream) {
-    if (fn < MC_FN_LOG || fn > MC_FN_ONE_MINUS_EXP_NEG || n < 0) return MC_ERR_INVALID_ARG;
+    if (fn < MC_FN_LOG || fn > MC_FN_EXP_F32 || n < 0) return MC_ERR_INVALID_ARG;
     if (n > 0 && (!x || !y)) return MC_ERR_INVALID_ARG;
     HIP_TRY(launch_math_eval(fn, x, y, n, (hipStream_t)stream));
     return MC_OK;

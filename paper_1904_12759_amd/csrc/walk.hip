@@ -196,7 +196,10 @@ __global__ void k_math_eval(int fn, const double *__restrict__ x, double *__rest
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double a = x[i];
-    y[i] = fn == 0 ? log_unit(a) : fn == 1 ? exp_f64(a) : one_minus_exp_neg(a);
+    y[i] = fn == 0   ? log_unit(a)
+           : fn == 1 ? exp_f64(a)
+           : fn == 2 ? one_minus_exp_neg(a)
+                     : (double)exp_f32((float)a);
 }
 
 hipError_t launch_math_eval(int fn, const double *x, double *y, int64_t n, hipStream_t s) {

@@ -300,10 +300,25 @@ __device__ __forceinline__ uint32_t sorted_source(uint32_t x, bool active, int l
     return (uint32_t)(key & (WAVE - 1));
 }
 
+// e^x in FP32 for the FP32 weights: x log2(e) = p + c exactly to about 2^-48
+// (p the rounded product, c its rounding error by an FMA plus x times the low
+// part of log2(e)), k = rint(p), then 2^((p - k) + c) from the hardware exp2
+// (|p - k + c| <= 1/2) scaled by 2^k.  Within a few ulp; overflow gives +inf
+// through the scaling, and x below -104 (beyond the smallest denormal, and
+// -inf) gives 0.
+__device__ __forceinline__ float exp_f32(float x) {
+    const float p = x * 1.44269502f;
+    const float c = fmaf(x, 1.92596299e-8f, fmaf(x, 1.44269502f, -p));
+    const float k = rintf(p);
+    const float y = __builtin_amdgcn_exp2f((p - k) + c);
+    const float r = ldexpf(y, (int)k);
+    return x < -104.0f ? 0.0f : r;
+}
+
 template <bool FP32>
 __device__ __forceinline__ typename WeightT<FP32>::T wexp(typename WeightT<FP32>::T x) {
     if constexpr (FP32)
-        return expf(x);
+        return exp_f32(x);
     else
         return exp_f64(x);
 }

@@ -788,6 +788,31 @@ def test_wave_resort_does_not_change_results(fp32):
             assert np.array_equal(x, y)
 
 
+def test_walk_fp32_exp_within_two_ulp():
+    """The FP32 weights' own e^x (x log2 e split in two, the hardware exp2, scaling
+    by 2^k) against the correctly rounded FP32 value (long double, rounded), within 2
+    ulp of FP32 over the normal range, and its ends: 0 below -104 and for -inf,
+    denormals near the bottom of the range, +inf above it."""
+    rng = np.random.default_rng(12)
+    x = np.concatenate([rng.uniform(-87.0, 88.7, 200_000), rng.uniform(-1, 1, 50_000),
+                        rng.normal(0, 1e-3, 20_000), [0.0, -0.0, 1.0, -1.0, 88.0, -87.0]])
+    x = x.astype(np.float32).astype(np.float64)
+    y = mc.math_eval("exp_f32", x).cpu().numpy()
+    ref = np.exp(x.astype(np.longdouble)).astype(np.float32).astype(np.float64)
+    ulp = np.spacing(ref.astype(np.float32)).astype(np.float64)
+    err = np.abs(y - ref) / ulp
+    k = int(np.argmax(err))
+    print(f"exp_f32: max error {float(err[k]):.3f} ulp at x = {x[k]!r}", flush=True)
+    assert float(err.max()) <= 2.0
+    ends = np.array([-np.inf, -104.5, -200.0, 89.0, 100.0, -95.0, -100.0])
+    ye = mc.math_eval("exp_f32", ends).cpu().numpy()
+    assert ye[0] == 0.0 and ye[1] == 0.0 and ye[2] == 0.0
+    assert np.isposinf(ye[3]) and np.isposinf(ye[4])
+    for xe, v in zip(ends[5:], ye[5:]):           # FP32 denormals, to their spacing
+        r = float(np.float32(np.exp(np.longdouble(xe))))
+        assert 0.0 < v and abs(v - r) <= 2 * 2.0 ** -149, (xe, v, r)
+
+
 @pytest.mark.parametrize("mode,cond,prop", [(mc.LIE, False, False), (mc.EXACT, True, False),
                                             (mc.EXACT, False, True)])
 def test_wave_resort_other_walks(mode, cond, prop):
