@@ -26,6 +26,18 @@ __device__ __forceinline__ double sconst(double c) {
     return c;
 }
 
+// The lanes of the wave where b holds, as a 64-bit mask (the compiler's own
+// ballot of a bool, without the detour through an int that __ballot takes).
+__device__ __forceinline__ unsigned long long lanes_where(bool b) {
+    return __builtin_amdgcn_ballot_w64(b);
+}
+
+// Number of lanes below this one whose bit is set in mask (mbcnt on the two halves).
+__device__ __forceinline__ uint32_t set_below(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 // Natural logarithm of u in (0, 1].  With u = m 2^e, m in [1/sqrt2, sqrt2),
 // log u = e ln2 + 2 atanh(f), f = (m-1)/(m+1), |f| < 0.1716, and atanh(f)/f is
 // the Taylor series sum_k f^{2k}/(2k+1), kept to f^24 (truncation < 1e-19).
@@ -571,7 +583,6 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                                           unsigned long long &my_jumps, uint32_t &err_out) {
     using WT = typename WeightT<FP32>::T;
     const int lane = threadIdx.x & (WAVE - 1);
-    const unsigned long long lanemask_lt = (1ull << lane) - 1ull;
     const double t = P.t;
     uint32_t err = 0;
     // the task's shape is the same in every lane: scalar registers and scalar branches
@@ -708,25 +719,27 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     }
                     const uint32_t w = b + (uint32_t)lane;
                     const bool valid = w < cg;
-                    bool go = false;
-                    if (valid) {
-                        const uint32_t wo = og + w;
-                        U4 o;
-                        if constexpr (QMC) {
-                            o = lattice_words(one_rep ? shift
-                                                      : philox(kQmcShiftMark, wo >> qb, node, P.inst,
-                                                               P.key0, P.key1),
-                                              wo, qb);
-                        } else {
-                            o = philox(0u, wo, node, P.inst, P.key0, P.key1);
-                        }
-                        const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
-                        go = m + 1ull >= m_thr;
+                    // drawn in every lane (a lane past the entry's walkers would idle
+                    // under the exec mask anyway), so that `go` needs no branch
+                    const uint32_t wo = og + w;
+                    U4 o;
+                    if constexpr (QMC) {
+                        o = lattice_words(one_rep ? shift
+                                                  : philox(kQmcShiftMark, wo >> qb, node, P.inst,
+                                                           P.key0, P.key1),
+                                          wo, qb);
+                    } else {
+                        o = philox(0u, wo, node, P.inst, P.key0, P.key1);
                     }
-                    const unsigned long long gmask = __ballot(go);
-                    if (go) L.list[nlist + (uint32_t)__popcll(gmask & lanemask_lt)] = (uint16_t)((g << 10) | w);
+                    const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
+                    const bool up = m >= m_thr - 1ull;
+                    const bool go = valid && up;
+                    // ballots of single comparisons, combined on the scalar unit
+                    const unsigned long long vmask = lanes_where(valid);
+                    const unsigned long long gmask = vmask & lanes_where(up);
+                    if (go) L.list[nlist + set_below(gmask)] = (uint16_t)((g << 10) | w);
                     nlist += (uint32_t)__popcll(gmask);
-                    stay += (uint32_t)__popcll(__ballot(valid && !go));
+                    stay += (uint32_t)__popcll(vmask & ~gmask);
                     if constexpr (TRACE) {
                         if (valid && !go) {
                             tr.x[tr.base + w] = (int32_t)node;
@@ -902,9 +915,9 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     }
                 }
             }
-            const unsigned long long fmask = __ballot(fin);
+            const unsigned long long fmask = lanes_where(fin);
             if (fin) {
-                wl = next + (uint32_t)__popcll(fmask & lanemask_lt);
+                wl = next + set_below(fmask);
                 if (wl < nlist) {
                     code = L.list[wl];
                     node = L.node[code >> 10];
@@ -925,7 +938,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 }
             }
             next += (uint32_t)__popcll(fmask);
-        } while (__ballot(active) != 0ull);
+        } while (lanes_where(active) != 0ull);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -942,8 +955,8 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             const uint32_t g = g_begin + (uint32_t)lane;
             const bool in = g < g_end;
             const uint32_t b0 = in ? L.seg[g] : 0u, J = in ? L.seg[g + 1] - b0 : 0u;
-            rowm = __ballot(in && J > kShortSeg && J <= kRowSeg);
-            widem = __ballot(in && J > kRowSeg);
+            rowm = lanes_where(in && J > kShortSeg && J <= kRowSeg);
+            widem = lanes_where(in && J > kRowSeg);
             if (in && J <= kShortSeg) {
                 double mean, m2, count;
                 if (L.node[g] == 0xFFFFFFFFu) {
