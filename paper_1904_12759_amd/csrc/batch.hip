@@ -60,11 +60,13 @@ __device__ __forceinline__ void do_task(const BatchArgs &a, const int64_t *tb, i
 }
 
 // Persistent kernel over the tasks of one class.  Dynamic LDS: one task
-// scratch per wave.
+// scratch per wave, then the class's task offsets (ninst of them: sized to the
+// class, so that a small batch leaves the LDS to more resident waves).
 template <int MODE, bool FP32>
 __global__ __launch_bounds__(256) void k_walk_batched(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char dyn_lds[];
-    __shared__ int64_t sh_tb[kMaxBatch];
+    int64_t *sh_tb = reinterpret_cast<int64_t *>(
+        dyn_lds + (size_t)(blockDim.x / WAVE) * sizeof(GroupLds<typename WeightT<FP32>::T>));
     __shared__ unsigned long long sh_count[256 / WAVE][2];
     for (int i = threadIdx.x; i < a.ninst; i += blockDim.x) sh_tb[i] = a.inst[i].task_begin - a.task0;
     __syncthreads();
@@ -168,7 +170,8 @@ hipError_t launch_batch(const BatchArgs &base, const BatchClass *classes, int nc
             if (e != hipSuccess) return e;
         }
         const size_t lds =
-            (size_t)(block / WAVE) * (C.fp32 ? sizeof(GroupLds<float>) : sizeof(GroupLds<double>));
+            (size_t)(block / WAVE) * (C.fp32 ? sizeof(GroupLds<float>) : sizeof(GroupLds<double>)) +
+            sizeof(int64_t) * (size_t)C.ninst;
 #define MC_BATCH(M, F) hipLaunchKernelGGL((k_walk_batched<M, F>), dim3((unsigned)grid), dim3(block), lds, s, a)
         switch (C.mode * 2 + (C.fp32 ? 1 : 0)) {
             case MC_EXACT * 2: MC_BATCH(MC_EXACT, false); break;
