@@ -315,15 +315,17 @@ __device__ __forceinline__ uint32_t sorted_source(uint32_t x, bool active, int l
 // e^x in FP32 for the FP32 weights: x log2(e) = p + c exactly to about 2^-48
 // (p the rounded product, c its rounding error by an FMA plus x times the low
 // part of log2(e)), k = rint(p), then 2^((p - k) + c) from the hardware exp2
-// (|p - k + c| <= 1/2) scaled by 2^k.  Within a few ulp; overflow gives +inf
-// through the scaling, and x below -104 (beyond the smallest denormal, and
-// -inf) gives 0.
+// (|p - k + c| <= 1/2) scaled by 2^k.  Within 2 ulp; a finite x beyond the
+// range gives +inf through the scaling, x below -104 (past the smallest
+// denormal, and -inf) gives 0, NaN and +inf give NaN.  k is clamped to
+// [-512, 512] before its conversion to an integer (a no-op wherever the result
+// is kept), so that the conversion is defined for every x.
 __device__ __forceinline__ float exp_f32(float x) {
     const float p = x * 1.44269502f;
     const float c = fmaf(x, 1.92596299e-8f, fmaf(x, 1.44269502f, -p));
     const float k = rintf(p);
     const float y = __builtin_amdgcn_exp2f((p - k) + c);
-    const float r = ldexpf(y, (int)k);
+    const float r = ldexpf(y, (int)__builtin_amdgcn_fmed3f(k, -512.0f, 512.0f));
     return x < -104.0f ? 0.0f : r;
 }
 
