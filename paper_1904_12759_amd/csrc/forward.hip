@@ -77,7 +77,6 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs a) {
     using WT = typename WeightT<FP32>::T;
     __shared__ double ys[kFwdChunk];
     const int lane = threadIdx.x & (WAVE - 1);
-    const unsigned long long lanemask_lt = (1ull << lane) - 1ull;
     const InstArgs &P = a.P;
     const double t = P.t;
     const double V = a.n > 0 ? a.cdf[a.n - 1] : 0.0;
@@ -127,7 +126,8 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs a) {
             };
             if (active) start(wl);
             uint32_t next = WAVE;
-            while (__ballot(active) != 0ull) {
+            // (tested at the bottom: lane 0 is active iff the chunk has walkers)
+            if (cnt > 0) do {
                 bool fin = false;
                 if (active) {
                     if (deg == 0) {
@@ -190,14 +190,14 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs a) {
                         }
                     }
                 }
-                const unsigned long long fmask = __ballot(fin);
+                const unsigned long long fmask = lanes_where(fin);
                 if (fin) {
-                    wl = next + (uint32_t)__popcll(fmask & lanemask_lt);
+                    wl = next + set_below(fmask);
                     if (wl < cnt) start(wl);
                     else active = false;
                 }
                 next += (uint32_t)__popcll(fmask);
-            }
+            } while (lanes_where(active) != 0ull);
         }
         __syncthreads();
         // chunk statistics of Y in ordinal order: two passes, fixed DPP tree
