@@ -26,8 +26,7 @@ __device__ __forceinline__ double sconst(double c) {
     return c;
 }
 
-// The lanes of the wave where b holds, as a 64-bit mask (the compiler's own
-// ballot of a bool, without the detour through an int that __ballot takes).
+// The lanes of the wave where b holds, as a 64-bit mask.
 __device__ __forceinline__ unsigned long long lanes_where(bool b) {
     return __builtin_amdgcn_ballot_w64(b);
 }
