@@ -705,6 +705,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
             } else {
                 // U >= e0  <=>  m + 1 >= e0 2^53 (U = (m+1) 2^-53 exactly), i.e. m + 1 >= ceil(e0 2^53)
                 const uint64_t m_thr = (uint64_t)ceil(eg * 0x1p53);
+                const uint64_t t_pair = (((m_thr - 1ull) >> 21) << 32) | (((m_thr - 1ull) & 0x1FFFFFull) << 11);
                 // lattice first events: a chunk starting on a replicate boundary is one
                 // replicate (every run but a per-walker trace from an unaligned
                 // ordinal), whose shift the whole entry shares
@@ -732,8 +733,10 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     } else {
                         o = philox(0u, wo, node, P.inst, P.key0, P.key1);
                     }
-                    const uint64_t m = ((uint64_t)o.x << 21) | ((uint64_t)o.y >> 11);
-                    const bool up = m >= m_thr - 1ull;
+                    // m = o.x 2^21 + (o.y >> 11) >= T = m_thr - 1 compared without forming
+                    // m: with T = A 2^21 + B (B < 2^21) it holds iff o.x > A, or o.x = A
+                    // and o.y >= B 2^11, i.e. iff the word pair (o.x, o.y) >= (A, B 2^11)
+                    const bool up = (((uint64_t)o.x << 32) | o.y) >= t_pair;
                     const bool go = valid && up;
                     // ballots of single comparisons, combined on the scalar unit
                     const unsigned long long vmask = lanes_where(valid);
