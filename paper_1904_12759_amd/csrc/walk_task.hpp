@@ -26,6 +26,11 @@ __device__ __forceinline__ double sconst(double c) {
     return c;
 }
 
+// Predicates of the compiler's lane-mask comparisons (the integer comparison
+// codes of its IR): unsigned >= and unsigned <.
+constexpr int kCmpUge = 35;
+constexpr int kCmpUlt = 36;
+
 // The lanes of the wave where b holds, as a 64-bit mask.
 __device__ __forceinline__ unsigned long long lanes_where(bool b) {
     return __builtin_amdgcn_ballot_w64(b);
@@ -740,7 +745,11 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                     const bool go = valid && up;
                     // ballots of single comparisons, combined on the scalar unit
                     const unsigned long long vmask = lanes_where(valid);
-                    const unsigned long long gmask = vmask & lanes_where(up);
+                    // (the ballot taken by the comparison itself: a ballot of the bool
+                    // `up` would turn it into a vector value and back)
+                    const unsigned long long gmask =
+                        vmask & __builtin_amdgcn_uicmpl(((uint64_t)o.x << 32) | o.y, t_pair,
+                                                        kCmpUge);
                     if (go) L.list[nlist + set_below(gmask)] = (uint16_t)((g << 10) | w);
                     nlist += (uint32_t)__popcll(gmask);
                     stay += (uint32_t)__popcll(vmask & ~gmask);
@@ -942,7 +951,7 @@ __device__ __forceinline__ void run_group(const InstArgs &P, const int64_t *idx,
                 }
             }
             next += (uint32_t)__popcll(fmask);
-        } while (lanes_where(active) != 0ull);
+        } while (__builtin_amdgcn_uicmp(wl, nlist, kCmpUlt) != 0ull);   // = lanes_where(active)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
